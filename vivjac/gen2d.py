@@ -1,0 +1,329 @@
+"""2D synthetic Jacobian: rectangle [0,4]x[0,2] with a square hole (the cylinder).
+
+Construction (all readings of the paper's silent points are listed in the
+project design notes; each is restated here where it is used):
+
+* Mesh: nx x ny cells, each split along its (i,j)->(i+1,j+1) diagonal.  The
+  hole is the cell block [nx/2-a, nx/2+a) x [ny/2-b, ny/2+b) with
+  a = max(1, nx//16), b = max(1, ny//8), i.e. the same physical square at every
+  refinement.  P2 nodes are exactly the half-cell lattice points of fluid cells.
+* Unknowns (Sec. 3.3): Taylor-Hood P2 velocity u and P1 pressure p, P2 mesh
+  displacement d, P2 multiplier lambda on the hole boundary Gamma, and the two
+  rigid-position dofs s of the global position master (Sec. 4.2, last scheme,
+  with a single partition).
+* Numbering: u (P2 nodes in lexicographic (ix, iy) lattice order, component
+  fastest), p (P1 vertices, same order), d, lambda, s.
+* Boundary conditions (eq. flowBC, eq. psBC): inlet x=0 removes both u
+  components; the slip walls y=0, y=2 remove u_y; the outflow x=4 is natural.
+  d is fixed on x=0 and x=4 and slides (d_y removed) on y=0, y=2.  Dirichlet
+  dofs are removed from the system, not kept as identity rows.
+* Blocks (eq. weak_system, Jacobian of Sec. 3.2):
+    u rows: alpha0 (v,u) + (v,(w.grad)u) + 2 nu (eps(v),eps(u)) - (div v, p)
+            - <v, lambda>_Gamma
+    p rows: -(q, div u)
+    d rows: (lam_s div dhat div d + 2 mu_s eps(dhat):eps(d)), lam_s = mu_s = 1/|K|
+    lambda rows: -<mu, u>_Gamma + alpha0 <mu, 1> s   (no-slip u = d/dt x with
+            x = X + s on Gamma, BDF1 coefficient alpha0 = 1/dt)
+    d rows on Gamma: d_{i,c} - s_c = 0 (position masters, eq. coupling_constraint)
+    s rows: k s_c + sum_j m_j lambda_{j,c} = 0 with m_j = int_Gamma phi_j
+            (spring balance, eq. solid_balance, F_fluid = -int lambda)
+* Quadrature: the 7-point degree-5 Radon rule (exact for every volume term);
+  Gamma terms use the exact P2 edge mass matrix.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclass
+class System:
+    """One coupled Jacobian in CSR form plus its seeded right-hand-side stream."""
+
+    n: int
+    rowptr: np.ndarray          # int64[n+1]
+    colind: np.ndarray          # int32[nnz]
+    values: np.ndarray          # float64[nnz], Newton step 0
+    root: np.ndarray            # int32[2]: the rigid-position dofs s
+    blocks: dict                # name -> (start, end) dof range
+    meta: dict = field(default_factory=dict)
+    b0: np.ndarray | None = None  # float64[nrhs0, n]: step-0 right-hand sides
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self, values=None):
+        v = self.values if values is None else values
+        return sp.csr_matrix((v, self.colind, self.rowptr), shape=(self.n, self.n))
+
+
+# ---------------------------------------------------------------- quadrature
+def radon7():
+    """Degree-5, 7-point rule on the reference triangle (area 1/2)."""
+    r = np.sqrt(15.0)
+    a = (6.0 - r) / 21.0
+    b = (6.0 + r) / 21.0
+    wa = (155.0 - r) / 1200.0
+    wb = (155.0 + r) / 1200.0
+    pts = np.array([[1 / 3, 1 / 3],
+                    [a, a], [1 - 2 * a, a], [a, 1 - 2 * a],
+                    [b, b], [1 - 2 * b, b], [b, 1 - 2 * b]])
+    w = np.array([9 / 40, wa, wa, wa, wb, wb, wb]) * 0.5
+    return pts, w
+
+
+def p2_tri(pts):
+    """P2 basis values (Q,6) and reference gradients (Q,6,2) on the triangle.
+
+    Local order: vertices 0,1,2 then edge midpoints (0,1), (1,2), (2,0)."""
+    xi, eta = pts[:, 0], pts[:, 1]
+    L = np.stack([1 - xi - eta, xi, eta], axis=1)
+    dL = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])
+    Q = pts.shape[0]
+    phi = np.empty((Q, 6))
+    g = np.empty((Q, 6, 2))
+    for v in range(3):
+        phi[:, v] = L[:, v] * (2 * L[:, v] - 1)
+        g[:, v, :] = (4 * L[:, v] - 1)[:, None] * dL[v][None, :]
+    for e, (a, b) in enumerate([(0, 1), (1, 2), (2, 0)]):
+        phi[:, 3 + e] = 4 * L[:, a] * L[:, b]
+        g[:, 3 + e, :] = 4 * (L[:, b][:, None] * dL[a][None, :] + L[:, a][:, None] * dL[b][None, :])
+    return phi, g, L
+
+
+# ---------------------------------------------------------------- assembly
+class _Triplets:
+    """COO triplets; removed dofs carry index -1 and are dropped once at the end."""
+
+    def __init__(self):
+        self.r, self.c, self.v = [], [], []
+
+    def add(self, rows, cols, vals):
+        rows = np.asarray(rows, dtype=np.int32)
+        cols = np.asarray(cols, dtype=np.int32)
+        vals = np.asarray(vals, dtype=np.float64)
+        shape = np.broadcast_shapes(rows.shape, cols.shape, vals.shape)
+        self.r.append(np.broadcast_to(rows, shape).ravel())
+        self.c.append(np.broadcast_to(cols, shape).ravel())
+        self.v.append(np.broadcast_to(vals, shape).ravel())
+
+    def csr(self, n, drop_rows=None):
+        r = np.concatenate(self.r)
+        c = np.concatenate(self.c)
+        v = np.concatenate(self.v)
+        keep = (r >= 0) & (c >= 0)
+        if drop_rows is not None:
+            keep &= ~drop_rows[np.maximum(r, 0)]
+        r, c, v = r[keep], c[keep], v[keep]
+        m = sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+        m.sort_indices()
+        return m
+
+
+def _vector_block_rows(dofmap, nodes):
+    """Global dof index for local vector dof 2*i+c of each element."""
+    # dofmap: (Nnodes, 2); nodes: (E, nloc)  -> (E, 2*nloc)
+    g = dofmap[nodes]                  # (E, nloc, 2)
+    return g.reshape(nodes.shape[0], -1)
+
+
+def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
+             alpha0: float = 100.0, nrhs: int = 1, Lx: float = 4.0, Ly: float = 2.0) -> System:
+    """Assemble the coupled Jacobian on an nx x ny mesh (nx, ny even)."""
+    if nx < 4 or ny < 4 or nx % 2 or ny % 2:
+        raise ValueError("nx, ny must be even and >= 4")
+    hx, hy = Lx / nx, Ly / ny
+    NX, NY = 2 * nx + 1, 2 * ny + 1
+    a = max(1, nx // 16)
+    b = max(1, ny // 8)
+    i0, i1 = nx // 2 - a, nx // 2 + a
+    j0, j1 = ny // 2 - b, ny // 2 + b
+
+    # fluid cells and triangles (lattice coordinates)
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    ci, cj = ci.ravel(), cj.ravel()
+    fluid = ~((ci >= i0) & (ci < i1) & (cj >= j0) & (cj < j1))
+    ci, cj = ci[fluid], cj[fluid]
+    I0, J0 = 2 * ci, 2 * cj
+    # T1 = (00, 10, 11), T2 = (00, 11, 01)
+    vI = np.concatenate([np.stack([I0, I0 + 2, I0 + 2], 1), np.stack([I0, I0 + 2, I0], 1)])
+    vJ = np.concatenate([np.stack([J0, J0, J0 + 2], 1), np.stack([J0, J0 + 2, J0 + 2], 1)])
+    E = vI.shape[0]
+    mI = np.stack([(vI[:, 0] + vI[:, 1]) // 2, (vI[:, 1] + vI[:, 2]) // 2, (vI[:, 2] + vI[:, 0]) // 2], 1)
+    mJ = np.stack([(vJ[:, 0] + vJ[:, 1]) // 2, (vJ[:, 1] + vJ[:, 2]) // 2, (vJ[:, 2] + vJ[:, 0]) // 2], 1)
+    LI = np.concatenate([vI, mI], 1)
+    LJ = np.concatenate([vJ, mJ], 1)
+
+    used = np.zeros(NX * NY, dtype=bool)
+    used[(LI * NY + LJ).ravel()] = True
+    node_of = -np.ones(NX * NY, dtype=np.int64)
+    node_lat = np.flatnonzero(used)                    # lexicographic in (ix, iy)
+    node_of[node_lat] = np.arange(node_lat.size)
+    nn = node_lat.size
+    nI, nJ = node_lat // NY, node_lat % NY
+    tri = node_of[LI * NY + LJ]                        # (E, 6)
+
+    vert_mask = (nI % 2 == 0) & (nJ % 2 == 0)
+    vert_of = -np.ones(nn, dtype=np.int64)
+    vert_of[vert_mask] = np.arange(int(vert_mask.sum()))
+    nv = int(vert_mask.sum())
+    tri_p = vert_of[tri[:, :3]]
+
+    inlet = nI == 0
+    outlet = nI == NX - 1
+    wall = (nJ == 0) | (nJ == NY - 1)
+    on_gamma = (nI >= 2 * i0) & (nI <= 2 * i1) & (nJ >= 2 * j0) & (nJ <= 2 * j1)
+
+    # ---- dof numbering
+    nxt = 0
+    u_keep = np.ones((nn, 2), dtype=bool)
+    u_keep[inlet, :] = False
+    u_keep[wall, 1] = False
+    u_dof = -np.ones((nn, 2), dtype=np.int64)
+    u_dof[u_keep] = np.arange(int(u_keep.sum()))       # node-major, component fastest
+    nxt = int(u_keep.sum())
+    blocks = {"u": (0, nxt)}
+    p_dof = np.arange(nv) + nxt
+    blocks["p"] = (nxt, nxt + nv)
+    nxt += nv
+    d_keep = np.ones((nn, 2), dtype=bool)
+    d_keep[inlet | outlet, :] = False
+    d_keep[wall, 1] = False
+    d_dof = -np.ones((nn, 2), dtype=np.int64)
+    d_dof[d_keep] = np.arange(int(d_keep.sum())) + nxt
+    blocks["d"] = (nxt, nxt + int(d_keep.sum()))
+    nxt += int(d_keep.sum())
+    g_nodes = np.flatnonzero(on_gamma)
+    lam_dof = -np.ones((nn, 2), dtype=np.int64)
+    lam_dof[g_nodes, :] = (np.arange(2 * g_nodes.size) + nxt).reshape(-1, 2)
+    blocks["lam"] = (nxt, nxt + 2 * g_nodes.size)
+    nxt += 2 * g_nodes.size
+    s_dof = np.array([nxt, nxt + 1])
+    blocks["s"] = (nxt, nxt + 2)
+    n = nxt + 2
+
+    # ---- geometry (affine triangles)
+    X = nI * (hx / 2)
+    Y = nJ * (hy / 2)
+    x0, y0 = X[tri[:, 0]], Y[tri[:, 0]]
+    Jm = np.empty((E, 2, 2))
+    Jm[:, 0, 0] = X[tri[:, 1]] - x0
+    Jm[:, 0, 1] = X[tri[:, 2]] - x0
+    Jm[:, 1, 0] = Y[tri[:, 1]] - y0
+    Jm[:, 1, 1] = Y[tri[:, 2]] - y0
+    det = Jm[:, 0, 0] * Jm[:, 1, 1] - Jm[:, 0, 1] * Jm[:, 1, 0]
+    area = 0.5 * np.abs(det)
+    invT = np.empty((E, 2, 2))                          # J^{-T}
+    invT[:, 0, 0] = Jm[:, 1, 1] / det
+    invT[:, 0, 1] = -Jm[:, 1, 0] / det
+    invT[:, 1, 0] = -Jm[:, 0, 1] / det
+    invT[:, 1, 1] = Jm[:, 0, 0] / det
+
+    qp, qw = radon7()
+    phi, gref, Lq = p2_tri(qp)                          # (Q,6), (Q,6,2), (Q,3)
+    W = qw[None, :] * np.abs(det)[:, None]              # (E,Q)
+    G = np.einsum("eab,qib->eqia", invT, gref)          # physical grads (E,Q,6,2)
+
+    # seeded convecting velocity (nodal P2, U[-1,1] per component), then RHS
+    rng = np.random.default_rng(seed)
+    wnod = rng.uniform(-1.0, 1.0, size=(nn, 2))
+    b0 = rng.standard_normal((nrhs, n))
+
+    M = np.einsum("eq,qi,qj->eij", W, phi, phi)
+    K = np.einsum("eq,eqia,eqja->eij", W, G, G)
+    D = np.einsum("eq,eqia,eqjb->eiajb", W, G, G)       # int d_a phi_i d_b phi_j
+    wq = np.einsum("qk,ekd->eqd", phi, wnod[tri])        # w at quadrature points
+    C = np.einsum("eq,qi,eqd,eqjd->eij", W, phi, wq, G)  # int phi_i (w.grad) phi_j
+    Bq = -np.einsum("eq,qk,eqjc->ekjc", W, Lq, G)       # -int psi_k d_c phi_j  (E,3,6,2)
+
+    eye2 = np.eye(2)
+    # velocity block, local (i,c),(j,c'):
+    Avel = (alpha0 * M + C)[:, :, None, :, None] * eye2[None, None, :, None, :]
+    Avel = Avel + nu * (K[:, :, None, :, None] * eye2[None, None, :, None, :]
+                        + np.transpose(D, (0, 1, 4, 3, 2)))
+    # pseudo-solid with lam_s = mu_s = 1/|K|
+    lam_s = (1.0 / area)[:, None, None, None, None]
+    Ad = lam_s * (D + K[:, :, None, :, None] * eye2[None, None, :, None, :]
+                  + np.transpose(D, (0, 1, 4, 3, 2)))
+
+    T = _Triplets()
+    ur = _vector_block_rows(u_dof, tri)                 # (E,12)
+    dr = _vector_block_rows(d_dof, tri)
+    T.add(ur[:, :, None], ur[:, None, :], Avel.reshape(E, 12, 12))
+    pr = p_dof[tri_p]                                   # (E,3)
+    Bflat = Bq.reshape(E, 3, 12)
+    T.add(pr[:, :, None], ur[:, None, :], Bflat)                     # p rows
+    T.add(ur[:, :, None], pr[:, None, :], np.transpose(Bflat, (0, 2, 1)))  # u rows
+    T.add(dr[:, :, None], dr[:, None, :], Ad.reshape(E, 12, 12))
+
+    # ---- Gamma edges (hole perimeter), nodes (end, end, mid)
+    edges = []
+    for i in range(i0, i1):
+        for jj in (j0, j1):
+            edges.append(((2 * i, 2 * jj), (2 * i + 2, 2 * jj), (2 * i + 1, 2 * jj), hx))
+    for j in range(j0, j1):
+        for ii in (i0, i1):
+            edges.append(((2 * ii, 2 * j), (2 * ii, 2 * j + 2), (2 * ii, 2 * j + 1), hy))
+    Me_ref = np.array([[4.0, -1.0, 2.0], [-1.0, 4.0, 2.0], [2.0, 2.0, 16.0]]) / 30.0
+    m_int = np.zeros(nn)
+    for (pa, pb, pm, Le) in edges:
+        en = np.array([node_of[pa[0] * NY + pa[1]], node_of[pb[0] * NY + pb[1]], node_of[pm[0] * NY + pm[1]]])
+        Me = Le * Me_ref
+        m_int[en] += Le * np.array([1 / 6, 1 / 6, 2 / 3])
+        for c in range(2):
+            uu = u_dof[en, c]
+            ll = lam_dof[en, c]
+            T.add(uu[:, None], ll[None, :], -Me)        # -<v, lambda>
+            T.add(ll[:, None], uu[None, :], -Me)        # -<mu, u>
+    gl = g_nodes
+    R = _Triplets()                                     # rows that replace the Gamma d rows
+    for c in range(2):
+        T.add(lam_dof[gl, c], s_dof[c], alpha0 * m_int[gl])   # +alpha0 <mu,1> s_c
+        T.add(s_dof[c], lam_dof[gl, c], m_int[gl])            # spring row: sum m_j lambda_j
+        T.add(s_dof[c], s_dof[c], k)
+        # position masters: d_{i,c} - s_c = 0 replaces the Gamma displacement rows
+        R.add(d_dof[gl, c], d_dof[gl, c], 1.0)
+        R.add(d_dof[gl, c], s_dof[c], -1.0)
+
+    drop = np.zeros(n, dtype=bool)
+    drop[d_dof[gl].ravel()] = True
+    rr = np.concatenate(T.r)
+    T.r, T.c, T.v = [np.where(drop[np.maximum(rr, 0)], -1, rr).astype(np.int32)] + R.r, \
+        [np.concatenate(T.c)] + R.c, [np.concatenate(T.v)] + R.v
+    del rr
+    A = T.csr(n)
+
+    meta = dict(dim=2, nx=nx, ny=ny, seed=seed, k=k, nu=nu, alpha0=alpha0,
+                hole=(i0, i1, j0, j1), n_nodes=nn, n_vertices=nv, n_gamma_nodes=int(gl.size),
+                gamma_length=float(m_int.sum()))
+    return System(n=n, rowptr=A.indptr.astype(np.int64), colind=A.indices.astype(np.int32),
+                  values=A.data.astype(np.float64), root=s_dof.astype(np.int32),
+                  blocks=blocks, meta=meta, b0=b0)
+
+
+# ---------------------------------------------------------------- Newton stream
+def newton_values(system: System, step: int) -> np.ndarray:
+    """Values at Newton step t: a_t = a_{t-1} * (1 + 0.01 xi_t), xi_t ~ N(0,1).
+
+    Step 0 is unperturbed; step t draws xi_t first from default_rng([seed, t])."""
+    v = system.values.copy()
+    for t in range(1, step + 1):
+        rng = np.random.default_rng([system.meta["seed"], t])
+        v *= 1.0 + 0.01 * rng.standard_normal(v.size)
+    return v
+
+
+def newton_rhs(system: System, step: int, nrhs: int = 1) -> np.ndarray:
+    """Right-hand sides (nrhs, n) at Newton step t (fresh N(0,1) each step)."""
+    if step == 0:
+        if system.b0 is not None and system.b0.shape[0] >= nrhs:
+            return system.b0[:nrhs].copy()
+        rng = np.random.default_rng(system.meta["seed"])
+        rng.uniform(-1.0, 1.0, size=(system.meta["n_nodes"], system.meta["dim"]))
+        return rng.standard_normal((nrhs, system.n))
+    rng = np.random.default_rng([system.meta["seed"], step])
+    rng.standard_normal(system.nnz)
+    return rng.standard_normal((nrhs, system.n))
