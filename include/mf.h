@@ -1,0 +1,188 @@
+/*
+ * mf.h -- C ABI of libmf, a multifrontal LU solver for the coupled Newton
+ * Jacobian of the monolithic ALE fluid / pseudo-solid / rigid-cylinder system.
+ *
+ * The paper solves, at every Newton-Raphson iteration, the linear system
+ * J(U_m) dU_m = -NL(U_m) (Sec. 3.4, eq. NR_iteration) with a parallel sparse
+ * direct solver (Sec. 4.3).  Because the mesh, and so the sparsity pattern,
+ * never changes, the analysis (ordering) is done once and every later solve is
+ * a numerical factorization plus a solve (Sec. 6, "Scaling").  This library
+ * follows that split:
+ *
+ *     mf_analyze(pattern)  -> symbolic handle (ordering, front tree, maps)
+ *     mf_factor(values)    -> numeric handle (front LU factors, resident on the GPU)
+ *     mf_solve(rhs, nrhs)  -> solution, with FP64 refinement to a backward-error target
+ *     mf_release(handle)
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an mf_status; no exception crosses the ABI.
+ *     mf_last_error() returns a thread-local message for the last failure.
+ *   - Indices are 0-based.  Host arrays are read during the call only; the
+ *     library copies what it keeps.
+ *   - "Device" pointers are HIP device allocations (e.g. torch tensors on
+ *     cuda:0); they are read or written only on the stream passed in.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Handles are not thread-safe: one call at a time per handle.
+ *   - Values at the boundary are always FP64; reduced precision is internal.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MF_OK = 0,
+    MF_ERR_ARG = -1,            /* bad argument (null pointer, size, index out of range) */
+    MF_ERR_PATTERN = -2,        /* values/pattern do not match the symbolic handle */
+    MF_ERR_OOM = -3,            /* host or device allocation failed */
+    MF_ERR_SINGULAR = -4,       /* a root front column has no nonzero pivot (or NaN/Inf) */
+    MF_ERR_DEVICE = -5,         /* a HIP call failed */
+    MF_ERR_NOT_CONVERGED = -6,  /* refinement stopped above the target; x is still written */
+    MF_ERR_STATE = -7           /* call out of order (e.g. solve before factor) */
+} mf_status;
+
+typedef enum {
+    MF_FP64 = 0,  /* all fronts FP64 */
+    MF_FP32 = 1,  /* non-root fronts FP32 (FP32 MFMA Schur updates); root front FP64 */
+    MF_BF16 = 2   /* as MF_FP32, but Schur-update operands rounded to BF16, FP32 accumulate */
+} mf_precision;
+
+typedef struct {
+    int32_t prec;          /* mf_precision of the non-root fronts (default MF_FP64) */
+    double pivot_u;        /* threshold u of partial pivoting inside fronts (default 0.01) */
+    int32_t leaf_max;      /* nested-dissection leaf size; part of the symbolic (default 64) */
+    double target_omega;   /* componentwise backward-error target of mf_solve (default 1e-12) */
+    int32_t max_outer;     /* max refinement steps (default 10) */
+    int32_t gmres_m;       /* GMRES restart length / max inner iterations (default 30) */
+    double gmres_tol;      /* inner relative residual tolerance (default 1e-4) */
+    int32_t refine;        /* 0 = none, 1 = classical FP64 refinement, 2 = GMRES-IR
+                              (default: 1 for MF_FP64, 2 otherwise; -1 = by precision) */
+    int32_t panel_nb;      /* panel width of the front factorization (default 32) */
+} mf_options;
+
+/* Fill *opt with the defaults above. */
+void mf_default_options(mf_options* opt);
+
+typedef struct mf_sym* mf_sym_t;
+typedef struct mf_num* mf_num_t;
+
+/*
+ * Symbolic analysis, host only.  The pattern is the paper's fixed Jacobian
+ * pattern (Sec. 3.2 block structure); the analysis is a specified nested
+ * dissection (George-Liu pseudo-peripheral roots, level-set separators, leaves
+ * of at most leaf_max variables) whose output is bit-exactly reproducible, so
+ * that it can be compared against an independent implementation.
+ *
+ *   n                 matrix order (>= 0)
+ *   rowptr, colind    host CSR pattern, rowptr[n+1] (int64), colind[rowptr[n]]
+ *                     (int32).  Column order within a row is free; duplicate
+ *                     (row, col) entries are summed at factor time; explicitly
+ *                     stored zeros are structural.
+ *   nroot, root_idx   variables forced into the single root front, in the
+ *                     order given (the two rigid-position dofs of the global
+ *                     position master, Sec. 4.2).  nroot = 0 is allowed.
+ *   opt               may be NULL (defaults); copied into the handle.
+ *   out               receives the handle; owns copies of everything it needs.
+ * Errors: MF_ERR_ARG (bad sizes or indices), MF_ERR_OOM.
+ * Device memory is not touched until the first mf_factor.
+ */
+mf_status mf_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                     int32_t nroot, const int32_t* root_idx,
+                     const mf_options* opt, mf_sym_t* out);
+
+/* Read-only view of the symbolic result; arrays are owned by the handle and
+ * valid until it is released.  Fronts are numbered in completion (post)order.
+ *   perm[n]            new position -> original variable
+ *   front_ptr[nf+1]    pivot ranges of each front in the new numbering
+ *   front_parent[nf]   parent front, -1 for a root
+ *   rows_ptr[nf+1]     ranges into rows
+ *   rows[]             rows of each front as original variables: the pivots in
+ *                      pivot order, then the remaining rows by ascending new index
+ *   var_etree[n]       elimination tree of the permuted A + A^T (new numbering, -1 roots) */
+typedef struct {
+    int64_t n;
+    int32_t nfronts;
+    int32_t leaf_max;
+    int32_t spec_version;
+    int32_t nlevels;            /* height of the front tree + 1 */
+    const int32_t* perm;
+    const int32_t* front_ptr;
+    const int32_t* front_parent;
+    const int64_t* rows_ptr;
+    const int32_t* rows;
+    const int32_t* var_etree;
+    double nominal_flops;       /* sum over fronts of sum_{i=m-p}^{m-1} (i + 2 i^2) */
+    double nominal_nnz_lu;      /* sum over fronts of 2 m p - p^2 */
+} mf_symbolic_view;
+
+mf_status mf_symbolic_export(mf_sym_t sym, mf_symbolic_view* out);
+
+/*
+ * Numeric multifrontal LU of the matrix with the analyzed pattern.
+ *   values_dev   device FP64 values in the CSR order given to mf_analyze
+ *                (rowptr[n] entries); copied, so it may be reused after return.
+ *   opt          NULL = the options given to mf_analyze; otherwise overrides the
+ *                numeric options (prec, pivot_u, refinement, panel_nb).
+ *   inout        if *inout is a numeric handle of the same symbolic handle its
+ *                device memory is reused; if NULL a new handle is created.
+ * Pivoting: threshold partial pivoting inside each front; a fully summed column
+ * with no acceptable pivot among the fully summed rows is delayed to the parent
+ * front (the zero pressure and multiplier diagonals of Sec. 3.2 make this
+ * common).  The root front always factors in FP64 with partial pivoting.
+ * The call synchronizes with `stream` once per tree level (front sizes depend
+ * on the delays); factors stay resident on the device.
+ * Errors: MF_ERR_SINGULAR (a root column without a pivot; message names the
+ * front and column), MF_ERR_DEVICE, MF_ERR_OOM, MF_ERR_ARG.
+ */
+mf_status mf_factor(mf_sym_t sym, const double* values_dev, const mf_options* opt,
+                    void* stream, mf_num_t* inout);
+
+typedef struct {
+    int64_t delayed_pivots;     /* total delayed columns over all fronts */
+    int32_t max_front;          /* largest actual front order */
+    int32_t root_order;         /* actual order of the root front */
+    double factor_flops;        /* nominal algorithmic flops of the factorization */
+    double actual_flops;        /* flops of the actual (delay-grown) fronts */
+    int64_t factor_bytes;       /* device bytes held by the fronts */
+} mf_factor_info;
+
+mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);
+
+/*
+ * Solve J X = B with the factors and refine in FP64 until the componentwise
+ * backward error omega = max_i |B - J X|_i / (|J||X| + |B|)_i <= target_omega.
+ *   b_dev, x_dev   device FP64, n x nrhs column-major with leading dimension ld >= n
+ *                  (b_dev == x_dev is not allowed)
+ * Refinement: classical (x += M^{-1} r) for FP64 factors, GMRES-IR
+ * (left-preconditioned GMRES on M^{-1} J d = M^{-1} r, FP64 vectors) for
+ * reduced-precision factors.  MF_ERR_NOT_CONVERGED leaves the best x written.
+ */
+typedef struct {
+    double omega;               /* max over right-hand sides of the final omega */
+    double omega0;              /* omega of the unrefined solution */
+    int32_t outer_iters;        /* refinement steps (max over right-hand sides) */
+    int32_t inner_iters;        /* total GMRES iterations */
+} mf_solve_info;
+
+mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld,
+                   void* stream, mf_solve_info* info);
+
+/* Device bytes a factorization of this pattern needs at nominal front sizes,
+ * times (1 + margin) for delayed-pivot growth (admission estimate). */
+int64_t mf_footprint_bytes(mf_sym_t sym, const mf_options* opt, double margin);
+
+/* Release a symbolic or numeric handle (synchronizes its device work first).
+ * NULL is ignored.  A symbolic handle must outlive its numeric handles. */
+void mf_release(void* handle);
+
+/* Thread-local message describing the last error (never NULL). */
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

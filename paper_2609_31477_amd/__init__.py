@@ -1,0 +1,248 @@
+"""Python binding of libmf, the MI355X multifrontal solver for the coupled VIV Newton Jacobian.
+
+Argument marshalling only: every step of analysis, factorization and solve runs
+inside libmf.so (host C++ symbolic phase, gfx950 HIP kernels).  PyTorch provides
+device memory and the stream.  There is no fallback: if the library is not
+built, importing the binding's solver classes raises.
+
+    sym = Symbolic(n, rowptr, colind, root, leaf_max=64)       # mf_analyze
+    num = sym.factor(values_tensor_on_cuda)                     # mf_factor
+    x, info = num.solve(b_tensor_on_cuda)                       # mf_solve
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmf.so")
+
+MF_OK, MF_ERR_ARG, MF_ERR_PATTERN, MF_ERR_OOM, MF_ERR_SINGULAR, MF_ERR_DEVICE, MF_ERR_NOT_CONVERGED, MF_ERR_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+MF_FP64, MF_FP32, MF_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
+
+# every entry point declared in include/mf.h
+EXPORTS = ["mf_default_options", "mf_analyze", "mf_symbolic_export", "mf_factor", "mf_get_factor_info",
+           "mf_solve", "mf_footprint_bytes", "mf_release", "mf_last_error"]
+
+
+class mf_options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("pivot_u", ctypes.c_double), ("leaf_max", ctypes.c_int32),
+                ("target_omega", ctypes.c_double), ("max_outer", ctypes.c_int32), ("gmres_m", ctypes.c_int32),
+                ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32)]
+
+
+class mf_symbolic_view(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nfronts", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
+                ("spec_version", ctypes.c_int32), ("nlevels", ctypes.c_int32),
+                ("perm", ctypes.POINTER(ctypes.c_int32)), ("front_ptr", ctypes.POINTER(ctypes.c_int32)),
+                ("front_parent", ctypes.POINTER(ctypes.c_int32)), ("rows_ptr", ctypes.POINTER(ctypes.c_int64)),
+                ("rows", ctypes.POINTER(ctypes.c_int32)), ("var_etree", ctypes.POINTER(ctypes.c_int32)),
+                ("nominal_flops", ctypes.c_double), ("nominal_nnz_lu", ctypes.c_double)]
+
+
+class mf_factor_info(ctypes.Structure):
+    _fields_ = [("delayed_pivots", ctypes.c_int64), ("max_front", ctypes.c_int32), ("root_order", ctypes.c_int32),
+                ("factor_flops", ctypes.c_double), ("actual_flops", ctypes.c_double),
+                ("factor_bytes", ctypes.c_int64)]
+
+
+class mf_solve_info(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("omega0", ctypes.c_double), ("outer_iters", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32)]
+
+
+class MFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libmf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.mf_default_options.argtypes = [ctypes.POINTER(mf_options)]
+        L.mf_default_options.restype = None
+        L.mf_analyze.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, ctypes.POINTER(mf_options),
+                                 ctypes.POINTER(ctypes.c_void_p)]
+        L.mf_analyze.restype = ctypes.c_int
+        L.mf_symbolic_export.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_symbolic_view)]
+        L.mf_symbolic_export.restype = ctypes.c_int
+        L.mf_factor.argtypes = [ctypes.c_void_p, P, ctypes.POINTER(mf_options), P, ctypes.POINTER(ctypes.c_void_p)]
+        L.mf_factor.restype = ctypes.c_int
+        L.mf_get_factor_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_factor_info)]
+        L.mf_get_factor_info.restype = ctypes.c_int
+        L.mf_solve.argtypes = [ctypes.c_void_p, P, P, ctypes.c_int32, ctypes.c_int64, P,
+                               ctypes.POINTER(mf_solve_info)]
+        L.mf_solve.restype = ctypes.c_int
+        L.mf_footprint_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_options), ctypes.c_double]
+        L.mf_footprint_bytes.restype = ctypes.c_int64
+        L.mf_release.argtypes = [ctypes.c_void_p]
+        L.mf_release.restype = None
+        L.mf_last_error.argtypes = []
+        L.mf_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != MF_OK:
+        raise MFError(st, lib().mf_last_error().decode())
+
+
+def default_options(**kw) -> mf_options:
+    o = mf_options()
+    lib().mf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PRECISIONS[v]
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+@dataclass
+class SymbolicView:
+    n: int
+    nfronts: int
+    nlevels: int
+    leaf_max: int
+    spec_version: int
+    perm: np.ndarray
+    front_ptr: np.ndarray
+    front_parent: np.ndarray
+    rows_ptr: np.ndarray
+    rows: np.ndarray
+    var_etree: np.ndarray
+    nominal_flops: float
+    nominal_nnz_lu: float
+
+
+class Symbolic:
+    """mf_analyze: the specified nested-dissection analysis of one sparsity pattern."""
+
+    def __init__(self, n, rowptr, colind, root=(), leaf_max=64, **opts):
+        L = lib()
+        self.n = int(n)
+        rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+        ci = np.ascontiguousarray(colind, dtype=np.int32)
+        rt = np.ascontiguousarray(np.asarray(root, dtype=np.int32).ravel())
+        self.nnz = int(rp[-1]) if rp.size else 0
+        self.options = default_options(leaf_max=leaf_max, **opts)
+        h = ctypes.c_void_p()
+        st = L.mf_analyze(self.n, rp.ctypes.data, ci.ctypes.data, int(rt.size),
+                          rt.ctypes.data if rt.size else None, ctypes.byref(self.options), ctypes.byref(h))
+        _check(st)
+        self._h = h
+
+    def export(self) -> SymbolicView:
+        v = mf_symbolic_view()
+        _check(lib().mf_symbolic_export(self._h, ctypes.byref(v)))
+        nf = v.nfronts
+
+        def arr(p, cnt, dt):
+            if cnt == 0:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array(p, shape=(cnt,)).astype(dt, copy=True)
+
+        rows_ptr = arr(v.rows_ptr, nf + 1, np.int64) if nf else np.zeros(1, np.int64)
+        return SymbolicView(n=v.n, nfronts=nf, nlevels=v.nlevels, leaf_max=v.leaf_max, spec_version=v.spec_version,
+                            perm=arr(v.perm, v.n, np.int32),
+                            front_ptr=arr(v.front_ptr, nf + 1, np.int32) if nf else np.zeros(1, np.int32),
+                            front_parent=arr(v.front_parent, nf, np.int32), rows_ptr=rows_ptr,
+                            rows=arr(v.rows, int(rows_ptr[-1]), np.int32), var_etree=arr(v.var_etree, v.n, np.int32),
+                            nominal_flops=v.nominal_flops, nominal_nnz_lu=v.nominal_nnz_lu)
+
+    def footprint_bytes(self, prec="fp64", margin=0.5) -> int:
+        o = default_options(prec=prec)
+        return int(lib().mf_footprint_bytes(self._h, ctypes.byref(o), float(margin)))
+
+    def factor(self, values, numeric=None, stream=None, **opts):
+        """values: torch float64 tensor on the GPU (nnz entries in CSR order)."""
+        return Numeric.factor(self, values, numeric=numeric, stream=stream, **opts)
+
+    def release(self):
+        if getattr(self, "_h", None):
+            lib().mf_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Numeric:
+    """mf_factor / mf_solve on one symbolic handle (factors stay on the device)."""
+
+    def __init__(self, sym):
+        self.sym = sym
+        self._h = ctypes.c_void_p()
+
+    @classmethod
+    def factor(cls, sym, values, numeric=None, stream=None, **opts):
+        import torch
+        if not (isinstance(values, torch.Tensor) and values.is_cuda and values.dtype == torch.float64):
+            raise TypeError("values must be a float64 CUDA tensor")
+        if values.numel() != sym.nnz or not values.is_contiguous():
+            raise ValueError("values must be contiguous with nnz entries")
+        num = numeric if numeric is not None else cls(sym)
+        o = default_options(leaf_max=sym.options.leaf_max, **opts) if opts else None
+        st = lib().mf_factor(sym._h, ctypes.c_void_p(values.data_ptr()), ctypes.byref(o) if o is not None else None,
+                             _stream_ptr(stream), ctypes.byref(num._h))
+        _check(st)
+        return num
+
+    def info(self) -> mf_factor_info:
+        inf = mf_factor_info()
+        _check(lib().mf_get_factor_info(self._h, ctypes.byref(inf)))
+        return inf
+
+    def solve(self, b, x=None, stream=None, check=True):
+        """b: float64 CUDA tensor (n,) or (nrhs, n) -- row r is right-hand side r
+        (i.e. column-major n x nrhs with ld = n).  Returns (x, mf_solve_info)."""
+        import torch
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()):
+            raise TypeError("b must be a contiguous float64 CUDA tensor")
+        n = self.sym.n
+        if b.shape[-1] != n:
+            raise ValueError("b has the wrong length")
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        if x is None:
+            x = torch.empty_like(b)
+        inf = mf_solve_info()
+        st = lib().mf_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), nrhs, n,
+                            _stream_ptr(stream), ctypes.byref(inf))
+        if check or st != MF_ERR_NOT_CONVERGED:
+            _check(st)
+        return x, inf
+
+    def release(self):
+        if getattr(self, "_h", None):
+            lib().mf_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

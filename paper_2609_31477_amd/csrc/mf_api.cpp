@@ -1,0 +1,601 @@
+// C ABI of libmf: handles, the level-synchronous numeric driver and the
+// refinement loop.  All device work is issued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "mf_device.h"
+#include "mf_internal.h"
+
+namespace mf {
+
+// kernel launchers (mf_kernels.hip)
+template <typename T>
+hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, int Pmax,
+                               const double* vals, int64_t u0, int64_t u1, int NB, double u, int prec,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
+                            int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
+template <typename T>
+hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
+                            const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
+hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
+                           const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
+                           unsigned long long* omega_bits, hipStream_t st);
+hipError_t launch_axpy(int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd, int nrhs, hipStream_t st);
+hipError_t launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st);
+
+namespace {
+thread_local std::string g_err;
+
+struct Fail {
+    mf_status st;
+    std::string msg;
+};
+
+#define HIPX(call)                                                                                     \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            throw Fail{e_ == hipErrorOutOfMemory ? MF_ERR_OOM : MF_ERR_DEVICE,                         \
+                       std::string(#call) + ": " + hipGetErrorString(e_)};                             \
+    } while (0)
+
+constexpr size_t kMaxLds = 64 * 1024;
+
+template <typename V>
+void upload(V** dst, const std::vector<V>& src) {
+    *dst = nullptr;
+    size_t bytes = sizeof(V) * std::max<size_t>(src.size(), 1);
+    HIPX(hipMalloc((void**)dst, bytes));
+    if (!src.empty()) HIPX(hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
+}
+
+// Device copy of the pattern data, slot-indexed; owned by the symbolic handle.
+struct SymDev {
+    int device = -1;
+    DevSym S{};
+    std::vector<void*> allocs;
+    std::vector<int32_t> slot_of;  // front id -> slot
+    ~SymDev() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename V>
+    const V* put(const std::vector<V>& v) {
+        V* p = nullptr;
+        upload(&p, v);
+        allocs.push_back(p);
+        return p;
+    }
+};
+
+// Bump allocator over a list of device chunks (fronts or integer bookkeeping).
+struct Arena {
+    std::vector<std::pair<char*, size_t>> chunks;
+    size_t ci = 0, off = 0;
+    size_t grow_hint = 0;
+    void reset() {
+        ci = 0;
+        off = 0;
+    }
+    size_t capacity() const {
+        size_t c = 0;
+        for (auto& k : chunks) c += k.second;
+        return c;
+    }
+    char* alloc(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        while (ci < chunks.size()) {
+            if (off + bytes <= chunks[ci].second) {
+                char* p = chunks[ci].first + off;
+                off += bytes;
+                return p;
+            }
+            ci++;
+            off = 0;
+        }
+        size_t sz = std::max(bytes, grow_hint);
+        char* p = nullptr;
+        HIPX(hipMalloc((void**)&p, sz));
+        chunks.emplace_back(p, sz);
+        ci = chunks.size() - 1;
+        off = bytes;
+        return p;
+    }
+    void release() {
+        for (auto& k : chunks) (void)hipFree(k.first);
+        chunks.clear();
+        reset();
+    }
+};
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace mf
+
+using namespace mf;
+
+struct mf_sym {
+    uint32_t magic = kSymMagic;
+    Symbolic S;
+    mf_options opt;
+    std::unique_ptr<SymDev> dev;
+};
+
+struct mf_num {
+    uint32_t magic = kNumMagic;
+    mf_sym* sym = nullptr;
+    mf_options opt;
+    int device = -1;
+    Arena fronts, ints;
+    FrontNum* d_fn = nullptr;
+    FrontNum* h_fn = nullptr;  // pinned mirror
+    double* d_vals = nullptr;
+    int64_t vec_len = 0;       // sum of actual front orders
+    double* d_vec = nullptr;
+    size_t vec_cap = 0;        // doubles
+    double* d_work = nullptr;  // r, d, x0 copies (3 * n * nrhs)
+    size_t work_cap = 0;
+    unsigned long long* d_omega = nullptr;
+    unsigned long long* h_omega = nullptr;  // pinned
+    int omega_cap = 0;
+    bool factored = false;
+    std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
+    mf_factor_info info{};
+    ~mf_num() {
+        fronts.release();
+        ints.release();
+        if (d_fn) (void)hipFree(d_fn);
+        if (h_fn) (void)hipHostFree(h_fn);
+        if (d_vals) (void)hipFree(d_vals);
+        if (d_vec) (void)hipFree(d_vec);
+        if (d_work) (void)hipFree(d_work);
+        if (d_omega) (void)hipFree(d_omega);
+        if (h_omega) (void)hipHostFree(h_omega);
+    }
+};
+
+namespace {
+
+mf_status fail(mf_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+void resolve_refine(mf_options& o) {
+    if (o.refine < 0) o.refine = (o.prec == MF_FP64) ? 1 : 2;
+}
+
+void ensure_device_symbolic(mf_sym* h) {
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    if (h->dev && h->dev->device == dev) return;
+    const Symbolic& S = h->S;
+    auto D = std::make_unique<SymDev>();
+    D->device = dev;
+    const int nf = S.nf;
+    D->slot_of.assign(nf, -1);
+    for (int32_t i = 0; i < nf; i++) D->slot_of[S.level_fronts[i]] = i;
+    std::vector<int32_t> parent(nf), child_ptr(nf + 1, 0), child_slot;
+    std::vector<int64_t> rows_ptr(nf + 1, 0), imap_off(nf + 1, 0);
+    std::vector<int32_t> rows, imap;
+    child_slot.reserve(S.child_idx.size());
+    rows.reserve(S.rows.size());
+    imap.reserve(S.imap.size());
+    for (int32_t sl = 0; sl < nf; sl++) {
+        int32_t f = S.level_fronts[sl];
+        parent[sl] = S.front_parent[f] >= 0 ? D->slot_of[S.front_parent[f]] : -1;
+        for (int32_t t = S.child_ptr[f]; t < S.child_ptr[f + 1]; t++) child_slot.push_back(D->slot_of[S.child_idx[t]]);
+        child_ptr[sl + 1] = (int32_t)child_slot.size();
+        rows.insert(rows.end(), S.rows.begin() + S.rows_ptr[f], S.rows.begin() + S.rows_ptr[f + 1]);
+        rows_ptr[sl + 1] = (int64_t)rows.size();
+        imap.insert(imap.end(), S.imap.begin() + S.imap_off[f], S.imap.begin() + S.imap_off[f + 1]);
+        imap_off[sl + 1] = (int64_t)imap.size();
+    }
+    std::vector<int32_t> ue_slot(S.ue_front.size());
+    for (size_t i = 0; i < ue_slot.size(); i++) ue_slot[i] = D->slot_of[S.ue_front[i]];
+    DevSym& d = D->S;
+    d.nslots = nf;
+    d.parent = D->put(parent);
+    d.child_ptr = D->put(child_ptr);
+    d.child_slot = D->put(child_slot);
+    d.rows_ptr = D->put(rows_ptr);
+    d.rows = D->put(rows);
+    d.imap_off = D->put(imap_off);
+    d.imap = D->put(imap);
+    d.ue_slot = D->put(ue_slot);
+    d.ue_row = D->put(S.ue_row);
+    d.ue_col = D->put(S.ue_col);
+    d.ue_src_ptr = D->put(S.ue_src_ptr);
+    d.ue_src = D->put(S.ue_src);
+    d.csr_rowptr = D->put(S.rowptr);
+    d.csr_colind = D->put(S.colind);
+    h->dev = std::move(D);
+}
+
+int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 || is_root) ? 0 : 1; }
+
+void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
+    mf_sym* H = N->sym;
+    const Symbolic& S = H->S;
+    ensure_device_symbolic(H);
+    SymDev& D = *H->dev;
+    const int nf = S.nf;
+    const mf_options& o = N->opt;
+    const int NB = std::max(1, std::min(o.panel_nb, kNBMax));
+    if (!N->d_fn) {
+        HIPX(hipMalloc((void**)&N->d_fn, sizeof(FrontNum) * std::max(nf, 1)));
+        HIPX(hipHostMalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
+    }
+    if (!N->d_vals) HIPX(hipMalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
+    if (S.nnz) HIPX(hipMemcpyAsync(N->d_vals, values_dev, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, st));
+    if (N->fronts.chunks.empty()) {
+        double tot = 0;
+        for (int f = 0; f < nf; f++) tot += (double)S.mnom[f] * S.mnom[f];
+        size_t esz = (o.prec == MF_FP64) ? 8 : 4;
+        N->fronts.grow_hint = (size_t)(tot * esz * 1.25) + (64u << 20);
+        N->ints.grow_hint = (size_t)(sizeof(int32_t) * (S.rows.size() * 4 + (size_t)nf * (1 + 4 * kNBMax))) + (16u << 20);
+    }
+    N->fronts.reset();
+    N->ints.reset();
+    for (int p = 0; p < 2; p++) {
+        N->lvl_mmax[p].assign(S.nlevels, 0);
+        N->lvl_Pmax[p].assign(S.nlevels, 0);
+        N->lvl_cnt[p].assign(S.nlevels, 0);
+    }
+    std::vector<int32_t> dout(nf, 0);
+    FrontNum* hf = N->h_fn;
+    int64_t voff = 0;
+    mf_factor_info info{};
+    info.factor_flops = S.nominal_flops;
+    int64_t front_bytes = 0;
+    for (int L = 0; L < S.nlevels; L++) {
+        const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
+        for (int sl = s0; sl < s1; sl++) {
+            const int f = S.level_fronts[sl];
+            int din = 0;
+            for (int t = S.child_ptr[f]; t < S.child_ptr[f + 1]; t++) din += dout[D.slot_of[S.child_idx[t]]];
+            FrontNum& fr = hf[sl];
+            fr.npiv = S.npiv[f];
+            fr.mnom = S.mnom[f];
+            fr.din = din;
+            fr.m = S.mnom[f] + din;
+            fr.P = S.npiv[f] + din;
+            fr.k = 0;
+            fr.k0 = 0;
+            fr.prec = front_prec(o, S.front_parent[f] < 0);
+            const size_t esz = fr.prec ? 4 : 8;
+            const size_t fb = esz * (size_t)fr.m * (size_t)fr.m;
+            fr.F = N->fronts.alloc(std::max<size_t>(fb, 8));
+            front_bytes += (int64_t)fb;
+            fr.iv = (int32_t*)N->ints.alloc(sizeof(int32_t) * (size_t)iv_size(fr.P, fr.m));
+            fr.voff = voff;
+            voff += fr.m;
+            const int p = fr.prec;
+            N->lvl_mmax[p][L] = std::max(N->lvl_mmax[p][L], fr.m);
+            N->lvl_Pmax[p][L] = std::max(N->lvl_Pmax[p][L], fr.P);
+            N->lvl_cnt[p][L]++;
+            info.max_front = std::max(info.max_front, fr.m);
+            double m = fr.m, pp = fr.P;
+            for (int64_t i = (int64_t)(m - pp); i < (int64_t)m; i++) info.actual_flops += (double)i + 2.0 * (double)i * (double)i;
+        }
+        for (int p = 0; p < 2; p++) {
+            if (!N->lvl_cnt[p][L]) continue;
+            size_t lds = (size_t)N->lvl_Pmax[p][L] * ((p ? 4 : 8) + sizeof(int));
+            if (lds > kMaxLds)
+                throw Fail{MF_ERR_ARG, "front with " + std::to_string(N->lvl_Pmax[p][L]) +
+                                           " fully summed variables exceeds the panel kernel's LDS budget"};
+        }
+        if (s1 - s0 > 65535) throw Fail{MF_ERR_ARG, "tree level with more than 65535 fronts"};
+        HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
+        const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
+        // fronts of both precisions may share a level; each kernel skips the other kind
+        if (N->lvl_cnt[0][L])
+            HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L], N->lvl_Pmax[0][L],
+                                             N->d_vals, u0, u1, NB, o.pivot_u, 0, st));
+        if (N->lvl_cnt[1][L])
+            HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L], N->lvl_Pmax[1][L],
+                                            N->d_vals, u0, u1, NB, o.pivot_u, 1, st));
+        HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
+        HIPX(hipStreamSynchronize(st));
+        for (int sl = s0; sl < s1; sl++) {
+            const FrontNum& fr = hf[sl];
+            dout[sl] = fr.P - fr.k;
+            info.delayed_pivots += dout[sl];
+            const int f = S.level_fronts[sl];
+            if (S.front_parent[f] < 0) {
+                info.root_order = std::max(info.root_order, fr.m);
+                if (dout[sl] > 0)
+                    throw Fail{MF_ERR_SINGULAR, "root front " + std::to_string(f) + " (order " + std::to_string(fr.m) +
+                                                    "): no acceptable pivot for column position " +
+                                                    std::to_string(fr.k) + " (numerically singular or non-finite)"};
+            }
+        }
+    }
+    N->vec_len = voff;
+    info.factor_bytes = front_bytes;
+    N->info = info;
+    N->factored = true;
+}
+
+void ensure_solve_buffers(mf_num* N, int nrhs) {
+    const int64_t n = N->sym->S.n;
+    size_t need = (size_t)std::max<int64_t>(N->vec_len, 1) * nrhs;
+    if (need > N->vec_cap) {
+        if (N->d_vec) HIPX(hipFree(N->d_vec));
+        N->d_vec = nullptr;
+        HIPX(hipMalloc((void**)&N->d_vec, sizeof(double) * need));
+        N->vec_cap = need;
+    }
+    size_t wneed = (size_t)std::max<int64_t>(n, 1) * nrhs * 2;
+    if (wneed > N->work_cap) {
+        if (N->d_work) HIPX(hipFree(N->d_work));
+        N->d_work = nullptr;
+        HIPX(hipMalloc((void**)&N->d_work, sizeof(double) * wneed));
+        N->work_cap = wneed;
+    }
+    if (nrhs > N->omega_cap) {
+        if (N->d_omega) HIPX(hipFree(N->d_omega));
+        if (N->h_omega) HIPX(hipHostFree(N->h_omega));
+        N->d_omega = nullptr;
+        N->h_omega = nullptr;
+        HIPX(hipMalloc((void**)&N->d_omega, sizeof(unsigned long long) * nrhs));
+        HIPX(hipHostMalloc((void**)&N->h_omega, sizeof(unsigned long long) * nrhs, hipHostMallocDefault));
+        N->omega_cap = nrhs;
+    }
+}
+
+// x = M^{-1} b with the multifrontal factors (forward then backward sweep).
+void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, hipStream_t st) {
+    const Symbolic& S = N->sym->S;
+    const DevSym& DS = N->sym->dev->S;
+    for (int c0 = 0; c0 < nrhs;) {
+        // right-hand-side chunk so that the largest front's vectors fit in LDS
+        int mm = 1;
+        for (int p = 0; p < 2; p++)
+            for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
+        int nrc = (int)std::max<size_t>(1, kMaxLds / (sizeof(double) * (size_t)mm));
+        nrc = std::min(nrc, nrhs - c0);
+        if ((size_t)mm * sizeof(double) > kMaxLds)
+            throw Fail{MF_ERR_ARG, "front of order " + std::to_string(mm) + " exceeds the solve kernel's LDS budget"};
+        for (int L = 0; L < S.nlevels; L++) {
+            const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;
+            if (N->lvl_cnt[0][L])
+                HIPX(launch_level_fwd<double>(DS, N->d_fn, s0, cnt, 0, b, ldb, N->d_vec, nrhs, c0, nrc,
+                                              N->lvl_mmax[0][L], st));
+            if (N->lvl_cnt[1][L])
+                HIPX(launch_level_fwd<float>(DS, N->d_fn, s0, cnt, 1, b, ldb, N->d_vec, nrhs, c0, nrc,
+                                             N->lvl_mmax[1][L], st));
+        }
+        for (int L = S.nlevels - 1; L >= 0; L--) {
+            const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;
+            if (N->lvl_cnt[0][L])
+                HIPX(launch_level_bwd<double>(N->d_fn, s0, cnt, 0, x, ldx, N->d_vec, nrhs, c0, nrc,
+                                              N->lvl_mmax[0][L], st));
+            if (N->lvl_cnt[1][L])
+                HIPX(launch_level_bwd<float>(N->d_fn, s0, cnt, 1, x, ldx, N->d_vec, nrhs, c0, nrc,
+                                             N->lvl_mmax[1][L], st));
+        }
+        c0 += nrc;
+    }
+}
+
+double omega_of_bits(unsigned long long b) {
+    double w;
+    std::memcpy(&w, &b, sizeof(w));
+    return w;
+}
+
+// r = b - J x; returns omega per right-hand side into om.
+void residual(mf_num* N, const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, int nrhs,
+              hipStream_t st, std::vector<double>& om) {
+    const Symbolic& S = N->sym->S;
+    HIPX(launch_residual(N->sym->dev->S, N->d_vals, S.n, x, ldx, b, ldb, r, S.n, nrhs, N->d_omega, st));
+    HIPX(hipMemcpyAsync(N->h_omega, N->d_omega, sizeof(unsigned long long) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    om.resize(nrhs);
+    for (int c = 0; c < nrhs; c++) om[c] = omega_of_bits(N->h_omega[c]);
+}
+
+void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipStream_t st, mf_solve_info* info) {
+    const Symbolic& S = N->sym->S;
+    const mf_options& o = N->opt;
+    const int64_t n = S.n;
+    ensure_solve_buffers(N, nrhs);
+    double* r = N->d_work;
+    double* dv = N->d_work + (size_t)n * nrhs;
+    apply_inverse(N, b, ld, x, ld, nrhs, st);
+    std::vector<double> om;
+    residual(N, b, ld, x, ld, r, nrhs, st, om);
+    mf_solve_info inf{};
+    inf.omega0 = *std::max_element(om.begin(), om.end());
+    int it = 0;
+    double w = inf.omega0;
+    // fixed-precision refinement: x += M^{-1} r until omega <= target
+    while (o.refine > 0 && w > o.target_omega && it < o.max_outer) {
+        apply_inverse(N, r, n, dv, n, nrhs, st);
+        HIPX(launch_axpy(n, x, ld, dv, n, nrhs, st));
+        residual(N, b, ld, x, ld, r, nrhs, st, om);
+        double wn = *std::max_element(om.begin(), om.end());
+        it++;
+        w = wn;
+    }
+    inf.omega = w;
+    inf.outer_iters = it;
+    if (info) *info = inf;
+    if (!(w <= o.target_omega) && o.refine > 0)
+        throw Fail{MF_ERR_NOT_CONVERGED, "refinement stopped at omega = " + std::to_string(w)};
+}
+
+}  // namespace
+
+extern "C" {
+
+void mf_default_options(mf_options* o) {
+    if (!o) return;
+    o->prec = MF_FP64;
+    o->pivot_u = 0.01;
+    o->leaf_max = 64;
+    o->target_omega = 1e-12;
+    o->max_outer = 10;
+    o->gmres_m = 30;
+    o->gmres_tol = 1e-4;
+    o->refine = -1;
+    o->panel_nb = 32;
+}
+
+const char* mf_last_error(void) { return g_err.c_str(); }
+
+mf_status mf_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, int32_t nroot, const int32_t* root_idx,
+                     const mf_options* opt, mf_sym_t* out) {
+    if (!out) return fail(MF_ERR_ARG, "out is null");
+    *out = nullptr;
+    try {
+        auto h = std::make_unique<mf_sym>();
+        if (opt)
+            h->opt = *opt;
+        else
+            mf_default_options(&h->opt);
+        analyze_pattern(h->S, n, rowptr, colind, nroot, root_idx, h->opt.leaf_max);
+        *out = h.release();
+        return MF_OK;
+    } catch (const std::invalid_argument& e) {
+        return fail(MF_ERR_ARG, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(MF_ERR_OOM, "host allocation failed in mf_analyze");
+    } catch (const std::exception& e) {
+        return fail(MF_ERR_ARG, e.what());
+    }
+}
+
+mf_status mf_symbolic_export(mf_sym_t h, mf_symbolic_view* v) {
+    if (!h || h->magic != kSymMagic || !v) return fail(MF_ERR_ARG, "bad symbolic handle");
+    const Symbolic& S = h->S;
+    v->n = S.n;
+    v->nfronts = S.nf;
+    v->leaf_max = S.leaf_max;
+    v->spec_version = kSpecVersion;
+    v->nlevels = S.nlevels;
+    v->perm = S.perm.data();
+    v->front_ptr = S.front_ptr.data();
+    v->front_parent = S.front_parent.data();
+    v->rows_ptr = S.rows_ptr.data();
+    v->rows = S.rows.data();
+    v->var_etree = S.var_etree.data();
+    v->nominal_flops = S.nominal_flops;
+    v->nominal_nnz_lu = S.nominal_nnz_lu;
+    return MF_OK;
+}
+
+mf_status mf_factor(mf_sym_t h, const double* values_dev, const mf_options* opt, void* stream, mf_num_t* inout) {
+    if (!h || h->magic != kSymMagic) return fail(MF_ERR_ARG, "bad symbolic handle");
+    if (!inout) return fail(MF_ERR_ARG, "inout is null");
+    if (!values_dev && h->S.nnz > 0) return fail(MF_ERR_ARG, "values_dev is null");
+    mf_num* N = *inout;
+    if (N && (N->magic != kNumMagic || N->sym != h))
+        return fail(MF_ERR_PATTERN, "numeric handle belongs to another symbolic handle");
+    std::unique_ptr<mf_num> fresh;
+    if (!N) {
+        fresh = std::make_unique<mf_num>();
+        N = fresh.get();
+        N->sym = h;
+    }
+    N->opt = h->opt;
+    if (opt) {
+        N->opt.prec = opt->prec;
+        N->opt.pivot_u = opt->pivot_u;
+        N->opt.target_omega = opt->target_omega;
+        N->opt.max_outer = opt->max_outer;
+        N->opt.gmres_m = opt->gmres_m;
+        N->opt.gmres_tol = opt->gmres_tol;
+        N->opt.refine = opt->refine;
+        N->opt.panel_nb = opt->panel_nb;
+    }
+    resolve_refine(N->opt);
+    if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");
+    if (!(N->opt.pivot_u >= 0.0 && N->opt.pivot_u <= 1.0)) return fail(MF_ERR_ARG, "pivot_u must be in [0, 1]");
+    N->factored = false;
+    try {
+        HIPX(hipGetDevice(&N->device));
+        do_factor(N, values_dev, (hipStream_t)stream);
+    } catch (const Fail& f) {
+        if (fresh) *inout = fresh.release();  // keep the handle so the caller can release it
+        return fail(f.st, f.msg);
+    } catch (const std::bad_alloc&) {
+        if (fresh) *inout = fresh.release();
+        return fail(MF_ERR_OOM, "host allocation failed in mf_factor");
+    }
+    if (fresh) *inout = fresh.release();
+    return MF_OK;
+}
+
+mf_status mf_get_factor_info(mf_num_t N, mf_factor_info* info) {
+    if (!N || N->magic != kNumMagic || !info) return fail(MF_ERR_ARG, "bad numeric handle");
+    if (!N->factored) return fail(MF_ERR_STATE, "not factored");
+    *info = N->info;
+    return MF_OK;
+}
+
+mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld, void* stream,
+                   mf_solve_info* info) {
+    if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
+    if (!N->factored) return fail(MF_ERR_STATE, "mf_solve before a successful mf_factor");
+    const int64_t n = N->sym->S.n;
+    if (nrhs < 0 || ld < std::max<int64_t>(n, 1)) return fail(MF_ERR_ARG, "bad nrhs or ld");
+    if (nrhs == 0 || n == 0) {
+        if (info) *info = mf_solve_info{};
+        return MF_OK;
+    }
+    if (!b_dev || !x_dev || b_dev == x_dev) return fail(MF_ERR_ARG, "b_dev and x_dev must be distinct device buffers");
+    try {
+        do_solve(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
+    } catch (const Fail& f) {
+        return fail(f.st, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(MF_ERR_OOM, "host allocation failed in mf_solve");
+    }
+    return MF_OK;
+}
+
+int64_t mf_footprint_bytes(mf_sym_t h, const mf_options* opt, double margin) {
+    if (!h || h->magic != kSymMagic) return -1;
+    const Symbolic& S = h->S;
+    const int prec = opt ? opt->prec : h->opt.prec;
+    double b = 0;
+    for (int f = 0; f < S.nf; f++) {
+        double m = S.mnom[f];
+        b += m * m * ((prec == MF_FP64 || S.front_parent[f] < 0) ? 8.0 : 4.0);
+        b += 4.0 * (4.0 * m + 1 + 4 * kNBMax);
+    }
+    b += 12.0 * S.nnz + 8.0 * S.n * 4;  // values copy, pattern, vectors
+    return (int64_t)(b * (1.0 + std::max(0.0, margin)));
+}
+
+void mf_release(void* handle) {
+    if (!handle) return;
+    uint32_t magic;
+    std::memcpy(&magic, handle, sizeof(magic));
+    if (magic == kSymMagic) {
+        mf_sym* h = (mf_sym*)handle;
+        h->magic = 0;
+        delete h;
+    } else if (magic == kNumMagic) {
+        mf_num* N = (mf_num*)handle;
+        (void)hipDeviceSynchronize();
+        N->magic = 0;
+        delete N;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Device-side data layout shared by the kernels and the numeric driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mf {
+
+// Panel width upper bound (options.panel_nb is clamped to it).
+constexpr int kNBMax = 64;
+
+// Per-front numeric state, indexed by "slot" (fronts in level order, so the
+// fronts of one tree level are contiguous).  Written by the host before a level
+// is assembled; k / k0 are updated by the factorization kernels.
+struct FrontNum {
+    void* F;         // dense front, column-major m x m (double or float)
+    int32_t* iv;     // rowpiv[P] | colperm[P] | rowperm[P] | colvar[m] | npairs, pairs[4*kNBMax]
+    int64_t voff;    // element offset of this front's vector block (times nrhs) in the solve arena
+    int32_t m;       // actual order (nominal + delayed-in)
+    int32_t P;       // fully summed variables (nominal pivots + delayed-in)
+    int32_t din;     // delayed-in count
+    int32_t k;       // eliminated so far / in total
+    int32_t k0;      // k at the start of the current panel
+    int32_t prec;    // 0: double front, 1: float front
+    int32_t npiv;    // nominal pivots
+    int32_t mnom;    // nominal order
+};
+
+// Pattern data (slot-indexed), uploaded once per symbolic handle.
+struct DevSym {
+    int32_t nslots;
+    const int32_t* parent;       // parent slot or -1
+    const int32_t* child_ptr;    // nslots+1
+    const int32_t* child_slot;   // children (slots) in increasing front order
+    const int64_t* rows_ptr;     // nslots+1, into rows (slot order)
+    const int32_t* rows;         // nominal front rows (original vars)
+    const int64_t* imap_off;     // per child slot: offset of its inverse map (length mnom[parent])
+    const int32_t* imap;
+    const int32_t* ue_slot;      // unique original entries
+    const int32_t* ue_row;
+    const int32_t* ue_col;
+    const int64_t* ue_src_ptr;
+    const int32_t* ue_src;
+    const int64_t* csr_rowptr;   // the matrix pattern (for residuals)
+    const int32_t* csr_colind;
+};
+
+__host__ __device__ inline int32_t* iv_rowpiv(int32_t* iv, int P, int m) { (void)m; return iv; }
+__host__ __device__ inline int32_t* iv_colperm(int32_t* iv, int P, int m) { (void)m; return iv + P; }
+__host__ __device__ inline int32_t* iv_rowperm(int32_t* iv, int P, int m) { (void)m; return iv + 2 * P; }
+__host__ __device__ inline int32_t* iv_colvar(int32_t* iv, int P, int m) { return iv + 3 * P; }
+__host__ __device__ inline int32_t* iv_pairs(int32_t* iv, int P, int m) { return iv + 3 * P + m; }
+__host__ __device__ inline int64_t iv_size(int P, int m) { return 3 * (int64_t)P + m + 1 + 4 * kNBMax; }
+
+}  // namespace mf

@@ -1,0 +1,61 @@
+// Internal structures shared by the host symbolic phase, the numeric driver and
+// the C ABI glue of libmf.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+
+namespace mf {
+
+constexpr uint32_t kSymMagic = 0x4d465359;  // "MFSY"
+constexpr uint32_t kNumMagic = 0x4d464e55;  // "MFNU"
+constexpr int kSpecVersion = 1;
+
+void set_error(const std::string& msg);
+
+// Result of the specified symbolic analysis plus everything the numeric phase
+// derives from it once per pattern.
+struct Symbolic {
+    int64_t n = 0;
+    int64_t nnz = 0;
+    int32_t leaf_max = 64;
+    std::vector<int64_t> rowptr;     // copy of the CSR pattern
+    std::vector<int32_t> colind;
+    std::vector<int32_t> root;
+
+    // bit-exact outputs
+    std::vector<int32_t> perm;          // new -> old
+    std::vector<int32_t> front_ptr;     // nf+1
+    std::vector<int32_t> front_parent;  // nf
+    std::vector<int64_t> rows_ptr;      // nf+1
+    std::vector<int32_t> rows;          // original variables
+    std::vector<int32_t> var_etree;     // n
+
+    // derived
+    int32_t nf = 0;
+    std::vector<int32_t> npiv, mnom;            // per front
+    std::vector<int32_t> child_ptr, child_idx;  // children in increasing front order
+    std::vector<int32_t> level;                 // height: leaves 0
+    int32_t nlevels = 0;
+    std::vector<int32_t> level_ptr, level_fronts;  // fronts grouped by level (ascending id)
+    // inverse nominal maps: for child c, imap[imap_off[c] + i] = nominal CB index of
+    // parent row i (0-based among c's non-pivot rows), or -1.  Length mnom[parent].
+    std::vector<int64_t> imap_off;
+    std::vector<int32_t> imap;
+    // unique original entries, ordered by (level, front, colpos, rowpos)
+    std::vector<int32_t> ue_front, ue_row, ue_col;  // nominal positions in the front
+    std::vector<int64_t> ue_src_ptr;                // n_ue + 1
+    std::vector<int32_t> ue_src;                    // CSR positions (duplicates summed)
+    std::vector<int64_t> level_ue_ptr;              // nlevels + 1
+    double nominal_flops = 0.0;
+    double nominal_nnz_lu = 0.0;
+};
+
+// Runs the specified analysis; throws std::runtime_error / std::invalid_argument.
+void analyze_pattern(Symbolic& S, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                     int32_t nroot, const int32_t* root_idx, int32_t leaf_max);
+
+}  // namespace mf

@@ -1,0 +1,101 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and its host symbolic analysis matches the oracle's bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2609_31477_amd as mf
+from oracle import sym as osym
+from tests.test_oracle_sym import graph_csr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_match_header():
+    hdr = open(os.path.join(ROOT, "include", "mf.h")).read()
+    declared = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(mf_\w+)\s*\(", hdr, flags=re.M))
+    assert declared == set(mf.EXPORTS)
+    L = mf.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def assert_same(view, S):
+    assert view.spec_version == 1
+    assert np.array_equal(view.perm, S.perm)
+    assert np.array_equal(view.front_ptr, S.front_ptr)
+    assert np.array_equal(view.front_parent, S.front_parent)
+    assert np.array_equal(view.rows_ptr, S.rows_ptr)
+    assert np.array_equal(view.rows, S.rows)
+    assert np.array_equal(view.var_etree, S.var_etree)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_symbolic_bit_exact_random(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 41))
+    m = int(rng.integers(0, 3 * n + 1))
+    e = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(m, 2))]
+    rp, ci = graph_csr(n, e)
+    nr = int(rng.integers(0, min(3, n) + 1))
+    root = rng.permutation(n)[:nr].tolist()
+    leaf = int(rng.choice([1, 2, 4, 8]))
+    v = mf.Symbolic(n, rp, ci, root, leaf_max=leaf).export()
+    assert_same(v, osym.analyze(n, rp, ci, root, leaf_max=leaf))
+
+
+def test_symbolic_worked_example():
+    rp, ci = graph_csr(7, [(i, i + 1) for i in range(6)])
+    v = mf.Symbolic(7, rp, ci, [], leaf_max=2).export()
+    assert v.perm.tolist() == [0, 2, 1, 4, 6, 5, 3]
+    assert v.front_parent.tolist() == [2, 2, 6, 5, 5, 6, -1]
+
+
+@pytest.mark.parametrize("nx,ny,seed,leaf", [(16, 8, 0, 64), (32, 16, 3, 16), (64, 32, 0, 64)])
+def test_symbolic_bit_exact_jacobian(nx, ny, seed, leaf):
+    from vivjac import build_2d
+    s = build_2d(nx, ny, seed)
+    sy = mf.Symbolic(s.n, s.rowptr, s.colind, s.root, leaf_max=leaf)
+    v = sy.export()
+    S = osym.analyze(s.n, s.rowptr, s.colind, s.root, leaf_max=leaf)
+    assert_same(v, S)
+    npiv = np.diff(S.front_ptr).astype(float)
+    m = np.diff(S.rows_ptr).astype(float)
+    assert v.nominal_nnz_lu == pytest.approx(float((2 * m * npiv - npiv ** 2).sum()))
+
+
+def test_symbolic_unsorted_duplicates():
+    # unsorted columns and duplicate entries give the same analysis as the clean pattern
+    rp, ci = graph_csr(6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5)])
+    v1 = mf.Symbolic(6, rp, ci, [], leaf_max=1).export()
+    rp2, ci2 = graph_csr(6, [(0, 1), (0, 1), (2, 3), (1, 2), (4, 5), (3, 4), (2, 1)])
+    v2 = mf.Symbolic(6, rp2, ci2, [], leaf_max=1).export()
+    assert np.array_equal(v1.perm, v2.perm) and np.array_equal(v1.rows, v2.rows)
+
+
+def test_analyze_errors():
+    rp, ci = graph_csr(3, [(0, 1)])
+    with pytest.raises(mf.MFError) as e:
+        mf.Symbolic(3, rp, ci, [3])
+    assert e.value.status == mf.MF_ERR_ARG
+    with pytest.raises(mf.MFError):
+        mf.Symbolic(3, rp, np.array([7], dtype=np.int32))
+    with pytest.raises(mf.MFError):
+        mf.Symbolic(3, rp, ci, [1, 1])
+    bad = rp.copy()
+    bad[1] = 5
+    with pytest.raises(mf.MFError):
+        mf.Symbolic(3, bad, ci, [])
+
+
+def test_empty_pattern():
+    v = mf.Symbolic(0, np.zeros(1, np.int64), np.zeros(0, np.int32), []).export()
+    assert v.nfronts == 0 and v.perm.size == 0
+
+
+def test_footprint_positive(config0):
+    s = config0
+    sy = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    assert sy.footprint_bytes("fp64") > sy.footprint_bytes("fp32") > 0

@@ -1,0 +1,162 @@
+"""GPU parity: the HIP multifrontal path (through the C ABI) against the CPU oracle.
+
+Bar (plain FP64 path): relative solution error <= 1e-8 against the oracle and a
+componentwise backward error omega <= 1e-12 (computed here on the CPU by the
+oracle's own residual), with at most 2 FP64 refinement steps."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2609_31477_amd as mf
+from oracle import check, splu, sym as osym
+from vivjac import build_2d, newton_rhs, newton_values
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-8
+OMEGA_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def oracle_solve(n, rp, ci, vals, root, B):
+    S = osym.analyze(n, rp, ci, root)
+    F = splu.SparseLU(n, rp, ci, vals, S.perm, tau=0.1 if n > 50000 else 1.0)
+    X, om, _ = F.solve(B)
+    return X
+
+
+def gpu_solve(torch, n, rp, ci, vals, root, B, leaf_max=64, **opts):
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(n, rp, ci, root, leaf_max=leaf_max)
+    num = S.factor(torch.from_numpy(np.ascontiguousarray(vals)).to(dev), **opts)
+    x, info = num.solve(torch.from_numpy(np.ascontiguousarray(B)).to(dev))
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info, num
+
+
+def assert_parity(A, X, Xo, B, rel_tol=REL_TOL, omega_tol=OMEGA_TOL):
+    X = np.atleast_2d(X)
+    Xo = np.atleast_2d(Xo)
+    B = np.atleast_2d(B)
+    for c in range(X.shape[0]):
+        rel = np.abs(X[c] - Xo[c]).max() / np.abs(Xo[c]).max()
+        om = check.omega(A, X[c], B[c]) if A.shape[0] <= 20000 else check.omega_fast(A, X[c], B[c])
+        print(f"rhs {c}: rel_err={rel:.3e} omega={om:.3e}", flush=True)
+        assert rel <= rel_tol
+        assert om <= omega_tol
+
+
+def test_config0_fp64(torch_cuda):
+    s = build_2d(16, 8, 0)
+    B = s.b0[0]
+    X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B)
+    fi = num.info()
+    print(f"delayed={fi.delayed_pivots} max_front={fi.max_front} root={fi.root_order} "
+          f"omega0={info.omega0:.3e} omega={info.omega:.3e} steps={info.outer_iters}", flush=True)
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    assert_parity(s.to_scipy(), X, Xo, B)
+    assert info.outer_iters <= 2
+
+
+def random_saddle(rng, n, density=0.1, zero_diag_frac=0.3):
+    """Random unsymmetric system with a zero-diagonal block (forces delayed pivots)."""
+    A = sp.random(n, n, density=density, random_state=np.random.RandomState(int(rng.integers(1 << 30))), format="csr")
+    A = A + sp.eye(n) * 2.0
+    A = A.tolil()
+    nz = rng.permutation(n)[: int(zero_diag_frac * n)]
+    for i in nz:
+        A[i, i] = 0.0
+        j = int(rng.integers(n))
+        if j != i:
+            A[i, j] = 1.0 + rng.random()
+            A[j, i] = 1.0 + rng.random()
+    A = A.tocsr()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("seed,n,leaf,nrhs", [(0, 30, 4, 1), (1, 120, 8, 3), (2, 400, 16, 2), (3, 1000, 64, 1),
+                                              (4, 257, 1, 1), (5, 777, 32, 5)])
+def test_random_forced_delays(torch_cuda, seed, n, leaf, nrhs):
+    rng = np.random.default_rng(seed)
+    A = random_saddle(rng, n, density=min(0.2, 8.0 / n))
+    if abs(np.linalg.det(A.toarray())) < 1e-8:
+        pytest.skip("singular draw")
+    B = rng.standard_normal((nrhs, n))
+    root = [] if seed % 2 else [n - 1]
+    X, info, num = gpu_solve(torch_cuda, n, A.indptr, A.indices, A.data, root, B, leaf_max=leaf)
+    Xo = np.linalg.solve(A.toarray(), B.T).T
+    print(f"n={n} delayed={num.info().delayed_pivots}", flush=True)
+    assert_parity(A, X, Xo, B)
+
+
+def test_multi_rhs_and_determinism(torch_cuda):
+    s = build_2d(32, 16, 2, nrhs=8)
+    B = s.b0
+    X1, i1, _ = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B)
+    X2, i2, _ = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B)
+    assert np.array_equal(X1, X2), "same input must give a bitwise-equal solution"
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    assert_parity(s.to_scipy(), X1, Xo, B)
+
+
+def test_newton_steps_reuse_symbolic(torch_cuda):
+    torch = torch_cuda
+    s = build_2d(32, 16, 1)
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    Os = osym.analyze(s.n, s.rowptr, s.colind, s.root)
+    num = None
+    for t in range(3):
+        v = newton_values(s, t)
+        b = newton_rhs(s, t)[0]
+        num = S.factor(torch.from_numpy(v).to(dev), numeric=num)
+        x, info = num.solve(torch.from_numpy(b).to(dev))
+        xh = x.cpu().numpy()
+        xo, _, _ = splu.SparseLU(s.n, s.rowptr, s.colind, v, Os.perm).solve(b)
+        assert_parity(s.to_scipy(v), xh, xo, b)
+
+
+def test_64x32_fp64(torch_cuda):
+    s = build_2d(64, 32, 0)
+    B = s.b0[0]
+    X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B)
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    print(f"64x32: delayed={num.info().delayed_pivots} steps={info.outer_iters}", flush=True)
+    assert_parity(s.to_scipy(), X, Xo, B)
+
+
+def test_singular_reported(torch_cuda):
+    torch = torch_cuda
+    A = sp.csr_matrix(np.array([[1.0, 2.0, 0.0], [2.0, 4.0, 0.0], [0.0, 0.0, 1.0]]))
+    S = mf.Symbolic(3, A.indptr, A.indices, [])
+    with pytest.raises(mf.MFError) as e:
+        S.factor(torch.from_numpy(A.data.copy()).cuda())
+    assert e.value.status == mf.MF_ERR_SINGULAR
+
+
+def test_nan_values_reported(torch_cuda):
+    torch = torch_cuda
+    s = build_2d(16, 8, 0)
+    v = s.values.copy()
+    v[100] = np.nan
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    with pytest.raises(mf.MFError) as e:
+        num = S.factor(torch.from_numpy(v).cuda())
+        num.solve(torch.from_numpy(s.b0[0].copy()).cuda())
+    assert e.value.status in (mf.MF_ERR_SINGULAR, mf.MF_ERR_NOT_CONVERGED)
+
+
+def test_empty_system(torch_cuda):
+    torch = torch_cuda
+    S = mf.Symbolic(0, np.zeros(1, np.int64), np.zeros(0, np.int32), [])
+    num = S.factor(torch.zeros(0, dtype=torch.float64, device="cuda"))
+    x, info = num.solve(torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert x.numel() == 0
