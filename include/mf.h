@@ -62,6 +62,8 @@ typedef struct {
     int32_t refine;        /* 0 = none, 1 = classical FP64 refinement, 2 = GMRES-IR
                               (default: 1 for MF_FP64, 2 otherwise; -1 = by precision) */
     int32_t panel_nb;      /* panel width of the front factorization (default 32) */
+    int32_t profile;       /* 1 = time the factorization phases with HIP events on the
+                              caller's stream (reported in mf_factor_info; default 0) */
 } mf_options;
 
 /* Fill *opt with the defaults above. */
@@ -148,6 +150,14 @@ typedef struct {
     double factor_flops;        /* nominal algorithmic flops of the factorization */
     double actual_flops;        /* flops of the actual (delay-grown) fronts */
     int64_t factor_bytes;       /* device bytes held by the fronts */
+    /* filled when options.profile = 1 (milliseconds of device time, summed over levels) */
+    double t_assemble_ms;       /* extend-add gather + original-entry scatter */
+    double t_panel_ms;          /* panel factorization, row swaps + U12 solves, eager updates */
+    double t_schur_ms;          /* deferred contribution-block (Schur) GEMMs */
+    double t_finalize_ms;       /* column bookkeeping */
+    double schur_flops;         /* algorithmic flops of the Schur GEMMs: sum 2 (m-P)^2 k */
+    int32_t schur_launches;     /* Schur GEMM launches timed */
+    int32_t levels;             /* tree levels (one host synchronization each) */
 } mf_factor_info;
 
 mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);
@@ -174,6 +184,13 @@ mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrh
 /* Device bytes a factorization of this pattern needs at nominal front sizes,
  * times (1 + margin) for delayed-pivot growth (admission estimate). */
 int64_t mf_footprint_bytes(mf_sym_t sym, const mf_options* opt, double margin);
+
+/* Introspection of one factored front (for tests and debugging): copies the
+ * front's state to host memory.  meta[8] = {m, P, din, k, npiv, mnom, prec, slot};
+ * F_host (may be NULL) receives the m x m column-major front as FP64 (L\U, L21,
+ * U12 and the contribution block); iv_host (may be NULL) receives
+ * rowpiv[P], colperm[P], rowperm[P], colvar[m].  Synchronizes the device. */
+mf_status mf_debug_front(mf_num_t num, int32_t front, int32_t* meta, double* F_host, int32_t* iv_host);
 
 /* Release a symbolic or numeric handle (synchronizes its device work first).
  * NULL is ignored.  A symbolic handle must outlive its numeric handles. */

@@ -27,13 +27,14 @@ PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
 
 # every entry point declared in include/mf.h
 EXPORTS = ["mf_default_options", "mf_analyze", "mf_symbolic_export", "mf_factor", "mf_get_factor_info",
-           "mf_solve", "mf_footprint_bytes", "mf_release", "mf_last_error"]
+           "mf_solve", "mf_footprint_bytes", "mf_debug_front", "mf_release", "mf_last_error"]
 
 
 class mf_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("pivot_u", ctypes.c_double), ("leaf_max", ctypes.c_int32),
                 ("target_omega", ctypes.c_double), ("max_outer", ctypes.c_int32), ("gmres_m", ctypes.c_int32),
-                ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32)]
+                ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
 
 
 class mf_symbolic_view(ctypes.Structure):
@@ -48,7 +49,9 @@ class mf_symbolic_view(ctypes.Structure):
 class mf_factor_info(ctypes.Structure):
     _fields_ = [("delayed_pivots", ctypes.c_int64), ("max_front", ctypes.c_int32), ("root_order", ctypes.c_int32),
                 ("factor_flops", ctypes.c_double), ("actual_flops", ctypes.c_double),
-                ("factor_bytes", ctypes.c_int64)]
+                ("factor_bytes", ctypes.c_int64), ("t_assemble_ms", ctypes.c_double),
+                ("t_panel_ms", ctypes.c_double), ("t_schur_ms", ctypes.c_double), ("t_finalize_ms", ctypes.c_double),
+                ("schur_flops", ctypes.c_double), ("schur_launches", ctypes.c_int32), ("levels", ctypes.c_int32)]
 
 
 class mf_solve_info(ctypes.Structure):
@@ -89,6 +92,8 @@ def lib():
         L.mf_solve.restype = ctypes.c_int
         L.mf_footprint_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_options), ctypes.c_double]
         L.mf_footprint_bytes.restype = ctypes.c_int64
+        L.mf_debug_front.argtypes = [ctypes.c_void_p, ctypes.c_int32, P, P, P]
+        L.mf_debug_front.restype = ctypes.c_int
         L.mf_release.argtypes = [ctypes.c_void_p]
         L.mf_release.restype = None
         L.mf_last_error.argtypes = []
@@ -235,6 +240,18 @@ class Numeric:
         if check or st != MF_ERR_NOT_CONVERGED:
             _check(st)
         return x, inf
+
+    def debug_front(self, front):
+        """(meta dict, F (m x m, column-major as a numpy array F[i, j]), iv dict) of one front."""
+        meta = np.zeros(8, dtype=np.int32)
+        _check(lib().mf_debug_front(self._h, int(front), meta.ctypes.data, None, None))
+        m, P = int(meta[0]), int(meta[1])
+        F = np.zeros(m * m, dtype=np.float64)
+        iv = np.zeros(3 * P + m, dtype=np.int32)
+        _check(lib().mf_debug_front(self._h, int(front), meta.ctypes.data, F.ctypes.data, iv.ctypes.data))
+        keys = ["m", "P", "din", "k", "npiv", "mnom", "prec", "slot"]
+        return (dict(zip(keys, meta.tolist())), F.reshape(m, m).T.copy(),
+                dict(rowpiv=iv[:P], colperm=iv[P:2 * P], rowperm=iv[2 * P:3 * P], colvar=iv[3 * P:]))
 
     def release(self):
         if getattr(self, "_h", None):

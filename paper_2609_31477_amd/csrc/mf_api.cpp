@@ -18,10 +18,11 @@
 namespace mf {
 
 // kernel launchers (mf_kernels.hip)
+// ev (nullable): 4 events recorded after assembly, panels, Schur GEMM and finalize
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, int Pmax,
                                const double* vals, int64_t u0, int64_t u1, int NB, double u, int prec,
-                               hipStream_t st);
+                               hipStream_t st, hipEvent_t* ev);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
@@ -256,6 +257,20 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
     }
     std::vector<int32_t> dout(nf, 0);
     FrontNum* hf = N->h_fn;
+    const bool prof = o.profile != 0;
+    hipEvent_t ev[2][5] = {};
+    if (prof)
+        for (int p = 0; p < 2; p++)
+            for (int e = 0; e < 5; e++) HIPX(hipEventCreate(&ev[p][e]));
+    struct EvGuard {
+        hipEvent_t (*e)[5];
+        bool on;
+        ~EvGuard() {
+            if (on)
+                for (int p = 0; p < 2; p++)
+                    for (int k = 0; k < 5; k++) (void)hipEventDestroy(e[p][k]);
+        }
+    } evg{ev, prof};
     int64_t voff = 0;
     mf_factor_info info{};
     info.factor_flops = S.nominal_flops;
@@ -301,17 +316,37 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
         // fronts of both precisions may share a level; each kernel skips the other kind
-        if (N->lvl_cnt[0][L])
+        if (N->lvl_cnt[0][L]) {
+            if (prof) HIPX(hipEventRecord(ev[0][0], st));
             HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L], N->lvl_Pmax[0][L],
-                                             N->d_vals, u0, u1, NB, o.pivot_u, 0, st));
-        if (N->lvl_cnt[1][L])
+                                             N->d_vals, u0, u1, NB, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr));
+        }
+        if (N->lvl_cnt[1][L]) {
+            if (prof) HIPX(hipEventRecord(ev[1][0], st));
             HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L], N->lvl_Pmax[1][L],
-                                            N->d_vals, u0, u1, NB, o.pivot_u, 1, st));
+                                            N->d_vals, u0, u1, NB, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr));
+        }
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));
+        info.levels++;
+        if (prof)
+            for (int p = 0; p < 2; p++) {
+                if (!N->lvl_cnt[p][L]) continue;
+                float ms[4];
+                for (int e = 0; e < 4; e++) HIPX(hipEventElapsedTime(&ms[e], ev[p][e], ev[p][e + 1]));
+                info.t_assemble_ms += ms[0];
+                info.t_panel_ms += ms[1];
+                info.t_schur_ms += ms[2];
+                info.t_finalize_ms += ms[3];
+                info.schur_launches++;
+            }
         for (int sl = s0; sl < s1; sl++) {
             const FrontNum& fr = hf[sl];
             dout[sl] = fr.P - fr.k;
+            {
+                const double cb = (double)(fr.m - fr.P);
+                info.schur_flops += 2.0 * cb * cb * (double)fr.k;
+            }
             info.delayed_pivots += dout[sl];
             const int f = S.level_fronts[sl];
             if (S.front_parent[f] < 0) {
@@ -453,6 +488,7 @@ void mf_default_options(mf_options* o) {
     o->gmres_tol = 1e-4;
     o->refine = -1;
     o->panel_nb = 32;
+    o->profile = 0;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -521,6 +557,7 @@ mf_status mf_factor(mf_sym_t h, const double* values_dev, const mf_options* opt,
         N->opt.gmres_tol = opt->gmres_tol;
         N->opt.refine = opt->refine;
         N->opt.panel_nb = opt->panel_nb;
+        N->opt.profile = opt->profile;
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");
@@ -552,11 +589,12 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
     if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
     if (!N->factored) return fail(MF_ERR_STATE, "mf_solve before a successful mf_factor");
     const int64_t n = N->sym->S.n;
-    if (nrhs < 0 || ld < std::max<int64_t>(n, 1)) return fail(MF_ERR_ARG, "bad nrhs or ld");
+    if (nrhs < 0) return fail(MF_ERR_ARG, "bad nrhs");
     if (nrhs == 0 || n == 0) {
         if (info) *info = mf_solve_info{};
         return MF_OK;
     }
+    if (ld < n) return fail(MF_ERR_ARG, "ld < n");
     if (!b_dev || !x_dev || b_dev == x_dev) return fail(MF_ERR_ARG, "b_dev and x_dev must be distinct device buffers");
     try {
         do_solve(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
@@ -564,6 +602,34 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
         return fail(f.st, f.msg);
     } catch (const std::bad_alloc&) {
         return fail(MF_ERR_OOM, "host allocation failed in mf_solve");
+    }
+    return MF_OK;
+}
+
+mf_status mf_debug_front(mf_num_t N, int32_t front, int32_t* meta, double* F_host, int32_t* iv_host) {
+    if (!N || N->magic != kNumMagic || !meta) return fail(MF_ERR_ARG, "bad arguments");
+    if (!N->factored) return fail(MF_ERR_STATE, "not factored");
+    const Symbolic& S = N->sym->S;
+    if (front < 0 || front >= S.nf) return fail(MF_ERR_ARG, "front out of range");
+    try {
+        HIPX(hipDeviceSynchronize());
+        const int sl = N->sym->dev->slot_of[front];
+        const FrontNum fr = N->h_fn[sl];
+        int32_t mm[8] = {fr.m, fr.P, fr.din, fr.k, fr.npiv, fr.mnom, fr.prec, sl};
+        std::memcpy(meta, mm, sizeof(mm));
+        const size_t cnt = (size_t)fr.m * fr.m;
+        if (F_host) {
+            if (fr.prec == 0) {
+                HIPX(hipMemcpy(F_host, fr.F, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> tmp(cnt);
+                HIPX(hipMemcpy(tmp.data(), fr.F, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < cnt; i++) F_host[i] = tmp[i];
+            }
+        }
+        if (iv_host) HIPX(hipMemcpy(iv_host, fr.iv, sizeof(int32_t) * (3 * (size_t)fr.P + fr.m), hipMemcpyDeviceToHost));
+    } catch (const Fail& f) {
+        return fail(f.st, f.msg);
     }
     return MF_OK;
 }

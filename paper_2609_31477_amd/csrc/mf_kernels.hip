@@ -319,12 +319,16 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
 // ------------------------------------------------------------------ GEMM
 template <typename T>
 struct Mfma;
+// Operand layouts of both 16x16x4 MFMAs: lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  Result register r of lane l is D[row(l, r)][l%16], where the
+// row mapping differs between the FP64 and FP32 instructions (measured on gfx950).
 template <>
 struct Mfma<double> {
     typedef dbl4 acc_t;
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 template <>
 struct Mfma<float> {
@@ -332,6 +336,7 @@ struct Mfma<float> {
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 // C -= A * B on a 64x64 tile of one front, with A = F[rows, ka:kb], B = F[ka:kb, cols].
@@ -409,14 +414,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
         }
         __syncthreads();
     }
-    // D layout: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
 #pragma unroll
     for (int bi = 0; bi < 2; bi++)
 #pragma unroll
         for (int bj = 0; bj < 2; bj++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int i = wi * 32 + bi * 16 + 4 * (lane / 16) + r;
+                const int i = wi * 32 + bi * 16 + Mfma<T>::row(lane, r);
                 const int j = wj * 32 + bj * 16 + (lane & 15);
                 Cs[j * kLdsPad + i] = acc[bi][bj][r];
             }
@@ -662,13 +666,14 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const double* x, i
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, int Pmax,
                                const double* vals, int64_t u0, int64_t u1, int NB, double u, int prec,
-                               hipStream_t st) {
+                               hipStream_t st, hipEvent_t* ev) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
                        fn, slot0, prec);
     if (u1 > u0)
         hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                            st, S, fn, vals, u0, u1, prec);
+    if (ev) (void)hipEventRecord(ev[0], st);
     const int npan = (Pmax + NB - 1) / NB;
     const size_t panel_lds = (sizeof(T) + sizeof(int)) * (size_t)Pmax;
     const int tiles = (mmax + kTile - 1) / kTile;
@@ -677,15 +682,18 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
         hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tiles, count), dim3(kThreads), 0, st, fn, slot0, t, NB, prec);
         hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, t, NB, 0, prec);
     }
+    if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 0, NB, 1, prec);
+    if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_finalize<T>, dim3(count), dim3(kThreads), 0, st, S, fn, slot0, prec);
+    if (ev) (void)hipEventRecord(ev[3], st);
     return MF_CHECK_LAUNCH();
 }
 
 template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, int, const double*,
-                                                int64_t, int64_t, int, double, int, hipStream_t);
+                                                int64_t, int64_t, int, double, int, hipStream_t, hipEvent_t*);
 template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, int, const double*,
-                                               int64_t, int64_t, int, double, int, hipStream_t);
+                                               int64_t, int64_t, int, double, int, hipStream_t, hipEvent_t*);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
