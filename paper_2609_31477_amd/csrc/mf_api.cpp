@@ -29,6 +29,7 @@ hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int 
 template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
+int panel_nb(int prec, int mmax);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
                            unsigned long long* omega_bits, hipStream_t st);
@@ -139,7 +140,7 @@ struct mf_num {
     mf_sym* sym = nullptr;
     mf_options opt;
     int device = -1;
-    Arena fronts, ints;
+    Arena fronts, ints, wsp;  // fronts, integer bookkeeping, per-level panel scratch
     FrontNum* d_fn = nullptr;
     FrontNum* h_fn = nullptr;  // pinned mirror
     double* d_vals = nullptr;
@@ -157,6 +158,7 @@ struct mf_num {
     ~mf_num() {
         fronts.release();
         ints.release();
+        wsp.release();
         if (d_fn) (void)hipFree(d_fn);
         if (h_fn) (void)hipHostFree(h_fn);
         if (d_vals) (void)hipFree(d_vals);
@@ -246,7 +248,8 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
         for (int f = 0; f < nf; f++) tot += (double)S.mnom[f] * S.mnom[f];
         size_t esz = (o.prec == MF_FP64) ? 8 : 4;
         N->fronts.grow_hint = (size_t)(tot * esz * 1.25) + (64u << 20);
-        N->ints.grow_hint = (size_t)(sizeof(int32_t) * (S.rows.size() * 4 + (size_t)nf * (1 + 4 * kNBMax))) + (16u << 20);
+        N->ints.grow_hint = (size_t)(sizeof(int32_t) * (S.rows.size() * 4 + (size_t)nf * (3 + 7 * kNBMax))) + (16u << 20);
+        N->wsp.grow_hint = (64u << 20);
     }
     N->fronts.reset();
     N->ints.reset();
@@ -289,6 +292,10 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
             fr.P = S.npiv[f] + din;
             fr.k = 0;
             fr.k0 = 0;
+            fr.pcur = fr.P;
+            fr.x0 = 0;
+            fr.x1 = 0;
+            fr.pad_ = 0;
             fr.prec = front_prec(o, S.front_parent[f] < 0);
             const size_t esz = fr.prec ? 4 : 8;
             const size_t fb = esz * (size_t)fr.m * (size_t)fr.m;
@@ -307,12 +314,19 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
         }
         for (int p = 0; p < 2; p++) {
             if (!N->lvl_cnt[p][L]) continue;
-            size_t lds = (size_t)N->lvl_Pmax[p][L] * ((p ? 4 : 8) + sizeof(int));
-            if (lds > kMaxLds)
+            size_t lds = (size_t)N->lvl_Pmax[p][L] * 2 * sizeof(int);
+            if (lds > kMaxLds || N->lvl_mmax[p][L] > 4096)
                 throw Fail{MF_ERR_ARG, "front with " + std::to_string(N->lvl_Pmax[p][L]) +
                                            " fully summed variables exceeds the panel kernel's LDS budget"};
         }
         if (s1 - s0 > 65535) throw Fail{MF_ERR_ARG, "tree level with more than 65535 fronts"};
+        // panel scratch (reused level by level): m x NB entries per front
+        N->wsp.reset();
+        for (int sl = s0; sl < s1; sl++) {
+            FrontNum& fr = hf[sl];
+            const int nbp = panel_nb(fr.prec, N->lvl_mmax[fr.prec][L]);
+            fr.W = N->wsp.alloc((size_t)fr.m * nbp * (fr.prec ? 4 : 8));
+        }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
         // fronts of both precisions may share a level; each kernel skips the other kind

@@ -25,6 +25,10 @@ struct FrontNum {
     int32_t prec;    // 0: double front, 1: float front
     int32_t npiv;    // nominal pivots
     int32_t mnom;    // nominal order
+    int32_t pcur;    // end of the not-yet-tried fully summed columns [k, pcur); [pcur, P) are delayed
+    int32_t x0, x1;  // columns rejected by the last panel (already up to date): skipped by its updates
+    int32_t pad_;
+    void* W;         // panel scratch: rows [k0, m) of the last window, final row order (ld m - k0)
 };
 
 // Pattern data (slot-indexed), uploaded once per symbolic handle.
@@ -50,7 +54,9 @@ __host__ __device__ inline int32_t* iv_rowpiv(int32_t* iv, int P, int m) { (void
 __host__ __device__ inline int32_t* iv_colperm(int32_t* iv, int P, int m) { (void)m; return iv + P; }
 __host__ __device__ inline int32_t* iv_rowperm(int32_t* iv, int P, int m) { (void)m; return iv + 2 * P; }
 __host__ __device__ inline int32_t* iv_colvar(int32_t* iv, int P, int m) { return iv + 3 * P; }
+// panel area: npairs, pairs[2 * 2 * kNBMax] | w, nmove, col_dst[kNBMax], mv_src[kNBMax], mv_dst[kNBMax]
 __host__ __device__ inline int32_t* iv_pairs(int32_t* iv, int P, int m) { return iv + 3 * P + m; }
-__host__ __device__ inline int64_t iv_size(int P, int m) { return 3 * (int64_t)P + m + 1 + 4 * kNBMax; }
+__host__ __device__ inline int32_t* iv_commit(int32_t* iv, int P, int m) { return iv + 3 * P + m + 1 + 4 * kNBMax; }
+__host__ __device__ inline int64_t iv_size(int P, int m) { return 3 * (int64_t)P + m + 1 + 4 * kNBMax + 2 + 3 * kNBMax; }
 
 }  // namespace mf

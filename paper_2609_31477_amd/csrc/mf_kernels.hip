@@ -127,128 +127,246 @@ __global__ __launch_bounds__(kThreads) void k_scatter(DevSym S, FrontNum* fn, co
 }
 
 // ------------------------------------------------------------------ panel
-// Threshold partial pivoting on the window of fully summed columns
-// [t*NB, min(P, (t+1)*NB)).  Column q is accepted when its largest fully summed
-// entry (rows [k, P)) is at least u times its largest entry over all remaining
-// rows [k, m); otherwise it stays behind (delayed) and later pivots keep
-// updating it.  Accepted pivots are swapped to position k (column swap over the
-// whole front, row swap over the panel's columns).  The row swaps of the panel
-// are summarised as (destination, source) pairs for the other columns.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_panel(FrontNum* fn, int slot0, int t, int NB, double u,
-                                                    int want_prec) {
-    extern __shared__ char smem[];
-    __shared__ double red_a[kThreads / 64], red_f[kThreads / 64];
-    __shared__ int red_i[kThreads / 64];
+// Column bookkeeping of a front during its partial factorization:
+//   [0, k)        eliminated pivots
+//   [k, pcur)     fully summed columns not tried yet
+//   [pcur, P)     delayed columns (no acceptable pivot when tried)
+//   [P, m)        contribution-block columns
+// One panel tries the window [k, k + w), w = min(NB, pcur - k).  Column c is
+// accepted when its largest entry among the remaining fully summed rows is at
+// least u times its largest entry among all remaining rows (threshold partial
+// pivoting); otherwise it is delayed and keeps receiving the panel's updates.
+// Rows [k, m) of the window live in registers (RS rows per thread, 512
+// threads), so a column step costs two barriers and no global traffic.  At the
+// end, accepted columns go to [k, k + nb), delayed ones to the tail of the
+// untried range, and the untried columns they displace move into the freed
+// window slots; rows are permuted by the LAPACK-style swap sequence, which is
+// also published as (destination, source) pairs for the columns outside the
+// window.  Columns [x0, x1) (the ones just delayed) are already up to date.
+constexpr int kPanelThreads = 512;
+
+template <typename T, int NB>
+__device__ __forceinline__ T pick(const T (&v)[NB], int c) {
+    T x = v[0];
+#pragma unroll
+    for (int j = 1; j < NB; j++) x = (c == j) ? v[j] : x;
+    return x;
+}
+
+template <typename T, int NB, int RS>
+__global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0, double u, int want_prec) {
+    extern __shared__ int dyn[];                  // lmap[P] | dst[P] (row positions relative to k)
+    __shared__ T urow[NB];
+    __shared__ double red_a[kPanelThreads / 64], red_f[kPanelThreads / 64];
+    __shared__ int red_i[kPanelThreads / 64];
+    __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB];
+    __shared__ int mv_src[NB], mv_dst[NB], mv_tag[NB];
     __shared__ int npairs_s;
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
-    const int wstart = t * NB;
-    if (wstart >= P) return;
-    const int wend = min(P, wstart + NB);
+    const int kd0 = d.k, pc = d.pcur;
+    if (kd0 >= pc) {
+        // nothing left to try: mark an empty round so the trailing updates skip it
+        if (threadIdx.x == 0) {
+            fn[s].k0 = kd0;
+            iv_commit(d.iv, P, m)[0] = 0;
+        }
+        return;
+    }
+    const int w = min(NB, pc - kd0);
     T* F = (T*)d.F;
-    T* urow = (T*)smem;                                        // pivot row segment, P entries
-    int* lmap = (int*)(smem + sizeof(T) * (size_t)P);         // row position -> source, P entries
-    int32_t* rowpiv = iv_rowpiv(d.iv, P, m);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int* lmap = dyn;
+    int* dstm = dyn + (P - kd0);
+
+    T v[RS][NB];
+    int pstep[RS];
+#pragma unroll
+    for (int r = 0; r < RS; r++) {
+        const int row = kd0 + tid + kPanelThreads * r;
+        pstep[r] = row < m ? -1 : -2;
+#pragma unroll
+        for (int c = 0; c < NB; c++) v[r][c] = (row < m && c < w) ? F[row + (int64_t)(kd0 + c) * m] : T(0);
+    }
+    uint64_t elim = 0;
+    int nb = 0;
+    // fully unrolled so that every register index below is a compile-time constant
+#pragma clang loop unroll(full)
+    for (int c = 0; c < NB; c++) {
+        if (c < w) {
+            double aall = 0.0, afs = -1.0;
+            int ifs = INT_MAX;
+            T cv[RS];
+    #pragma unroll
+            for (int r = 0; r < RS; r++) {
+                cv[r] = pick<T, NB>(v[r], c);
+                if (pstep[r] == -1) {
+                    const double a = fabs((double)cv[r]);
+                    if (!(a <= aall)) aall = (a != a) ? INFINITY : a;
+                    const int row = kd0 + tid + kPanelThreads * r;
+                    if (row < P && a > afs) {
+                        afs = a;
+                        ifs = row;
+                    }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                aall = fmax(aall, __shfl_xor(aall, off));
+                const double of = __shfl_xor(afs, off);
+                const int oi = __shfl_xor(ifs, off);
+                if (of > afs || (of == afs && oi < ifs)) {
+                    afs = of;
+                    ifs = oi;
+                }
+            }
+            if (lane == 0) {
+                red_a[wid] = aall;
+                red_f[wid] = afs;
+                red_i[wid] = ifs;
+            }
+            __syncthreads();
+            aall = red_a[0];
+            afs = red_f[0];
+            ifs = red_i[0];
+    #pragma unroll
+            for (int q = 1; q < kPanelThreads / 64; q++) {
+                aall = fmax(aall, red_a[q]);
+                if (red_f[q] > afs || (red_f[q] == afs && red_i[q] < ifs)) {
+                    afs = red_f[q];
+                    ifs = red_i[q];
+                }
+            }
+            const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
+            if (accept) {
+                const int rel = ifs - kd0;
+                if ((rel % kPanelThreads) == tid) {
+                    const int rs = rel / kPanelThreads;
+    #pragma unroll
+                    for (int r = 0; r < RS; r++)
+                        if (r == rs) {
+    #pragma unroll
+                            for (int j = 0; j < NB; j++) urow[j] = v[r][j];
+                            pstep[r] = nb;
+                        }
+                }
+                if (tid == 0) {
+                    acc_col[nb] = c;
+                    piv_row[nb] = ifs;
+                }
+            }
+            __syncthreads();
+            if (accept) {
+                const T piv = urow[c];
+    #pragma unroll
+                for (int r = 0; r < RS; r++) {
+                    if (pstep[r] != -1) continue;
+                    const T l = cv[r] / piv;
+    #pragma unroll
+                    for (int j = 0; j < NB; j++) {
+                        if (j == c)
+                            v[r][j] = l;
+                        else if (j < w && !((elim >> j) & 1ull))
+                            v[r][j] -= l * urow[j];
+                    }
+                }
+                elim |= 1ull << c;
+                nb++;
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- final column and row positions
+    const int nrej = w - nb;
+    const int pc_new = pc - nrej;
+    if (tid == 0) {
+        int t = 0, rj = 0;
+        for (int c = 0; c < w; c++) {
+            if ((elim >> c) & 1ull) continue;
+            col_dst[c] = pc_new + rj++;
+        }
+        for (t = 0; t < nb; t++) col_dst[acc_col[t]] = kd0 + t;
+        // untried columns displaced by the delayed block move into freed window slots
+        int nm = 0;
+        int fslot = kd0 + nb;
+        for (int q = max(pc_new, kd0 + w); q < pc; q++) {
+            while (fslot >= pc_new && fslot < pc) fslot++;  // never reached: freed slots precede pc_new
+            mv_src[nm] = q;
+            mv_dst[nm] = fslot++;
+            nm++;
+        }
+        npairs_s = nm;  // reused below as the move count
+    }
+    for (int i = kd0 + tid; i < P; i += kPanelThreads) {
+        lmap[i - kd0] = i;   // position -> original row now there
+        dstm[i - kd0] = i;   // original row -> its current position
+    }
+    __syncthreads();
+    const int nmove = npairs_s;
+    if (tid == 0) {
+        // swap sequence: the pivot row of step t goes to position k0 + t, the row
+        // found there takes the pivot row's current position
+        for (int t = 0; t < nb; t++) {
+            const int a = kd0 + t, r = piv_row[t];
+            const int p = dstm[r - kd0];
+            const int ra = lmap[a - kd0];
+            lmap[a - kd0] = r;
+            lmap[p - kd0] = ra;
+            dstm[r - kd0] = a;
+            dstm[ra - kd0] = p;
+        }
+    }
+    __syncthreads();
+    // column tags (before any column moves)
     int32_t* colperm = iv_colperm(d.iv, P, m);
     int32_t* rowperm = iv_rowperm(d.iv, P, m);
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    int kd = d.k;
-    const int kd0 = kd;
-    for (int q = wstart; q < wend; q++) {
-        const T* col = F + (int64_t)q * m;
-        double aall = 0.0, afs = -1.0;
-        int ifs = INT_MAX;
-        for (int i = kd + tid; i < m; i += kThreads) {
-            const double a = fabs((double)col[i]);
-            if (!(a <= aall)) aall = (a != a) ? INFINITY : a;
-            if (i < P && a > afs) {
-                afs = a;
-                ifs = i;
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double oa = __shfl_xor(aall, off);
-            aall = fmax(aall, oa);
-            const double of = __shfl_xor(afs, off);
-            const int oi = __shfl_xor(ifs, off);
-            if (of > afs || (of == afs && oi < ifs)) {
-                afs = of;
-                ifs = oi;
-            }
-        }
-        if (lane == 0) {
-            red_a[wid] = aall;
-            red_f[wid] = afs;
-            red_i[wid] = ifs;
-        }
-        __syncthreads();
-        aall = red_a[0];
-        afs = red_f[0];
-        ifs = red_i[0];
+    if (tid < w) old_tag[tid] = colperm[kd0 + tid];
+    if (tid < nmove) mv_tag[tid] = colperm[mv_src[tid]];
+    int rtag[(4096 + kPanelThreads - 1) / kPanelThreads];
 #pragma unroll
-        for (int w = 1; w < kThreads / 64; w++) {
-            aall = fmax(aall, red_a[w]);
-            if (red_f[w] > afs || (red_f[w] == afs && red_i[w] < ifs)) {
-                afs = red_f[w];
-                ifs = red_i[w];
-            }
-        }
-        __syncthreads();
-        const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
-        if (!accept) continue;  // uniform: column q stays behind as a delayed column
-        const int r = ifs;
-        if (q != kd)
-            for (int i = tid; i < m; i += kThreads) {
-                const T a = F[i + (int64_t)q * m];
-                F[i + (int64_t)q * m] = F[i + (int64_t)kd * m];
-                F[i + (int64_t)kd * m] = a;
-            }
-        if (tid == 0) {
-            rowpiv[kd] = r;
-            const int cq = colperm[q];
-            colperm[q] = colperm[kd];
-            colperm[kd] = cq;
-            const int rr = rowperm[r];
-            rowperm[r] = rowperm[kd];
-            rowperm[kd] = rr;
-        }
-        __syncthreads();
-        if (r != kd)
-            for (int j = kd0 + tid; j < wend; j += kThreads) {
-                const T a = F[r + (int64_t)j * m];
-                F[r + (int64_t)j * m] = F[kd + (int64_t)j * m];
-                F[kd + (int64_t)j * m] = a;
-            }
-        __syncthreads();
-        for (int j = kd + 1 + tid; j < wend; j += kThreads) urow[j] = F[kd + (int64_t)j * m];
-        __syncthreads();
-        const T piv = F[kd + (int64_t)kd * m];
-        for (int i = kd + 1 + tid; i < m; i += kThreads) {
-            const T l = F[i + (int64_t)kd * m] / piv;
-            F[i + (int64_t)kd * m] = l;
-            for (int j = kd + 1; j < wend; j++) F[i + (int64_t)j * m] -= l * urow[j];
-        }
-        kd++;
-        __syncthreads();
+    for (int q = 0; q < (4096 + kPanelThreads - 1) / kPanelThreads; q++) {
+        const int i = kd0 + tid + kPanelThreads * q;
+        rtag[q] = (i < P) ? rowperm[lmap[i - kd0]] : 0;
     }
-    // composite row permutation of this panel on rows [kd0, P): (dest, source) pairs
-    for (int i = kd0 + tid; i < P; i += kThreads) lmap[i] = i;
+    __syncthreads();
+    // window rows [k0, m) in final row order go to the front's panel scratch; the
+    // column permutation of all rows is committed by k_commit
+    T* Wp = (T*)d.W;
+    const int R = m - kd0;
+#pragma unroll
+    for (int r = 0; r < RS; r++) {
+        const int row = kd0 + tid + kPanelThreads * r;
+        if (row >= m) continue;
+        const int drow = row < P ? dstm[row - kd0] : row;
+#pragma unroll
+        for (int c = 0; c < NB; c++)
+            if (c < w) Wp[(drow - kd0) + (int64_t)c * R] = v[r][c];
+    }
+    int32_t* cm = iv_commit(d.iv, P, m);
+    if (tid == 0) {
+        cm[0] = w;
+        cm[1] = nmove;
+    }
+    if (tid < w) cm[2 + tid] = col_dst[tid];
+    if (tid < nmove) {
+        cm[2 + kNBMax + tid] = mv_src[tid];
+        cm[2 + 2 * kNBMax + tid] = mv_dst[tid];
+    }
+    if (tid < w) colperm[col_dst[tid]] = old_tag[tid];
+    if (tid < nmove) colperm[mv_dst[tid]] = mv_tag[tid];
+#pragma unroll
+    for (int q = 0; q < (4096 + kPanelThreads - 1) / kPanelThreads; q++) {
+        const int i = kd0 + tid + kPanelThreads * q;
+        if (i < P) rowperm[i] = rtag[q];
+    }
+    // (destination, source) row pairs for the columns outside the window
     if (tid == 0) npairs_s = 0;
     __syncthreads();
-    if (tid == 0)
-        for (int qq = kd0; qq < kd; qq++) {
-            const int r = rowpiv[qq];
-            const int a = lmap[qq];
-            lmap[qq] = lmap[r];
-            lmap[r] = a;
-        }
-    __syncthreads();
     int32_t* pairs = iv_pairs(d.iv, P, m);
-    for (int i = kd0 + tid; i < P; i += kThreads) {
-        const int src = lmap[i];
+    for (int i = kd0 + tid; i < P; i += kPanelThreads) {
+        const int src = lmap[i - kd0];
         if (src != i) {
             const int slot = atomicAdd(&npairs_s, 1);
             pairs[1 + 2 * slot] = i;
@@ -258,24 +376,56 @@ __global__ __launch_bounds__(kThreads) void k_panel(FrontNum* fn, int slot0, int
     __syncthreads();
     if (tid == 0) {
         pairs[0] = npairs_s;
-        fn[s].k = kd;
+        fn[s].k = kd0 + nb;
         fn[s].k0 = kd0;
+        fn[s].pcur = pc_new;
+        fn[s].x0 = pc_new;
+        fn[s].x1 = pc;
     }
 }
 
-// Row swaps of the panel on every column outside the panel, then U12 rows of
-// the new pivots (unit-lower triangular solve with L11) for columns >= wend.
-// Block (x: 64-column tile, y: front); one wave per column at a time.
+// Commit the last panel's column permutation on every row: window column c of
+// the panel moves to col_dst[c] (rows >= k0 from the panel scratch, rows < k0
+// from the old column), and each displaced untried column moves whole from
+// mv_src to mv_dst.  Each thread owns one row and reads all its sources before
+// writing, so no two threads touch the same entry.  Block (x: 256 rows, y: front).
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, int want_prec) {
+    const int s = slot0 + blockIdx.y;
+    const FrontNum d = fn[s];
+    if (d.prec != want_prec) return;
+    const int m = d.m, P = d.P;
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= m) return;
+    const int32_t* cm = iv_commit(d.iv, P, m);
+    const int w = cm[0], nmove = cm[1];
+    if (w <= 0) return;
+    const int kd0 = d.k0, R = m - kd0;
+    T* F = (T*)d.F;
+    const T* Wp = (const T*)d.W;
+    T val[NB], mval[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c++) {
+        if (c < w) val[c] = i >= kd0 ? Wp[(i - kd0) + (int64_t)c * R] : F[i + (int64_t)(kd0 + c) * m];
+        if (c < nmove) mval[c] = F[i + (int64_t)cm[2 + kNBMax + c] * m];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; c++) {
+        if (c < nmove) F[i + (int64_t)cm[2 + 2 * kNBMax + c] * m] = mval[c];
+        if (c < w) F[i + (int64_t)cm[2 + c] * m] = val[c];
+    }
+}
+
+// Columns outside the last panel's window: apply its row swaps; for columns
+// ahead of it (>= k, outside the just-delayed block) also form the new U rows
+// with the unit-lower L11 of the panel.  Block (x: 64-column tile, y: front).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int t, int NB, int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec) {
     __shared__ T L11[kNBMax * kNBMax];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
-    const int wstart = t * NB;
-    if (wstart >= P) return;
-    const int wend = min(P, wstart + NB);
     const int kd0 = d.k0, kd1 = d.k, nb = kd1 - kd0;
     if (nb <= 0) return;
     const int c0 = blockIdx.x * kTile;
@@ -294,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     for (int cc = wid; cc < kTile; cc += kThreads / 64) {
         const int j = c0 + cc;
         if (j >= m) break;
-        if (j >= kd0 && j < wend) continue;
+        if ((j >= kd0 && j < kd1) || (j >= d.x0 && j < d.x1)) continue;
         T* colp = F + (int64_t)j * m;
         const T v0 = lane < np ? colp[s0] : T(0);
         const T v1 = lane + 64 < np ? colp[s1] : T(0);
@@ -305,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     for (int cc = wid; cc < kTile; cc += kThreads / 64) {
         const int j = c0 + cc;
         if (j >= m) break;
-        if (j < wend) continue;
+        if (j < kd1 || (j >= d.x0 && j < d.x1)) continue;
         T* colp = F + (int64_t)j * m + kd0;
         double x = lane < nb ? (double)colp[lane] : 0.0;
         for (int a = 0; a < nb - 1; a++) {
@@ -340,14 +490,14 @@ struct Mfma<float> {
 };
 
 // C -= A * B on a 64x64 tile of one front, with A = F[rows, ka:kb], B = F[ka:kb, cols].
-// mode 0 (eager, after panel t): rows [k, m) x cols [wend, m) except the deferred
-//        block rows >= P and cols >= P; K = the panel's pivots [k0, k).
+// mode 0 (eager, after a panel): rows [k, m) x cols [k, m) except the columns the
+//        panel just delayed [x0, x1) and the deferred block rows >= P and cols >= P;
+//        K = the panel's pivots [k0, k).
 // mode 1 (Schur): rows [P, m) x cols [P, m); K = all pivots [0, k).
 // Block (x: column tile, y: row tile, z: front).  4 waves, each a 32x32 quarter
 // made of 2x2 MFMA 16x16 blocks; K staged through LDS in chunks of 32.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int t, int NB, int mode,
-                                                   int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec) {
     // A and B chunks, then (aliased) the C tile for the transposed epilogue
     __shared__ T smem_ab[2 * kKC * kLdsPad];
     static_assert(2 * kKC * kLdsPad >= kTile * kLdsPad, "C tile must fit in the A/B buffer");
@@ -360,11 +510,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     const int m = d.m, P = d.P;
     int rlo, clo, ka, kb;
     if (mode == 0) {
-        const int wstart = t * NB;
-        if (wstart >= P) return;
-        const int wend = min(P, wstart + NB);
         rlo = d.k;
-        clo = wend;
+        clo = 0;
         ka = d.k0;
         kb = d.k;
     } else {
@@ -376,8 +523,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     if (kb <= ka) return;
     const int col0 = clo + blockIdx.x * kTile;
     const int row0 = (mode == 0 ? 0 : P) + blockIdx.y * kTile;
-    if (col0 >= m || row0 >= m || row0 + kTile <= rlo) return;
+    if (col0 >= m || row0 >= m || row0 + kTile <= rlo || col0 + kTile <= rlo) return;
     if (mode == 0 && row0 >= P && col0 >= P) return;
+    if (mode == 0 && col0 >= d.x0 && col0 + kTile <= d.x1) return;
     const T* F = (const T*)d.F;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wi = wid & 1, wj = wid >> 1;
@@ -429,8 +577,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     for (int idx = tid; idx < kTile * kTile; idx += kThreads) {
         const int i = idx % kTile, j = idx / kTile;
         const int row = row0 + i, col = col0 + j;
-        if (row < rlo || row >= m || col >= m) continue;
-        if (mode == 0 && row >= P && col >= P) continue;
+        if (row < rlo || row >= m || col >= m || col < rlo) continue;
+        if (mode == 0 && ((row >= P && col >= P) || (col >= d.x0 && col < d.x1))) continue;
         Fw[row + (int64_t)col * m] -= Cs[j * kLdsPad + i];
     }
 }
@@ -471,13 +619,22 @@ __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, i
 }
 
 // ------------------------------------------------------------------ solve
-// Forward sweep of one level: z = rows of (b + children's CB vectors) in final
-// row order; y = L11^{-1} z[0:k]; CB vector = z[k:m] - L21 y.  The front's block
-// of `vec` receives [y; CB vector].  One block per front; z lives in LDS.
+// Each front owns a block of `vec` (m x nrhs, column-major, ld m).  Forward
+// sweep (leaves to root), per front:
+//   z = rows of (b + the children's contribution vectors) in final row order
+//   y = L11^{-1} z[0:k]            (k_fwd_tri: one block; 16x16 diagonal blocks
+//                                    are solved by one wave from registers)
+//   c = z[k:m] - L21 y             (k_fwd_gemv: many blocks per large front)
+// and the block of `vec` holds [y; c].  Backward sweep (root to leaves):
+//   t = y - U12 x[colvar[k:m]]     (k_bwd_gemv)
+//   x[colvar[0:k]] = U11^{-1} t    (k_bwd_tri)
+constexpr int kBS = 16;       // diagonal block of the triangular sweeps
+constexpr int kGemvRows = 256;
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const FrontNum* fn, int slot0, int want_prec,
-                                                  const double* b, int64_t ldb, double* vec, int nrhs, int c0,
-                                                  int nrc) {
+__global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
+                                                      const double* b, int64_t ldb, double* vec, int nrhs, int c0,
+                                                      int nrc) {
     extern __shared__ double zs[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
@@ -507,26 +664,30 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const FrontNum* fn, 
         }
     }
     __syncthreads();
-    constexpr int BS = 16;
-    for (int j0 = 0; j0 < k; j0 += BS) {
-        const int bs = min(BS, k - j0);
+    for (int j0 = 0; j0 < k; j0 += kBS) {
+        const int bs = min(kBS, k - j0);
         if (wid == 0) {
+            double Lr[kBS];
+#pragma unroll
+            for (int a = 0; a < kBS; a++)
+                Lr[a] = (lane < bs && a < lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + a) * m] : 0.0;
             for (int c = 0; c < nrc; c++) {
                 double x = lane < bs ? zs[j0 + lane + c * m] : 0.0;
 #pragma unroll
-                for (int a = 0; a < BS - 1; a++) {
-                    if (a + 1 >= bs) break;
+                for (int a = 0; a < kBS - 1; a++) {
                     const double xa = __shfl(x, a);
-                    if (lane > a && lane < bs) x -= (double)F[(j0 + lane) + (int64_t)(j0 + a) * m] * xa;
+                    x -= Lr[a] * xa;
                 }
                 if (lane < bs) zs[j0 + lane + c * m] = x;
             }
         }
         __syncthreads();
-        for (int i = j0 + bs + tid; i < m; i += kThreads) {
+        for (int i = j0 + bs + tid; i < k; i += kThreads) {
             for (int c = 0; c < nrc; c++) {
                 double acc = zs[i + c * m];
-                for (int a = 0; a < bs; a++) acc -= (double)F[i + (int64_t)(j0 + a) * m] * zs[j0 + a + c * m];
+#pragma unroll
+                for (int a = 0; a < kBS; a++)
+                    if (a < bs) acc -= (double)F[i + (int64_t)(j0 + a) * m] * zs[j0 + a + c * m];
                 zs[i + c * m] = acc;
             }
         }
@@ -536,12 +697,81 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const FrontNum* fn, 
         for (int c = 0; c < nrc; c++) v[i + (int64_t)(c0 + c) * m] = zs[i + c * m];
 }
 
-// Backward sweep of one level (root first): x_f = U11^{-1} (y - U12 x_cb), where
-// x_cb is gathered from x at the front's remaining column variables.
+// c[i] = z[i] - sum_{j<k} L[i, j] y[j] for rows i in [k, m); block (x: row chunk, y: front)
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd(const FrontNum* fn, int slot0, int want_prec, double* x,
-                                                  int64_t ldx, const double* vec, int nrhs, int c0, int nrc) {
+__global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int slot0, int want_prec, double* vec,
+                                                       int nrhs, int c0, int nrc) {
+    extern __shared__ double ys[];
+    const int s = slot0 + blockIdx.y;
+    const FrontNum d = fn[s];
+    if (d.prec != want_prec) return;
+    const int m = d.m, k = d.k;
+    const int i0 = k + blockIdx.x * kGemvRows;
+    if (i0 >= m || k == 0) return;
+    const T* F = (const T*)d.F;
+    double* v = vec + d.voff * nrhs;
+    for (int j = threadIdx.x; j < k; j += kThreads)
+        for (int c = 0; c < nrc; c++) ys[j + c * k] = v[j + (int64_t)(c0 + c) * m];
+    __syncthreads();
+    const int i = i0 + threadIdx.x;
+    if (i >= m) return;
+    for (int c = 0; c < nrc; c++) {
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        const double* yc = ys + c * k;
+        int j = 0;
+        for (; j + 4 <= k; j += 4) {
+            acc0 += (double)F[i + (int64_t)j * m] * yc[j];
+            acc1 += (double)F[i + (int64_t)(j + 1) * m] * yc[j + 1];
+            acc2 += (double)F[i + (int64_t)(j + 2) * m] * yc[j + 2];
+            acc3 += (double)F[i + (int64_t)(j + 3) * m] * yc[j + 3];
+        }
+        for (; j < k; j++) acc0 += (double)F[i + (int64_t)j * m] * yc[j];
+        v[i + (int64_t)(c0 + c) * m] -= (acc0 + acc1) + (acc2 + acc3);
+    }
+}
+
+// t[i] = y[i] - sum_{j in [k,m)} U[i, j] x[colvar[j]] for rows i < k, in place in vec
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int slot0, int want_prec, const double* x,
+                                                       int64_t ldx, double* vec, int nrhs, int c0, int nrc) {
     extern __shared__ double xs[];
+    const int s = slot0 + blockIdx.y;
+    const FrontNum d = fn[s];
+    if (d.prec != want_prec) return;
+    const int m = d.m, P = d.P, k = d.k;
+    const int i0 = blockIdx.x * kGemvRows;
+    if (i0 >= k || k == m) return;
+    const T* F = (const T*)d.F;
+    const int32_t* colvar = iv_colvar(d.iv, P, m);
+    double* v = vec + d.voff * nrhs;
+    const int nc = m - k;
+    for (int j = threadIdx.x; j < nc; j += kThreads) {
+        const int var = colvar[k + j];
+        for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
+    }
+    __syncthreads();
+    const int i = i0 + threadIdx.x;
+    if (i >= k) return;
+    const T* Fr = F + i + (int64_t)k * m;
+    for (int c = 0; c < nrc; c++) {
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        const double* xc = xs + c * nc;
+        int j = 0;
+        for (; j + 4 <= nc; j += 4) {
+            acc0 += (double)Fr[(int64_t)j * m] * xc[j];
+            acc1 += (double)Fr[(int64_t)(j + 1) * m] * xc[j + 1];
+            acc2 += (double)Fr[(int64_t)(j + 2) * m] * xc[j + 2];
+            acc3 += (double)Fr[(int64_t)(j + 3) * m] * xc[j + 3];
+        }
+        for (; j < nc; j++) acc0 += (double)Fr[(int64_t)j * m] * xc[j];
+        v[i + (int64_t)(c0 + c) * m] -= (acc0 + acc1) + (acc2 + acc3);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
+                                                      int64_t ldx, const double* vec, int nrhs, int c0, int nrc) {
+    extern __shared__ double ts[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
@@ -550,39 +780,37 @@ __global__ __launch_bounds__(kThreads) void k_bwd(const FrontNum* fn, int slot0,
     const int32_t* colvar = iv_colvar(d.iv, P, m);
     const double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    for (int i = tid; i < m; i += kThreads)
-        for (int c = 0; c < nrc; c++)
-            xs[i + c * m] = (i < k) ? v[i + (int64_t)(c0 + c) * m]
-                                    : (colvar[i] >= 0 ? x[colvar[i] + (int64_t)(c0 + c) * ldx] : 0.0);
+    for (int i = tid; i < k; i += kThreads)
+        for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
     __syncthreads();
-    for (int i = tid; i < k; i += kThreads) {
-        for (int c = 0; c < nrc; c++) {
-            double acc = xs[i + c * m];
-            for (int j = k; j < m; j++) acc -= (double)F[i + (int64_t)j * m] * xs[j + c * m];
-            xs[i + c * m] = acc;
-        }
-    }
-    __syncthreads();
-    constexpr int BS = 16;
-    for (int j1 = k; j1 > 0; j1 -= BS) {
-        const int j0 = max(0, j1 - BS), bs = j1 - j0;
+    for (int j1 = k; j1 > 0; j1 -= kBS) {
+        const int j0 = max(0, j1 - kBS), bs = j1 - j0;
         if (wid == 0) {
+            double Ur[kBS];
+#pragma unroll
+            for (int a = 0; a < kBS; a++)
+                Ur[a] = (lane < bs && a >= lane && a < bs) ? (double)F[(j0 + lane) + (int64_t)(j0 + a) * m] : 0.0;
             for (int c = 0; c < nrc; c++) {
-                double xl = lane < bs ? xs[j0 + lane + c * m] : 0.0;
-                for (int a = bs - 1; a >= 0; a--) {
-                    if (lane == a) xl /= (double)F[(j0 + a) + (int64_t)(j0 + a) * m];
-                    const double xa = __shfl(xl, a);
-                    if (lane < a) xl -= (double)F[(j0 + lane) + (int64_t)(j0 + a) * m] * xa;
+                double xl = lane < bs ? ts[j0 + lane + c * k] : 0.0;
+#pragma unroll
+                for (int a = kBS - 1; a >= 0; a--) {
+                    if (a < bs) {
+                        if (lane == a) xl /= Ur[a];
+                        const double xa = __shfl(xl, a);
+                        if (lane < a) xl -= Ur[a] * xa;
+                    }
                 }
-                if (lane < bs) xs[j0 + lane + c * m] = xl;
+                if (lane < bs) ts[j0 + lane + c * k] = xl;
             }
         }
         __syncthreads();
         for (int i = tid; i < j0; i += kThreads) {
             for (int c = 0; c < nrc; c++) {
-                double acc = xs[i + c * m];
-                for (int a = 0; a < bs; a++) acc -= (double)F[i + (int64_t)(j0 + a) * m] * xs[j0 + a + c * m];
-                xs[i + c * m] = acc;
+                double acc = ts[i + c * k];
+#pragma unroll
+                for (int a = 0; a < kBS; a++)
+                    if (a < bs) acc -= (double)F[i + (int64_t)(j0 + a) * m] * ts[j0 + a + c * k];
+                ts[i + c * k] = acc;
             }
         }
         __syncthreads();
@@ -590,7 +818,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd(const FrontNum* fn, int slot0,
     for (int i = tid; i < k; i += kThreads) {
         const int var = colvar[i];
         if (var < 0) continue;
-        for (int c = 0; c < nrc; c++) x[var + (int64_t)(c0 + c) * ldx] = xs[i + c * m];
+        for (int c = 0; c < nrc; c++) x[var + (int64_t)(c0 + c) * ldx] = ts[i + c * k];
     }
 }
 
@@ -663,27 +891,58 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const double* x, i
 // ------------------------------------------------------------------ launchers
 #define MF_CHECK_LAUNCH() (hipGetLastError())
 
+template <typename T, int NB, int RS>
+static void launch_panels(FrontNum* fn, int slot0, int count, int mmax, int Pmax, double u, int prec, hipStream_t st,
+                          hipEvent_t* ev, const DevSym& S) {
+    const int npan = (Pmax + NB - 1) / NB;
+    const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
+    const int tiles = (mmax + kTile - 1) / kTile;
+    for (int t = 0; t < npan; t++) {
+        hipLaunchKernelGGL((k_panel<T, NB, RS>), dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+        hipLaunchKernelGGL((k_commit<T, NB>), dim3((mmax + kThreads - 1) / kThreads, count), dim3(kThreads), 0, st,
+                           fn, slot0, prec);
+        hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tiles, count), dim3(kThreads), 0, st, fn, slot0, prec);
+        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 0, prec);
+    }
+}
+
+// Panel shape per level (NB columns in registers, RS rows per thread) is chosen
+// from the level's largest front so that the window fits in 512 threads' VGPRs.
+int panel_nb(int prec, int mmax) {
+    if (mmax <= 1024) return 32;
+    if (mmax <= 2048) return prec ? 32 : 16;
+    return prec ? 16 : 8;
+}
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, int Pmax,
-                               const double* vals, int64_t u0, int64_t u1, int NB, double u, int prec,
+                               const double* vals, int64_t u0, int64_t u1, int NB_unused, double u, int prec,
                                hipStream_t st, hipEvent_t* ev) {
     if (count <= 0) return hipSuccess;
+    if (mmax > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
                        fn, slot0, prec);
     if (u1 > u0)
         hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                            st, S, fn, vals, u0, u1, prec);
     if (ev) (void)hipEventRecord(ev[0], st);
-    const int npan = (Pmax + NB - 1) / NB;
-    const size_t panel_lds = (sizeof(T) + sizeof(int)) * (size_t)Pmax;
-    const int tiles = (mmax + kTile - 1) / kTile;
-    for (int t = 0; t < npan; t++) {
-        hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kThreads), panel_lds, st, fn, slot0, t, NB, u, prec);
-        hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tiles, count), dim3(kThreads), 0, st, fn, slot0, t, NB, prec);
-        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, t, NB, 0, prec);
+    if (mmax <= 512)
+        launch_panels<T, 32, 1>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
+    else if (mmax <= 1024)
+        launch_panels<T, 32, 2>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
+    else if (mmax <= 2048) {
+        if constexpr (sizeof(T) == 8)
+            launch_panels<T, 16, 4>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
+        else
+            launch_panels<T, 32, 4>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
+    } else {
+        if constexpr (sizeof(T) == 8)
+            launch_panels<T, 8, 8>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
+        else
+            launch_panels<T, 16, 8>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
     }
+    const int tiles = (mmax + kTile - 1) / kTile;
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 0, NB, 1, prec);
+    hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 1, prec);
     if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_finalize<T>, dim3(count), dim3(kThreads), 0, st, S, fn, slot0, prec);
     if (ev) (void)hipEventRecord(ev[3], st);
@@ -699,15 +958,19 @@ template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd<T>, dim3(count), dim3(kThreads), sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0,
-                       prec, b, ldb, vec, nrhs, c0, nrc);
+    hipLaunchKernelGGL(k_fwd_tri<T>, dim3(count), dim3(kThreads), sizeof(double) * (size_t)mmax * nrc, st, S, fn,
+                       slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+    hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
 }
 template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bwd<T>, dim3(count), dim3(kThreads), sizeof(double) * (size_t)mmax * nrc, st, fn, slot0,
+    hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc);
+    hipLaunchKernelGGL(k_bwd_tri<T>, dim3(count), dim3(kThreads), sizeof(double) * (size_t)mmax * nrc, st, fn, slot0,
                        prec, x, ldx, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
 }
