@@ -30,6 +30,13 @@ template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
 int panel_nb(int prec, int mmax);
+hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, double* y, hipStream_t st);
+hipError_t launch_mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, double* out,
+                       hipStream_t st);
+hipError_t launch_vsub(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n, hipStream_t st);
+hipError_t launch_vadd(double* x, const double* V, int64_t ldv, int nv, const double* c, int64_t n, hipStream_t st);
+hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t st);
+hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
                            unsigned long long* omega_bits, hipStream_t st);
@@ -149,6 +156,10 @@ struct mf_num {
     size_t vec_cap = 0;        // doubles
     double* d_work = nullptr;  // r, d, x0 copies (3 * n * nrhs)
     size_t work_cap = 0;
+    double* d_kry = nullptr;   // GMRES basis (n x (m+1)), w, and reduction scratch
+    size_t kry_cap = 0;
+    double* d_small = nullptr;  // device coefficients (dots, combination weights)
+    double* h_small = nullptr;  // pinned mirror
     unsigned long long* d_omega = nullptr;
     unsigned long long* h_omega = nullptr;  // pinned
     int omega_cap = 0;
@@ -164,6 +175,9 @@ struct mf_num {
         if (d_vals) (void)hipFree(d_vals);
         if (d_vec) (void)hipFree(d_vec);
         if (d_work) (void)hipFree(d_work);
+        if (d_kry) (void)hipFree(d_kry);
+        if (d_small) (void)hipFree(d_small);
+        if (h_small) (void)hipHostFree(h_small);
         if (d_omega) (void)hipFree(d_omega);
         if (h_omega) (void)hipHostFree(h_omega);
     }
@@ -457,6 +471,111 @@ void residual(mf_num* N, const double* b, int64_t ldb, const double* x, int64_t 
     for (int c = 0; c < nrhs; c++) om[c] = omega_of_bits(N->h_omega[c]);
 }
 
+constexpr int kDotBlocksHost = 512;
+
+void ensure_krylov(mf_num* N, int mres) {
+    const int64_t n = N->sym->S.n;
+    size_t need = (size_t)n * (mres + 2) + (size_t)kDotBlocksHost * (mres + 2);
+    if (need > N->kry_cap) {
+        if (N->d_kry) HIPX(hipFree(N->d_kry));
+        N->d_kry = nullptr;
+        HIPX(hipMalloc((void**)&N->d_kry, sizeof(double) * need));
+        N->kry_cap = need;
+    }
+    if (!N->d_small) {
+        HIPX(hipMalloc((void**)&N->d_small, sizeof(double) * 1024));
+        HIPX(hipHostMalloc((void**)&N->h_small, sizeof(double) * 1024, hipHostMallocDefault));
+    }
+}
+
+// dots[0:nv] = V[:,0:nv]^T w, returned on the host (one synchronization)
+void mdot_host(mf_num* N, const double* V, int64_t ldv, int nv, const double* w, double* part, double* out,
+               hipStream_t st) {
+    const int64_t n = N->sym->S.n;
+    HIPX(launch_mdot(V, ldv, nv, w, n, part, N->d_small, st));
+    HIPX(hipMemcpyAsync(N->h_small, N->d_small, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    for (int i = 0; i < nv; i++) out[i] = N->h_small[i];
+}
+
+void put_small(mf_num* N, const double* v, int cnt, hipStream_t st) {
+    for (int i = 0; i < cnt; i++) N->h_small[512 + i] = v[i];
+    HIPX(hipMemcpyAsync(N->d_small + 512, N->h_small + 512, sizeof(double) * cnt, hipMemcpyHostToDevice, st));
+}
+
+// GMRES(m) on M^{-1} J d = M^{-1} r for one right-hand side column (r, d: length n,
+// FP64).  Classical Gram-Schmidt with one reorthogonalization; Givens rotations on
+// the host.  Returns the number of inner iterations.
+int gmres_correction(mf_num* N, const double* r, double* d, int mres, double tol, hipStream_t st) {
+    const Symbolic& S = N->sym->S;
+    const int64_t n = S.n;
+    const DevSym& DS = N->sym->dev->S;
+    double* V = N->d_kry;
+    double* w = V + (size_t)n * (mres + 1);
+    double* part = w + n;
+    // v0 = M^{-1} r
+    apply_inverse(N, r, n, w, n, 1, st);
+    double beta2;
+    mdot_host(N, w, n, 1, w, part, &beta2, st);
+    const double beta = std::sqrt(beta2);
+    HIPX(launch_fill(d, 0.0, n, st));
+    if (!(beta > 0.0) || !std::isfinite(beta)) return 0;
+    HIPX(launch_scale(V, w, 1.0 / beta, n, st));
+    std::vector<double> H((size_t)(mres + 1) * mres, 0.0), cs(mres), sn(mres), g(mres + 1, 0.0);
+    g[0] = beta;
+    int j = 0;
+    std::vector<double> h(mres + 1), h2(mres + 1);
+    for (; j < mres; j++) {
+        double* vj = V + (size_t)n * j;
+        double* vj1 = V + (size_t)n * (j + 1);
+        HIPX(launch_spmv(DS, N->d_vals, n, vj, vj1, st));          // vj1 = J vj (temporary)
+        apply_inverse(N, vj1, n, w, n, 1, st);                      // w = M^{-1} J vj
+        mdot_host(N, V, n, j + 1, w, part, h.data(), st);
+        put_small(N, h.data(), j + 1, st);
+        HIPX(launch_vsub(w, V, n, j + 1, N->d_small + 512, n, st));
+        mdot_host(N, V, n, j + 1, w, part, h2.data(), st);      // reorthogonalize
+        put_small(N, h2.data(), j + 1, st);
+        HIPX(launch_vsub(w, V, n, j + 1, N->d_small + 512, n, st));
+        for (int i = 0; i <= j; i++) h[i] += h2[i];
+        double hn2;
+        mdot_host(N, w, n, 1, w, part, &hn2, st);
+        const double hn = std::sqrt(hn2);
+        h[j + 1] = hn;
+        if (hn > 0.0) HIPX(launch_scale(vj1, w, 1.0 / hn, n, st));
+        // apply previous rotations, then a new one
+        for (int i = 0; i < j; i++) {
+            const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+            h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+            h[i] = t;
+        }
+        const double den = std::hypot(h[j], h[j + 1]);
+        cs[j] = den > 0 ? h[j] / den : 1.0;
+        sn[j] = den > 0 ? h[j + 1] / den : 0.0;
+        h[j] = den;
+        h[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= j; i++) H[(size_t)i + (size_t)j * (mres + 1)] = h[i];
+        if (std::fabs(g[j + 1]) <= tol * beta || !(hn > 0.0)) {
+            j++;
+            break;
+        }
+    }
+    // y = R^{-1} g, d = V y
+    std::vector<double> y(j, 0.0);
+    for (int i = j - 1; i >= 0; i--) {
+        double t = g[i];
+        for (int q = i + 1; q < j; q++) t -= H[(size_t)i + (size_t)q * (mres + 1)] * y[q];
+        const double rii = H[(size_t)i + (size_t)i * (mres + 1)];
+        y[i] = rii != 0.0 ? t / rii : 0.0;
+    }
+    if (j > 0) {
+        put_small(N, y.data(), j, st);
+        HIPX(launch_vadd(d, V, n, j, N->d_small + 512, n, st));
+    }
+    return j;
+}
+
 void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipStream_t st, mf_solve_info* info) {
     const Symbolic& S = N->sym->S;
     const mf_options& o = N->opt;
@@ -471,9 +590,23 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
     inf.omega0 = *std::max_element(om.begin(), om.end());
     int it = 0;
     double w = inf.omega0;
-    // fixed-precision refinement: x += M^{-1} r until omega <= target
+    int inner = 0;
+    // refinement until omega <= target: classical (x += M^{-1} r) or GMRES-IR
+    // (x += d with d from GMRES on M^{-1} J d = M^{-1} r), all vectors FP64
     while (o.refine > 0 && w > o.target_omega && it < o.max_outer) {
-        apply_inverse(N, r, n, dv, n, nrhs, st);
+        if (o.refine == 1) {
+            apply_inverse(N, r, n, dv, n, nrhs, st);
+        } else {
+            const int mres = std::max(1, std::min(o.gmres_m, 200));
+            ensure_krylov(N, mres);
+            for (int c = 0; c < nrhs; c++) {
+                if (om[c] <= o.target_omega) {
+                    HIPX(launch_fill(dv + (size_t)c * n, 0.0, n, st));
+                    continue;
+                }
+                inner += gmres_correction(N, r + (size_t)c * n, dv + (size_t)c * n, mres, o.gmres_tol, st);
+            }
+        }
         HIPX(launch_axpy(n, x, ld, dv, n, nrhs, st));
         residual(N, b, ld, x, ld, r, nrhs, st, om);
         double wn = *std::max_element(om.begin(), om.end());
@@ -482,6 +615,7 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
     }
     inf.omega = w;
     inf.outer_iters = it;
+    inf.inner_iters = inner;
     if (info) *info = inf;
     if (!(w <= o.target_omega) && o.refine > 0)
         throw Fail{MF_ERR_NOT_CONVERGED, "refinement stopped at omega = " + std::to_string(w)};

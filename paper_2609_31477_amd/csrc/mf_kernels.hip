@@ -16,6 +16,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <algorithm>
 #include <cmath>
 
 #include "mf_device.h"
@@ -867,6 +868,111 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
     }
 }
 
+#define MF_CHECK_LAUNCH() (hipGetLastError())
+
+// ------------------------------------------------------------------ Krylov vectors (FP64)
+// y = J x (one vector), 16 lanes per row
+__global__ __launch_bounds__(kThreads) void k_spmv(const int64_t* rp, const int32_t* ci, const double* val, int64_t n,
+                                                   const double* x, double* y) {
+    const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 16;
+    const int sub = threadIdx.x & 15;
+    double acc = 0.0;
+    if (row < n)
+        for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) acc = fma(val[t], x[ci[t]], acc);
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (row < n && sub == 0) y[row] = acc;
+}
+
+// Deterministic multi-dot, stage 1: part[b * nv + i] = sum over block b's rows of V[:, i] * w
+constexpr int kDotBlocks = 512;
+__global__ __launch_bounds__(kThreads) void k_mdot1(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                                                    double* part) {
+    __shared__ double red[kThreads / 64];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    for (int i = 0; i < nv; i++) {
+        double acc = 0.0;
+        for (int64_t r = lo + threadIdx.x; r < hi; r += kThreads) acc = fma(V[r + i * ldv], w[r], acc);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < kThreads / 64; q++) t += red[q];
+            part[blockIdx.x * nv + i] = t;
+        }
+        __syncthreads();
+    }
+}
+// stage 2: out[i] = sum_b part[b * nv + i] in block order
+__global__ void k_mdot2(const double* part, int nb, int nv, double* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; b++) t += part[b * nv + i];
+    out[i] = t;
+}
+// w -= V[:, 0:nv] h   (h on the device)
+__global__ __launch_bounds__(kThreads) void k_vsub(double* w, const double* V, int64_t ldv, int nv, const double* h,
+                                                   int64_t n) {
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) {
+        double acc = w[r];
+        for (int i = 0; i < nv; i++) acc -= V[r + i * ldv] * h[i];
+        w[r] = acc;
+    }
+}
+// y = a * x
+__global__ __launch_bounds__(kThreads) void k_scale(double* y, const double* x, double a, int64_t n) {
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads)
+        y[r] = a * x[r];
+}
+// x += V[:, 0:nv] c   (c on the device)
+__global__ __launch_bounds__(kThreads) void k_vadd(double* x, const double* V, int64_t ldv, int nv, const double* c,
+                                                   int64_t n) {
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) {
+        double acc = x[r];
+        for (int i = 0; i < nv; i++) acc += V[r + i * ldv] * c[i];
+        x[r] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(double* y, double v, int64_t n) {
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) y[r] = v;
+}
+
+static unsigned vec_blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 2048); }
+
+hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, double* y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n * 16 + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       S.csr_rowptr, S.csr_colind, val, n, x, y);
+    return MF_CHECK_LAUNCH();
+}
+// out[0:nv] (device) = V[:, 0:nv]^T w; part needs kDotBlocks * nv doubles
+hipError_t launch_mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, double* out,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_mdot1, dim3(kDotBlocks), dim3(kThreads), 0, st, V, ldv, nv, w, n, part);
+    hipLaunchKernelGGL(k_mdot2, dim3((nv + 63) / 64), dim3(64), 0, st, part, kDotBlocks, nv, out);
+    return MF_CHECK_LAUNCH();
+}
+hipError_t launch_vsub(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_vsub, dim3(vec_blocks(n)), dim3(kThreads), 0, st, w, V, ldv, nv, h, n);
+    return MF_CHECK_LAUNCH();
+}
+hipError_t launch_vadd(double* x, const double* V, int64_t ldv, int nv, const double* c, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_vadd, dim3(vec_blocks(n)), dim3(kThreads), 0, st, x, V, ldv, nv, c, n);
+    return MF_CHECK_LAUNCH();
+}
+hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n)), dim3(kThreads), 0, st, y, v, n);
+    return MF_CHECK_LAUNCH();
+}
+hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale, dim3(vec_blocks(n)), dim3(kThreads), 0, st, y, x, a, n);
+    return MF_CHECK_LAUNCH();
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -889,7 +995,6 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const double* x, i
 }
 
 // ------------------------------------------------------------------ launchers
-#define MF_CHECK_LAUNCH() (hipGetLastError())
 
 template <typename T, int NB, int RS>
 static void launch_panels(FrontNum* fn, int slot0, int count, int mmax, int Pmax, double u, int prec, hipStream_t st,

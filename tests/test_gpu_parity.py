@@ -160,3 +160,33 @@ def test_empty_system(torch_cuda):
     num = S.factor(torch.zeros(0, dtype=torch.float64, device="cuda"))
     x, info = num.solve(torch.zeros(0, dtype=torch.float64, device="cuda"))
     assert x.numel() == 0
+
+
+MIXED_OMEGA = 1e-10
+
+
+@pytest.mark.parametrize("nx,ny,seed,nrhs", [(16, 8, 0, 1), (32, 16, 4, 3), (64, 32, 0, 1)])
+def test_mixed_fp32_gmres_ir(torch_cuda, nx, ny, seed, nrhs):
+    """FP32 non-root fronts (FP64 root) + FP64 GMRES-IR reach omega <= 1e-10."""
+    s = build_2d(nx, ny, seed, nrhs=nrhs)
+    B = s.b0
+    X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B,
+                             prec="fp32", target_omega=MIXED_OMEGA)
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    A = s.to_scipy()
+    for c in range(B.shape[0]):
+        om = check.omega(A, X[c], B[c])
+        rel = np.abs(X[c] - Xo[c]).max() / np.abs(Xo[c]).max()
+        print(f"fp32 {nx}x{ny} rhs {c}: omega={om:.2e} rel={rel:.2e} omega0={info.omega0:.2e} "
+              f"outer={info.outer_iters} inner={info.inner_iters}", flush=True)
+        assert om <= MIXED_OMEGA
+        assert rel <= 1e-6
+    assert num.info().root_order >= 2
+
+
+def test_gmres_ir_with_fp64_factors_one_step(torch_cuda):
+    """With FP64 factors GMRES-IR needs at most one outer step to reach 1e-12."""
+    s = build_2d(32, 16, 7)
+    X, info, _ = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, s.b0[0], refine=2)
+    assert info.outer_iters <= 1
+    assert check.omega(s.to_scipy(), X, s.b0[0]) <= OMEGA_TOL
