@@ -61,7 +61,7 @@ typedef struct {
     double gmres_tol;      /* inner relative residual tolerance (default 1e-4) */
     int32_t refine;        /* 0 = none, 1 = classical FP64 refinement, 2 = GMRES-IR
                               (default: 1 for MF_FP64, 2 otherwise; -1 = by precision) */
-    int32_t panel_nb;      /* panel width of the front factorization (default 32) */
+    int32_t panel_nb;      /* reserved (the panel width is chosen per front from its order) */
     int32_t profile;       /* 1 = time the factorization phases with HIP events on the
                               caller's stream (reported in mf_factor_info; default 0) */
 } mf_options;
@@ -180,6 +180,33 @@ typedef struct {
 
 mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld,
                    void* stream, mf_solve_info* info);
+
+/*
+ * Batches of independent systems (many uneven small Newton systems, or
+ * concurrent requests of a serving loop) factor and solve in the same launches.
+ *
+ * mf_batch_analyze merges already-analyzed systems into one block-diagonal plan
+ * (a symbolic handle of its own; the inputs may be released afterwards).  Each
+ * system keeps its own fronts, tree heights, panel shapes and root front, and
+ * every reduction of the solve and of the refinement is done per system, so a
+ * system's factors and solution are bitwise the same alone and in any batch.
+ *   count     number of systems (>= 1)
+ *   syms      count symbolic handles (from mf_analyze)
+ * Errors: MF_ERR_ARG (null or foreign handles), MF_ERR_OOM.
+ */
+mf_status mf_batch_analyze(int32_t count, const mf_sym_t* syms, mf_sym_t* out);
+
+/* Factor every system of a batch plan: values_dev[i] are system i's device FP64
+ * values (its own CSR order).  Same semantics as mf_factor otherwise. */
+mf_status mf_factor_batched(mf_sym_t batch, const double* const* values_dev, const mf_options* opt,
+                            void* stream, mf_num_t* inout);
+
+/* Solve every system of a factored batch: b_dev[i], x_dev[i] are n_i x nrhs
+ * column-major with leading dimension n_i.  info (may be NULL) receives one
+ * mf_solve_info per system.  MF_ERR_NOT_CONVERGED if any system stopped above
+ * the target (all x are written). */
+mf_status mf_solve_batched(mf_num_t num, const double* const* b_dev, double* const* x_dev, int32_t nrhs,
+                           void* stream, mf_solve_info* info);
 
 /* Device bytes a factorization of this pattern needs at nominal front sizes,
  * times (1 + margin) for delayed-pivot growth (admission estimate). */

@@ -27,7 +27,8 @@ PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
 
 # every entry point declared in include/mf.h
 EXPORTS = ["mf_default_options", "mf_analyze", "mf_symbolic_export", "mf_factor", "mf_get_factor_info",
-           "mf_solve", "mf_footprint_bytes", "mf_debug_front", "mf_release", "mf_last_error"]
+           "mf_solve", "mf_batch_analyze", "mf_factor_batched", "mf_solve_batched", "mf_footprint_bytes",
+           "mf_debug_front", "mf_release", "mf_last_error"]
 
 
 class mf_options(ctypes.Structure):
@@ -92,6 +93,13 @@ def lib():
         L.mf_solve.restype = ctypes.c_int
         L.mf_footprint_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_options), ctypes.c_double]
         L.mf_footprint_bytes.restype = ctypes.c_int64
+        L.mf_batch_analyze.argtypes = [ctypes.c_int32, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.mf_batch_analyze.restype = ctypes.c_int
+        L.mf_factor_batched.argtypes = [ctypes.c_void_p, P, ctypes.POINTER(mf_options), P,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        L.mf_factor_batched.restype = ctypes.c_int
+        L.mf_solve_batched.argtypes = [ctypes.c_void_p, P, P, ctypes.c_int32, P, ctypes.POINTER(mf_solve_info)]
+        L.mf_solve_batched.restype = ctypes.c_int
         L.mf_debug_front.argtypes = [ctypes.c_void_p, ctypes.c_int32, P, P, P]
         L.mf_debug_front.restype = ctypes.c_int
         L.mf_release.argtypes = [ctypes.c_void_p]
@@ -254,6 +262,76 @@ class Numeric:
                 dict(rowpiv=iv[:P], colperm=iv[P:2 * P], rowperm=iv[2 * P:3 * P], colvar=iv[3 * P:]))
 
     def release(self):
+        if getattr(self, "_h", None):
+            lib().mf_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Batch:
+    """mf_batch_analyze / mf_factor_batched / mf_solve_batched over several analyzed systems."""
+
+    def __init__(self, syms):
+        L = lib()
+        self.syms = list(syms)
+        self.ns = [s.n for s in self.syms]
+        self.nnzs = [s.nnz for s in self.syms]
+        arr = (ctypes.c_void_p * len(self.syms))(*[s._h.value for s in self.syms])
+        h = ctypes.c_void_p()
+        _check(L.mf_batch_analyze(len(self.syms), ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(h)))
+        self._h = h
+        self._num = ctypes.c_void_p()
+        self.n = sum(self.ns)
+        self.nnz = sum(self.nnzs)
+
+    def export(self) -> SymbolicView:
+        return Symbolic.export(self)
+
+    def factor(self, values, stream=None, **opts):
+        """values: list of float64 CUDA tensors, one per system."""
+        import torch
+        if len(values) != len(self.syms):
+            raise ValueError("one values tensor per system")
+        for v, nz in zip(values, self.nnzs):
+            if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+                    and v.numel() == nz):
+                raise TypeError("values[i] must be a contiguous float64 CUDA tensor with nnz_i entries")
+        ptrs = (ctypes.c_void_p * len(values))(*[v.data_ptr() for v in values])
+        o = default_options(leaf_max=self.syms[0].options.leaf_max, **opts) if opts else None
+        _check(lib().mf_factor_batched(self._h, ctypes.cast(ptrs, ctypes.c_void_p),
+                                       ctypes.byref(o) if o is not None else None, _stream_ptr(stream),
+                                       ctypes.byref(self._num)))
+        return self
+
+    def info(self) -> mf_factor_info:
+        inf = mf_factor_info()
+        _check(lib().mf_get_factor_info(self._num, ctypes.byref(inf)))
+        return inf
+
+    def solve(self, bs, xs=None, stream=None, check=True):
+        """bs: list of float64 CUDA tensors (n_i,) or (nrhs, n_i).  Returns (xs, [mf_solve_info])."""
+        import torch
+        if xs is None:
+            xs = [torch.empty_like(b) for b in bs]
+        nrhs = 1 if bs[0].dim() == 1 else bs[0].shape[0]
+        bp = (ctypes.c_void_p * len(bs))(*[b.data_ptr() for b in bs])
+        xp = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        infos = (mf_solve_info * len(bs))()
+        st = lib().mf_solve_batched(self._num, ctypes.cast(bp, ctypes.c_void_p), ctypes.cast(xp, ctypes.c_void_p),
+                                    nrhs, _stream_ptr(stream), infos)
+        if check or st != MF_ERR_NOT_CONVERGED:
+            _check(st)
+        return xs, list(infos)
+
+    def release(self):
+        if getattr(self, "_num", None) and self._num.value:
+            lib().mf_release(self._num)
+            self._num = ctypes.c_void_p()
         if getattr(self, "_h", None):
             lib().mf_release(self._h)
             self._h = None

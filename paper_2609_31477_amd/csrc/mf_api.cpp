@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,8 +21,8 @@ namespace mf {
 // kernel launchers (mf_kernels.hip)
 // ev (nullable): 4 events recorded after assembly, panels, Schur GEMM and finalize
 template <typename T>
-hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, int Pmax,
-                               const double* vals, int64_t u0, int64_t u1, int NB, double u, int prec,
+hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
+                               const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
                                hipStream_t st, hipEvent_t* ev);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
@@ -31,17 +32,20 @@ hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, 
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
 int panel_nb(int prec, int mmax);
 hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, double* y, hipStream_t st);
-hipError_t launch_mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, double* out,
-                       hipStream_t st);
-hipError_t launch_vsub(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n, hipStream_t st);
-hipError_t launch_vadd(double* x, const double* V, int64_t ldv, int nv, const double* c, int64_t n, hipStream_t st);
-hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t st);
+hipError_t launch_mdot(const DevSym& S, const double* V, int64_t ldv, int nv, const double* w, double* part,
+                       double* out, int ostride, hipStream_t st);
+hipError_t launch_vsub(const DevSym& S, double* w, const double* V, int64_t ldv, int nv, const double* h, int hstride,
+                       int64_t n, hipStream_t st);
+hipError_t launch_vadd(const DevSym& S, double* x, const double* V, int64_t ldv, int nv, const double* c,
+                       int cstride, int64_t n, hipStream_t st);
+hipError_t launch_scale(const DevSym& S, double* y, const double* x, const double* a, int astride, int64_t n,
+                        hipStream_t st);
 hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
                            unsigned long long* omega_bits, hipStream_t st);
-hipError_t launch_axpy(int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd, int nrhs, hipStream_t st);
-hipError_t launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st);
+hipError_t launch_axpy(const DevSym& S, int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd,
+                       const int32_t* active, int nrhs, hipStream_t st);
 
 namespace {
 thread_local std::string g_err;
@@ -162,9 +166,16 @@ struct mf_num {
     double* h_small = nullptr;  // pinned mirror
     unsigned long long* d_omega = nullptr;
     unsigned long long* h_omega = nullptr;  // pinned
+    int32_t* d_active = nullptr;            // per (system, rhs): still refining
+    int32_t* h_active = nullptr;            // pinned
     int omega_cap = 0;
+    size_t small_cap = 0;
+    std::vector<mf_solve_info> seg_info;    // per system of the last solve
+    double* d_cat = nullptr;                // batched solve: concatenated b and x
+    size_t cat_cap = 0;
     bool factored = false;
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
+    std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
     mf_factor_info info{};
     ~mf_num() {
         fronts.release();
@@ -180,6 +191,9 @@ struct mf_num {
         if (h_small) (void)hipHostFree(h_small);
         if (d_omega) (void)hipFree(d_omega);
         if (h_omega) (void)hipHostFree(h_omega);
+        if (d_active) (void)hipFree(d_active);
+        if (d_cat) (void)hipFree(d_cat);
+        if (h_active) (void)hipHostFree(h_active);
     }
 };
 
@@ -238,25 +252,42 @@ void ensure_device_symbolic(mf_sym* h) {
     d.ue_src = D->put(S.ue_src);
     d.csr_rowptr = D->put(S.rowptr);
     d.csr_colind = D->put(S.colind);
+    d.nseg = (int32_t)S.seg_n.size();
+    d.seg_row0 = D->put(S.seg_row0);
+    d.seg_n = D->put(S.seg_n);
+    d.row_seg = nullptr;
+    if (d.nseg > 1) {
+        std::vector<int32_t> rs(S.n);
+        for (int32_t q = 0; q < d.nseg; q++)
+            for (int64_t i = 0; i < S.seg_n[q]; i++) rs[S.seg_row0[q] + i] = q;
+        d.row_seg = D->put(rs);
+    }
     h->dev = std::move(D);
 }
 
 int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 || is_root) ? 0 : 1; }
 
-void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
+void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double* const* seg_values = nullptr) {
     mf_sym* H = N->sym;
     const Symbolic& S = H->S;
     ensure_device_symbolic(H);
     SymDev& D = *H->dev;
     const int nf = S.nf;
     const mf_options& o = N->opt;
-    const int NB = std::max(1, std::min(o.panel_nb, kNBMax));
     if (!N->d_fn) {
         HIPX(hipMalloc((void**)&N->d_fn, sizeof(FrontNum) * std::max(nf, 1)));
         HIPX(hipHostMalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
     }
     if (!N->d_vals) HIPX(hipMalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
-    if (S.nnz) HIPX(hipMemcpyAsync(N->d_vals, values_dev, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, st));
+    if (seg_values) {
+        for (size_t q = 0; q < S.seg_n.size(); q++) {
+            const int64_t nz = (q + 1 < S.seg_n.size() ? S.seg_nnz0[q + 1] : S.nnz) - S.seg_nnz0[q];
+            if (nz) HIPX(hipMemcpyAsync(N->d_vals + S.seg_nnz0[q], seg_values[q], sizeof(double) * nz,
+                                        hipMemcpyDeviceToDevice, st));
+        }
+    } else if (S.nnz) {
+        HIPX(hipMemcpyAsync(N->d_vals, values_dev, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, st));
+    }
     if (N->fronts.chunks.empty()) {
         double tot = 0;
         for (int f = 0; f < nf; f++) tot += (double)S.mnom[f] * S.mnom[f];
@@ -271,6 +302,8 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
         N->lvl_mmax[p].assign(S.nlevels, 0);
         N->lvl_Pmax[p].assign(S.nlevels, 0);
         N->lvl_cnt[p].assign(S.nlevels, 0);
+        N->lvl_cls_mmax[p].assign(S.nlevels, {0, 0, 0, 0});
+        N->lvl_cls_Pmax[p].assign(S.nlevels, {0, 0, 0, 0});
     }
     std::vector<int32_t> dout(nf, 0);
     FrontNum* hf = N->h_fn;
@@ -319,6 +352,9 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
             fr.voff = voff;
             voff += fr.m;
             const int p = fr.prec;
+            const int cls = fr.m <= 512 ? 0 : (fr.m <= 1024 ? 1 : (fr.m <= 2048 ? 2 : 3));
+            N->lvl_cls_mmax[p][L][cls] = std::max(N->lvl_cls_mmax[p][L][cls], fr.m);
+            N->lvl_cls_Pmax[p][L][cls] = std::max(N->lvl_cls_Pmax[p][L][cls], fr.P);
             N->lvl_mmax[p][L] = std::max(N->lvl_mmax[p][L], fr.m);
             N->lvl_Pmax[p][L] = std::max(N->lvl_Pmax[p][L], fr.P);
             N->lvl_cnt[p][L]++;
@@ -338,7 +374,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
         N->wsp.reset();
         for (int sl = s0; sl < s1; sl++) {
             FrontNum& fr = hf[sl];
-            const int nbp = panel_nb(fr.prec, N->lvl_mmax[fr.prec][L]);
+            const int nbp = panel_nb(fr.prec, fr.m);
             fr.W = N->wsp.alloc((size_t)fr.m * nbp * (fr.prec ? 4 : 8));
         }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
@@ -346,13 +382,15 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
         // fronts of both precisions may share a level; each kernel skips the other kind
         if (N->lvl_cnt[0][L]) {
             if (prof) HIPX(hipEventRecord(ev[0][0], st));
-            HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L], N->lvl_Pmax[0][L],
-                                             N->d_vals, u0, u1, NB, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr));
+            HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
+                                             N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), N->d_vals,
+                                             u0, u1, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr));
         }
         if (N->lvl_cnt[1][L]) {
             if (prof) HIPX(hipEventRecord(ev[1][0], st));
-            HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L], N->lvl_Pmax[1][L],
-                                            N->d_vals, u0, u1, NB, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr));
+            HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
+                                            N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), N->d_vals,
+                                            u0, u1, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr));
         }
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));
@@ -393,7 +431,9 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st) {
 }
 
 void ensure_solve_buffers(mf_num* N, int nrhs) {
-    const int64_t n = N->sym->S.n;
+    const Symbolic& S = N->sym->S;
+    const int64_t n = S.n;
+    const int nseg = (int)S.seg_n.size();
     size_t need = (size_t)std::max<int64_t>(N->vec_len, 1) * nrhs;
     if (need > N->vec_cap) {
         if (N->d_vec) HIPX(hipFree(N->d_vec));
@@ -408,14 +448,21 @@ void ensure_solve_buffers(mf_num* N, int nrhs) {
         HIPX(hipMalloc((void**)&N->d_work, sizeof(double) * wneed));
         N->work_cap = wneed;
     }
-    if (nrhs > N->omega_cap) {
+    if (nrhs * nseg > N->omega_cap) {
         if (N->d_omega) HIPX(hipFree(N->d_omega));
         if (N->h_omega) HIPX(hipHostFree(N->h_omega));
+        if (N->d_active) HIPX(hipFree(N->d_active));
+        if (N->h_active) HIPX(hipHostFree(N->h_active));
         N->d_omega = nullptr;
         N->h_omega = nullptr;
-        HIPX(hipMalloc((void**)&N->d_omega, sizeof(unsigned long long) * nrhs));
-        HIPX(hipHostMalloc((void**)&N->h_omega, sizeof(unsigned long long) * nrhs, hipHostMallocDefault));
-        N->omega_cap = nrhs;
+        N->d_active = nullptr;
+        N->h_active = nullptr;
+        const int cnt = nrhs * nseg;
+        HIPX(hipMalloc((void**)&N->d_omega, sizeof(unsigned long long) * cnt));
+        HIPX(hipHostMalloc((void**)&N->h_omega, sizeof(unsigned long long) * cnt, hipHostMallocDefault));
+        HIPX(hipMalloc((void**)&N->d_active, sizeof(int32_t) * cnt));
+        HIPX(hipHostMalloc((void**)&N->h_active, sizeof(int32_t) * cnt, hipHostMallocDefault));
+        N->omega_cap = cnt;
     }
 }
 
@@ -423,15 +470,15 @@ void ensure_solve_buffers(mf_num* N, int nrhs) {
 void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, hipStream_t st) {
     const Symbolic& S = N->sym->S;
     const DevSym& DS = N->sym->dev->S;
+    int mm = 1;
+    for (int p = 0; p < 2; p++)
+        for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
+    if ((size_t)mm * sizeof(double) > kMaxLds)
+        throw Fail{MF_ERR_ARG, "front of order " + std::to_string(mm) + " exceeds the solve kernel's LDS budget"};
     for (int c0 = 0; c0 < nrhs;) {
         // right-hand-side chunk so that the largest front's vectors fit in LDS
-        int mm = 1;
-        for (int p = 0; p < 2; p++)
-            for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
         int nrc = (int)std::max<size_t>(1, kMaxLds / (sizeof(double) * (size_t)mm));
         nrc = std::min(nrc, nrhs - c0);
-        if ((size_t)mm * sizeof(double) > kMaxLds)
-            throw Fail{MF_ERR_ARG, "front of order " + std::to_string(mm) + " exceeds the solve kernel's LDS budget"};
         for (int L = 0; L < S.nlevels; L++) {
             const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;
             if (N->lvl_cnt[0][L])
@@ -460,165 +507,229 @@ double omega_of_bits(unsigned long long b) {
     return w;
 }
 
-// r = b - J x; returns omega per right-hand side into om.
+// r = b - J x; om[seg * nrhs + c] = omega of system seg, right-hand side c.
 void residual(mf_num* N, const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, int nrhs,
               hipStream_t st, std::vector<double>& om) {
     const Symbolic& S = N->sym->S;
+    const int nseg = (int)S.seg_n.size();
     HIPX(launch_residual(N->sym->dev->S, N->d_vals, S.n, x, ldx, b, ldb, r, S.n, nrhs, N->d_omega, st));
-    HIPX(hipMemcpyAsync(N->h_omega, N->d_omega, sizeof(unsigned long long) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(N->h_omega, N->d_omega, sizeof(unsigned long long) * nrhs * nseg, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
-    om.resize(nrhs);
-    for (int c = 0; c < nrhs; c++) om[c] = omega_of_bits(N->h_omega[c]);
+    om.resize((size_t)nrhs * nseg);
+    for (int q = 0; q < nrhs * nseg; q++) om[q] = omega_of_bits(N->h_omega[q]);
 }
 
-constexpr int kDotBlocksHost = 512;
-
 void ensure_krylov(mf_num* N, int mres) {
-    const int64_t n = N->sym->S.n;
-    size_t need = (size_t)n * (mres + 2) + (size_t)kDotBlocksHost * (mres + 2);
+    const Symbolic& S = N->sym->S;
+    const int64_t n = S.n;
+    const int nseg = (int)S.seg_n.size();
+    size_t need = (size_t)n * (mres + 2) + (size_t)512 * nseg * (mres + 2);
     if (need > N->kry_cap) {
         if (N->d_kry) HIPX(hipFree(N->d_kry));
         N->d_kry = nullptr;
         HIPX(hipMalloc((void**)&N->d_kry, sizeof(double) * need));
         N->kry_cap = need;
     }
-    if (!N->d_small) {
-        HIPX(hipMalloc((void**)&N->d_small, sizeof(double) * 1024));
-        HIPX(hipHostMalloc((void**)&N->h_small, sizeof(double) * 1024, hipHostMallocDefault));
+    size_t sneed = (size_t)2 * nseg * (mres + 2);
+    if (sneed > N->small_cap) {
+        if (N->d_small) HIPX(hipFree(N->d_small));
+        if (N->h_small) HIPX(hipHostFree(N->h_small));
+        N->d_small = nullptr;
+        N->h_small = nullptr;
+        HIPX(hipMalloc((void**)&N->d_small, sizeof(double) * sneed));
+        HIPX(hipHostMalloc((void**)&N->h_small, sizeof(double) * sneed, hipHostMallocDefault));
+        N->small_cap = sneed;
     }
 }
 
-// dots[0:nv] = V[:,0:nv]^T w, returned on the host (one synchronization)
-void mdot_host(mf_num* N, const double* V, int64_t ldv, int nv, const double* w, double* part, double* out,
+// Per-system dots of V[:, 0:nv] with w, returned on the host: out[seg * stride + i].
+void mdot_host(mf_num* N, const double* V, int nv, const double* w, double* part, int stride, std::vector<double>& out,
                hipStream_t st) {
-    const int64_t n = N->sym->S.n;
-    HIPX(launch_mdot(V, ldv, nv, w, n, part, N->d_small, st));
-    HIPX(hipMemcpyAsync(N->h_small, N->d_small, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+    const Symbolic& S = N->sym->S;
+    const int nseg = (int)S.seg_n.size();
+    HIPX(launch_mdot(N->sym->dev->S, V, S.n, nv, w, part, N->d_small, stride, st));
+    HIPX(hipMemcpyAsync(N->h_small, N->d_small, sizeof(double) * nseg * stride, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
-    for (int i = 0; i < nv; i++) out[i] = N->h_small[i];
+    out.assign(N->h_small, N->h_small + (size_t)nseg * stride);
 }
 
-void put_small(mf_num* N, const double* v, int cnt, hipStream_t st) {
-    for (int i = 0; i < cnt; i++) N->h_small[512 + i] = v[i];
-    HIPX(hipMemcpyAsync(N->d_small + 512, N->h_small + 512, sizeof(double) * cnt, hipMemcpyHostToDevice, st));
+// per-system coefficients to the device (second half of the small buffer)
+double* put_small(mf_num* N, const std::vector<double>& v, hipStream_t st) {
+    const size_t off = N->small_cap / 2;
+    for (size_t i = 0; i < v.size(); i++) N->h_small[off + i] = v[i];
+    HIPX(hipMemcpyAsync(N->d_small + off, N->h_small + off, sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
+    return N->d_small + off;
 }
 
-// GMRES(m) on M^{-1} J d = M^{-1} r for one right-hand side column (r, d: length n,
-// FP64).  Classical Gram-Schmidt with one reorthogonalization; Givens rotations on
-// the host.  Returns the number of inner iterations.
-int gmres_correction(mf_num* N, const double* r, double* d, int mres, double tol, hipStream_t st) {
+// GMRES(m) on M^{-1} J d = M^{-1} r, one instance per system of the batch, run in
+// lockstep on the concatenated vectors (column c of r and d).  Classical
+// Gram-Schmidt with one reorthogonalization, Givens rotations on the host.  A
+// system's numbers depend only on its own rows.  Returns inner iterations per system.
+std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mres, double tol,
+                                  const std::vector<char>& act, hipStream_t st) {
     const Symbolic& S = N->sym->S;
     const int64_t n = S.n;
+    const int nseg = (int)S.seg_n.size();
     const DevSym& DS = N->sym->dev->S;
+    const int stride = mres + 2;
     double* V = N->d_kry;
     double* w = V + (size_t)n * (mres + 1);
     double* part = w + n;
-    // v0 = M^{-1} r
-    apply_inverse(N, r, n, w, n, 1, st);
-    double beta2;
-    mdot_host(N, w, n, 1, w, part, &beta2, st);
-    const double beta = std::sqrt(beta2);
+    std::vector<int> iters(nseg, 0);
+    apply_inverse(N, r, n, w, n, 1, st);  // w = M^{-1} r
+    std::vector<double> dots, beta(nseg), coef((size_t)nseg * stride, 0.0);
+    mdot_host(N, w, 1, w, part, stride, dots, st);
+    std::vector<char> live(nseg, 0);
+    for (int q = 0; q < nseg; q++) {
+        beta[q] = std::sqrt(dots[(size_t)q * stride]);
+        live[q] = act[q] && beta[q] > 0.0 && std::isfinite(beta[q]);
+        coef[(size_t)q * stride] = live[q] ? 1.0 / beta[q] : 0.0;
+    }
     HIPX(launch_fill(d, 0.0, n, st));
-    if (!(beta > 0.0) || !std::isfinite(beta)) return 0;
-    HIPX(launch_scale(V, w, 1.0 / beta, n, st));
-    std::vector<double> H((size_t)(mres + 1) * mres, 0.0), cs(mres), sn(mres), g(mres + 1, 0.0);
-    g[0] = beta;
-    int j = 0;
-    std::vector<double> h(mres + 1), h2(mres + 1);
-    for (; j < mres; j++) {
+    HIPX(launch_scale(DS, V, w, put_small(N, coef, st), stride, n, st));
+    std::vector<std::vector<double>> H(nseg, std::vector<double>((size_t)(mres + 1) * mres, 0.0)), cs(nseg),
+        sn(nseg), g(nseg);
+    std::vector<int> jdone(nseg, 0);
+    for (int q = 0; q < nseg; q++) {
+        cs[q].assign(mres, 0.0);
+        sn[q].assign(mres, 0.0);
+        g[q].assign(mres + 1, 0.0);
+        g[q][0] = beta[q];
+    }
+    std::vector<char> running = live;
+    std::vector<double> h((size_t)nseg * stride), h2;
+    for (int j = 0; j < mres; j++) {
+        bool any = false;
+        for (int q = 0; q < nseg; q++) any = any || running[q];
+        if (!any) break;
         double* vj = V + (size_t)n * j;
         double* vj1 = V + (size_t)n * (j + 1);
-        HIPX(launch_spmv(DS, N->d_vals, n, vj, vj1, st));          // vj1 = J vj (temporary)
-        apply_inverse(N, vj1, n, w, n, 1, st);                      // w = M^{-1} J vj
-        mdot_host(N, V, n, j + 1, w, part, h.data(), st);
-        put_small(N, h.data(), j + 1, st);
-        HIPX(launch_vsub(w, V, n, j + 1, N->d_small + 512, n, st));
-        mdot_host(N, V, n, j + 1, w, part, h2.data(), st);      // reorthogonalize
-        put_small(N, h2.data(), j + 1, st);
-        HIPX(launch_vsub(w, V, n, j + 1, N->d_small + 512, n, st));
-        for (int i = 0; i <= j; i++) h[i] += h2[i];
-        double hn2;
-        mdot_host(N, w, n, 1, w, part, &hn2, st);
-        const double hn = std::sqrt(hn2);
-        h[j + 1] = hn;
-        if (hn > 0.0) HIPX(launch_scale(vj1, w, 1.0 / hn, n, st));
-        // apply previous rotations, then a new one
-        for (int i = 0; i < j; i++) {
-            const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-            h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-            h[i] = t;
+        HIPX(launch_spmv(DS, N->d_vals, n, vj, vj1, st));  // vj1 = J vj (temporary)
+        apply_inverse(N, vj1, n, w, n, 1, st);              // w = M^{-1} J vj
+        mdot_host(N, V, j + 1, w, part, stride, h, st);
+        HIPX(launch_vsub(DS, w, V, n, j + 1, put_small(N, h, st), stride, n, st));
+        mdot_host(N, V, j + 1, w, part, stride, h2, st);  // reorthogonalize
+        HIPX(launch_vsub(DS, w, V, n, j + 1, put_small(N, h2, st), stride, n, st));
+        for (size_t i = 0; i < h.size(); i++) h[i] += h2[i];
+        mdot_host(N, w, 1, w, part, stride, dots, st);
+        for (int q = 0; q < nseg; q++) {
+            const double hn = std::sqrt(dots[(size_t)q * stride]);
+            h[(size_t)q * stride + j + 1] = hn;
+            coef[(size_t)q * stride] = hn > 0.0 ? 1.0 / hn : 0.0;
         }
-        const double den = std::hypot(h[j], h[j + 1]);
-        cs[j] = den > 0 ? h[j] / den : 1.0;
-        sn[j] = den > 0 ? h[j + 1] / den : 0.0;
-        h[j] = den;
-        h[j + 1] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        for (int i = 0; i <= j; i++) H[(size_t)i + (size_t)j * (mres + 1)] = h[i];
-        if (std::fabs(g[j + 1]) <= tol * beta || !(hn > 0.0)) {
-            j++;
-            break;
+        HIPX(launch_scale(DS, vj1, w, put_small(N, coef, st), stride, n, st));
+        for (int q = 0; q < nseg; q++) {
+            if (!running[q]) continue;
+            double* hq = h.data() + (size_t)q * stride;
+            const double hn = hq[j + 1];
+            for (int i = 0; i < j; i++) {
+                const double t = cs[q][i] * hq[i] + sn[q][i] * hq[i + 1];
+                hq[i + 1] = -sn[q][i] * hq[i] + cs[q][i] * hq[i + 1];
+                hq[i] = t;
+            }
+            const double den = std::hypot(hq[j], hq[j + 1]);
+            cs[q][j] = den > 0 ? hq[j] / den : 1.0;
+            sn[q][j] = den > 0 ? hq[j + 1] / den : 0.0;
+            hq[j] = den;
+            hq[j + 1] = 0.0;
+            g[q][j + 1] = -sn[q][j] * g[q][j];
+            g[q][j] = cs[q][j] * g[q][j];
+            for (int i = 0; i <= j; i++) H[q][(size_t)i + (size_t)j * (mres + 1)] = hq[i];
+            jdone[q] = j + 1;
+            if (std::fabs(g[q][j + 1]) <= tol * beta[q] || !(hn > 0.0)) running[q] = 0;
         }
     }
-    // y = R^{-1} g, d = V y
-    std::vector<double> y(j, 0.0);
-    for (int i = j - 1; i >= 0; i--) {
-        double t = g[i];
-        for (int q = i + 1; q < j; q++) t -= H[(size_t)i + (size_t)q * (mres + 1)] * y[q];
-        const double rii = H[(size_t)i + (size_t)i * (mres + 1)];
-        y[i] = rii != 0.0 ? t / rii : 0.0;
+    // y = R^{-1} g per system, d = V y
+    std::fill(coef.begin(), coef.end(), 0.0);
+    int jmax = 0;
+    for (int q = 0; q < nseg; q++) {
+        if (!live[q]) continue;
+        const int jq = jdone[q];
+        iters[q] = jq;
+        jmax = std::max(jmax, jq);
+        for (int i = jq - 1; i >= 0; i--) {
+            double t = g[q][i];
+            for (int k = i + 1; k < jq; k++) t -= H[q][(size_t)i + (size_t)k * (mres + 1)] * coef[(size_t)q * stride + k];
+            const double rii = H[q][(size_t)i + (size_t)i * (mres + 1)];
+            coef[(size_t)q * stride + i] = rii != 0.0 ? t / rii : 0.0;
+        }
     }
-    if (j > 0) {
-        put_small(N, y.data(), j, st);
-        HIPX(launch_vadd(d, V, n, j, N->d_small + 512, n, st));
-    }
-    return j;
+    if (jmax > 0) HIPX(launch_vadd(DS, d, V, n, jmax, put_small(N, coef, st), stride, n, st));
+    return iters;
 }
 
+// Solve and refine.  b, x: n x nrhs (ld) over the whole (possibly batched) system.
+// Every system of a batch refines on its own: its update stops as soon as its own
+// omega meets the target, so its result equals the one it gets when solved alone.
 void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipStream_t st, mf_solve_info* info) {
     const Symbolic& S = N->sym->S;
     const mf_options& o = N->opt;
     const int64_t n = S.n;
+    const int nseg = (int)S.seg_n.size();
     ensure_solve_buffers(N, nrhs);
     double* r = N->d_work;
     double* dv = N->d_work + (size_t)n * nrhs;
     apply_inverse(N, b, ld, x, ld, nrhs, st);
     std::vector<double> om;
     residual(N, b, ld, x, ld, r, nrhs, st, om);
-    mf_solve_info inf{};
-    inf.omega0 = *std::max_element(om.begin(), om.end());
+    N->seg_info.assign(nseg, mf_solve_info{});
+    for (int q = 0; q < nseg; q++)
+        for (int c = 0; c < nrhs; c++) {
+            N->seg_info[q].omega0 = std::max(N->seg_info[q].omega0, om[(size_t)q * nrhs + c]);
+            N->seg_info[q].omega = N->seg_info[q].omega0;
+        }
+    std::vector<char> active((size_t)nseg * nrhs);
     int it = 0;
-    double w = inf.omega0;
-    int inner = 0;
-    // refinement until omega <= target: classical (x += M^{-1} r) or GMRES-IR
-    // (x += d with d from GMRES on M^{-1} J d = M^{-1} r), all vectors FP64
-    while (o.refine > 0 && w > o.target_omega && it < o.max_outer) {
+    while (o.refine > 0 && it < o.max_outer) {
+        bool any = false;
+        for (size_t q = 0; q < active.size(); q++) {
+            active[q] = !(om[q] <= o.target_omega);
+            any = any || active[q];
+        }
+        if (!any) break;
         if (o.refine == 1) {
             apply_inverse(N, r, n, dv, n, nrhs, st);
         } else {
             const int mres = std::max(1, std::min(o.gmres_m, 200));
             ensure_krylov(N, mres);
             for (int c = 0; c < nrhs; c++) {
-                if (om[c] <= o.target_omega) {
-                    HIPX(launch_fill(dv + (size_t)c * n, 0.0, n, st));
-                    continue;
+                std::vector<char> act(nseg);
+                bool anyc = false;
+                for (int q = 0; q < nseg; q++) {
+                    act[q] = active[(size_t)q * nrhs + c];
+                    anyc = anyc || act[q];
                 }
-                inner += gmres_correction(N, r + (size_t)c * n, dv + (size_t)c * n, mres, o.gmres_tol, st);
+                if (!anyc) continue;
+                std::vector<int> its = gmres_correction(N, r + (size_t)c * n, dv + (size_t)c * n, mres, o.gmres_tol, act, st);
+                for (int q = 0; q < nseg; q++) N->seg_info[q].inner_iters += its[q];
             }
         }
-        HIPX(launch_axpy(n, x, ld, dv, n, nrhs, st));
+        for (size_t q = 0; q < active.size(); q++) N->h_active[q] = active[q];
+        HIPX(hipMemcpyAsync(N->d_active, N->h_active, sizeof(int32_t) * active.size(), hipMemcpyHostToDevice, st));
+        HIPX(launch_axpy(N->sym->dev->S, n, x, ld, dv, n, N->d_active, nrhs, st));
         residual(N, b, ld, x, ld, r, nrhs, st, om);
-        double wn = *std::max_element(om.begin(), om.end());
         it++;
-        w = wn;
+        for (int q = 0; q < nseg; q++) {
+            bool stepped = false;
+            double wq = 0.0;
+            for (int c = 0; c < nrhs; c++) {
+                stepped = stepped || active[(size_t)q * nrhs + c];
+                wq = std::max(wq, om[(size_t)q * nrhs + c]);
+            }
+            if (stepped) N->seg_info[q].outer_iters++;
+            N->seg_info[q].omega = wq;
+        }
     }
-    inf.omega = w;
-    inf.outer_iters = it;
-    inf.inner_iters = inner;
+    mf_solve_info inf{};
+    for (int q = 0; q < nseg; q++) {
+        inf.omega = std::max(inf.omega, N->seg_info[q].omega);
+        inf.omega0 = std::max(inf.omega0, N->seg_info[q].omega0);
+        inf.outer_iters = std::max(inf.outer_iters, N->seg_info[q].outer_iters);
+        inf.inner_iters += N->seg_info[q].inner_iters;
+    }
     if (info) *info = inf;
-    if (!(w <= o.target_omega) && o.refine > 0)
-        throw Fail{MF_ERR_NOT_CONVERGED, "refinement stopped at omega = " + std::to_string(w)};
+    if (!(inf.omega <= o.target_omega) && o.refine > 0)
+        throw Fail{MF_ERR_NOT_CONVERGED, "refinement stopped at omega = " + std::to_string(inf.omega)};
 }
 
 }  // namespace
@@ -682,10 +793,14 @@ mf_status mf_symbolic_export(mf_sym_t h, mf_symbolic_view* v) {
     return MF_OK;
 }
 
-mf_status mf_factor(mf_sym_t h, const double* values_dev, const mf_options* opt, void* stream, mf_num_t* inout) {
+static mf_status factor_common(mf_sym_t h, const double* values_dev, const double* const* seg_values,
+                               const mf_options* opt, void* stream, mf_num_t* inout) {
     if (!h || h->magic != kSymMagic) return fail(MF_ERR_ARG, "bad symbolic handle");
     if (!inout) return fail(MF_ERR_ARG, "inout is null");
-    if (!values_dev && h->S.nnz > 0) return fail(MF_ERR_ARG, "values_dev is null");
+    if (!seg_values && !values_dev && h->S.nnz > 0) return fail(MF_ERR_ARG, "values_dev is null");
+    if (seg_values)
+        for (size_t q = 0; q < h->S.seg_n.size(); q++)
+            if (!seg_values[q] && h->S.seg_n[q] > 0) return fail(MF_ERR_ARG, "values_dev[i] is null");
     mf_num* N = *inout;
     if (N && (N->magic != kNumMagic || N->sym != h))
         return fail(MF_ERR_PATTERN, "numeric handle belongs to another symbolic handle");
@@ -713,7 +828,7 @@ mf_status mf_factor(mf_sym_t h, const double* values_dev, const mf_options* opt,
     N->factored = false;
     try {
         HIPX(hipGetDevice(&N->device));
-        do_factor(N, values_dev, (hipStream_t)stream);
+        do_factor(N, values_dev, (hipStream_t)stream, seg_values);
     } catch (const Fail& f) {
         if (fresh) *inout = fresh.release();  // keep the handle so the caller can release it
         return fail(f.st, f.msg);
@@ -723,6 +838,39 @@ mf_status mf_factor(mf_sym_t h, const double* values_dev, const mf_options* opt,
     }
     if (fresh) *inout = fresh.release();
     return MF_OK;
+}
+
+mf_status mf_factor(mf_sym_t h, const double* values_dev, const mf_options* opt, void* stream, mf_num_t* inout) {
+    return factor_common(h, values_dev, nullptr, opt, stream, inout);
+}
+
+mf_status mf_batch_analyze(int32_t count, const mf_sym_t* syms, mf_sym_t* out) {
+    if (!out) return fail(MF_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (count < 1 || !syms) return fail(MF_ERR_ARG, "count must be >= 1");
+    std::vector<const Symbolic*> parts;
+    for (int32_t i = 0; i < count; i++) {
+        if (!syms[i] || syms[i]->magic != kSymMagic) return fail(MF_ERR_ARG, "bad symbolic handle in batch");
+        if (syms[i]->S.seg_n.size() != 1) return fail(MF_ERR_ARG, "nested batches are not supported");
+        parts.push_back(&syms[i]->S);
+    }
+    try {
+        auto h = std::make_unique<mf_sym>();
+        h->opt = syms[0]->opt;
+        merge_symbolic(h->S, parts);
+        *out = h.release();
+        return MF_OK;
+    } catch (const std::invalid_argument& e) {
+        return fail(MF_ERR_ARG, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(MF_ERR_OOM, "host allocation failed in mf_batch_analyze");
+    }
+}
+
+mf_status mf_factor_batched(mf_sym_t batch, const double* const* values_dev, const mf_options* opt, void* stream,
+                            mf_num_t* inout) {
+    if (!values_dev) return fail(MF_ERR_ARG, "values_dev is null");
+    return factor_common(batch, nullptr, values_dev, opt, stream, inout);
 }
 
 mf_status mf_get_factor_info(mf_num_t N, mf_factor_info* info) {
@@ -750,6 +898,58 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
         return fail(f.st, f.msg);
     } catch (const std::bad_alloc&) {
         return fail(MF_ERR_OOM, "host allocation failed in mf_solve");
+    }
+    return MF_OK;
+}
+
+mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const* x_dev, int32_t nrhs, void* stream,
+                           mf_solve_info* info) {
+    if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
+    if (!N->factored) return fail(MF_ERR_STATE, "mf_solve_batched before a successful mf_factor_batched");
+    if (!b_dev || !x_dev || nrhs < 0) return fail(MF_ERR_ARG, "bad arguments");
+    const Symbolic& S = N->sym->S;
+    const int nseg = (int)S.seg_n.size();
+    for (int q = 0; q < nseg; q++)
+        if (S.seg_n[q] > 0 && (!b_dev[q] || !x_dev[q] || b_dev[q] == x_dev[q]))
+            return fail(MF_ERR_ARG, "b_dev[i] and x_dev[i] must be distinct device buffers");
+    if (nrhs == 0 || S.n == 0) return MF_OK;
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        const size_t need = (size_t)S.n * nrhs * 2;
+        if (need > N->cat_cap) {
+            if (N->d_cat) HIPX(hipFree(N->d_cat));
+            N->d_cat = nullptr;
+            HIPX(hipMalloc((void**)&N->d_cat, sizeof(double) * need));
+            N->cat_cap = need;
+        }
+        double* B = N->d_cat;
+        double* X = N->d_cat + (size_t)S.n * nrhs;
+        for (int q = 0; q < nseg; q++) {
+            if (!S.seg_n[q]) continue;
+            HIPX(hipMemcpy2DAsync(B + S.seg_row0[q], sizeof(double) * S.n, b_dev[q], sizeof(double) * S.seg_n[q],
+                                  sizeof(double) * S.seg_n[q], nrhs, hipMemcpyDeviceToDevice, st));
+        }
+        mf_status rc = MF_OK;
+        std::string msg;
+        try {
+            do_solve(N, B, X, nrhs, S.n, st, nullptr);
+        } catch (const Fail& f) {
+            if (f.st != MF_ERR_NOT_CONVERGED) throw;
+            rc = f.st;
+            msg = f.msg;
+        }
+        for (int q = 0; q < nseg; q++) {
+            if (!S.seg_n[q]) continue;
+            HIPX(hipMemcpy2DAsync(x_dev[q], sizeof(double) * S.seg_n[q], X + S.seg_row0[q], sizeof(double) * S.n,
+                                  sizeof(double) * S.seg_n[q], nrhs, hipMemcpyDeviceToDevice, st));
+        }
+        if (info)
+            for (int q = 0; q < nseg; q++) info[q] = N->seg_info[q];
+        if (rc != MF_OK) return fail(rc, msg);
+    } catch (const Fail& f) {
+        return fail(f.st, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(MF_ERR_OOM, "host allocation failed in mf_solve_batched");
     }
     return MF_OK;
 }

@@ -48,6 +48,10 @@ struct DevSym {
     const int32_t* ue_src;
     const int64_t* csr_rowptr;   // the matrix pattern (for residuals)
     const int32_t* csr_colind;
+    int32_t nseg;                // systems (segments) in a batch; 1 for a single system
+    const int32_t* row_seg;      // row -> segment (nullptr when nseg == 1)
+    const int64_t* seg_row0;     // nseg: first row of each segment
+    const int64_t* seg_n;        // nseg: rows of each segment
 };
 
 __host__ __device__ inline int32_t* iv_rowpiv(int32_t* iv, int P, int m) { (void)m; return iv; }

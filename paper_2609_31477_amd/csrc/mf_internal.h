@@ -52,7 +52,14 @@ struct Symbolic {
     std::vector<int64_t> level_ue_ptr;              // nlevels + 1
     double nominal_flops = 0.0;
     double nominal_nnz_lu = 0.0;
+    // systems of a batch (block-diagonal merge); one segment for a single system
+    std::vector<int64_t> seg_row0{0}, seg_n{0}, seg_nnz0{0};
 };
+
+// Block-diagonal merge of several analyzed patterns (a batch): fronts, rows and
+// maps are concatenated with offsets; each front keeps its height in its own
+// tree, so a tree level of the batch is the union of the systems' levels.
+void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts);
 
 // Runs the specified analysis; throws std::runtime_error / std::invalid_argument.
 void analyze_pattern(Symbolic& S, int64_t n, const int64_t* rowptr, const int32_t* colind,

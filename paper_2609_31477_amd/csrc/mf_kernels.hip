@@ -146,6 +146,17 @@ __global__ __launch_bounds__(kThreads) void k_scatter(DevSym S, FrontNum* fn, co
 // window.  Columns [x0, x1) (the ones just delayed) are already up to date.
 constexpr int kPanelThreads = 512;
 
+// Panel shape class of a front, from its order and precision: the window width
+// NB and rows per thread RS are per front (never per launch), so a front's
+// arithmetic does not depend on the other fronts it is batched with.
+//   class 0: m <= 512  (NB 32, RS 1)     class 1: m <= 1024 (NB 32, RS 2)
+//   class 2: m <= 2048 (FP64 NB 16, FP32 NB 32; RS 4)
+//   class 3: m <= 4096 (FP64 NB 8, FP32 NB 16; RS 8)
+__host__ __device__ inline int front_class(int m) { return m <= 512 ? 0 : (m <= 1024 ? 1 : (m <= 2048 ? 2 : 3)); }
+__host__ __device__ inline int class_nb(int cls, int prec) {
+    return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 16) : (prec ? 16 : 8));
+}
+
 template <typename T, int NB>
 __device__ __forceinline__ T pick(const T (&v)[NB], int c) {
     T x = v[0];
@@ -155,7 +166,7 @@ __device__ __forceinline__ T pick(const T (&v)[NB], int c) {
 }
 
 template <typename T, int NB, int RS>
-__global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0, double u, int want_prec) {
+__global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0, double u, int want_prec, int cls) {
     extern __shared__ int dyn[];                  // lmap[P] | dst[P] (row positions relative to k)
     __shared__ T urow[NB];
     __shared__ double red_a[kPanelThreads / 64], red_f[kPanelThreads / 64];
@@ -165,7 +176,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     __shared__ int npairs_s;
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || front_class(d.m) != cls) return;
     const int m = d.m, P = d.P;
     const int kd0 = d.k, pc = d.pcur;
     if (kd0 >= pc) {
@@ -391,10 +402,10 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
 // mv_src to mv_dst.  Each thread owns one row and reads all its sources before
 // writing, so no two threads touch the same entry.  Block (x: 256 rows, y: front).
 template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, int want_prec, int cls) {
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || front_class(d.m) != cls) return;
     const int m = d.m, P = d.P;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= m) return;
@@ -421,11 +432,11 @@ __global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, in
 // ahead of it (>= k, outside the just-delayed block) also form the new U rows
 // with the unit-lower L11 of the panel.  Block (x: 64-column tile, y: front).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec, int cls) {
     __shared__ T L11[kNBMax * kNBMax];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || front_class(d.m) != cls) return;
     const int m = d.m, P = d.P;
     const int kd0 = d.k0, kd1 = d.k, nb = kd1 - kd0;
     if (nb <= 0) return;
@@ -498,7 +509,7 @@ struct Mfma<float> {
 // Block (x: column tile, y: row tile, z: front).  4 waves, each a 32x32 quarter
 // made of 2x2 MFMA 16x16 blocks; K staged through LDS in chunks of 32.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec, int cls) {
     // A and B chunks, then (aliased) the C tile for the transposed epilogue
     __shared__ T smem_ab[2 * kKC * kLdsPad];
     static_assert(2 * kKC * kLdsPad >= kTile * kLdsPad, "C tile must fit in the A/B buffer");
@@ -507,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     T* Cs = smem_ab;
     const int s = slot0 + blockIdx.z;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || (cls >= 0 && front_class(d.m) != cls)) return;
     const int m = d.m, P = d.P;
     int rlo, clo, ka, kb;
     if (mode == 0) {
@@ -825,12 +836,14 @@ __global__ __launch_bounds__(kThreads) void k_bwd_tri(const FrontNum* fn, int sl
 
 // ------------------------------------------------------------------ residual
 // r = b - J x and omega = max_i |r_i| / (|J||x| + |b|)_i per right-hand side
-// (blockIdx.y), 16 lanes per row.  omega is accumulated as the bit pattern of a
-// non-negative double with an unsigned atomic max.
+// (blockIdx.y) and per system of a batch, 16 lanes per row.  omega is kept as the
+// bit pattern of a non-negative double and combined with an unsigned atomic max
+// (exact and order-independent).
 __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const int32_t* ci, const double* val,
                                                        int64_t n, const double* x, int64_t ldx, const double* b,
                                                        int64_t ldb, double* r, int64_t ldr,
-                                                       unsigned long long* omega_bits) {
+                                                       unsigned long long* omega_bits, const int32_t* row_seg,
+                                                       int nrhs) {
     __shared__ double wmax[kThreads / 64];
     const int c = blockIdx.y;
     const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 16;
@@ -857,7 +870,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
         const double dd = den + fabs(bi);
         w = dd > 0.0 ? fabs(ri) / dd : (ri == 0.0 ? 0.0 : INFINITY);
         if (w != w) w = INFINITY;
+        if (row_seg) atomicMax(omega_bits + (int64_t)row_seg[row] * nrhs + c, (unsigned long long)__double_as_longlong(w));
     }
+    if (row_seg) return;
     for (int off = 32; off > 0; off >>= 1) w = fmax(w, __shfl_xor(w, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = w;
     __syncthreads();
@@ -865,6 +880,22 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
         double mx = wmax[0];
         for (int i = 1; i < kThreads / 64; i++) mx = fmax(mx, wmax[i]);
         atomicMax(omega_bits + c, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// x[:, c] += d[:, c] on the rows of systems still refining (active[seg * nrhs + c])
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, double* x, int64_t ldx, const double* dvec,
+                                                   int64_t ldd, const int32_t* active, const int32_t* row_seg,
+                                                   int nrhs) {
+    const int c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const int sg = row_seg ? row_seg[i] : 0;
+        if (active[sg * nrhs + c]) x[i + c * ldx] += dvec[i + c * ldd];
     }
 }
 
@@ -883,13 +914,18 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int64_t* rp, const int3
     if (row < n && sub == 0) y[row] = acc;
 }
 
-// Deterministic multi-dot, stage 1: part[b * nv + i] = sum over block b's rows of V[:, i] * w
+// Deterministic segmented multi-dot, stage 1: block (b, s) reduces chunk b of
+// system s: part[(s * nblk + b) * nv + i] = sum over its rows of V[:, i] * w.
+// A system's chunks depend only on its own size, so its dots are the same alone
+// and in a batch.
 constexpr int kDotBlocks = 512;
-__global__ __launch_bounds__(kThreads) void k_mdot1(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
-                                                    double* part) {
+__global__ __launch_bounds__(kThreads) void k_mdot1(const double* V, int64_t ldv, int nv, const double* w,
+                                                    const int64_t* seg_row0, const int64_t* seg_n, double* part) {
     __shared__ double red[kThreads / 64];
+    const int sg = blockIdx.y;
+    const int64_t n = seg_n[sg], base = seg_row0[sg];
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    const int64_t lo = base + blockIdx.x * chunk, hi = base + min(n, (int64_t)(blockIdx.x + 1) * chunk);
     for (int i = 0; i < nv; i++) {
         double acc = 0.0;
         for (int64_t r = lo + threadIdx.x; r < hi; r += kThreads) acc = fma(V[r + i * ldv], w[r], acc);
@@ -899,43 +935,46 @@ __global__ __launch_bounds__(kThreads) void k_mdot1(const double* V, int64_t ldv
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int q = 0; q < kThreads / 64; q++) t += red[q];
-            part[blockIdx.x * nv + i] = t;
+            part[((int64_t)sg * gridDim.x + blockIdx.x) * nv + i] = t;
         }
         __syncthreads();
     }
 }
-// stage 2: out[i] = sum_b part[b * nv + i] in block order
-__global__ void k_mdot2(const double* part, int nb, int nv, double* out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
+// stage 2: out[s * ostride + i] = sum_b part[(s * nb + b) * nv + i] in block order
+__global__ void k_mdot2(const double* part, int nb, int nv, int nseg, int ostride, double* out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nv * nseg) return;
+    const int sg = q / nv, i = q % nv;
     double t = 0.0;
-    for (int b = 0; b < nb; b++) t += part[b * nv + i];
-    out[i] = t;
+    for (int b = 0; b < nb; b++) t += part[((int64_t)sg * nb + b) * nv + i];
+    out[sg * ostride + i] = t;
 }
-// w -= V[:, 0:nv] h   (h on the device)
+// w -= V[:, 0:nv] h_seg   (coefficients of the row's system: h[seg * hstride + i])
 __global__ __launch_bounds__(kThreads) void k_vsub(double* w, const double* V, int64_t ldv, int nv, const double* h,
-                                                   int64_t n) {
+                                                   int hstride, int64_t n, const int32_t* row_seg) {
     for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) {
+        const double* hs = h + (row_seg ? row_seg[r] : 0) * hstride;
         double acc = w[r];
-        for (int i = 0; i < nv; i++) acc -= V[r + i * ldv] * h[i];
+        for (int i = 0; i < nv; i++) acc -= V[r + i * ldv] * hs[i];
         w[r] = acc;
     }
 }
-// y = a * x
-__global__ __launch_bounds__(kThreads) void k_scale(double* y, const double* x, double a, int64_t n) {
+// y = a_seg * x
+__global__ __launch_bounds__(kThreads) void k_scale(double* y, const double* x, const double* a, int astride, int64_t n,
+                                                    const int32_t* row_seg) {
     for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads)
-        y[r] = a * x[r];
+        y[r] = a[(row_seg ? row_seg[r] : 0) * astride] * x[r];
 }
-// x += V[:, 0:nv] c   (c on the device)
+// x += V[:, 0:nv] c_seg
 __global__ __launch_bounds__(kThreads) void k_vadd(double* x, const double* V, int64_t ldv, int nv, const double* c,
-                                                   int64_t n) {
+                                                   int cstride, int64_t n, const int32_t* row_seg) {
     for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) {
+        const double* cs = c + (row_seg ? row_seg[r] : 0) * cstride;
         double acc = x[r];
-        for (int i = 0; i < nv; i++) acc += V[r + i * ldv] * c[i];
+        for (int i = 0; i < nv; i++) acc += V[r + i * ldv] * cs[i];
         x[r] = acc;
     }
 }
-
 __global__ __launch_bounds__(kThreads) void k_fill(double* y, double v, int64_t n) {
     for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) y[r] = v;
 }
@@ -948,19 +987,28 @@ hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const doub
                        S.csr_rowptr, S.csr_colind, val, n, x, y);
     return MF_CHECK_LAUNCH();
 }
-// out[0:nv] (device) = V[:, 0:nv]^T w; part needs kDotBlocks * nv doubles
-hipError_t launch_mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, double* out,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_mdot1, dim3(kDotBlocks), dim3(kThreads), 0, st, V, ldv, nv, w, n, part);
-    hipLaunchKernelGGL(k_mdot2, dim3((nv + 63) / 64), dim3(64), 0, st, part, kDotBlocks, nv, out);
+// out[s * ostride + i] (device) = V_s[:, 0:nv]^T w_s per system; part: kDotBlocks * nseg * nv doubles
+hipError_t launch_mdot(const DevSym& S, const double* V, int64_t ldv, int nv, const double* w, double* part,
+                       double* out, int ostride, hipStream_t st) {
+    hipLaunchKernelGGL(k_mdot1, dim3(kDotBlocks, S.nseg), dim3(kThreads), 0, st, V, ldv, nv, w, S.seg_row0, S.seg_n,
+                       part);
+    hipLaunchKernelGGL(k_mdot2, dim3((nv * S.nseg + 63) / 64), dim3(64), 0, st, part, kDotBlocks, nv, S.nseg, ostride,
+                       out);
     return MF_CHECK_LAUNCH();
 }
-hipError_t launch_vsub(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_vsub, dim3(vec_blocks(n)), dim3(kThreads), 0, st, w, V, ldv, nv, h, n);
+hipError_t launch_vsub(const DevSym& S, double* w, const double* V, int64_t ldv, int nv, const double* h, int hstride,
+                       int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_vsub, dim3(vec_blocks(n)), dim3(kThreads), 0, st, w, V, ldv, nv, h, hstride, n, S.row_seg);
     return MF_CHECK_LAUNCH();
 }
-hipError_t launch_vadd(double* x, const double* V, int64_t ldv, int nv, const double* c, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_vadd, dim3(vec_blocks(n)), dim3(kThreads), 0, st, x, V, ldv, nv, c, n);
+hipError_t launch_vadd(const DevSym& S, double* x, const double* V, int64_t ldv, int nv, const double* c,
+                       int cstride, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_vadd, dim3(vec_blocks(n)), dim3(kThreads), 0, st, x, V, ldv, nv, c, cstride, n, S.row_seg);
+    return MF_CHECK_LAUNCH();
+}
+hipError_t launch_scale(const DevSym& S, double* y, const double* x, const double* a, int astride, int64_t n,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_scale, dim3(vec_blocks(n)), dim3(kThreads), 0, st, y, x, a, astride, n, S.row_seg);
     return MF_CHECK_LAUNCH();
 }
 hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
@@ -968,59 +1016,31 @@ hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n)), dim3(kThreads), 0, st, y, v, n);
     return MF_CHECK_LAUNCH();
 }
-hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale, dim3(vec_blocks(n)), dim3(kThreads), 0, st, y, x, a, n);
-    return MF_CHECK_LAUNCH();
-}
-
-__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-// x[:, c] += d[:, c]
-__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, double* x, int64_t ldx, const double* dvec,
-                                                   int64_t ldd) {
-    const int c = blockIdx.y;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        x[i + c * ldx] += dvec[i + c * ldd];
-}
-
-// Column copy y[:, c] = x[:, c]
-__global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const double* x, int64_t ldx, double* y,
-                                                   int64_t ldy) {
-    const int c = blockIdx.y;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        y[i + c * ldy] = x[i + c * ldx];
-}
 
 // ------------------------------------------------------------------ launchers
 
 template <typename T, int NB, int RS>
-static void launch_panels(FrontNum* fn, int slot0, int count, int mmax, int Pmax, double u, int prec, hipStream_t st,
-                          hipEvent_t* ev, const DevSym& S) {
+static void launch_panels(FrontNum* fn, int slot0, int count, int mmax, int Pmax, double u, int prec, int cls,
+                          hipStream_t st) {
     const int npan = (Pmax + NB - 1) / NB;
     const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
     const int tiles = (mmax + kTile - 1) / kTile;
     for (int t = 0; t < npan; t++) {
-        hipLaunchKernelGGL((k_panel<T, NB, RS>), dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+        hipLaunchKernelGGL((k_panel<T, NB, RS>), dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec,
+                           cls);
         hipLaunchKernelGGL((k_commit<T, NB>), dim3((mmax + kThreads - 1) / kThreads, count), dim3(kThreads), 0, st,
-                           fn, slot0, prec);
-        hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tiles, count), dim3(kThreads), 0, st, fn, slot0, prec);
-        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 0, prec);
+                           fn, slot0, prec, cls);
+        hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tiles, count), dim3(kThreads), 0, st, fn, slot0, prec, cls);
+        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 0, prec, cls);
     }
 }
 
-// Panel shape per level (NB columns in registers, RS rows per thread) is chosen
-// from the level's largest front so that the window fits in 512 threads' VGPRs.
-int panel_nb(int prec, int mmax) {
-    if (mmax <= 1024) return 32;
-    if (mmax <= 2048) return prec ? 32 : 16;
-    return prec ? 16 : 8;
-}
+int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
+
+// cls_mmax[4], cls_Pmax[4]: per panel class of this precision in the level (0 = none)
 template <typename T>
-hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, int Pmax,
-                               const double* vals, int64_t u0, int64_t u1, int NB_unused, double u, int prec,
+hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
+                               const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
                                hipStream_t st, hipEvent_t* ev) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
@@ -1030,34 +1050,32 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
         hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                            st, S, fn, vals, u0, u1, prec);
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (mmax <= 512)
-        launch_panels<T, 32, 1>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
-    else if (mmax <= 1024)
-        launch_panels<T, 32, 2>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
-    else if (mmax <= 2048) {
-        if constexpr (sizeof(T) == 8)
-            launch_panels<T, 16, 4>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
-        else
-            launch_panels<T, 32, 4>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
-    } else {
-        if constexpr (sizeof(T) == 8)
-            launch_panels<T, 8, 8>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
-        else
-            launch_panels<T, 16, 8>(fn, slot0, count, mmax, Pmax, u, prec, st, ev, S);
+    for (int c = 0; c < 4; c++) {
+        const int cm = cls_mmax[c], cp = cls_Pmax[c];
+        if (cm <= 0) continue;
+        if (c == 0) launch_panels<T, 32, 1>(fn, slot0, count, cm, cp, u, prec, 0, st);
+        else if (c == 1) launch_panels<T, 32, 2>(fn, slot0, count, cm, cp, u, prec, 1, st);
+        else if (c == 2) {
+            if constexpr (sizeof(T) == 8) launch_panels<T, 16, 4>(fn, slot0, count, cm, cp, u, prec, 2, st);
+            else launch_panels<T, 32, 4>(fn, slot0, count, cm, cp, u, prec, 2, st);
+        } else {
+            if constexpr (sizeof(T) == 8) launch_panels<T, 8, 8>(fn, slot0, count, cm, cp, u, prec, 3, st);
+            else launch_panels<T, 16, 8>(fn, slot0, count, cm, cp, u, prec, 3, st);
+        }
     }
     const int tiles = (mmax + kTile - 1) / kTile;
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 1, prec);
+    hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 1, prec, -1);
     if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_finalize<T>, dim3(count), dim3(kThreads), 0, st, S, fn, slot0, prec);
     if (ev) (void)hipEventRecord(ev[3], st);
     return MF_CHECK_LAUNCH();
 }
 
-template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, int, const double*,
-                                                int64_t, int64_t, int, double, int, hipStream_t, hipEvent_t*);
-template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, int, const double*,
-                                               int64_t, int64_t, int, double, int, hipStream_t, hipEvent_t*);
+template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
+                                                const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*);
+template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
+                                               const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
@@ -1091,26 +1109,21 @@ template hipError_t launch_level_bwd<float>(const FrontNum*, int, int, int, doub
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
                            unsigned long long* omega_bits, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_u64, dim3((nrhs + 63) / 64), dim3(64), 0, st, omega_bits, nrhs, 0ull);
+    const int nom = nrhs * S.nseg;
+    hipLaunchKernelGGL(k_fill_u64, dim3((nom + 63) / 64), dim3(64), 0, st, omega_bits, nom, 0ull);
     if (n > 0) {
         const int64_t blocks = (n * 16 + kThreads - 1) / kThreads;
         hipLaunchKernelGGL(k_residual, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, st, S.csr_rowptr,
-                           S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits);
+                           S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits, S.row_seg, nrhs);
     }
     return MF_CHECK_LAUNCH();
 }
 
-hipError_t launch_axpy(int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd, int nrhs, hipStream_t st) {
+hipError_t launch_axpy(const DevSym& S, int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd,
+                       const int32_t* active, int nrhs, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
-    hipLaunchKernelGGL(k_axpy, dim3(blocks, nrhs), dim3(kThreads), 0, st, n, x, ldx, d, ldd);
-    return MF_CHECK_LAUNCH();
-}
-
-hipError_t launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
-    hipLaunchKernelGGL(k_copy, dim3(blocks, nrhs), dim3(kThreads), 0, st, n, x, ldx, y, ldy);
+    hipLaunchKernelGGL(k_axpy, dim3(blocks, nrhs), dim3(kThreads), 0, st, n, x, ldx, d, ldd, active, S.row_seg, nrhs);
     return MF_CHECK_LAUNCH();
 }
 

@@ -284,6 +284,9 @@ void analyze_pattern(Symbolic& S, int64_t n, const int64_t* rowptr, const int32_
     S.n = n;
     S.nnz = nnz;
     S.leaf_max = leaf_max;
+    S.seg_row0 = {0};
+    S.seg_n = {n};
+    S.seg_nnz0 = {0};
     S.rowptr.assign(rowptr, rowptr + n + 1);
     S.colind.assign(colind, colind + nnz);
     S.root.assign(root_idx, root_idx + nroot);
@@ -499,6 +502,98 @@ void analyze_pattern(Symbolic& S, int64_t n, const int64_t* rowptr, const int32_
         for (int32_t l = 0; l < S.nlevels; l++)
             S.level_ue_ptr[l + 1] = std::max(S.level_ue_ptr[l + 1], S.level_ue_ptr[l]);
     }
+}
+
+void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
+    M = Symbolic();
+    M.seg_row0.clear();
+    M.seg_n.clear();
+    M.seg_nnz0.clear();
+    int64_t voff = 0, eoff = 0;
+    int32_t foff = 0, poff = 0;
+    M.rowptr.assign(1, 0);
+    M.front_ptr.assign(1, 0);
+    M.rows_ptr.assign(1, 0);
+    M.leaf_max = parts.empty() ? 64 : parts[0]->leaf_max;
+    std::vector<int32_t> part_of_front;
+    std::vector<int64_t> imap_len;
+    for (size_t q = 0; q < parts.size(); q++) {
+        const Symbolic& P = *parts[q];
+        M.seg_row0.push_back(voff);
+        M.seg_n.push_back(P.n);
+        M.seg_nnz0.push_back(eoff);
+        for (int64_t r = 0; r < P.n; r++) M.rowptr.push_back(P.rowptr[r + 1] + eoff);
+        for (int64_t t = 0; t < P.nnz; t++) M.colind.push_back((int32_t)(P.colind[t] + voff));
+        for (int32_t v : P.root) M.root.push_back((int32_t)(v + voff));
+        for (int64_t i = 0; i < P.n; i++) {
+            M.perm.push_back((int32_t)(P.perm[i] + voff));
+            M.var_etree.push_back(P.var_etree[i] < 0 ? -1 : (int32_t)(P.var_etree[i] + voff));
+        }
+        for (int32_t f = 0; f < P.nf; f++) {
+            M.front_ptr.push_back(P.front_ptr[f + 1] + poff);
+            M.front_parent.push_back(P.front_parent[f] < 0 ? -1 : P.front_parent[f] + foff);
+            for (int64_t t = P.rows_ptr[f]; t < P.rows_ptr[f + 1]; t++) M.rows.push_back((int32_t)(P.rows[t] + voff));
+            M.rows_ptr.push_back((int64_t)M.rows.size());
+            M.npiv.push_back(P.npiv[f]);
+            M.mnom.push_back(P.mnom[f]);
+            M.level.push_back(P.level[f]);
+            part_of_front.push_back((int32_t)q);
+            M.imap.insert(M.imap.end(), P.imap.begin() + P.imap_off[f], P.imap.begin() + P.imap_off[f + 1]);
+            imap_len.push_back(P.imap_off[f + 1] - P.imap_off[f]);
+        }
+        M.nominal_flops += P.nominal_flops;
+        M.nominal_nnz_lu += P.nominal_nnz_lu;
+        M.nlevels = std::max(M.nlevels, P.nlevels);
+        voff += P.n;
+        eoff += P.nnz;
+        foff += P.nf;
+        poff += (int32_t)P.n;
+    }
+    M.n = voff;
+    M.nnz = eoff;
+    M.nf = foff;
+    const int32_t nf = M.nf;
+    M.imap_off.assign(nf + 1, 0);
+    for (int32_t f = 0; f < nf; f++) M.imap_off[f + 1] = M.imap_off[f] + imap_len[f];
+    M.child_ptr.assign(nf + 1, 0);
+    for (int32_t f = 0; f < nf; f++)
+        if (M.front_parent[f] >= 0) M.child_ptr[M.front_parent[f] + 1]++;
+    for (int32_t f = 0; f < nf; f++) M.child_ptr[f + 1] += M.child_ptr[f];
+    M.child_idx.assign(M.child_ptr[nf], 0);
+    {
+        std::vector<int32_t> nx(M.child_ptr.begin(), M.child_ptr.end() - 1);
+        for (int32_t f = 0; f < nf; f++)
+            if (M.front_parent[f] >= 0) M.child_idx[nx[M.front_parent[f]]++] = f;
+    }
+    M.level_ptr.assign(M.nlevels + 1, 0);
+    for (int32_t f = 0; f < nf; f++) M.level_ptr[M.level[f] + 1]++;
+    for (int32_t l = 0; l < M.nlevels; l++) M.level_ptr[l + 1] += M.level_ptr[l];
+    M.level_fronts.assign(nf, 0);
+    {
+        std::vector<int32_t> nx(M.level_ptr.begin(), M.level_ptr.end() - 1);
+        for (int32_t f = 0; f < nf; f++) M.level_fronts[nx[M.level[f]]++] = f;
+    }
+    // unique entries in level order, system by system within a level
+    M.level_ue_ptr.assign(M.nlevels + 1, 0);
+    M.ue_src_ptr.assign(1, 0);
+    std::vector<int32_t> foffs(parts.size() + 1, 0);
+    for (size_t q = 0; q < parts.size(); q++) foffs[q + 1] = foffs[q] + parts[q]->nf;
+    for (int32_t l = 0; l < M.nlevels; l++) {
+        for (size_t q = 0; q < parts.size(); q++) {
+            const Symbolic& P = *parts[q];
+            if (l >= P.nlevels) continue;
+            for (int64_t u = P.level_ue_ptr[l]; u < P.level_ue_ptr[l + 1]; u++) {
+                M.ue_front.push_back(P.ue_front[u] + foffs[q]);
+                M.ue_row.push_back(P.ue_row[u]);
+                M.ue_col.push_back(P.ue_col[u]);
+                for (int64_t t = P.ue_src_ptr[u]; t < P.ue_src_ptr[u + 1]; t++)
+                    M.ue_src.push_back((int32_t)(P.ue_src[t] + M.seg_nnz0[q]));
+                M.ue_src_ptr.push_back((int64_t)M.ue_src.size());
+            }
+        }
+        M.level_ue_ptr[l + 1] = (int64_t)M.ue_front.size();
+    }
+    if (M.nnz > INT32_MAX) throw std::invalid_argument("batch nnz above 2^31-1 is not supported");
 }
 
 }  // namespace mf

@@ -1,0 +1,240 @@
+"""Continuous-batching request loop for parametric VIV Newton-step solves.
+
+Each request is one time step of the paper's solver (Sec. 3.4: Newton-Raphson
+iterations, each a linear solve with the fixed-pattern Jacobian) for its own
+mesh, Reynolds number and spring stiffness (the reduced velocity of Sec. 1 gives
+k = pi^3 / U_r^2 for a massless cylinder with rho = L = U_inf = D = 1).  A request
+runs ``newton_steps`` factor+solve steps with its symbolic analysis done once
+(Sec. 6, "Scaling").
+
+Scheduling (continuous batching, not a queue): requests arrive on a Poisson
+clock; a request is admitted when a slot and its HBM footprint fit; every tick
+takes all admitted requests with a pending Newton step and runs that step for
+all of them in one batched factorization and one batched solve (shared
+launches).  Requests that arrive while others are on the GPU join at the next
+tick; finished requests free their slot and memory immediately.  Because the
+batched kernels keep every system's arithmetic separate, a request's result is
+the same alone and in any mix.
+
+The scheduler is backend-agnostic: ``MFBackend`` drives libmf on the GPU;
+``FakeBackend`` simulates durations and footprints for CPU tests of the logic.
+"""
+from __future__ import annotations
+
+import heapq
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                  # seconds on the scheduler clock
+    mesh: tuple                     # ("2d", nx, ny) or ("3d", nx, ny, nz)
+    reynolds: float
+    reduced_velocity: float
+    seed: int
+    newton_steps: int = 5
+    # filled by the scheduler
+    admitted: float | None = None
+    finished: float | None = None
+    steps_done: int = 0
+    step_latency: list = field(default_factory=list)
+    footprint: int = 0
+    results: list = field(default_factory=list)   # per-step info (omega, ...)
+    state: object = None                           # backend state
+
+    @property
+    def nu(self) -> float:
+        return 1.0 / self.reynolds
+
+    @property
+    def k(self) -> float:
+        return math.pi ** 3 / self.reduced_velocity ** 2
+
+
+def poisson_requests(n, rate, seed=0, mix_3d=0.3, newton_steps=5, mesh_2d=range(32, 129, 4), allow_3d=True):
+    """Poisson arrivals (rate per second) of mixed 2D/3D requests with Re ~ U[100,300],
+    U_r ~ U[2,12] (2D) or U[2.5,17.5] (3D)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    meshes = list(mesh_2d)
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        is3d = allow_3d and rng.random() < mix_3d
+        if is3d:
+            mesh = ("3d", 24, 12, 6)
+            ur = rng.uniform(2.5, 17.5)
+        else:
+            nx = int(meshes[rng.integers(len(meshes))])
+            mesh = ("2d", nx, nx // 2)
+            ur = rng.uniform(2.0, 12.0)
+        out.append(Request(rid=i, arrival=t, mesh=mesh, reynolds=float(rng.uniform(100, 300)),
+                           reduced_velocity=float(ur), seed=1000 + i, newton_steps=newton_steps))
+    return out
+
+
+class Scheduler:
+    """Admission by footprint + continuous batching over Newton steps."""
+
+    def __init__(self, backend, hbm_budget: int, max_slots: int = 64):
+        self.backend = backend
+        self.budget = int(hbm_budget)
+        self.max_slots = max_slots
+        self.used = 0
+        self.active: list[Request] = []
+        self.waiting: list = []       # heap of (arrival, rid, request)
+        self.done: list[Request] = []
+        self.ticks = 0
+        self.batch_sizes = []
+
+    def submit(self, req: Request):
+        heapq.heappush(self.waiting, (req.arrival, req.rid, req))
+
+    def _admit(self, now):
+        while self.waiting and self.waiting[0][0] <= now and len(self.active) < self.max_slots:
+            _, _, req = self.waiting[0]
+            if not req.footprint:
+                req.footprint = self.backend.prepare(req)
+            if req.footprint > self.budget:
+                raise MemoryError(f"request {req.rid} needs {req.footprint} B, above the whole budget")
+            if self.used + req.footprint > self.budget:
+                break                  # wait until memory frees up (FIFO admission)
+            heapq.heappop(self.waiting)
+            self.used += req.footprint
+            req.admitted = now
+            self.active.append(req)
+
+    def run(self, clock=None, idle_sleep=True):
+        """Serve until every submitted request is done.  ``clock()`` returns seconds
+        since the start (wall clock by default; the fake backend advances its own)."""
+        t0 = time.perf_counter()
+        clock = clock or (lambda: time.perf_counter() - t0)
+        while self.waiting or self.active:
+            now = clock()
+            self._admit(now)
+            if not self.active:
+                nxt = self.waiting[0][0]
+                if idle_sleep:
+                    self.backend.idle_until(nxt, clock)
+                continue
+            batch = list(self.active)
+            ts = clock()
+            infos = self.backend.step(batch)
+            te = clock()
+            self.ticks += 1
+            self.batch_sizes.append(len(batch))
+            for req, inf in zip(batch, infos):
+                req.step_latency.append(te - ts)
+                req.results.append(inf)
+                req.steps_done += 1
+                if req.steps_done >= req.newton_steps:
+                    req.finished = te
+                    self.active.remove(req)
+                    self.used -= req.footprint
+                    self.backend.release(req)
+                    self.done.append(req)
+        return self.done
+
+
+def summarize(done):
+    lat = np.array([r.finished - r.arrival for r in done])
+    steps = np.array([s for r in done for s in r.step_latency])
+    span = max(r.finished for r in done) - min(r.arrival for r in done)
+    return {"requests": len(done), "solves": int(sum(r.steps_done for r in done)),
+            "solves_per_s": float(sum(r.steps_done for r in done) / span),
+            "p50_request_s": float(np.percentile(lat, 50)), "p99_request_s": float(np.percentile(lat, 99)),
+            "p50_step_s": float(np.percentile(steps, 50)), "p99_step_s": float(np.percentile(steps, 99))}
+
+
+class FakeBackend:
+    """CPU stand-in: footprint and step time proportional to the mesh size; the
+    clock is simulated so the scheduling logic is testable without a GPU."""
+
+    def __init__(self, sec_per_dof=1e-8, bytes_per_dof=4000):
+        self.sec_per_dof = sec_per_dof
+        self.bytes_per_dof = bytes_per_dof
+        self.now = 0.0
+        self.calls = []
+
+    def dofs(self, req):
+        m = req.mesh
+        return m[1] * m[2] * 8 if m[0] == "2d" else m[1] * m[2] * m[3] * 50
+
+    def clock(self):
+        return self.now
+
+    def prepare(self, req):
+        return self.dofs(req) * self.bytes_per_dof
+
+    def step(self, batch):
+        self.calls.append([r.rid for r in batch])
+        self.now += self.sec_per_dof * sum(self.dofs(r) for r in batch) + 1e-4
+        return [{"omega": 0.0} for _ in batch]
+
+    def release(self, req):
+        pass
+
+    def idle_until(self, t, clock):
+        self.now = max(self.now, t)
+
+
+class MFBackend:
+    """libmf on the GPU: one symbolic handle per request (analysis once), the
+    request's Newton values and right-hand sides resident in HBM, one batched
+    factorization + batched solve per tick."""
+
+    def __init__(self, prec="fp32", target_omega=1e-10, margin=0.5, device="cuda:0"):
+        import torch
+
+        from . import Symbolic
+        self.torch = torch
+        self.Symbolic = Symbolic
+        self.prec = prec
+        self.target = target_omega
+        self.margin = margin
+        self.dev = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.dev)
+
+    def build(self, req):
+        from vivjac import build_2d, build_3d
+        if req.mesh[0] == "2d":
+            return build_2d(req.mesh[1], req.mesh[2], req.seed, nu=req.nu, k=req.k)
+        return build_3d(req.mesh[1], req.mesh[2], req.mesh[3], req.seed, nu=req.nu, k=req.k)
+
+    def prepare(self, req):
+        from vivjac import newton_rhs, newton_values
+        s = self.build(req)
+        sym = self.Symbolic(s.n, s.rowptr, s.colind, s.root)
+        vals = [self.torch.from_numpy(newton_values(s, t)).to(self.dev) for t in range(req.newton_steps)]
+        rhs = [self.torch.from_numpy(newton_rhs(s, t)[0].copy()).to(self.dev) for t in range(req.newton_steps)]
+        xs = [self.torch.empty(s.n, dtype=self.torch.float64, device=self.dev) for _ in range(req.newton_steps)]
+        req.state = dict(system=s, sym=sym, vals=vals, rhs=rhs, xs=xs)
+        return sym.footprint_bytes(self.prec, self.margin) + 8 * (s.nnz + 2 * s.n) * req.newton_steps
+
+    def step(self, batch):
+        from . import Batch
+        B = Batch([r.state["sym"] for r in batch])
+        vals = [r.state["vals"][r.steps_done] for r in batch]
+        bs = [r.state["rhs"][r.steps_done] for r in batch]
+        xs = [r.state["xs"][r.steps_done] for r in batch]
+        B.factor(vals, stream=self.stream, prec=self.prec, target_omega=self.target)
+        _, infos = B.solve(bs, xs=xs, stream=self.stream)
+        self.torch.cuda.synchronize()
+        B.release()
+        return [{"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters} for inf in infos]
+
+    def release(self, req):
+        st = req.state
+        st["sym"] = None
+        st["vals"] = None
+        st["rhs"] = None
+
+    def idle_until(self, t, clock):
+        dt = t - clock()
+        if dt > 0:
+            time.sleep(min(dt, 0.05))

@@ -1,0 +1,103 @@
+"""Serving loop: admission by footprint and continuous batching (CPU, fake device
+backend), plus a GPU check that each request's result is the same alone and in
+the mix."""
+import numpy as np
+import pytest
+
+from paper_2609_31477_amd.serving import FakeBackend, Request, Scheduler, poisson_requests, summarize
+
+
+def run_fake(reqs, budget, slots=64):
+    be = FakeBackend()
+    sch = Scheduler(be, hbm_budget=budget, max_slots=slots)
+    for r in reqs:
+        sch.submit(r)
+    done = sch.run(clock=be.clock)
+    return sch, be, done
+
+
+def test_all_requests_complete_with_all_steps():
+    reqs = poisson_requests(40, rate=50.0, seed=1, allow_3d=True)
+    sch, be, done = run_fake(reqs, budget=10 ** 12)
+    assert len(done) == 40
+    assert all(r.steps_done == r.newton_steps == 5 for r in done)
+    assert all(r.finished >= r.admitted >= r.arrival for r in done)
+    s = summarize(done)
+    assert s["solves"] == 200 and s["p99_request_s"] >= s["p50_request_s"] > 0
+
+
+def test_continuous_batching_admits_during_service():
+    # requests arriving while others run join later ticks (batches overlap in time)
+    reqs = poisson_requests(30, rate=200.0, seed=2, allow_3d=False)
+    sch, be, done = run_fake(reqs, budget=10 ** 12)
+    assert max(sch.batch_sizes) > 1
+    # some request was admitted while another was mid-way through its Newton steps
+    mixed = any(len(set(c1) & set(c2)) and set(c2) - set(c1) for c1, c2 in zip(be.calls, be.calls[1:]))
+    assert mixed
+
+
+def test_admission_respects_hbm_budget():
+    reqs = poisson_requests(20, rate=1000.0, seed=3, allow_3d=False)
+    be = FakeBackend()
+    fp = max(be.prepare(r) for r in reqs)
+    budget = 2 * fp + 1
+    sch = Scheduler(be, hbm_budget=budget)
+    for r in reqs:
+        sch.submit(r)
+    seen = []
+    orig = be.step
+
+    def step(batch):
+        seen.append(sum(r.footprint for r in batch))
+        return orig(batch)
+    be.step = step
+    done = sch.run(clock=be.clock)
+    assert len(done) == 20
+    assert max(seen) <= budget
+    assert sch.used == 0
+
+
+def test_slot_limit():
+    reqs = poisson_requests(12, rate=1000.0, seed=4, allow_3d=False)
+    sch, be, done = run_fake(reqs, budget=10 ** 12, slots=3)
+    assert max(sch.batch_sizes) <= 3 and len(done) == 12
+
+
+def test_oversized_request_rejected():
+    be = FakeBackend()
+    sch = Scheduler(be, hbm_budget=10)
+    sch.submit(Request(rid=0, arrival=0.0, mesh=("2d", 32, 16), reynolds=150, reduced_velocity=5, seed=1))
+    with pytest.raises(MemoryError):
+        sch.run(clock=be.clock)
+
+
+def test_request_parameters_follow_reduced_velocity():
+    r = Request(rid=0, arrival=0.0, mesh=("2d", 32, 16), reynolds=200.0, reduced_velocity=np.pi, seed=0)
+    assert r.k == pytest.approx(np.pi) and r.nu == pytest.approx(1 / 200)
+
+
+@pytest.mark.gpu
+def test_gpu_serving_mix_equals_alone():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31477_amd.serving import MFBackend
+    reqs = poisson_requests(6, rate=200.0, seed=7, allow_3d=False, mesh_2d=range(16, 41, 4), newton_steps=2)
+    be = MFBackend(prec="fp32", target_omega=1e-10)
+    sch = Scheduler(be, hbm_budget=64 << 30)
+    for r in reqs:
+        sch.submit(r)
+    done = sch.run()
+    assert max(sch.batch_sizes) > 1
+    for r in done:
+        for t in range(r.newton_steps):
+            xm = r.state["xs"][t].cpu().numpy()
+            be1 = MFBackend(prec="fp32", target_omega=1e-10)
+            alone = Request(rid=r.rid, arrival=0.0, mesh=r.mesh, reynolds=r.reynolds,
+                            reduced_velocity=r.reduced_velocity, seed=r.seed, newton_steps=r.newton_steps)
+            be1.prepare(alone)
+            alone.steps_done = t
+            be1.step([alone])
+            xa = alone.state["xs"][t].cpu().numpy()
+            assert np.array_equal(xm, xa), f"request {r.rid} step {t} differs alone vs in the mix"
+            assert r.results[t]["omega"] <= 1e-10
