@@ -51,6 +51,78 @@ def cpu_baseline(seconds_cap=60.0):
     return dt, flops_sample, float(om[0])
 
 
+def bench_batch(args):
+    """64 independent 2D systems (seeds 100-163, nx = 16 + 4 U{0..12}, ny = nx/2) factored
+    and solved together, FP32 fronts (FP64 roots) with FP64 GMRES-IR to omega <= 1e-10."""
+    import numpy as np
+    import torch
+
+    import paper_2609_31477_amd as mf
+    from vivjac import build_2d
+    dev = torch.device("cuda:0")
+    systems = []
+    for i in range(64):
+        rng = np.random.default_rng(100 + i)
+        nx = 16 + 4 * int(rng.integers(0, 13))
+        systems.append(build_2d(nx, nx // 2, 100 + i))
+    syms = [mf.Symbolic(s.n, s.rowptr, s.colind, s.root) for s in systems]
+    B = mf.Batch(syms)
+    view = B.export()
+    vals = [torch.from_numpy(s.values).to(dev) for s in systems]
+    bs = [torch.from_numpy(s.b0[0].copy()).to(dev) for s in systems]
+    xs = [torch.empty_like(b) for b in bs]
+    prec = "fp32" if args.prec == "fp64" else args.prec
+    stream = torch.cuda.current_stream()
+    def step():
+        B.factor(vals, stream=stream, prec=prec, target_omega=args.target_omega)
+        _, infos = B.solve(bs, xs=xs, stream=stream)
+        torch.cuda.synchronize()
+        return infos
+    for _ in range(args.warmup):
+        step()
+    ts = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        infos = step()
+        ts.append(time.perf_counter() - t1)
+    el = time.perf_counter() - t0
+    res = {"metric": METRIC, "value": round(64 * args.steps / el, 3), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "64 uneven 2D VIV Jacobians (16x8..64x32 cells, seeds 100-163), one batched "
+                                  "factor+solve per step, FP32 fronts, FP64 roots, FP64 GMRES-IR, omega<=1e-10",
+                      "n_total": int(sum(s.n for s in systems)), "fronts": view.nfronts, "levels": view.nlevels},
+           "front_tflops": round(view.nominal_flops * args.steps / el / 1e12, 4),
+           "p99_ms": round(1e3 * float(np.percentile(ts, 99)), 3),
+           "omega_max": float(max(i.omega for i in infos)), "outer_max": int(max(i.outer_iters for i in infos))}
+    print(json.dumps(res), flush=True)
+
+
+def bench_serving(args):
+    """Poisson stream of 2D requests (32x16..128x64 cells, Re ~ U[100,300], U_r ~ U[2,12]),
+    5 Newton steps each, FP32 fronts + FP64 GMRES-IR to 1e-10, continuous batching."""
+    import torch
+
+    from paper_2609_31477_amd.serving import MFBackend, Scheduler, poisson_requests, summarize
+    reqs = poisson_requests(args.requests, rate=args.rate, seed=args.seed, allow_3d=False)
+    be = MFBackend(prec="fp32", target_omega=args.target_omega)
+    sch = Scheduler(be, hbm_budget=200 << 30, max_slots=64)
+    for r in reqs:
+        sch.submit(r)
+    done = sch.run()
+    s = summarize(done)
+    res = {"metric": METRIC, "value": round(s["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1,
+           "steps": s["solves"], "warmup": 0, "ms_per_step": round(1e3 / s["solves_per_s"], 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"serving: {args.requests} Poisson requests at {args.rate}/s, 2D meshes "
+                                  "32x16..128x64, 5 Newton steps each, continuous batching, omega<=1e-10"},
+           "p50_request_ms": round(1e3 * s["p50_request_s"], 2), "p99_request_ms": round(1e3 * s["p99_request_s"], 2),
+           "p50_step_ms": round(1e3 * s["p50_step_s"], 2), "p99_step_ms": round(1e3 * s["p99_step_s"], 2),
+           "mean_batch": round(sum(sch.batch_sizes) / len(sch.batch_sizes), 2)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,9 +133,14 @@ def main():
     ap.add_argument("--ny", type=int, default=128)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--target-omega", type=float, default=1e-10)
-    ap.add_argument("--panel-nb", type=int, default=32)
+    ap.add_argument("--workload", default="newton", choices=["newton", "batch", "serving"],
+                    help="newton: 256x128 Newton steps (default); batch: 64 uneven systems in one batched "
+                         "factor+solve; serving: Poisson request stream through the continuous-batching loop")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: arrival rate (requests/s)")
+    ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the separate event-timed profiling pass")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 fronts) comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1"}))
@@ -75,6 +152,10 @@ def main():
     import paper_2609_31477_amd as mf
     from vivjac import build_2d, newton_rhs, newton_values
 
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     dev = torch.device("cuda:0")
     t = time.perf_counter()
     s = build_2d(args.nx, args.ny, args.seed)
@@ -83,59 +164,64 @@ def main():
     vals = [torch.from_numpy(newton_values(s, k)).to(dev) for k in range(nsteps_newton)]
     rhs = [torch.from_numpy(newton_rhs(s, k)[0].copy()).to(dev) for k in range(nsteps_newton)]
     x = torch.empty(s.n, dtype=torch.float64, device=dev)
+    x.zero_()
     t = time.perf_counter()
     S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
     t_analyze = time.perf_counter() - t
     view = S.export()
     log(f"analyze {t_analyze:.2f}s: fronts={view.nfronts} levels={view.nlevels} "
         f"nominal flops={view.nominal_flops:.3e} nnz(L+U)={view.nominal_nnz_lu:.3e}")
-    opts = dict(prec=args.prec, target_omega=args.target_omega, panel_nb=args.panel_nb)
     stream = torch.cuda.current_stream()
 
-    num = None
-    step_ms = []
-    omegas = []
-    iters = []
+    def run_path(prec):
+        """Time args.steps Newton-step solves (factor + solve + refinement) in one precision."""
+        opts = dict(prec=prec, target_omega=args.target_omega)
+        state = {"num": None}
+        step_ms, omegas, iters, inner = [], [], [], []
 
-    def step(i, timed):
-        nonlocal num
-        k = i % nsteps_newton
+        def step(i, timed):
+            k = i % nsteps_newton
+            t0 = time.perf_counter()
+            state["num"] = S.factor(vals[k], numeric=state["num"], stream=stream, **opts)
+            _, info = state["num"].solve(rhs[k], x=x, stream=stream)
+            torch.cuda.synchronize()
+            if timed:
+                step_ms.append(1e3 * (time.perf_counter() - t0))
+                omegas.append(info.omega)
+                iters.append(info.outer_iters)
+                inner.append(info.inner_iters)
+
+        for i in range(args.warmup):
+            step(i, False)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        num = S.factor(vals[k], numeric=num, stream=stream, **opts)
-        _, info = num.solve(rhs[k], x=x, stream=stream)
+        for i in range(args.steps):
+            step(i, True)
         torch.cuda.synchronize()
-        if timed:
-            step_ms.append(1e3 * (time.perf_counter() - t0))
-            omegas.append(info.omega)
-            iters.append(info.outer_iters)
-
-    for i in range(args.warmup):
-        step(i, False)
-        log(f"warmup step {i} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i, True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"timed {args.steps} steps in {elapsed:.3f}s")
-
-    # separate pass with per-phase HIP events (not part of the timed region)
-    finfo = None
-    if not args.no_profile:
-        num = S.factor(vals[0], numeric=num, stream=stream, profile=1, **opts)
+        elapsed = time.perf_counter() - t0
+        log(f"{prec}: timed {args.steps} steps in {elapsed:.3f}s")
+        num = state["num"]
+        finfo = None
+        if not args.no_profile:
+            num = S.factor(vals[0], numeric=num, stream=stream, profile=1, **opts)
+            torch.cuda.synchronize()
+            finfo = num.info()
+        t_f0 = time.perf_counter()
+        nf_rep = 3
+        for i in range(nf_rep):
+            num = S.factor(vals[i % nsteps_newton], numeric=num, stream=stream, **opts)
         torch.cuda.synchronize()
-        finfo = num.info()
-    else:
-        finfo = num.info()
+        t_factor = (time.perf_counter() - t_f0) / nf_rep
+        if finfo is None:
+            finfo = num.info()
+        num.release()
+        return dict(elapsed=elapsed, step_ms=step_ms, omegas=omegas, iters=iters, inner=inner, finfo=finfo,
+                    t_factor=t_factor)
 
-    # front TFLOP/s: nominal algorithmic flops over the mean factor time of a step
-    t_f0 = time.perf_counter()
-    nf_rep = 3
-    for i in range(nf_rep):
-        num = S.factor(vals[i % nsteps_newton], numeric=num, stream=stream, **opts)
-    torch.cuda.synchronize()
-    t_factor = (time.perf_counter() - t_f0) / nf_rep
+    main = run_path(args.prec)
+    mixed = None if args.no_mixed or args.prec != "fp64" else run_path("fp32")
+    elapsed, step_ms, omegas, iters, finfo, t_factor = (main["elapsed"], main["step_ms"], main["omegas"],
+                                                         main["iters"], main["finfo"], main["t_factor"])
 
     dtype = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.prec]
     value = args.steps / elapsed
@@ -157,7 +243,7 @@ def main():
                         f"P2 multiplier, 2 position dofs), seed {args.seed}, {nsteps_newton} Newton steps cycled, "
                         f"1 RHS, multifrontal factor+solve, omega<=" + f"{args.target_omega:g}",
             "n": s.n, "nnz": s.nnz, "fronts": view.nfronts, "levels": view.nlevels,
-            "precision": args.prec, "panel_nb": args.panel_nb,
+            "precision": args.prec,
         },
         "front_tflops": round(view.nominal_flops / t_factor / 1e12, 4),
         "factor_ms": round(1e3 * t_factor, 3),
@@ -168,6 +254,16 @@ def main():
         "delayed_pivots": int(finfo.delayed_pivots),
         "analyze_s": round(t_analyze, 3),
     }
+    if mixed is not None:
+        mv = args.steps / mixed["elapsed"]
+        res["mixed"] = {"precision": "fp32 fronts, fp64 root + GMRES-IR", "value": round(mv, 4), "unit": "solves/s",
+                        "ms_per_step": round(1e3 * mixed["elapsed"] / args.steps, 3),
+                        "p99_ms": round(float(np.percentile(mixed["step_ms"], 99)), 3),
+                        "factor_ms": round(1e3 * mixed["t_factor"], 3),
+                        "front_tflops": round(view.nominal_flops / mixed["t_factor"] / 1e12, 4),
+                        "omega_max": float(max(mixed["omegas"])), "outer_max": int(max(mixed["iters"])),
+                        "inner_total": int(sum(mixed["inner"])),
+                        "speedup_vs_fp64": round(mv / value, 4)}
     if finfo is not None and finfo.schur_launches:
         res["phases_ms"] = {"assemble": round(finfo.t_assemble_ms, 3), "panel": round(finfo.t_panel_ms, 3),
                             "schur": round(finfo.t_schur_ms, 3), "finalize": round(finfo.t_finalize_ms, 3)}
