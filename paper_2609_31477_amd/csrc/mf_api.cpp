@@ -23,7 +23,7 @@ namespace mf {
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
-                               hipStream_t st, hipEvent_t* ev);
+                               hipStream_t st, hipEvent_t* ev, bool bf16_schur);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
@@ -384,13 +384,14 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             if (prof) HIPX(hipEventRecord(ev[0][0], st));
             HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
                                              N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), N->d_vals,
-                                             u0, u1, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr));
+                                             u0, u1, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr, false));
         }
         if (N->lvl_cnt[1][L]) {
             if (prof) HIPX(hipEventRecord(ev[1][0], st));
             HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
                                             N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), N->d_vals,
-                                            u0, u1, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr));
+                                            u0, u1, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr,
+                                            o.prec == MF_BF16));
         }
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));

@@ -166,17 +166,14 @@ __device__ __forceinline__ T pick(const T (&v)[NB], int c) {
 }
 
 template <typename T, int NB, int RS>
-__global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0, double u, int want_prec, int cls) {
-    extern __shared__ int dyn[];                  // lmap[P] | dst[P] (row positions relative to k)
+__device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* dyn) {
     __shared__ T urow[NB];
     __shared__ double red_a[kPanelThreads / 64], red_f[kPanelThreads / 64];
     __shared__ int red_i[kPanelThreads / 64];
     __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB];
     __shared__ int mv_src[NB], mv_dst[NB], mv_tag[NB];
     __shared__ int npairs_s;
-    const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec || front_class(d.m) != cls) return;
     const int m = d.m, P = d.P;
     const int kd0 = d.k, pc = d.pcur;
     if (kd0 >= pc) {
@@ -317,17 +314,40 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     }
     __syncthreads();
     const int nmove = npairs_s;
-    if (tid == 0) {
-        // swap sequence: the pivot row of step t goes to position k0 + t, the row
-        // found there takes the pivot row's current position
-        for (int t = 0; t < nb; t++) {
-            const int a = kd0 + t, r = piv_row[t];
-            const int p = dstm[r - kd0];
-            const int ra = lmap[a - kd0];
-            lmap[a - kd0] = r;
-            lmap[p - kd0] = ra;
-            dstm[r - kd0] = a;
-            dstm[ra - kd0] = p;
+    // row permutation: the pivot row of step t goes to position k0 + t; the rows
+    // displaced from [k0, k0 + nb) take, in increasing order, the positions the
+    // pivot rows vacated beyond k0 + nb (one wave, ballots for the ranks)
+    if (wid == 0) {
+        const bool has = lane < nb;
+        const int pr = has ? piv_row[lane] : 0;
+        if (has) {
+            lmap[lane] = pr;             // position k0 + lane receives pivot row pr
+            dstm[pr - kd0] = kd0 + lane;
+        }
+        // is position k0 + lane itself a pivot row?
+        bool slot_is_piv = false;
+        for (int t = 0; t < nb; t++) slot_is_piv = slot_is_piv || (piv_row[t] == kd0 + lane);
+        const bool displaced = has && !slot_is_piv;           // row k0 + lane must move away
+        const bool vacancy = has && (pr >= kd0 + nb);          // position pr frees up
+        const uint64_t bd = __ballot(displaced), bv = __ballot(vacancy);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        // the i-th displaced row (in lane order) takes the i-th vacancy (in lane order)
+        if (displaced) {
+            int rd = __popcll(bd & below);
+            uint64_t rest = bv;
+            int q = 0;
+            for (int b = 0; b < 64; b++) {
+                if ((rest >> b) & 1ull) {
+                    if (rd == 0) {
+                        q = b;
+                        break;
+                    }
+                    rd--;
+                }
+            }
+            const int p = piv_row[q];
+            lmap[p - kd0] = kd0 + lane;
+            dstm[lane] = p;
         }
     }
     __syncthreads();
@@ -396,16 +416,38 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     }
 }
 
+// One launch per panel round for all fronts of a level: each block runs the
+// register panel specialised for its front's class.
+template <typename T>
+__global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0, double u, int want_prec) {
+    extern __shared__ int dyn[];  // lmap[P] | dst[P] (row positions relative to k)
+    const int s = slot0 + blockIdx.x;
+    const int prec = fn[s].prec;
+    if (prec != want_prec) return;
+    switch (front_class(fn[s].m)) {
+        case 0: panel_front<T, 32, 1>(fn, s, u, dyn); break;
+        case 1: panel_front<T, 32, 2>(fn, s, u, dyn); break;
+        case 2:
+            if constexpr (sizeof(T) == 8) panel_front<T, 16, 4>(fn, s, u, dyn);
+            else panel_front<T, 32, 4>(fn, s, u, dyn);
+            break;
+        default:
+            if constexpr (sizeof(T) == 8) panel_front<T, 8, 8>(fn, s, u, dyn);
+            else panel_front<T, 16, 8>(fn, s, u, dyn);
+            break;
+    }
+}
+
 // Commit the last panel's column permutation on every row: window column c of
 // the panel moves to col_dst[c] (rows >= k0 from the panel scratch, rows < k0
 // from the old column), and each displaced untried column moves whole from
 // mv_src to mv_dst.  Each thread owns one row and reads all its sources before
 // writing, so no two threads touch the same entry.  Block (x: 256 rows, y: front).
 template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, int want_prec, int cls) {
+__global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, int want_prec) {
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec || front_class(d.m) != cls) return;
+    if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= m) return;
@@ -432,11 +474,11 @@ __global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, in
 // ahead of it (>= k, outside the just-delayed block) also form the new U rows
 // with the unit-lower L11 of the panel.  Block (x: 64-column tile, y: front).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec, int cls) {
+__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec) {
     __shared__ T L11[kNBMax * kNBMax];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec || front_class(d.m) != cls) return;
+    if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
     const int kd0 = d.k0, kd1 = d.k, nb = kd1 - kd0;
     if (nb <= 0) return;
@@ -509,7 +551,7 @@ struct Mfma<float> {
 // Block (x: column tile, y: row tile, z: front).  4 waves, each a 32x32 quarter
 // made of 2x2 MFMA 16x16 blocks; K staged through LDS in chunks of 32.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec, int cls) {
+__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec) {
     // A and B chunks, then (aliased) the C tile for the transposed epilogue
     __shared__ T smem_ab[2 * kKC * kLdsPad];
     static_assert(2 * kKC * kLdsPad >= kTile * kLdsPad, "C tile must fit in the A/B buffer");
@@ -518,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     T* Cs = smem_ab;
     const int s = slot0 + blockIdx.z;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec || (cls >= 0 && front_class(d.m) != cls)) return;
+    if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
     int rlo, clo, ka, kb;
     if (mode == 0) {
@@ -595,6 +637,83 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     }
 }
 
+// BF16 variant of the deferred Schur update (mode 1) for FP32 fronts:
+// C[P:m, P:m] -= bf16(L21) * bf16(U12), FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  Operand layout (measured on gfx950): lane l holds
+// A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. +7][l%16]; result register r of
+// lane l is D[4(l/16) + r][l%16].  LDS keeps A as [row][k] and B as [col][k] so a
+// lane's 8 operands are one 16-byte read.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kKB = 32;          // K per MFMA
+constexpr int kKBPad = kKB + 8;  // row pitch in LDS (bf16 elements)
+
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[kTile * kKBPad];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kTile * kKBPad];
+    __shared__ float Cs[kTile * kLdsPad];
+    const int s = slot0 + blockIdx.z;
+    const FrontNum d = fn[s];
+    if (d.prec != 1) return;
+    const int m = d.m, P = d.P, kb = d.k;
+    if (kb <= 0) return;
+    const int col0 = P + blockIdx.x * kTile;
+    const int row0 = P + blockIdx.y * kTile;
+    if (col0 >= m || row0 >= m) return;
+    const float* F = (const float*)d.F;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wi = wid & 1, wj = wid >> 1;
+    flt4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = flt4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < kb; k0 += kKB) {
+        const int kc = min(kKB, kb - k0);
+        for (int idx = tid; idx < kKB * kTile; idx += kThreads) {
+            const int r = idx % kTile, a = idx / kTile;
+            const int row = row0 + r;
+            As[r * kKBPad + a] = (__bf16)((a < kc && row < m) ? F[row + (int64_t)(k0 + a) * m] : 0.0f);
+        }
+        for (int idx = tid; idx < kKB * kTile; idx += kThreads) {
+            const int a = idx % kKB, c = idx / kKB;
+            const int col = col0 + c;
+            Bs[c * kKBPad + a] = (__bf16)((a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : 0.0f);
+        }
+        __syncthreads();
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; bi++)
+            av[bi] = *(const bf16x8*)&As[(wi * 32 + bi * 16 + (lane & 15)) * kKBPad + 8 * (lane >> 4)];
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++)
+            bv[bj] = *(const bf16x8*)&Bs[(wj * 32 + bj * 16 + (lane & 15)) * kKBPad + 8 * (lane >> 4)];
+#pragma unroll
+        for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+            for (int bj = 0; bj < 2; bj++)
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = wi * 32 + bi * 16 + 4 * (lane >> 4) + r;
+                const int j = wj * 32 + bj * 16 + (lane & 15);
+                Cs[j * kLdsPad + i] = acc[bi][bj][r];
+            }
+    __syncthreads();
+    float* Fw = (float*)d.F;
+    for (int idx = tid; idx < kTile * kTile; idx += kThreads) {
+        const int i = idx % kTile, j = idx / kTile;
+        const int row = row0 + i, col = col0 + j;
+        if (row >= m || col >= m) continue;
+        Fw[row + (int64_t)col * m] -= Cs[j * kLdsPad + i];
+    }
+}
+
 // Post-factorization bookkeeping: column variables in final order.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, int slot0, int want_prec) {
@@ -640,11 +759,12 @@ __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, i
 // and the block of `vec` holds [y; c].  Backward sweep (root to leaves):
 //   t = y - U12 x[colvar[k:m]]     (k_bwd_gemv)
 //   x[colvar[0:k]] = U11^{-1} t    (k_bwd_tri)
-constexpr int kBS = 16;       // diagonal block of the triangular sweeps
+constexpr int kBS = 64;       // diagonal block of the triangular sweeps (one lane per row)
+constexpr int kTriThreads = 512;
 constexpr int kGemvRows = 256;
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
+__global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
                                                       int nrc) {
     extern __shared__ double zs[];
@@ -658,7 +778,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const FrontNum* 
     double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int cb = S.child_ptr[s], ce = S.child_ptr[s + 1];
-    for (int i = tid; i < m; i += kThreads) {
+    for (int i = tid; i < m; i += kTriThreads) {
         const int src = i < P ? rowperm[i] : i;
         for (int c = 0; c < nrc; c++)
             zs[i + c * m] = (src < d.npiv) ? b[rows[src] + (int64_t)(c0 + c) * ldb] : 0.0;
@@ -694,18 +814,25 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const FrontNum* 
             }
         }
         __syncthreads();
-        for (int i = j0 + bs + tid; i < k; i += kThreads) {
+        for (int i = j0 + bs + tid; i < k; i += kTriThreads) {
+            const T* Fi = F + i + (int64_t)j0 * m;
             for (int c = 0; c < nrc; c++) {
-                double acc = zs[i + c * m];
-#pragma unroll
-                for (int a = 0; a < kBS; a++)
-                    if (a < bs) acc -= (double)F[i + (int64_t)(j0 + a) * m] * zs[j0 + a + c * m];
-                zs[i + c * m] = acc;
+                const double* zc = zs + j0 + c * m;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int a = 0;
+                for (; a + 4 <= bs; a += 4) {
+                    a0 += (double)Fi[(int64_t)a * m] * zc[a];
+                    a1 += (double)Fi[(int64_t)(a + 1) * m] * zc[a + 1];
+                    a2 += (double)Fi[(int64_t)(a + 2) * m] * zc[a + 2];
+                    a3 += (double)Fi[(int64_t)(a + 3) * m] * zc[a + 3];
+                }
+                for (; a < bs; a++) a0 += (double)Fi[(int64_t)a * m] * zc[a];
+                zs[i + c * m] -= (a0 + a1) + (a2 + a3);
             }
         }
         __syncthreads();
     }
-    for (int i = tid; i < m; i += kThreads)
+    for (int i = tid; i < m; i += kTriThreads)
         for (int c = 0; c < nrc; c++) v[i + (int64_t)(c0 + c) * m] = zs[i + c * m];
 }
 
@@ -781,7 +908,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
+__global__ __launch_bounds__(kTriThreads) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
                                                       int64_t ldx, const double* vec, int nrhs, int c0, int nrc) {
     extern __shared__ double ts[];
     const int s = slot0 + blockIdx.x;
@@ -792,7 +919,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_tri(const FrontNum* fn, int sl
     const int32_t* colvar = iv_colvar(d.iv, P, m);
     const double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    for (int i = tid; i < k; i += kThreads)
+    for (int i = tid; i < k; i += kTriThreads)
         for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
     __syncthreads();
     for (int j1 = k; j1 > 0; j1 -= kBS) {
@@ -816,18 +943,25 @@ __global__ __launch_bounds__(kThreads) void k_bwd_tri(const FrontNum* fn, int sl
             }
         }
         __syncthreads();
-        for (int i = tid; i < j0; i += kThreads) {
+        for (int i = tid; i < j0; i += kTriThreads) {
+            const T* Fi = F + i + (int64_t)j0 * m;
             for (int c = 0; c < nrc; c++) {
-                double acc = ts[i + c * k];
-#pragma unroll
-                for (int a = 0; a < kBS; a++)
-                    if (a < bs) acc -= (double)F[i + (int64_t)(j0 + a) * m] * ts[j0 + a + c * k];
-                ts[i + c * k] = acc;
+                const double* tc = ts + j0 + c * k;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int a = 0;
+                for (; a + 4 <= bs; a += 4) {
+                    a0 += (double)Fi[(int64_t)a * m] * tc[a];
+                    a1 += (double)Fi[(int64_t)(a + 1) * m] * tc[a + 1];
+                    a2 += (double)Fi[(int64_t)(a + 2) * m] * tc[a + 2];
+                    a3 += (double)Fi[(int64_t)(a + 3) * m] * tc[a + 3];
+                }
+                for (; a < bs; a++) a0 += (double)Fi[(int64_t)a * m] * tc[a];
+                ts[i + c * k] -= (a0 + a1) + (a2 + a3);
             }
         }
         __syncthreads();
     }
-    for (int i = tid; i < k; i += kThreads) {
+    for (int i = tid; i < k; i += kTriThreads) {
         const int var = colvar[i];
         if (var < 0) continue;
         for (int c = 0; c < nrc; c++) x[var + (int64_t)(c0 + c) * ldx] = ts[i + c * k];
@@ -1019,29 +1153,13 @@ hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
 
 // ------------------------------------------------------------------ launchers
 
-template <typename T, int NB, int RS>
-static void launch_panels(FrontNum* fn, int slot0, int count, int mmax, int Pmax, double u, int prec, int cls,
-                          hipStream_t st) {
-    const int npan = (Pmax + NB - 1) / NB;
-    const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
-    const int tiles = (mmax + kTile - 1) / kTile;
-    for (int t = 0; t < npan; t++) {
-        hipLaunchKernelGGL((k_panel<T, NB, RS>), dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec,
-                           cls);
-        hipLaunchKernelGGL((k_commit<T, NB>), dim3((mmax + kThreads - 1) / kThreads, count), dim3(kThreads), 0, st,
-                           fn, slot0, prec, cls);
-        hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tiles, count), dim3(kThreads), 0, st, fn, slot0, prec, cls);
-        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 0, prec, cls);
-    }
-}
-
 int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 
 // cls_mmax[4], cls_Pmax[4]: per panel class of this precision in the level (0 = none)
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
-                               hipStream_t st, hipEvent_t* ev) {
+                               hipStream_t st, hipEvent_t* ev, bool bf16_schur) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
@@ -1050,22 +1168,30 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
         hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                            st, S, fn, vals, u0, u1, prec);
     if (ev) (void)hipEventRecord(ev[0], st);
+    int rounds = 0, Pmax = 0;
     for (int c = 0; c < 4; c++) {
-        const int cm = cls_mmax[c], cp = cls_Pmax[c];
-        if (cm <= 0) continue;
-        if (c == 0) launch_panels<T, 32, 1>(fn, slot0, count, cm, cp, u, prec, 0, st);
-        else if (c == 1) launch_panels<T, 32, 2>(fn, slot0, count, cm, cp, u, prec, 1, st);
-        else if (c == 2) {
-            if constexpr (sizeof(T) == 8) launch_panels<T, 16, 4>(fn, slot0, count, cm, cp, u, prec, 2, st);
-            else launch_panels<T, 32, 4>(fn, slot0, count, cm, cp, u, prec, 2, st);
-        } else {
-            if constexpr (sizeof(T) == 8) launch_panels<T, 8, 8>(fn, slot0, count, cm, cp, u, prec, 3, st);
-            else launch_panels<T, 16, 8>(fn, slot0, count, cm, cp, u, prec, 3, st);
+        if (cls_mmax[c] <= 0) continue;
+        const int nbc = class_nb(c, prec);
+        rounds = std::max(rounds, (cls_Pmax[c] + nbc - 1) / nbc);
+        Pmax = std::max(Pmax, cls_Pmax[c]);
+    }
+    {
+        const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
+        const int tl = (mmax + kTile - 1) / kTile;
+        for (int t = 0; t < rounds; t++) {
+            hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+            hipLaunchKernelGGL((k_commit<T, kNBMax>), dim3((mmax + kThreads - 1) / kThreads, count), dim3(kThreads), 0,
+                               st, fn, slot0, prec);
+            hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tl, count), dim3(kThreads), 0, st, fn, slot0, prec);
+            hipLaunchKernelGGL(k_gemm<T>, dim3(tl, tl, count), dim3(kThreads), 0, st, fn, slot0, 0, prec);
         }
     }
     const int tiles = (mmax + kTile - 1) / kTile;
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 1, prec, -1);
+    if (bf16_schur && sizeof(T) == 4)
+        hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0);
+    else
+        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 1, prec);
     if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_finalize<T>, dim3(count), dim3(kThreads), 0, st, S, fn, slot0, prec);
     if (ev) (void)hipEventRecord(ev[3], st);
@@ -1073,15 +1199,17 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
 }
 
 template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
-                                                const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*);
+                                                const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*,
+                                                bool);
 template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
-                                               const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*);
+                                               const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*,
+                                               bool);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd_tri<T>, dim3(count), dim3(kThreads), sizeof(double) * (size_t)mmax * nrc, st, S, fn,
+    hipLaunchKernelGGL(k_fwd_tri<T>, dim3(count), dim3(kTriThreads), sizeof(double) * (size_t)mmax * nrc, st, S, fn,
                        slot0, prec, b, ldb, vec, nrhs, c0, nrc);
     hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
                        sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc);
@@ -1093,7 +1221,7 @@ hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, 
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
                        sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc);
-    hipLaunchKernelGGL(k_bwd_tri<T>, dim3(count), dim3(kThreads), sizeof(double) * (size_t)mmax * nrc, st, fn, slot0,
+    hipLaunchKernelGGL(k_bwd_tri<T>, dim3(count), dim3(kTriThreads), sizeof(double) * (size_t)mmax * nrc, st, fn, slot0,
                        prec, x, ldx, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
 }

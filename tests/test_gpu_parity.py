@@ -165,19 +165,22 @@ def test_empty_system(torch_cuda):
 MIXED_OMEGA = 1e-10
 
 
-@pytest.mark.parametrize("nx,ny,seed,nrhs", [(16, 8, 0, 1), (32, 16, 4, 3), (64, 32, 0, 1)])
-def test_mixed_fp32_gmres_ir(torch_cuda, nx, ny, seed, nrhs):
-    """FP32 non-root fronts (FP64 root) + FP64 GMRES-IR reach omega <= 1e-10."""
+@pytest.mark.parametrize("prec,nx,ny,seed,nrhs", [("fp32", 16, 8, 0, 1), ("fp32", 32, 16, 4, 3), ("fp32", 64, 32, 0, 1),
+                                                   ("bf16", 16, 8, 0, 1), ("bf16", 32, 16, 4, 2),
+                                                   ("bf16", 64, 32, 0, 1)])
+def test_mixed_gmres_ir(torch_cuda, prec, nx, ny, seed, nrhs):
+    """FP32 non-root fronts (Schur updates in FP32, or BF16 operands with FP32
+    accumulation), FP64 root, FP64 GMRES-IR: omega <= 1e-10."""
     s = build_2d(nx, ny, seed, nrhs=nrhs)
     B = s.b0
     X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B,
-                             prec="fp32", target_omega=MIXED_OMEGA)
+                             prec=prec, target_omega=MIXED_OMEGA, max_outer=20)
     Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
     A = s.to_scipy()
     for c in range(B.shape[0]):
         om = check.omega(A, X[c], B[c])
         rel = np.abs(X[c] - Xo[c]).max() / np.abs(Xo[c]).max()
-        print(f"fp32 {nx}x{ny} rhs {c}: omega={om:.2e} rel={rel:.2e} omega0={info.omega0:.2e} "
+        print(f"{prec} {nx}x{ny} rhs {c}: omega={om:.2e} rel={rel:.2e} omega0={info.omega0:.2e} "
               f"outer={info.outer_iters} inner={info.inner_iters}", flush=True)
         assert om <= MIXED_OMEGA
         assert rel <= 1e-6
