@@ -158,6 +158,9 @@ typedef struct {
     double schur_flops;         /* algorithmic flops of the Schur GEMMs: sum 2 (m-P)^2 k */
     int32_t schur_launches;     /* Schur GEMM launches timed */
     int32_t levels;             /* tree levels (one host synchronization each) */
+    double t_panel_kernel_ms;   /* the panel kernel alone (sum over its launches) */
+    double panel_flops;         /* nominal panel flops (no delays): per window pivot, scaling + rank-1 update */
+    int32_t panel_launches;     /* panel kernel launches timed */
 } mf_factor_info;
 
 mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);

@@ -52,7 +52,9 @@ class mf_factor_info(ctypes.Structure):
                 ("factor_flops", ctypes.c_double), ("actual_flops", ctypes.c_double),
                 ("factor_bytes", ctypes.c_int64), ("t_assemble_ms", ctypes.c_double),
                 ("t_panel_ms", ctypes.c_double), ("t_schur_ms", ctypes.c_double), ("t_finalize_ms", ctypes.c_double),
-                ("schur_flops", ctypes.c_double), ("schur_launches", ctypes.c_int32), ("levels", ctypes.c_int32)]
+                ("schur_flops", ctypes.c_double), ("schur_launches", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("t_panel_kernel_ms", ctypes.c_double), ("panel_flops", ctypes.c_double),
+                ("panel_launches", ctypes.c_int32)]
 
 
 class mf_solve_info(ctypes.Structure):

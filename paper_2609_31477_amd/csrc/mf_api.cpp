@@ -23,7 +23,7 @@ namespace mf {
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
-                               hipStream_t st, hipEvent_t* ev, bool bf16_schur);
+                               hipStream_t st, hipEvent_t* ev, bool bf16_schur, std::vector<hipEvent_t>* pev);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
@@ -321,6 +321,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
                     for (int k = 0; k < 5; k++) (void)hipEventDestroy(e[p][k]);
         }
     } evg{ev, prof};
+    std::vector<hipEvent_t> pev;  // (start, end) of every panel launch (profile mode)
     int64_t voff = 0;
     mf_factor_info info{};
     info.factor_flops = S.nominal_flops;
@@ -384,14 +385,15 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             if (prof) HIPX(hipEventRecord(ev[0][0], st));
             HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
                                              N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), N->d_vals,
-                                             u0, u1, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr, false));
+                                             u0, u1, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr, false,
+                                             prof ? &pev : nullptr));
         }
         if (N->lvl_cnt[1][L]) {
             if (prof) HIPX(hipEventRecord(ev[1][0], st));
             HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
                                             N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), N->d_vals,
                                             u0, u1, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr,
-                                            o.prec == MF_BF16));
+                                            o.prec == MF_BF16, prof ? &pev : nullptr));
         }
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));
@@ -407,6 +409,30 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
                 info.t_finalize_ms += ms[3];
                 info.schur_launches++;
             }
+        if (prof) {
+            for (size_t q = 0; q + 1 < pev.size(); q += 2) {
+                float ms = 0.f;
+                HIPX(hipEventElapsedTime(&ms, pev[q], pev[q + 1]));
+                info.t_panel_kernel_ms += ms;
+                info.panel_launches++;
+            }
+            for (hipEvent_t e : pev) (void)hipEventDestroy(e);
+            pev.clear();
+            // nominal panel work of this level (windows of the front's class width, no delays):
+            // for each pivot of a window, scale the column below it and update the rest of the window
+            for (int sl = s0; sl < s1; sl++) {
+                const FrontNum& fr = hf[sl];
+                const int cls = fr.m <= 512 ? 0 : (fr.m <= 1024 ? 1 : (fr.m <= 2048 ? 2 : 3));
+                const int nbp = cls <= 1 ? 32 : (cls == 2 ? (fr.prec ? 32 : 16) : (fr.prec ? 16 : 8));
+                for (int k0 = 0; k0 < fr.P; k0 += nbp) {
+                    const int w = std::min(nbp, fr.P - k0);
+                    for (int t = 0; t < w; t++) {
+                        const double rows = (double)(fr.m - k0 - t - 1);
+                        info.panel_flops += rows + 2.0 * rows * (double)(w - t - 1);
+                    }
+                }
+            }
+        }
         for (int sl = s0; sl < s1; sl++) {
             const FrontNum& fr = hf[sl];
             dout[sl] = fr.P - fr.k;

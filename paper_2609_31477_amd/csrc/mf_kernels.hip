@@ -18,6 +18,7 @@
 #include <climits>
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "mf_device.h"
 
@@ -1159,7 +1160,7 @@ int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
-                               hipStream_t st, hipEvent_t* ev, bool bf16_schur) {
+                               hipStream_t st, hipEvent_t* ev, bool bf16_schur, std::vector<hipEvent_t>* pev) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
@@ -1179,7 +1180,14 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
         const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
         const int tl = (mmax + kTile - 1) / kTile;
         for (int t = 0; t < rounds; t++) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (pev && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+                (void)hipEventRecord(e0, st);
+                pev->push_back(e0);
+                pev->push_back(e1);
+            }
             hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+            if (e1) (void)hipEventRecord(e1, st);
             hipLaunchKernelGGL((k_commit<T, kNBMax>), dim3((mmax + kThreads - 1) / kThreads, count), dim3(kThreads), 0,
                                st, fn, slot0, prec);
             hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tl, count), dim3(kThreads), 0, st, fn, slot0, prec);
@@ -1200,10 +1208,10 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
 
 template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
                                                 const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*,
-                                                bool);
+                                                bool, std::vector<hipEvent_t>*);
 template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
                                                const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*,
-                                               bool);
+                                               bool, std::vector<hipEvent_t>*);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
