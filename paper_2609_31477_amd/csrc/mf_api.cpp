@@ -376,7 +376,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         for (int sl = s0; sl < s1; sl++) {
             FrontNum& fr = hf[sl];
             const int nbp = panel_nb(fr.prec, fr.m);
-            fr.W = N->wsp.alloc((size_t)fr.m * nbp * (fr.prec ? 4 : 8));
+            fr.W = N->wsp.alloc((size_t)2 * fr.m * nbp * (fr.prec ? 4 : 8));
         }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
@@ -423,7 +423,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             for (int sl = s0; sl < s1; sl++) {
                 const FrontNum& fr = hf[sl];
                 const int cls = fr.m <= 512 ? 0 : (fr.m <= 1024 ? 1 : (fr.m <= 2048 ? 2 : 3));
-                const int nbp = cls <= 1 ? 32 : (cls == 2 ? (fr.prec ? 32 : 16) : (fr.prec ? 16 : 8));
+                const int nbp = panel_nb(fr.prec, fr.m);
                 for (int k0 = 0; k0 < fr.P; k0 += nbp) {
                     const int w = std::min(nbp, fr.P - k0);
                     for (int t = 0; t < w; t++) {

@@ -8,7 +8,7 @@
 namespace mf {
 
 // Panel width upper bound (options.panel_nb is clamped to it).
-constexpr int kNBMax = 64;
+constexpr int kNBMax = 32;
 
 // Per-front numeric state, indexed by "slot" (fronts in level order, so the
 // fronts of one tree level are contiguous).  Written by the host before a level

@@ -151,11 +151,11 @@ constexpr int kPanelThreads = 512;
 // NB and rows per thread RS are per front (never per launch), so a front's
 // arithmetic does not depend on the other fronts it is batched with.
 //   class 0: m <= 512  (NB 32, RS 1)     class 1: m <= 1024 (NB 32, RS 2)
-//   class 2: m <= 2048 (FP64 NB 16, FP32 NB 32; RS 4)
+//   class 2: m <= 2048 (FP64 NB 24, FP32 NB 32; RS 4)
 //   class 3: m <= 4096 (FP64 NB 8, FP32 NB 16; RS 8)
 __host__ __device__ inline int front_class(int m) { return m <= 512 ? 0 : (m <= 1024 ? 1 : (m <= 2048 ? 2 : 3)); }
 __host__ __device__ inline int class_nb(int cls, int prec) {
-    return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 16) : (prec ? 16 : 8));
+    return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 24) : (prec ? 16 : 8));
 }
 
 template <typename T, int NB>
@@ -179,10 +179,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     const int kd0 = d.k, pc = d.pcur;
     if (kd0 >= pc) {
         // nothing left to try: mark an empty round so the trailing updates skip it
-        if (threadIdx.x == 0) {
-            fn[s].k0 = kd0;
-            iv_commit(d.iv, P, m)[0] = 0;
-        }
+        if (threadIdx.x == 0) fn[s].k0 = kd0;
         return;
     }
     const int w = min(NB, pc - kd0);
@@ -364,10 +361,29 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         rtag[q] = (i < P) ? rowperm[lmap[i - kd0]] : 0;
     }
     __syncthreads();
-    // window rows [k0, m) in final row order go to the front's panel scratch; the
-    // column permutation of all rows is committed by k_commit
+    // commit the column permutation on every row, inside this block:
+    //   scratch = [ old rows [0, k0) of the w window columns | whole displaced columns ]
+    // then window columns go to col_dst (rows < k0 from scratch, rows >= k0 from
+    // registers in final row order) and displaced columns to mv_dst
     T* Wp = (T*)d.W;
-    const int R = m - kd0;
+    T* Wm = Wp + (int64_t)kd0 * w;
+    for (int64_t q = tid; q < (int64_t)kd0 * w; q += kPanelThreads) {
+        const int c = (int)(q / kd0), i = (int)(q % kd0);
+        Wp[q] = F[i + (int64_t)(kd0 + c) * m];
+    }
+    for (int64_t q = tid; q < (int64_t)m * nmove; q += kPanelThreads) {
+        const int t = (int)(q / m), i = (int)(q % m);
+        Wm[q] = F[i + (int64_t)mv_src[t] * m];
+    }
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)kd0 * w; q += kPanelThreads) {
+        const int c = (int)(q / kd0), i = (int)(q % kd0);
+        F[i + (int64_t)col_dst[c] * m] = Wp[q];
+    }
+    for (int64_t q = tid; q < (int64_t)m * nmove; q += kPanelThreads) {
+        const int t = (int)(q / m), i = (int)(q % m);
+        F[i + (int64_t)mv_dst[t] * m] = Wm[q];
+    }
 #pragma unroll
     for (int r = 0; r < RS; r++) {
         const int row = kd0 + tid + kPanelThreads * r;
@@ -375,17 +391,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         const int drow = row < P ? dstm[row - kd0] : row;
 #pragma unroll
         for (int c = 0; c < NB; c++)
-            if (c < w) Wp[(drow - kd0) + (int64_t)c * R] = v[r][c];
-    }
-    int32_t* cm = iv_commit(d.iv, P, m);
-    if (tid == 0) {
-        cm[0] = w;
-        cm[1] = nmove;
-    }
-    if (tid < w) cm[2 + tid] = col_dst[tid];
-    if (tid < nmove) {
-        cm[2 + kNBMax + tid] = mv_src[tid];
-        cm[2 + 2 * kNBMax + tid] = mv_dst[tid];
+            if (c < w) F[drow + (int64_t)col_dst[c] * m] = v[r][c];
     }
     if (tid < w) colperm[col_dst[tid]] = old_tag[tid];
     if (tid < nmove) colperm[mv_dst[tid]] = mv_tag[tid];
@@ -429,7 +435,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
         case 0: panel_front<T, 32, 1>(fn, s, u, dyn); break;
         case 1: panel_front<T, 32, 2>(fn, s, u, dyn); break;
         case 2:
-            if constexpr (sizeof(T) == 8) panel_front<T, 16, 4>(fn, s, u, dyn);
+            if constexpr (sizeof(T) == 8) panel_front<T, 24, 4>(fn, s, u, dyn);
             else panel_front<T, 32, 4>(fn, s, u, dyn);
             break;
         default:
@@ -439,85 +445,67 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     }
 }
 
-// Commit the last panel's column permutation on every row: window column c of
-// the panel moves to col_dst[c] (rows >= k0 from the panel scratch, rows < k0
-// from the old column), and each displaced untried column moves whole from
-// mv_src to mv_dst.  Each thread owns one row and reads all its sources before
-// writing, so no two threads touch the same entry.  Block (x: 256 rows, y: front).
-template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void k_commit(FrontNum* fn, int slot0, int want_prec) {
-    const int s = slot0 + blockIdx.y;
-    const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
-    const int m = d.m, P = d.P;
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= m) return;
-    const int32_t* cm = iv_commit(d.iv, P, m);
-    const int w = cm[0], nmove = cm[1];
-    if (w <= 0) return;
-    const int kd0 = d.k0, R = m - kd0;
-    T* F = (T*)d.F;
-    const T* Wp = (const T*)d.W;
-    T val[NB], mval[NB];
-#pragma unroll
-    for (int c = 0; c < NB; c++) {
-        if (c < w) val[c] = i >= kd0 ? Wp[(i - kd0) + (int64_t)c * R] : F[i + (int64_t)(kd0 + c) * m];
-        if (c < nmove) mval[c] = F[i + (int64_t)cm[2 + kNBMax + c] * m];
-    }
-#pragma unroll
-    for (int c = 0; c < NB; c++) {
-        if (c < nmove) F[i + (int64_t)cm[2 + 2 * kNBMax + c] * m] = mval[c];
-        if (c < w) F[i + (int64_t)cm[2 + c] * m] = val[c];
-    }
-}
-
 // Columns outside the last panel's window: apply its row swaps; for columns
 // ahead of it (>= k, outside the just-delayed block) also form the new U rows
-// with the unit-lower L11 of the panel.  Block (x: 64-column tile, y: front).
+// with the unit-lower L11 of the panel.  Block (x: kSwapCols-column tile, y: front).
+constexpr int kSwapCols = 64;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec) {
     __shared__ T L11[kNBMax * kNBMax];
+    __shared__ int pd[2 * kNBMax], ps[2 * kNBMax];
+    __shared__ T stage[2 * kNBMax * 64];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
     const int kd0 = d.k0, kd1 = d.k, nb = kd1 - kd0;
     if (nb <= 0) return;
-    const int c0 = blockIdx.x * kTile;
+    const int c0 = blockIdx.x * kSwapCols;
     if (c0 >= m) return;
     T* F = (T*)d.F;
     const int32_t* pairs = iv_pairs(d.iv, P, m);
     const int np = pairs[0];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x;
     for (int idx = tid; idx < nb * nb; idx += kThreads) {
         const int a = idx % nb, b = idx / nb;
         L11[a + b * kNBMax] = F[(kd0 + a) + (int64_t)(kd0 + b) * m];
     }
-    const int d0 = lane < np ? pairs[1 + 2 * lane] : 0, s0 = lane < np ? pairs[2 + 2 * lane] : 0;
-    const int d1 = lane + 64 < np ? pairs[1 + 2 * (lane + 64)] : 0,
-              s1 = lane + 64 < np ? pairs[2 + 2 * (lane + 64)] : 0;
-    for (int cc = wid; cc < kTile; cc += kThreads / 64) {
-        const int j = c0 + cc;
-        if (j >= m) break;
-        if ((j >= kd0 && j < kd1) || (j >= d.x0 && j < d.x1)) continue;
-        T* colp = F + (int64_t)j * m;
-        const T v0 = lane < np ? colp[s0] : T(0);
-        const T v1 = lane + 64 < np ? colp[s1] : T(0);
-        if (lane < np) colp[d0] = v0;
-        if (lane + 64 < np) colp[d1] = v1;
+    for (int q = tid; q < np; q += kThreads) {
+        pd[q] = pairs[1 + 2 * q];
+        ps[q] = pairs[2 + 2 * q];
     }
     __syncthreads();
-    for (int cc = wid; cc < kTile; cc += kThreads / 64) {
-        const int j = c0 + cc;
-        if (j >= m) break;
-        if (j < kd1 || (j >= d.x0 && j < d.x1)) continue;
+    // row swaps of the panel, 64 columns at a time staged through LDS: every source
+    // of a column is read before any destination is written
+    for (int cc = c0; cc < min(c0 + kSwapCols, m); cc += 64) {
+        const int jl = cc + (tid & 63);
+        const bool live = jl < m && !(jl >= kd0 && jl < kd1) && !(jl >= d.x0 && jl < d.x1);
+        T* cp = F + (int64_t)jl * m;
+        for (int q = tid >> 6; q < np; q += kThreads / 64)
+            if (live) stage[q * 64 + (tid & 63)] = cp[ps[q]];
+        __syncthreads();
+        for (int q = tid >> 6; q < np; q += kThreads / 64)
+            if (live) cp[pd[q]] = stage[q * 64 + (tid & 63)];
+        __syncthreads();
+    }
+    // new U rows: unit-lower solve with L11, half a wave per column (lane = row of
+    // the panel), the pivot row's value broadcast with readlane at each step
+    const int lane = tid & 63, half = lane >> 5, r = lane & 31;
+    for (int jj = c0 + 2 * (tid >> 6); jj < min(c0 + kSwapCols, m); jj += 2 * (kThreads / 64)) {
+        const int j = jj + half;
+        const bool live = j < m && j >= kd1 && !(j >= d.x0 && j < d.x1);
         T* colp = F + (int64_t)j * m + kd0;
-        double x = lane < nb ? (double)colp[lane] : 0.0;
+        double x = (live && r < nb) ? (double)colp[r] : 0.0;
         for (int a = 0; a < nb - 1; a++) {
-            const double xa = __shfl(x, a);
-            if (lane > a && lane < nb) x -= (double)L11[lane + a * kNBMax] * xa;
+            const long long xb = __double_as_longlong(x);
+            const int lo0 = __builtin_amdgcn_readlane((int)xb, a), hi0 = __builtin_amdgcn_readlane((int)(xb >> 32), a);
+            const int lo1 = __builtin_amdgcn_readlane((int)xb, 32 + a),
+                      hi1 = __builtin_amdgcn_readlane((int)(xb >> 32), 32 + a);
+            const int lo = half ? lo1 : lo0, hi = half ? hi1 : hi0;
+            const double xa = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+            if (r > a) x -= (double)L11[r + a * kNBMax] * xa;
         }
-        if (lane < nb) colp[lane] = (T)x;
+        if (live && r < nb) colp[r] = (T)x;
     }
 }
 
@@ -1188,9 +1176,8 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
             }
             hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
             if (e1) (void)hipEventRecord(e1, st);
-            hipLaunchKernelGGL((k_commit<T, kNBMax>), dim3((mmax + kThreads - 1) / kThreads, count), dim3(kThreads), 0,
-                               st, fn, slot0, prec);
-            hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tl, count), dim3(kThreads), 0, st, fn, slot0, prec);
+            hipLaunchKernelGGL(k_swap_trsm<T>, dim3((mmax + kSwapCols - 1) / kSwapCols, count), dim3(kThreads), 0, st, fn,
+                               slot0, prec);
             hipLaunchKernelGGL(k_gemm<T>, dim3(tl, tl, count), dim3(kThreads), 0, st, fn, slot0, 0, prec);
         }
     }
