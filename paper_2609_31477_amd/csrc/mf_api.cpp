@@ -23,7 +23,8 @@ namespace mf {
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
-                               hipStream_t st, hipEvent_t* ev, bool bf16_schur, std::vector<hipEvent_t>* pev);
+                               const LevelTasks& tk, hipStream_t st, hipEvent_t* ev, bool bf16_schur,
+                               std::vector<hipEvent_t>* pev);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
@@ -176,6 +177,10 @@ struct mf_num {
     bool factored = false;
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
     std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
+    int32_t* d_tasks = nullptr;  // per-level tile work lists (LevelTasks)
+    int32_t* h_tasks = nullptr;  // pinned staging
+    size_t tasks_cap = 0;        // entries
+    std::vector<int32_t> task_scratch;
     mf_factor_info info{};
     ~mf_num() {
         fronts.release();
@@ -194,6 +199,8 @@ struct mf_num {
         if (d_active) (void)hipFree(d_active);
         if (d_cat) (void)hipFree(d_cat);
         if (h_active) (void)hipHostFree(h_active);
+        if (d_tasks) (void)hipFree(d_tasks);
+        if (h_tasks) (void)hipHostFree(h_tasks);
     }
 };
 
@@ -266,6 +273,53 @@ void ensure_device_symbolic(mf_sym* h) {
 }
 
 int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 || is_root) ? 0 : 1; }
+
+// Tile work lists of one level (entries as in LevelTasks), uploaded once per level
+// and shared by both precisions (each kernel skips fronts of the other one).  The
+// previous level has been synchronized, so the pinned staging can be reused.
+LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st) {
+    std::vector<int32_t>& t = N->task_scratch;
+    t.clear();
+    for (int i = 0; i < count; i++) {
+        const int T = (hf[i].m + 63) / 64;
+        for (int a = 0; a < T; a++) t.push_back(task_code(i, 0, a));
+    }
+    const size_t nswap = t.size();
+    for (int i = 0; i < count; i++) {
+        const int m = hf[i].m, P = hf[i].P, T = (m + 63) / 64;
+        for (int a = 0; a < T; a++)
+            for (int b = 0; b < T; b++)
+                if (!(a * 64 >= P && b * 64 >= P)) t.push_back(task_code(i, a, b));
+    }
+    const size_t ng0 = t.size() - nswap;
+    for (int i = 0; i < count; i++) {
+        const int T = (hf[i].m - hf[i].P + 63) / 64;
+        for (int a = 0; a < T; a++)
+            for (int b = 0; b < T; b++) t.push_back(task_code(i, a, b));
+    }
+    const size_t ng1 = t.size() - nswap - ng0;
+    if (t.size() > N->tasks_cap) {
+        if (N->d_tasks) HIPX(hipFree(N->d_tasks));
+        if (N->h_tasks) HIPX(hipHostFree(N->h_tasks));
+        N->d_tasks = nullptr;
+        N->h_tasks = nullptr;
+        N->tasks_cap = 0;
+        const size_t cap = t.size() + t.size() / 2 + 1024;
+        HIPX(hipMalloc((void**)&N->d_tasks, sizeof(int32_t) * cap));
+        HIPX(hipHostMalloc((void**)&N->h_tasks, sizeof(int32_t) * cap, hipHostMallocDefault));
+        N->tasks_cap = cap;
+    }
+    std::copy(t.begin(), t.end(), N->h_tasks);
+    if (!t.empty()) HIPX(hipMemcpyAsync(N->d_tasks, N->h_tasks, sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, st));
+    LevelTasks tk;
+    tk.swap = N->d_tasks;
+    tk.nswap = (int32_t)nswap;
+    tk.g0 = N->d_tasks + nswap;
+    tk.ng0 = (int32_t)ng0;
+    tk.g1 = N->d_tasks + nswap + ng0;
+    tk.ng1 = (int32_t)ng1;
+    return tk;
+}
 
 void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double* const* seg_values = nullptr) {
     mf_sym* H = N->sym;
@@ -379,20 +433,21 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             fr.W = N->wsp.alloc((size_t)2 * fr.m * nbp * (fr.prec ? 4 : 8));
         }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
+        const LevelTasks tk = upload_level_tasks(N, hf + s0, s1 - s0, st);
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
         // fronts of both precisions may share a level; each kernel skips the other kind
         if (N->lvl_cnt[0][L]) {
             if (prof) HIPX(hipEventRecord(ev[0][0], st));
             HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
                                              N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), N->d_vals,
-                                             u0, u1, o.pivot_u, 0, st, prof ? &ev[0][1] : nullptr, false,
+                                             u0, u1, o.pivot_u, 0, tk, st, prof ? &ev[0][1] : nullptr, false,
                                              prof ? &pev : nullptr));
         }
         if (N->lvl_cnt[1][L]) {
             if (prof) HIPX(hipEventRecord(ev[1][0], st));
             HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
                                             N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), N->d_vals,
-                                            u0, u1, o.pivot_u, 1, st, prof ? &ev[1][1] : nullptr,
+                                            u0, u1, o.pivot_u, 1, tk, st, prof ? &ev[1][1] : nullptr,
                                             o.prec == MF_BF16, prof ? &pev : nullptr));
         }
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));

@@ -31,6 +31,20 @@ struct FrontNum {
     void* W;         // panel scratch: rows [k0, m) of the last window, final row order (ld m - k0)
 };
 
+// Per-level work lists of the tiled factorization kernels, built on the host
+// once a level's front orders are known (one block per entry, no idle blocks for
+// the small fronts of a level).  Entry = (slot - first slot of the level) << 12 |
+// tile_a << 6 | tile_b, tiles of 64 (front orders are at most 4096).
+struct LevelTasks {
+    const int32_t* swap;  // (front, column tile) over [0, m)
+    int32_t nswap;
+    const int32_t* g0;    // (front, row tile, column tile) over [0, m)^2 minus the block >= P x >= P
+    int32_t ng0;
+    const int32_t* g1;    // (front, row tile, column tile) over the contribution block [P, m)^2
+    int32_t ng1;
+};
+__host__ __device__ inline int32_t task_code(int rel, int a, int b) { return (rel << 12) | (a << 6) | b; }
+
 // Pattern data (slot-indexed), uploaded once per symbolic handle.
 struct DevSym {
     int32_t nslots;

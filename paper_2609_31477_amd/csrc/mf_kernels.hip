@@ -138,8 +138,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(DevSym S, FrontNum* fn, co
 // accepted when its largest entry among the remaining fully summed rows is at
 // least u times its largest entry among all remaining rows (threshold partial
 // pivoting); otherwise it is delayed and keeps receiving the panel's updates.
-// Rows [k, m) of the window live in registers (RS rows per thread, 512
-// threads), so a column step costs two barriers and no global traffic.  At the
+// Rows [k, m) of the window live in registers (RS rows per thread, TH threads:
+// 512, or 256 on levels whose fronts are all small), so a column step costs two
+// barriers, a DPP wave reduction and no global traffic.  At the
 // end, accepted columns go to [k, k + nb), delayed ones to the tail of the
 // untried range, and the untried columns they displace move into the freed
 // window slots; rows are permuted by the LAPACK-style swap sequence, which is
@@ -158,19 +159,64 @@ __host__ __device__ inline int class_nb(int cls, int prec) {
     return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 24) : (prec ? 16 : 8));
 }
 
-template <typename T, int NB>
-__device__ __forceinline__ T pick(const T (&v)[NB], int c) {
-    T x = v[0];
+// Candidate of a column step: largest magnitude over all remaining rows (aall),
+// largest over the remaining fully summed rows (afs) and its row (ifs, lowest
+// row among equal magnitudes).
+struct PivCand {
+    double aall, afs;
+    int ifs;
+};
+__device__ __forceinline__ void cand_merge(PivCand& a, double oa, double of, int oi) {
+    a.aall = fmax(a.aall, oa);
+    if (of > a.afs || (of == a.afs && oi < a.ifs)) {
+        a.afs = of;
+        a.ifs = oi;
+    }
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ void cand_dpp_step(PivCand& a) {
+    cand_merge(a, dpp_d<CTRL>(a.aall), dpp_d<CTRL>(a.afs), dpp_i<CTRL>(a.ifs));
+}
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Wave-wide candidate: within each quad (DPP quad permutations), across the
+// quads of a 16-lane row (row rotations by 4 and 8), then across the four rows
+// (readlane); the result is uniform over the wave.  Merging is commutative and
+// associative, so every lane ends with the same candidate.
+__device__ __forceinline__ PivCand cand_wave(PivCand a) {
+    cand_dpp_step<0xB1>(a);   // quad_perm [1,0,3,2]
+    cand_dpp_step<0x4E>(a);   // quad_perm [2,3,0,1]
+    cand_dpp_step<0x124>(a);  // row_ror:4
+    cand_dpp_step<0x128>(a);  // row_ror:8
+    PivCand r;
+    r.aall = readlane_d(a.aall, 0);
+    r.afs = readlane_d(a.afs, 0);
+    r.ifs = __builtin_amdgcn_readlane(a.ifs, 0);
 #pragma unroll
-    for (int j = 1; j < NB; j++) x = (c == j) ? v[j] : x;
-    return x;
+    for (int q = 1; q < 4; q++)
+        cand_merge(r, readlane_d(a.aall, 16 * q), readlane_d(a.afs, 16 * q), __builtin_amdgcn_readlane(a.ifs, 16 * q));
+    return r;
 }
 
-template <typename T, int NB, int RS>
+template <typename T, int NB, int RS, int TH>
 __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* dyn) {
     __shared__ T urow[NB];
-    __shared__ double red_a[kPanelThreads / 64], red_f[kPanelThreads / 64];
-    __shared__ int red_i[kPanelThreads / 64];
+    constexpr int kWaves = TH / 64;
+    __shared__ double red_a[kWaves], red_f[kWaves];
+    __shared__ int red_i[kWaves];
     __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB];
     __shared__ int mv_src[NB], mv_dst[NB], mv_tag[NB];
     __shared__ int npairs_s;
@@ -192,68 +238,65 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     int pstep[RS];
 #pragma unroll
     for (int r = 0; r < RS; r++) {
-        const int row = kd0 + tid + kPanelThreads * r;
+        const int row = kd0 + tid + TH * r;
         pstep[r] = row < m ? -1 : -2;
 #pragma unroll
         for (int c = 0; c < NB; c++) v[r][c] = (row < m && c < w) ? F[row + (int64_t)(kd0 + c) * m] : T(0);
     }
     uint64_t elim = 0;
     int nb = 0;
-    // fully unrolled so that every register index below is a compile-time constant
-#pragma clang loop unroll(full)
+    // The window rotates through the registers: at step c, slot j of every row holds
+    // window column (c + j) mod NB, so the column being factored is always slot 0 and
+    // every register index is a compile-time constant while the step loop stays
+    // rolled (a fully unrolled loop would not fit the instruction cache).  After NB
+    // steps each column is back in its own slot.
+    const uint64_t wmask = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
+#pragma unroll 1
     for (int c = 0; c < NB; c++) {
         if (c < w) {
-            double aall = 0.0, afs = -1.0;
-            int ifs = INT_MAX;
-            T cv[RS];
-    #pragma unroll
+            PivCand cd{0.0, -1.0, INT_MAX};
+#pragma unroll
             for (int r = 0; r < RS; r++) {
-                cv[r] = pick<T, NB>(v[r], c);
                 if (pstep[r] == -1) {
-                    const double a = fabs((double)cv[r]);
-                    if (!(a <= aall)) aall = (a != a) ? INFINITY : a;
-                    const int row = kd0 + tid + kPanelThreads * r;
-                    if (row < P && a > afs) {
-                        afs = a;
-                        ifs = row;
+                    const double a = fabs((double)v[r][0]);
+                    if (!(a <= cd.aall)) cd.aall = (a != a) ? INFINITY : a;
+                    const int row = kd0 + tid + TH * r;
+                    if (row < P && a > cd.afs) {
+                        cd.afs = a;
+                        cd.ifs = row;
                     }
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                aall = fmax(aall, __shfl_xor(aall, off));
-                const double of = __shfl_xor(afs, off);
-                const int oi = __shfl_xor(ifs, off);
-                if (of > afs || (of == afs && oi < ifs)) {
-                    afs = of;
-                    ifs = oi;
-                }
-            }
+            cd = cand_wave(cd);
             if (lane == 0) {
-                red_a[wid] = aall;
-                red_f[wid] = afs;
-                red_i[wid] = ifs;
+                red_a[wid] = cd.aall;
+                red_f[wid] = cd.afs;
+                red_i[wid] = cd.ifs;
             }
             __syncthreads();
-            aall = red_a[0];
-            afs = red_f[0];
-            ifs = red_i[0];
-    #pragma unroll
-            for (int q = 1; q < kPanelThreads / 64; q++) {
-                aall = fmax(aall, red_a[q]);
-                if (red_f[q] > afs || (red_f[q] == afs && red_i[q] < ifs)) {
-                    afs = red_f[q];
-                    ifs = red_i[q];
-                }
+            // all wave candidates are read before any is merged (one LDS round trip)
+            double ra[kWaves], rf[kWaves];
+            int ri[kWaves];
+#pragma unroll
+            for (int q = 0; q < kWaves; q++) {
+                ra[q] = red_a[q];
+                rf[q] = red_f[q];
+                ri[q] = red_i[q];
             }
+            PivCand bc{ra[0], rf[0], ri[0]};
+#pragma unroll
+            for (int q = 1; q < kWaves; q++) cand_merge(bc, ra[q], rf[q], ri[q]);
+            const double aall = bc.aall, afs = bc.afs;
+            const int ifs = bc.ifs;
             const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
             if (accept) {
                 const int rel = ifs - kd0;
-                if ((rel % kPanelThreads) == tid) {
-                    const int rs = rel / kPanelThreads;
-    #pragma unroll
+                if ((rel % TH) == tid) {
+                    const int rs = rel / TH;
+#pragma unroll
                     for (int r = 0; r < RS; r++)
                         if (r == rs) {
-    #pragma unroll
+#pragma unroll
                             for (int j = 0; j < NB; j++) urow[j] = v[r][j];
                             pstep[r] = nb;
                         }
@@ -265,23 +308,40 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             }
             __syncthreads();
             if (accept) {
-                const T piv = urow[c];
-    #pragma unroll
+                // small windows read the pivot row into registers first (one LDS round
+                // trip); the widest ones have no registers to spare and read it in place
+                constexpr bool kPre = RS * NB <= 64;
+                T ur[kPre ? NB : 1];
+                if constexpr (kPre) {
+#pragma unroll
+                    for (int j = 0; j < NB; j++) ur[j] = urow[j];
+                }
+                const T piv = urow[0];
+                // window columns still to update, in slot order
+                const uint64_t um = wmask & ~elim;
+                const uint64_t rot = (c == 0) ? um : ((um >> c) | (um << (NB - c)));
+#pragma unroll
                 for (int r = 0; r < RS; r++) {
                     if (pstep[r] != -1) continue;
-                    const T l = cv[r] / piv;
-    #pragma unroll
-                    for (int j = 0; j < NB; j++) {
-                        if (j == c)
-                            v[r][j] = l;
-                        else if (j < w && !((elim >> j) & 1ull))
-                            v[r][j] -= l * urow[j];
-                    }
+                    const T l = v[r][0] / piv;
+                    v[r][0] = l;
+#pragma unroll
+                    for (int j = 1; j < NB; j++)
+                        if ((rot >> j) & 1ull) v[r][j] -= l * (kPre ? ur[kPre ? j : 0] : urow[j]);
                 }
                 elim |= 1ull << c;
                 nb++;
             }
-            __syncthreads();
+            // no third barrier: the next step writes red_* only after every wave has
+            // passed this step's second barrier (so all reads of red_* are done), and
+            // writes urow only after its first barrier (so all reads of urow are done)
+        }
+#pragma unroll
+        for (int r = 0; r < RS; r++) {
+            const T t0 = v[r][0];
+#pragma unroll
+            for (int j = 0; j + 1 < NB; j++) v[r][j] = v[r][j + 1];
+            v[r][NB - 1] = t0;
         }
     }
 
@@ -306,7 +366,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         }
         npairs_s = nm;  // reused below as the move count
     }
-    for (int i = kd0 + tid; i < P; i += kPanelThreads) {
+    for (int i = kd0 + tid; i < P; i += TH) {
         lmap[i - kd0] = i;   // position -> original row now there
         dstm[i - kd0] = i;   // original row -> its current position
     }
@@ -354,10 +414,10 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     int32_t* rowperm = iv_rowperm(d.iv, P, m);
     if (tid < w) old_tag[tid] = colperm[kd0 + tid];
     if (tid < nmove) mv_tag[tid] = colperm[mv_src[tid]];
-    int rtag[(4096 + kPanelThreads - 1) / kPanelThreads];
+    int rtag[RS];  // rows [k0, P) lie within the TH * RS register rows
 #pragma unroll
-    for (int q = 0; q < (4096 + kPanelThreads - 1) / kPanelThreads; q++) {
-        const int i = kd0 + tid + kPanelThreads * q;
+    for (int q = 0; q < RS; q++) {
+        const int i = kd0 + tid + TH * q;
         rtag[q] = (i < P) ? rowperm[lmap[i - kd0]] : 0;
     }
     __syncthreads();
@@ -367,26 +427,26 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // registers in final row order) and displaced columns to mv_dst
     T* Wp = (T*)d.W;
     T* Wm = Wp + (int64_t)kd0 * w;
-    for (int64_t q = tid; q < (int64_t)kd0 * w; q += kPanelThreads) {
+    for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
         const int c = (int)(q / kd0), i = (int)(q % kd0);
         Wp[q] = F[i + (int64_t)(kd0 + c) * m];
     }
-    for (int64_t q = tid; q < (int64_t)m * nmove; q += kPanelThreads) {
+    for (int64_t q = tid; q < (int64_t)m * nmove; q += TH) {
         const int t = (int)(q / m), i = (int)(q % m);
         Wm[q] = F[i + (int64_t)mv_src[t] * m];
     }
     __syncthreads();
-    for (int64_t q = tid; q < (int64_t)kd0 * w; q += kPanelThreads) {
+    for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
         const int c = (int)(q / kd0), i = (int)(q % kd0);
         F[i + (int64_t)col_dst[c] * m] = Wp[q];
     }
-    for (int64_t q = tid; q < (int64_t)m * nmove; q += kPanelThreads) {
+    for (int64_t q = tid; q < (int64_t)m * nmove; q += TH) {
         const int t = (int)(q / m), i = (int)(q % m);
         F[i + (int64_t)mv_dst[t] * m] = Wm[q];
     }
 #pragma unroll
     for (int r = 0; r < RS; r++) {
-        const int row = kd0 + tid + kPanelThreads * r;
+        const int row = kd0 + tid + TH * r;
         if (row >= m) continue;
         const int drow = row < P ? dstm[row - kd0] : row;
 #pragma unroll
@@ -396,15 +456,15 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     if (tid < w) colperm[col_dst[tid]] = old_tag[tid];
     if (tid < nmove) colperm[mv_dst[tid]] = mv_tag[tid];
 #pragma unroll
-    for (int q = 0; q < (4096 + kPanelThreads - 1) / kPanelThreads; q++) {
-        const int i = kd0 + tid + kPanelThreads * q;
+    for (int q = 0; q < RS; q++) {
+        const int i = kd0 + tid + TH * q;
         if (i < P) rowperm[i] = rtag[q];
     }
     // (destination, source) row pairs for the columns outside the window
     if (tid == 0) npairs_s = 0;
     __syncthreads();
     int32_t* pairs = iv_pairs(d.iv, P, m);
-    for (int i = kd0 + tid; i < P; i += kPanelThreads) {
+    for (int i = kd0 + tid; i < P; i += TH) {
         const int src = lmap[i - kd0];
         if (src != i) {
             const int slot = atomicAdd(&npairs_s, 1);
@@ -432,17 +492,28 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     const int prec = fn[s].prec;
     if (prec != want_prec) return;
     switch (front_class(fn[s].m)) {
-        case 0: panel_front<T, 32, 1>(fn, s, u, dyn); break;
-        case 1: panel_front<T, 32, 2>(fn, s, u, dyn); break;
+        case 0: panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn); break;
+        case 1: panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn); break;
         case 2:
-            if constexpr (sizeof(T) == 8) panel_front<T, 24, 4>(fn, s, u, dyn);
-            else panel_front<T, 32, 4>(fn, s, u, dyn);
+            if constexpr (sizeof(T) == 8) panel_front<T, 24, 4, kPanelThreads>(fn, s, u, dyn);
+            else panel_front<T, 32, 4, kPanelThreads>(fn, s, u, dyn);
             break;
         default:
-            if constexpr (sizeof(T) == 8) panel_front<T, 8, 8>(fn, s, u, dyn);
-            else panel_front<T, 16, 8>(fn, s, u, dyn);
+            if constexpr (sizeof(T) == 8) panel_front<T, 8, 8, kPanelThreads>(fn, s, u, dyn);
+            else panel_front<T, 16, 8, kPanelThreads>(fn, s, u, dyn);
             break;
     }
+}
+
+// Levels whose fronts all have order <= 256: the class-0 panel (same window, same
+// arithmetic) on 256 threads, so more fronts share a compute unit.
+constexpr int kPanelSmallThreads = 256;
+template <typename T>
+__global__ __launch_bounds__(kPanelSmallThreads) void k_panel_small(FrontNum* fn, int slot0, double u, int want_prec) {
+    extern __shared__ int dyn[];
+    const int s = slot0 + blockIdx.x;
+    if (fn[s].prec != want_prec) return;
+    panel_front<T, 32, 1, kPanelSmallThreads>(fn, s, u, dyn);
 }
 
 // Columns outside the last panel's window: apply its row swaps; for columns
@@ -450,17 +521,18 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
 // with the unit-lower L11 of the panel.  Block (x: kSwapCols-column tile, y: front).
 constexpr int kSwapCols = 64;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec, const int32_t* tasks) {
     __shared__ T L11[kNBMax * kNBMax];
     __shared__ int pd[2 * kNBMax], ps[2 * kNBMax];
     __shared__ T stage[2 * kNBMax * 64];
-    const int s = slot0 + blockIdx.y;
+    const int task = tasks[blockIdx.x];
+    const int s = slot0 + (task >> 12);
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
     const int kd0 = d.k0, kd1 = d.k, nb = kd1 - kd0;
     if (nb <= 0) return;
-    const int c0 = blockIdx.x * kSwapCols;
+    const int c0 = (task & 63) * kSwapCols;
     if (c0 >= m) return;
     T* F = (T*)d.F;
     const int32_t* pairs = iv_pairs(d.iv, P, m);
@@ -540,14 +612,16 @@ struct Mfma<float> {
 // Block (x: column tile, y: row tile, z: front).  4 waves, each a 32x32 quarter
 // made of 2x2 MFMA 16x16 blocks; K staged through LDS in chunks of 32.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec) {
+__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec,
+                                                   const int32_t* tasks) {
     // A and B chunks, then (aliased) the C tile for the transposed epilogue
     __shared__ T smem_ab[2 * kKC * kLdsPad];
     static_assert(2 * kKC * kLdsPad >= kTile * kLdsPad, "C tile must fit in the A/B buffer");
     T* As = smem_ab;
     T* Bs = smem_ab + kKC * kLdsPad;
     T* Cs = smem_ab;
-    const int s = slot0 + blockIdx.z;
+    const int task = tasks[blockIdx.x];
+    const int s = slot0 + (task >> 12);
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
@@ -564,8 +638,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
         kb = d.k;
     }
     if (kb <= ka) return;
-    const int col0 = clo + blockIdx.x * kTile;
-    const int row0 = (mode == 0 ? 0 : P) + blockIdx.y * kTile;
+    const int col0 = clo + (task & 63) * kTile;
+    const int row0 = (mode == 0 ? 0 : P) + ((task >> 6) & 63) * kTile;
     if (col0 >= m || row0 >= m || row0 + kTile <= rlo || col0 + kTile <= rlo) return;
     if (mode == 0 && row0 >= P && col0 >= P) return;
     if (mode == 0 && col0 >= d.x0 && col0 + kTile <= d.x1) return;
@@ -636,17 +710,18 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kKB = 32;          // K per MFMA
 constexpr int kKBPad = kKB + 8;  // row pitch in LDS (bf16 elements)
 
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0) {
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0, const int32_t* tasks) {
     __shared__ __attribute__((aligned(16))) __bf16 As[kTile * kKBPad];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[kTile * kKBPad];
     __shared__ float Cs[kTile * kLdsPad];
-    const int s = slot0 + blockIdx.z;
+    const int task = tasks[blockIdx.x];
+    const int s = slot0 + (task >> 12);
     const FrontNum d = fn[s];
     if (d.prec != 1) return;
     const int m = d.m, P = d.P, kb = d.k;
     if (kb <= 0) return;
-    const int col0 = P + blockIdx.x * kTile;
-    const int row0 = P + blockIdx.y * kTile;
+    const int col0 = P + (task & 63) * kTile;
+    const int row0 = P + ((task >> 6) & 63) * kTile;
     if (col0 >= m || row0 >= m) return;
     const float* F = (const float*)d.F;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1148,7 +1223,8 @@ int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
-                               hipStream_t st, hipEvent_t* ev, bool bf16_schur, std::vector<hipEvent_t>* pev) {
+                               const LevelTasks& tk, hipStream_t st, hipEvent_t* ev, bool bf16_schur,
+                               std::vector<hipEvent_t>* pev) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
@@ -1166,7 +1242,6 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
     }
     {
         const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
-        const int tl = (mmax + kTile - 1) / kTile;
         for (int t = 0; t < rounds; t++) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (pev && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
@@ -1174,19 +1249,24 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                 pev->push_back(e0);
                 pev->push_back(e1);
             }
-            hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+            if (mmax <= kPanelSmallThreads)
+                hipLaunchKernelGGL(k_panel_small<T>, dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn, slot0, u,
+                                   prec);
+            else
+                hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
             if (e1) (void)hipEventRecord(e1, st);
-            hipLaunchKernelGGL(k_swap_trsm<T>, dim3((mmax + kSwapCols - 1) / kSwapCols, count), dim3(kThreads), 0, st, fn,
-                               slot0, prec);
-            hipLaunchKernelGGL(k_gemm<T>, dim3(tl, tl, count), dim3(kThreads), 0, st, fn, slot0, 0, prec);
+            if (tk.nswap)
+                hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tk.nswap), dim3(kThreads), 0, st, fn, slot0, prec, tk.swap);
+            if (tk.ng0) hipLaunchKernelGGL(k_gemm<T>, dim3(tk.ng0), dim3(kThreads), 0, st, fn, slot0, 0, prec, tk.g0);
         }
     }
-    const int tiles = (mmax + kTile - 1) / kTile;
     if (ev) (void)hipEventRecord(ev[1], st);
-    if (bf16_schur && sizeof(T) == 4)
-        hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0);
-    else
-        hipLaunchKernelGGL(k_gemm<T>, dim3(tiles, tiles, count), dim3(kThreads), 0, st, fn, slot0, 1, prec);
+    if (tk.ng1) {
+        if (bf16_schur && sizeof(T) == 4)
+            hipLaunchKernelGGL(k_gemm_bf16, dim3(tk.ng1), dim3(kThreads), 0, st, fn, slot0, tk.g1);
+        else
+            hipLaunchKernelGGL(k_gemm<T>, dim3(tk.ng1), dim3(kThreads), 0, st, fn, slot0, 1, prec, tk.g1);
+    }
     if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_finalize<T>, dim3(count), dim3(kThreads), 0, st, S, fn, slot0, prec);
     if (ev) (void)hipEventRecord(ev[3], st);
@@ -1194,11 +1274,11 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
 }
 
 template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
-                                                const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*,
-                                                bool, std::vector<hipEvent_t>*);
+                                                const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
+                                                hipEvent_t*, bool, std::vector<hipEvent_t>*);
 template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
-                                               const double*, int64_t, int64_t, double, int, hipStream_t, hipEvent_t*,
-                                               bool, std::vector<hipEvent_t>*);
+                                               const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
+                                               hipEvent_t*, bool, std::vector<hipEvent_t>*);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
