@@ -18,6 +18,7 @@
 #include <climits>
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "mf_device.h"
@@ -152,11 +153,20 @@ constexpr int kPanelThreads = 512;
 // NB and rows per thread RS are per front (never per launch), so a front's
 // arithmetic does not depend on the other fronts it is batched with.
 //   class 0: m <= 512  (NB 32, RS 1)     class 1: m <= 1024 (NB 32, RS 2)
-//   class 2: m <= 2048 (FP64 NB 24, FP32 NB 32; RS 4)
+//   class 2: m <= 2048 (FP64 NB 20, FP32 NB 32; RS 4)
 //   class 3: m <= 4096 (FP64 NB 8, FP32 NB 16; RS 8)
 __host__ __device__ inline int front_class(int m) { return m <= 512 ? 0 : (m <= 1024 ? 1 : (m <= 2048 ? 2 : 3)); }
 __host__ __device__ inline int class_nb(int cls, int prec) {
-    return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 24) : (prec ? 16 : 8));
+    return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 20) : (prec ? 16 : 8));
+}
+
+// x where keep (a wave-uniform flag), else +0, as a bitwise mask (no branch and
+// no per-lane select on a uniform condition).
+__device__ __forceinline__ double keep_if(double x, uint64_t keep) {
+    return __longlong_as_double(__double_as_longlong(x) & (long long)(0ull - keep));
+}
+__device__ __forceinline__ float keep_if(float x, uint64_t keep) {
+    return __int_as_float(__float_as_int(x) & (int)(0u - (unsigned)keep));
 }
 
 // Candidate of a column step: largest magnitude over all remaining rows (aall),
@@ -167,56 +177,60 @@ struct PivCand {
     int ifs;
 };
 __device__ __forceinline__ void cand_merge(PivCand& a, double oa, double of, int oi) {
-    a.aall = fmax(a.aall, oa);
-    if (of > a.afs || (of == a.afs && oi < a.ifs)) {
-        a.afs = of;
-        a.ifs = oi;
-    }
+    // branch-free: aall and afs are never NaN (a NaN entry counts as +inf in aall
+    // and never wins afs), so plain comparisons are exact
+    a.aall = (oa > a.aall) ? oa : a.aall;
+    const bool take = (of > a.afs) | ((of == a.afs) & (oi < a.ifs));
+    a.afs = take ? of : a.afs;
+    a.ifs = take ? oi : a.ifs;
 }
-template <int CTRL>
+template <int CTRL, int RM>
 __device__ __forceinline__ int dpp_i(int x) {
-    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xf, false);
 }
-template <int CTRL>
+template <int CTRL, int RM>
 __device__ __forceinline__ double dpp_d(double x) {
     const long long b = __double_as_longlong(x);
-    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    const int lo = dpp_i<CTRL, RM>((int)b), hi = dpp_i<CTRL, RM>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-template <int CTRL>
+// Lanes outside the row mask keep their own value, which merging leaves unchanged.
+template <int CTRL, int RM>
 __device__ __forceinline__ void cand_dpp_step(PivCand& a) {
-    cand_merge(a, dpp_d<CTRL>(a.aall), dpp_d<CTRL>(a.afs), dpp_i<CTRL>(a.ifs));
+    cand_merge(a, dpp_d<CTRL, RM>(a.aall), dpp_d<CTRL, RM>(a.afs), dpp_i<CTRL, RM>(a.ifs));
 }
 __device__ __forceinline__ double readlane_d(double x, int l) {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-// Wave-wide candidate: within each quad (DPP quad permutations), across the
-// quads of a 16-lane row (row rotations by 4 and 8), then across the four rows
-// (readlane); the result is uniform over the wave.  Merging is commutative and
-// associative, so every lane ends with the same candidate.
+// Wave-wide candidate, all in DPP: within each quad (quad permutations), across
+// the quads of a 16-lane row (row rotations by 4 and 8), then across rows (row 0
+// into row 1 and row 2 into row 3 by the row-15 broadcast, then row 1 into rows 2
+// and 3 by the lane-31 broadcast), so lane 63 holds the merge of all 64 lanes and
+// is read out uniformly.  Merging is commutative and associative.
 __device__ __forceinline__ PivCand cand_wave(PivCand a) {
-    cand_dpp_step<0xB1>(a);   // quad_perm [1,0,3,2]
-    cand_dpp_step<0x4E>(a);   // quad_perm [2,3,0,1]
-    cand_dpp_step<0x124>(a);  // row_ror:4
-    cand_dpp_step<0x128>(a);  // row_ror:8
+    cand_dpp_step<0xB1, 0xF>(a);   // quad_perm [1,0,3,2]
+    cand_dpp_step<0x4E, 0xF>(a);   // quad_perm [2,3,0,1]
+    cand_dpp_step<0x124, 0xF>(a);  // row_ror:4
+    cand_dpp_step<0x128, 0xF>(a);  // row_ror:8
+    cand_dpp_step<0x142, 0xA>(a);  // row_bcast:15 into rows 1 and 3
+    cand_dpp_step<0x143, 0xC>(a);  // row_bcast:31 into rows 2 and 3
     PivCand r;
-    r.aall = readlane_d(a.aall, 0);
-    r.afs = readlane_d(a.afs, 0);
-    r.ifs = __builtin_amdgcn_readlane(a.ifs, 0);
-#pragma unroll
-    for (int q = 1; q < 4; q++)
-        cand_merge(r, readlane_d(a.aall, 16 * q), readlane_d(a.afs, 16 * q), __builtin_amdgcn_readlane(a.ifs, 16 * q));
+    r.aall = readlane_d(a.aall, 63);
+    r.afs = readlane_d(a.afs, 63);
+    r.ifs = __builtin_amdgcn_readlane(a.ifs, 63);
     return r;
 }
 
 template <typename T, int NB, int RS, int TH>
 __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* dyn) {
-    __shared__ T urow[NB];
     constexpr int kWaves = TH / 64;
-    __shared__ double red_a[kWaves], red_f[kWaves];
-    __shared__ int red_i[kWaves];
+    // per wave: its candidate (magnitudes, row) and that row's window values;
+    // double-buffered by step parity so that one barrier per column suffices
+    __shared__ T urow_w[2][kWaves][NB];
+    __shared__ double red_a[2][kWaves], red_f[2][kWaves];
+    __shared__ int red_i[2][kWaves];
     __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB];
     __shared__ int mv_src[NB], mv_dst[NB], mv_tag[NB];
     __shared__ int npairs_s;
@@ -245,103 +259,121 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     }
     uint64_t elim = 0;
     int nb = 0;
-    // The window rotates through the registers: at step c, slot j of every row holds
-    // window column (c + j) mod NB, so the column being factored is always slot 0 and
-    // every register index is a compile-time constant while the step loop stays
-    // rolled (a fully unrolled loop would not fit the instruction cache).  After NB
-    // steps each column is back in its own slot.
+    // The window rotates through the registers two columns at a time: in the pair
+    // of steps starting at column c0, slot j of every row holds window column
+    // (c0 + j) mod NB, so the columns being factored are slots 0 and 1, every
+    // register index is a compile-time constant and the step loop stays rolled (a
+    // fully unrolled loop would not fit the instruction cache).  After NB / 2 pairs
+    // each column is back in its own slot.
+    static_assert(NB % 2 == 0, "window width must be even");
     const uint64_t wmask = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
-#pragma unroll 1
-    for (int c = 0; c < NB; c++) {
-        if (c < w) {
-            PivCand cd{0.0, -1.0, INT_MAX};
-#pragma unroll
-            for (int r = 0; r < RS; r++) {
-                if (pstep[r] == -1) {
-                    const double a = fabs((double)v[r][0]);
-                    if (!(a <= cd.aall)) cd.aall = (a != a) ? INFINITY : a;
-                    const int row = kd0 + tid + TH * r;
-                    if (row < P && a > cd.afs) {
-                        cd.afs = a;
-                        cd.ifs = row;
-                    }
-                }
-            }
-            cd = cand_wave(cd);
-            if (lane == 0) {
-                red_a[wid] = cd.aall;
-                red_f[wid] = cd.afs;
-                red_i[wid] = cd.ifs;
-            }
-            __syncthreads();
-            // all wave candidates are read before any is merged (one LDS round trip)
-            double ra[kWaves], rf[kWaves];
-            int ri[kWaves];
-#pragma unroll
-            for (int q = 0; q < kWaves; q++) {
-                ra[q] = red_a[q];
-                rf[q] = red_f[q];
-                ri[q] = red_i[q];
-            }
-            PivCand bc{ra[0], rf[0], ri[0]};
-#pragma unroll
-            for (int q = 1; q < kWaves; q++) cand_merge(bc, ra[q], rf[q], ri[q]);
-            const double aall = bc.aall, afs = bc.afs;
-            const int ifs = bc.ifs;
-            const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
-            if (accept) {
-                const int rel = ifs - kd0;
-                if ((rel % TH) == tid) {
-                    const int rs = rel / TH;
-#pragma unroll
-                    for (int r = 0; r < RS; r++)
-                        if (r == rs) {
-#pragma unroll
-                            for (int j = 0; j < NB; j++) urow[j] = v[r][j];
-                            pstep[r] = nb;
-                        }
-                }
-                if (tid == 0) {
-                    acc_col[nb] = c;
-                    piv_row[nb] = ifs;
-                }
-            }
-            __syncthreads();
-            if (accept) {
-                // small windows read the pivot row into registers first (one LDS round
-                // trip); the widest ones have no registers to spare and read it in place
-                constexpr bool kPre = RS * NB <= 64;
-                T ur[kPre ? NB : 1];
-                if constexpr (kPre) {
-#pragma unroll
-                    for (int j = 0; j < NB; j++) ur[j] = urow[j];
-                }
-                const T piv = urow[0];
-                // window columns still to update, in slot order
-                const uint64_t um = wmask & ~elim;
-                const uint64_t rot = (c == 0) ? um : ((um >> c) | (um << (NB - c)));
-#pragma unroll
-                for (int r = 0; r < RS; r++) {
-                    if (pstep[r] != -1) continue;
-                    const T l = v[r][0] / piv;
-                    v[r][0] = l;
-#pragma unroll
-                    for (int j = 1; j < NB; j++)
-                        if ((rot >> j) & 1ull) v[r][j] -= l * (kPre ? ur[kPre ? j : 0] : urow[j]);
-                }
-                elim |= 1ull << c;
-                nb++;
-            }
-            // no third barrier: the next step writes red_* only after every wave has
-            // passed this step's second barrier (so all reads of red_* are done), and
-            // writes urow only after its first barrier (so all reads of urow are done)
-        }
+    auto step = [&](int c0, auto Uc) {
+        constexpr int U = decltype(Uc)::value;
+        const int c = c0 + U;
+        if (c >= w) return;
+        PivCand cd{0.0, -1.0, INT_MAX};
 #pragma unroll
         for (int r = 0; r < RS; r++) {
-            const T t0 = v[r][0];
+            if (pstep[r] == -1) {
+                const double a = fabs((double)v[r][U]);
+                if (!(a <= cd.aall)) cd.aall = (a != a) ? INFINITY : a;
+                const int row = kd0 + tid + TH * r;
+                if (row < P && a > cd.afs) {
+                    cd.afs = a;
+                    cd.ifs = row;
+                }
+            }
+        }
+        cd = cand_wave(cd);
+        const int par = c & 1;
+        // the lane holding the wave's candidate row publishes it with the candidate
+        if (cd.ifs != INT_MAX && ((cd.ifs - kd0) % TH) == tid) {
+            const int rs = (cd.ifs - kd0) / TH;
 #pragma unroll
-            for (int j = 0; j + 1 < NB; j++) v[r][j] = v[r][j + 1];
-            v[r][NB - 1] = t0;
+            for (int r = 0; r < RS; r++)
+                if (r == rs) {
+#pragma unroll
+                    for (int j = 0; j < NB; j++) urow_w[par][wid][j] = v[r][j];
+                }
+        }
+        if (lane == 0) {
+            red_a[par][wid] = cd.aall;
+            red_f[par][wid] = cd.afs;
+            red_i[par][wid] = cd.ifs;
+        }
+        __syncthreads();
+        // all wave candidates are read before any is merged (one LDS round trip)
+        double ra[kWaves], rf[kWaves];
+        int ri[kWaves];
+#pragma unroll
+        for (int q = 0; q < kWaves; q++) {
+            ra[q] = red_a[par][q];
+            rf[q] = red_f[par][q];
+            ri[q] = red_i[par][q];
+        }
+        PivCand bc{ra[0], rf[0], ri[0]};
+#pragma unroll
+        for (int q = 1; q < kWaves; q++) cand_merge(bc, ra[q], rf[q], ri[q]);
+        const double aall = bc.aall, afs = bc.afs;
+        const int ifs = bc.ifs;
+        const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
+        if (accept) {
+            int qwin = 0;
+#pragma unroll
+            for (int q = 1; q < kWaves; q++)
+                if (ri[q] == ifs) qwin = q;
+            const T* ur = urow_w[par][qwin];
+            const int rel = ifs - kd0;
+            if ((rel % TH) == tid) {
+                const int rs = rel / TH;
+#pragma unroll
+                for (int r = 0; r < RS; r++)
+                    if (r == rs) pstep[r] = nb;
+            }
+            if (tid == 0) {
+                acc_col[nb] = c;
+                piv_row[nb] = ifs;
+            }
+            const T piv = ur[U];
+            // window columns still to update, in slot order
+            const uint64_t um = wmask & ~(elim | (1ull << c));
+            const uint64_t rot = (c0 == 0) ? um : ((um >> c0) | (um << (NB - c0)));
+            // multipliers (zero for rows that are not updated) and a pivot row with
+            // zeros in the columns that are not updated: the update is branch-free and
+            // leaves those entries exactly unchanged
+            T lr[RS];
+#pragma unroll
+            for (int r = 0; r < RS; r++) {
+                const bool act = pstep[r] == -1;
+                const T l = v[r][U] / piv;
+                lr[r] = act ? l : T(0);
+                if (act) v[r][U] = l;
+            }
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                if (j == U) continue;
+                const T uj = keep_if(ur[j], (rot >> j) & 1ull);
+#pragma unroll
+                for (int r = 0; r < RS; r++) v[r][j] -= lr[r] * uj;
+            }
+            elim |= 1ull << c;
+            nb++;
+        }
+        // one barrier per column: the buffers written in the next step are the
+        // other parity, and this parity is rewritten only after every wave has
+        // passed the next step's barrier (so all of this step's reads are done)
+    };
+#pragma unroll 1
+    for (int c0 = 0; c0 < NB; c0 += 2) {
+        step(c0, std::integral_constant<int, 0>());
+        step(c0, std::integral_constant<int, 1>());
+#pragma unroll
+        for (int r = 0; r < RS; r++) {
+            const T t0 = v[r][0], t1 = v[r][1];
+#pragma unroll
+            for (int j = 0; j + 2 < NB; j++) v[r][j] = v[r][j + 2];
+            v[r][NB - 2] = t0;
+            v[r][NB - 1] = t1;
         }
     }
 
@@ -495,7 +527,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
         case 0: panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn); break;
         case 1: panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn); break;
         case 2:
-            if constexpr (sizeof(T) == 8) panel_front<T, 24, 4, kPanelThreads>(fn, s, u, dyn);
+            if constexpr (sizeof(T) == 8) panel_front<T, 20, 4, kPanelThreads>(fn, s, u, dyn);
             else panel_front<T, 32, 4, kPanelThreads>(fn, s, u, dyn);
             break;
         default:

@@ -193,3 +193,31 @@ def test_gmres_ir_with_fp64_factors_one_step(torch_cuda):
     X, info, _ = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, s.b0[0], refine=2)
     assert info.outer_iters <= 1
     assert check.omega(s.to_scipy(), X, s.b0[0]) <= OMEGA_TOL
+
+
+@pytest.mark.parametrize("prec,nx,ny,seed", [("fp64", 64, 32, 0), ("fp32", 32, 16, 3)])
+def test_pivot_rule(torch_cuda, prec, nx, ny, seed):
+    """Threshold partial pivoting inside every front (u = 0.01; partial pivoting,
+    u = 1, in the FP64 root): each eliminated column's pivot is the largest
+    remaining fully summed entry, so its multipliers are at most 1 in magnitude on
+    the fully summed rows and at most 1/u on the contribution rows."""
+    torch = torch_cuda
+    s = build_2d(nx, ny, seed)
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    num = S.factor(torch.from_numpy(s.values).to("cuda:0"), prec=prec)
+    torch.cuda.synchronize()
+    v = S.export()
+    worst_fs = worst_cb = 0.0
+    for f in range(v.nfronts):
+        meta, F, _ = num.debug_front(f)
+        m, P, k = meta["m"], meta["P"], meta["k"]
+        root = v.front_parent[f] < 0
+        u = 1.0 if root else 0.01
+        for t in range(k):
+            fs = np.abs(F[t + 1:P, t]).max(initial=0.0)
+            cb = np.abs(F[P:m, t]).max(initial=0.0)
+            worst_fs = max(worst_fs, fs)
+            worst_cb = max(worst_cb, cb * u)
+            assert fs <= 1.0, (f, t, fs)
+            assert cb <= 1.0 / u, (f, t, cb)
+    print(f"{prec} {nx}x{ny}: max FS multiplier {worst_fs:.3f}, max u*CB multiplier {worst_cb:.3f}", flush=True)
