@@ -555,11 +555,13 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
     int mm = 1;
     for (int p = 0; p < 2; p++)
         for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
-    if ((size_t)mm * sizeof(double) > kMaxLds)
+    // vectors of the largest front per right-hand side, beside 2 KB of static LDS
+    const size_t budget = kMaxLds - 4096;
+    if ((size_t)mm * sizeof(double) > budget)
         throw Fail{MF_ERR_ARG, "front of order " + std::to_string(mm) + " exceeds the solve kernel's LDS budget"};
     for (int c0 = 0; c0 < nrhs;) {
         // right-hand-side chunk so that the largest front's vectors fit in LDS
-        int nrc = (int)std::max<size_t>(1, kMaxLds / (sizeof(double) * (size_t)mm));
+        int nrc = (int)std::max<size_t>(1, budget / (sizeof(double) * (size_t)mm));
         nrc = std::min(nrc, nrhs - c0);
         for (int L = 0; L < S.nlevels; L++) {
             const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;

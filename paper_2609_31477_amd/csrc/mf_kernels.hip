@@ -857,7 +857,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, i
 //   x[colvar[0:k]] = U11^{-1} t    (k_bwd_tri)
 constexpr int kBS = 64;       // diagonal block of the triangular sweeps (one lane per row)
 constexpr int kTriThreads = 512;
-constexpr int kGemvRows = 256;
+constexpr int kGemvRows = 64;    // rows per block of the solve GEMVs
 
 template <typename T>
 __global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
@@ -903,7 +903,7 @@ __global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNu
                 double x = lane < bs ? zs[j0 + lane + c * m] : 0.0;
 #pragma unroll
                 for (int a = 0; a < kBS - 1; a++) {
-                    const double xa = __shfl(x, a);
+                    const double xa = readlane_d(x, a);  // uniform broadcast, no LDS round trip
                     x -= Lr[a] * xa;
                 }
                 if (lane < bs) zs[j0 + lane + c * m] = x;
@@ -932,11 +932,37 @@ __global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNu
         for (int c = 0; c < nrc; c++) v[i + (int64_t)(c0 + c) * m] = zs[i + c * m];
 }
 
-// c[i] = z[i] - sum_{j<k} L[i, j] y[j] for rows i in [k, m); block (x: row chunk, y: front)
+// Row tile of a front times a vector staged in LDS: 64 rows per block (one lane
+// per row, coalesced column reads), the columns split over the block's 4 waves
+// (column j to wave j mod 4, four independent accumulators per lane), and the 4
+// partial sums added in wave order (deterministic).  Returns the row's dot
+// product in wave 0; other waves return 0.
+template <typename T>
+__device__ __forceinline__ double tile_dot(const T* Fcol0, int64_t m, const double* xv, int ncols, double* part) {
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = g;
+    for (; j + 12 < ncols; j += 16) {
+        a0 += (double)Fcol0[(int64_t)j * m] * xv[j];
+        a1 += (double)Fcol0[(int64_t)(j + 4) * m] * xv[j + 4];
+        a2 += (double)Fcol0[(int64_t)(j + 8) * m] * xv[j + 8];
+        a3 += (double)Fcol0[(int64_t)(j + 12) * m] * xv[j + 12];
+    }
+    for (; j < ncols; j += 4) a0 += (double)Fcol0[(int64_t)j * m] * xv[j];
+    part[g * 64 + lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    double r = 0.0;
+    if (g == 0) r = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+    __syncthreads();
+    return r;
+}
+
+// c[i] = z[i] - sum_{j<k} L[i, j] y[j] for rows i in [k, m); block (x: 64-row tile, y: front)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int slot0, int want_prec, double* vec,
                                                        int nrhs, int c0, int nrc) {
     extern __shared__ double ys[];
+    __shared__ double part[kThreads];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
@@ -948,20 +974,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int s
     for (int j = threadIdx.x; j < k; j += kThreads)
         for (int c = 0; c < nrc; c++) ys[j + c * k] = v[j + (int64_t)(c0 + c) * m];
     __syncthreads();
-    const int i = i0 + threadIdx.x;
-    if (i >= m) return;
+    const int i = min(i0 + (int)(threadIdx.x & 63), m - 1);  // clamped rows compute, never store
     for (int c = 0; c < nrc; c++) {
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        const double* yc = ys + c * k;
-        int j = 0;
-        for (; j + 4 <= k; j += 4) {
-            acc0 += (double)F[i + (int64_t)j * m] * yc[j];
-            acc1 += (double)F[i + (int64_t)(j + 1) * m] * yc[j + 1];
-            acc2 += (double)F[i + (int64_t)(j + 2) * m] * yc[j + 2];
-            acc3 += (double)F[i + (int64_t)(j + 3) * m] * yc[j + 3];
-        }
-        for (; j < k; j++) acc0 += (double)F[i + (int64_t)j * m] * yc[j];
-        v[i + (int64_t)(c0 + c) * m] -= (acc0 + acc1) + (acc2 + acc3);
+        const double t = tile_dot<T>(F + i, m, ys + c * k, k, part);
+        if (threadIdx.x < 64 && i0 + (int)threadIdx.x < m) v[i + (int64_t)(c0 + c) * m] -= t;
     }
 }
 
@@ -970,6 +986,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int slot0, int want_prec, const double* x,
                                                        int64_t ldx, double* vec, int nrhs, int c0, int nrc) {
     extern __shared__ double xs[];
+    __shared__ double part[kThreads];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
@@ -985,21 +1002,10 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
         for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
     }
     __syncthreads();
-    const int i = i0 + threadIdx.x;
-    if (i >= k) return;
-    const T* Fr = F + i + (int64_t)k * m;
+    const int i = min(i0 + (int)(threadIdx.x & 63), k - 1);  // clamped rows compute, never store
     for (int c = 0; c < nrc; c++) {
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        const double* xc = xs + c * nc;
-        int j = 0;
-        for (; j + 4 <= nc; j += 4) {
-            acc0 += (double)Fr[(int64_t)j * m] * xc[j];
-            acc1 += (double)Fr[(int64_t)(j + 1) * m] * xc[j + 1];
-            acc2 += (double)Fr[(int64_t)(j + 2) * m] * xc[j + 2];
-            acc3 += (double)Fr[(int64_t)(j + 3) * m] * xc[j + 3];
-        }
-        for (; j < nc; j++) acc0 += (double)Fr[(int64_t)j * m] * xc[j];
-        v[i + (int64_t)(c0 + c) * m] -= (acc0 + acc1) + (acc2 + acc3);
+        const double t = tile_dot<T>(F + i + (int64_t)k * m, m, xs + c * nc, nc, part);
+        if (threadIdx.x < 64 && i0 + (int)threadIdx.x < k) v[i + (int64_t)(c0 + c) * m] -= t;
     }
 }
 
@@ -1030,8 +1036,9 @@ __global__ __launch_bounds__(kTriThreads) void k_bwd_tri(const FrontNum* fn, int
 #pragma unroll
                 for (int a = kBS - 1; a >= 0; a--) {
                     if (a < bs) {
-                        if (lane == a) xl /= Ur[a];
-                        const double xa = __shfl(xl, a);
+                        // row a's value and diagonal are broadcast from lane a
+                        const double xa = readlane_d(xl, a) / readlane_d(Ur[a], a);
+                        if (lane == a) xl = xa;
                         if (lane < a) xl -= Ur[a] * xa;
                     }
                 }
