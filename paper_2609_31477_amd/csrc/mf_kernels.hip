@@ -857,10 +857,26 @@ __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, i
 //   x[colvar[0:k]] = U11^{-1} t    (k_bwd_tri)
 constexpr int kBS = 64;       // diagonal block of the triangular sweeps (one lane per row)
 constexpr int kTriThreads = 512;
+constexpr int kTriSmallOrder = 256;  // levels whose fronts are all at most this order sweep with one wave per front
 constexpr int kGemvRows = 64;    // rows per block of the solve GEMVs
 
+// Dot product of one row of a diagonal block's column strip (bs <= kBS columns,
+// stride m) with a vector in LDS.  A full strip is unrolled with 8 accumulators,
+// so all 64 loads of the row are in flight together.
 template <typename T>
-__global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
+__device__ __forceinline__ double block_dot(const T* Fi, int64_t m, const double* z, int bs) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (bs == kBS) {
+#pragma unroll
+        for (int a = 0; a < kBS; a++) acc[a & 7] += (double)Fi[(int64_t)a * m] * z[a];
+    } else {
+        for (int a = 0; a < bs; a++) acc[a & 7] += (double)Fi[(int64_t)a * m] * z[a];
+    }
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+template <typename T, int TT>
+__global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
                                                       int nrc) {
     extern __shared__ double zs[];
@@ -874,7 +890,7 @@ __global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNu
     double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int cb = S.child_ptr[s], ce = S.child_ptr[s + 1];
-    for (int i = tid; i < m; i += kTriThreads) {
+    for (int i = tid; i < m; i += TT) {
         const int src = i < P ? rowperm[i] : i;
         for (int c = 0; c < nrc; c++)
             zs[i + c * m] = (src < d.npiv) ? b[rows[src] + (int64_t)(c0 + c) * ldb] : 0.0;
@@ -910,25 +926,13 @@ __global__ __launch_bounds__(kTriThreads) void k_fwd_tri(DevSym S, const FrontNu
             }
         }
         __syncthreads();
-        for (int i = j0 + bs + tid; i < k; i += kTriThreads) {
+        for (int i = j0 + bs + tid; i < k; i += TT) {
             const T* Fi = F + i + (int64_t)j0 * m;
-            for (int c = 0; c < nrc; c++) {
-                const double* zc = zs + j0 + c * m;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int a = 0;
-                for (; a + 4 <= bs; a += 4) {
-                    a0 += (double)Fi[(int64_t)a * m] * zc[a];
-                    a1 += (double)Fi[(int64_t)(a + 1) * m] * zc[a + 1];
-                    a2 += (double)Fi[(int64_t)(a + 2) * m] * zc[a + 2];
-                    a3 += (double)Fi[(int64_t)(a + 3) * m] * zc[a + 3];
-                }
-                for (; a < bs; a++) a0 += (double)Fi[(int64_t)a * m] * zc[a];
-                zs[i + c * m] -= (a0 + a1) + (a2 + a3);
-            }
+            for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
         }
         __syncthreads();
     }
-    for (int i = tid; i < m; i += kTriThreads)
+    for (int i = tid; i < m; i += TT)
         for (int c = 0; c < nrc; c++) v[i + (int64_t)(c0 + c) * m] = zs[i + c * m];
 }
 
@@ -1009,8 +1013,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTriThreads) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
+template <typename T, int TT>
+__global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
                                                       int64_t ldx, const double* vec, int nrhs, int c0, int nrc) {
     extern __shared__ double ts[];
     const int s = slot0 + blockIdx.x;
@@ -1021,7 +1025,7 @@ __global__ __launch_bounds__(kTriThreads) void k_bwd_tri(const FrontNum* fn, int
     const int32_t* colvar = iv_colvar(d.iv, P, m);
     const double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    for (int i = tid; i < k; i += kTriThreads)
+    for (int i = tid; i < k; i += TT)
         for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
     __syncthreads();
     for (int j1 = k; j1 > 0; j1 -= kBS) {
@@ -1046,25 +1050,13 @@ __global__ __launch_bounds__(kTriThreads) void k_bwd_tri(const FrontNum* fn, int
             }
         }
         __syncthreads();
-        for (int i = tid; i < j0; i += kTriThreads) {
+        for (int i = tid; i < j0; i += TT) {
             const T* Fi = F + i + (int64_t)j0 * m;
-            for (int c = 0; c < nrc; c++) {
-                const double* tc = ts + j0 + c * k;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int a = 0;
-                for (; a + 4 <= bs; a += 4) {
-                    a0 += (double)Fi[(int64_t)a * m] * tc[a];
-                    a1 += (double)Fi[(int64_t)(a + 1) * m] * tc[a + 1];
-                    a2 += (double)Fi[(int64_t)(a + 2) * m] * tc[a + 2];
-                    a3 += (double)Fi[(int64_t)(a + 3) * m] * tc[a + 3];
-                }
-                for (; a < bs; a++) a0 += (double)Fi[(int64_t)a * m] * tc[a];
-                ts[i + c * k] -= (a0 + a1) + (a2 + a3);
-            }
+            for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
         }
         __syncthreads();
     }
-    for (int i = tid; i < k; i += kTriThreads) {
+    for (int i = tid; i < k; i += TT) {
         const int var = colvar[i];
         if (var < 0) continue;
         for (int c = 0; c < nrc; c++) x[var + (int64_t)(c0 + c) * ldx] = ts[i + c * k];
@@ -1323,8 +1315,13 @@ template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd_tri<T>, dim3(count), dim3(kTriThreads), sizeof(double) * (size_t)mmax * nrc, st, S, fn,
-                       slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+    // levels of small fronts: one wave per front (the diagonal sweep is one wave's work anyway)
+    if (mmax <= kTriSmallOrder)
+        hipLaunchKernelGGL((k_fwd_tri<T, 64>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st, S, fn,
+                           slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+    else
+        hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads>), dim3(count), dim3(kTriThreads),
+                           sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc);
     hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
                        sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
@@ -1335,8 +1332,12 @@ hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, 
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
                        sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc);
-    hipLaunchKernelGGL(k_bwd_tri<T>, dim3(count), dim3(kTriThreads), sizeof(double) * (size_t)mmax * nrc, st, fn, slot0,
-                       prec, x, ldx, vec, nrhs, c0, nrc);
+    if (mmax <= kTriSmallOrder)
+        hipLaunchKernelGGL((k_bwd_tri<T, 64>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st, fn,
+                           slot0, prec, x, ldx, vec, nrhs, c0, nrc);
+    else
+        hipLaunchKernelGGL((k_bwd_tri<T, kTriThreads>), dim3(count), dim3(kTriThreads),
+                           sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
 }
 template hipError_t launch_level_fwd<double>(const DevSym&, const FrontNum*, int, int, int, const double*, int64_t,
