@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Newton-step solves/s & front TFLOP/s, mixed vs FP64 @1e-10 bwd err; p99"
+PANEL_TRAFFIC = {(256, 128, "fp64"): 9.31e6}
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}      # dense MFMA TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0
 
@@ -282,9 +283,14 @@ def main():
         # level factors one window); FP64 arithmetic on the vector ALUs
         avg_ms = finfo.t_panel_kernel_ms / max(1, finfo.panel_launches)
         ach = finfo.panel_flops / (finfo.t_panel_kernel_ms * 1e-3) / 1e12
+        # HBM bytes per panel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the same
+        # counters read for a 1 GiB device copy (profiles/panel_traffic_256x128.txt); known only
+        # for that workload and the panel kernel as profiled there
+        traffic = PANEL_TRAFFIC.get((args.nx, args.ny, args.prec))
         res["roofline"] = {"bound": "alu", "kernel": "k_panel (threshold-pivoting window factorization)",
                            "achieved": round(ach, 5), "peak": PEAK[dtype], "unit": "TFLOP/s",
-                           "frac": round(ach / PEAK[dtype], 6), "traffic": None,
+                           "frac": round(ach / PEAK[dtype], 6), "traffic": traffic,
+                           "traffic_unit": "bytes per launch (HBM, measured)",
                            "avg_launch_ms": round(avg_ms, 4), "launches": int(finfo.panel_launches),
                            "per_launch": "nominal window flops of one panel round over a tree level: "
                                          f"{finfo.panel_flops / max(1, finfo.panel_launches):.3e} flops"}
