@@ -160,13 +160,12 @@ __host__ __device__ inline int class_nb(int cls, int prec) {
     return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 20) : (prec ? 16 : 8));
 }
 
-// x where keep (a wave-uniform flag), else +0, as a bitwise mask (no branch and
-// no per-lane select on a uniform condition).
-__device__ __forceinline__ double keep_if(double x, uint64_t keep) {
-    return __longlong_as_double(__double_as_longlong(x) & (long long)(0ull - keep));
-}
-__device__ __forceinline__ float keep_if(float x, uint64_t keep) {
-    return __int_as_float(__float_as_int(x) & (int)(0u - (unsigned)keep));
+// Work-group barrier that orders LDS only: global stores issued before it stay in
+// flight (the panel streams its multipliers to scratch while it factors).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Candidate of a column step: largest magnitude over all remaining rows (aall),
@@ -231,7 +230,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     __shared__ T urow_w[2][kWaves][NB];
     __shared__ double red_a[2][kWaves], red_f[2][kWaves];
     __shared__ int red_i[2][kWaves];
-    __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB];
+    __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB], col_step[NB];
     __shared__ int mv_src[NB], mv_dst[NB], mv_tag[NB];
     __shared__ int npairs_s;
     const FrontNum d = fn[s];
@@ -266,7 +265,12 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // fully unrolled loop would not fit the instruction cache).  After NB / 2 pairs
     // each column is back in its own slot.
     static_assert(NB % 2 == 0, "window width must be even");
-    const uint64_t wmask = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
+    // Multipliers leave the window as soon as they are formed: each active row streams
+    // its multiplier of elimination step t to WL[t][row] and zeroes its slot.  A pivot
+    // row is active at every earlier step, so its eliminated slots are zero too, and
+    // the rank-1 updates leave eliminated slots at zero without any column mask.
+    T* WL = (T*)d.W + (int64_t)2 * m * NB;
+    const int mr = m - kd0;
     auto step = [&](int c0, auto Uc) {
         constexpr int U = decltype(Uc)::value;
         const int c = c0 + U;
@@ -301,27 +305,26 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             red_f[par][wid] = cd.afs;
             red_i[par][wid] = cd.ifs;
         }
-        __syncthreads();
-        // all wave candidates are read before any is merged (one LDS round trip)
-        double ra[kWaves], rf[kWaves];
-        int ri[kWaves];
-#pragma unroll
-        for (int q = 0; q < kWaves; q++) {
-            ra[q] = red_a[par][q];
-            rf[q] = red_f[par][q];
-            ri[q] = red_i[par][q];
+        lds_barrier();
+        // the wave candidates are merged lane-parallel: lane l holds candidate
+        // l mod kWaves, so after the quad (and, for 8 waves, the row-rotation) DPP
+        // steps every lane of row 0 holds the merge of all of them
+        PivCand bc;
+        {
+            const int q = lane & (kWaves - 1);
+            bc.aall = red_a[par][q];
+            bc.afs = red_f[par][q];
+            bc.ifs = red_i[par][q];
         }
-        PivCand bc{ra[0], rf[0], ri[0]};
-#pragma unroll
-        for (int q = 1; q < kWaves; q++) cand_merge(bc, ra[q], rf[q], ri[q]);
-        const double aall = bc.aall, afs = bc.afs;
-        const int ifs = bc.ifs;
+        cand_dpp_step<0xB1, 0xF>(bc);
+        cand_dpp_step<0x4E, 0xF>(bc);
+        if constexpr (kWaves > 4) cand_dpp_step<0x124, 0xF>(bc);
+        static_assert(kWaves == 4 || kWaves == 8, "panel blocks of 4 or 8 waves");
+        const double aall = readlane_d(bc.aall, 0), afs = readlane_d(bc.afs, 0);
+        const int ifs = __builtin_amdgcn_readlane(bc.ifs, 0);
         const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
         if (accept) {
-            int qwin = 0;
-#pragma unroll
-            for (int q = 1; q < kWaves; q++)
-                if (ri[q] == ifs) qwin = q;
+            const int qwin = ((ifs - kd0) % TH) >> 6;  // the wave holding the pivot row
             const T* ur = urow_w[par][qwin];
             const int rel = ifs - kd0;
             if ((rel % TH) == tid) {
@@ -335,24 +338,23 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
                 piv_row[nb] = ifs;
             }
             const T piv = ur[U];
-            // window columns still to update, in slot order
-            const uint64_t um = wmask & ~(elim | (1ull << c));
-            const uint64_t rot = (c0 == 0) ? um : ((um >> c0) | (um << (NB - c0)));
-            // multipliers (zero for rows that are not updated) and a pivot row with
-            // zeros in the columns that are not updated: the update is branch-free and
-            // leaves those entries exactly unchanged
+            // multipliers (zero for rows that are not updated, so their entries stay
+            // exactly unchanged); the active rows' multipliers go to scratch
             T lr[RS];
 #pragma unroll
             for (int r = 0; r < RS; r++) {
                 const bool act = pstep[r] == -1;
                 const T l = v[r][U] / piv;
                 lr[r] = act ? l : T(0);
-                if (act) v[r][U] = l;
+                if (act) {
+                    WL[(int64_t)nb * mr + tid + TH * r] = l;
+                    v[r][U] = T(0);
+                }
             }
 #pragma unroll
             for (int j = 0; j < NB; j++) {
                 if (j == U) continue;
-                const T uj = keep_if(ur[j], (rot >> j) & 1ull);
+                const T uj = ur[j];
 #pragma unroll
                 for (int r = 0; r < RS; r++) v[r][j] -= lr[r] * uj;
             }
@@ -387,6 +389,8 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             col_dst[c] = pc_new + rj++;
         }
         for (t = 0; t < nb; t++) col_dst[acc_col[t]] = kd0 + t;
+        for (int c = 0; c < NB; c++) col_step[c] = -1;
+        for (t = 0; t < nb; t++) col_step[acc_col[t]] = t;
         // untried columns displaced by the delayed block move into freed window slots
         int nm = 0;
         int fslot = kd0 + nb;
@@ -482,8 +486,14 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         if (row >= m) continue;
         const int drow = row < P ? dstm[row - kd0] : row;
 #pragma unroll
-        for (int c = 0; c < NB; c++)
-            if (c < w) F[drow + (int64_t)col_dst[c] * m] = v[r][c];
+        for (int c = 0; c < NB; c++) {
+            if (c >= w) continue;
+            T val = v[r][c];
+            // eliminated column whose step found this row active: its multiplier
+            const int t = col_step[c];
+            if (t >= 0 && (pstep[r] == -1 || pstep[r] > t)) val = WL[(int64_t)t * mr + tid + TH * r];
+            F[drow + (int64_t)col_dst[c] * m] = val;
+        }
     }
     if (tid < w) colperm[col_dst[tid]] = old_tag[tid];
     if (tid < nmove) colperm[mv_dst[tid]] = mv_tag[tid];
