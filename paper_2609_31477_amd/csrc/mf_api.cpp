@@ -430,8 +430,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         for (int sl = s0; sl < s1; sl++) {
             FrontNum& fr = hf[sl];
             const int nbp = panel_nb(fr.prec, fr.m);
-            // commit staging (2 m NB) + the panel's streamed multipliers (m NB)
-            fr.W = N->wsp.alloc((size_t)3 * fr.m * nbp * (fr.prec ? 4 : 8));
+            fr.W = N->wsp.alloc((size_t)2 * fr.m * nbp * (fr.prec ? 4 : 8));
         }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
         const LevelTasks tk = upload_level_tasks(N, hf + s0, s1 - s0, st);

@@ -28,7 +28,7 @@ struct FrontNum {
     int32_t pcur;    // end of the not-yet-tried fully summed columns [k, pcur); [pcur, P) are delayed
     int32_t x0, x1;  // columns rejected by the last panel (already up to date): skipped by its updates
     int32_t pad_;
-    void* W;         // panel scratch (3 m NB entries): column-commit staging (2 m NB), then the multipliers of the last window by elimination step (m NB)
+    void* W;         // panel scratch (2 m NB entries): staging of the column commit
 };
 
 // Per-level work lists of the tiled factorization kernels, built on the host

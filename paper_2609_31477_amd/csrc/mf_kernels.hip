@@ -230,7 +230,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     __shared__ T urow_w[2][kWaves][NB];
     __shared__ double red_a[2][kWaves], red_f[2][kWaves];
     __shared__ int red_i[2][kWaves];
-    __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB], col_step[NB];
+    __shared__ int acc_col[NB], piv_row[NB], col_dst[NB], old_tag[NB];
     __shared__ int mv_src[NB], mv_dst[NB], mv_tag[NB];
     __shared__ int npairs_s;
     const FrontNum d = fn[s];
@@ -265,12 +265,10 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // fully unrolled loop would not fit the instruction cache).  After NB / 2 pairs
     // each column is back in its own slot.
     static_assert(NB % 2 == 0, "window width must be even");
-    // Multipliers leave the window as soon as they are formed: each active row streams
-    // its multiplier of elimination step t to WL[t][row] and zeroes its slot.  A pivot
-    // row is active at every earlier step, so its eliminated slots are zero too, and
-    // the rank-1 updates leave eliminated slots at zero without any column mask.
-    T* WL = (T*)d.W + (int64_t)2 * m * NB;
-    const int mr = m - kd0;
+    // Eliminated columns keep their multipliers in place.  The published pivot row
+    // carries zeros in the eliminated slots (written by the lanes of those slots after
+    // the owner's row), so the rank-1 updates leave the multipliers exactly unchanged
+    // without any per-column mask in the update.
     auto step = [&](int c0, auto Uc) {
         constexpr int U = decltype(Uc)::value;
         const int c = c0 + U;
@@ -290,7 +288,8 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         }
         cd = cand_wave(cd);
         const int par = c & 1;
-        // the lane holding the wave's candidate row publishes it with the candidate
+        // the lane holding the wave's candidate row publishes it with the candidate;
+        // LDS writes of one wave land in order, so the zeros follow the row
         if (cd.ifs != INT_MAX && ((cd.ifs - kd0) % TH) == tid) {
             const int rs = (cd.ifs - kd0) / TH;
 #pragma unroll
@@ -299,6 +298,10 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
 #pragma unroll
                     for (int j = 0; j < NB; j++) urow_w[par][wid][j] = v[r][j];
                 }
+        }
+        {
+            const uint64_t er = (c0 == 0) ? elim : ((elim >> c0) | (elim << (NB - c0)));  // slot order
+            if (lane < NB && ((er >> lane) & 1ull)) urow_w[par][wid][lane] = T(0);
         }
         if (lane == 0) {
             red_a[par][wid] = cd.aall;
@@ -339,17 +342,14 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             }
             const T piv = ur[U];
             // multipliers (zero for rows that are not updated, so their entries stay
-            // exactly unchanged); the active rows' multipliers go to scratch
+            // exactly unchanged)
             T lr[RS];
 #pragma unroll
             for (int r = 0; r < RS; r++) {
                 const bool act = pstep[r] == -1;
                 const T l = v[r][U] / piv;
                 lr[r] = act ? l : T(0);
-                if (act) {
-                    WL[(int64_t)nb * mr + tid + TH * r] = l;
-                    v[r][U] = T(0);
-                }
+                if (act) v[r][U] = l;
             }
 #pragma unroll
             for (int j = 0; j < NB; j++) {
@@ -389,8 +389,6 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             col_dst[c] = pc_new + rj++;
         }
         for (t = 0; t < nb; t++) col_dst[acc_col[t]] = kd0 + t;
-        for (int c = 0; c < NB; c++) col_step[c] = -1;
-        for (t = 0; t < nb; t++) col_step[acc_col[t]] = t;
         // untried columns displaced by the delayed block move into freed window slots
         int nm = 0;
         int fslot = kd0 + nb;
@@ -486,14 +484,8 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         if (row >= m) continue;
         const int drow = row < P ? dstm[row - kd0] : row;
 #pragma unroll
-        for (int c = 0; c < NB; c++) {
-            if (c >= w) continue;
-            T val = v[r][c];
-            // eliminated column whose step found this row active: its multiplier
-            const int t = col_step[c];
-            if (t >= 0 && (pstep[r] == -1 || pstep[r] > t)) val = WL[(int64_t)t * mr + tid + TH * r];
-            F[drow + (int64_t)col_dst[c] * m] = val;
-        }
+        for (int c = 0; c < NB; c++)
+            if (c < w) F[drow + (int64_t)col_dst[c] * m] = v[r][c];
     }
     if (tid < w) colperm[col_dst[tid]] = old_tag[tid];
     if (tid < nmove) colperm[mv_dst[tid]] = mv_tag[tid];
