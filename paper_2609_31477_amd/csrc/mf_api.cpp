@@ -280,9 +280,11 @@ int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 ||
 LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st) {
     std::vector<int32_t>& t = N->task_scratch;
     t.clear();
+    // few (large) fronts: narrow swap tiles so that more blocks share the latency-bound work
+    const int sw = count < 32 ? 16 : 64;
     for (int i = 0; i < count; i++) {
-        const int T = (hf[i].m + 63) / 64;
-        for (int a = 0; a < T; a++) t.push_back(task_code(i, 0, a));
+        const int T = (hf[i].m + sw - 1) / sw;
+        for (int a = 0; a < T; a++) t.push_back(task_code(i, a >> 6, a & 63));
     }
     const size_t nswap = t.size();
     for (int i = 0; i < count; i++) {
@@ -314,6 +316,7 @@ LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStrea
     LevelTasks tk;
     tk.swap = N->d_tasks;
     tk.nswap = (int32_t)nswap;
+    tk.swap_cols = sw;
     tk.g0 = N->d_tasks + nswap;
     tk.ng0 = (int32_t)ng0;
     tk.g1 = N->d_tasks + nswap + ng0;

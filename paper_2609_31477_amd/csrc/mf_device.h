@@ -36,8 +36,9 @@ struct FrontNum {
 // the small fronts of a level).  Entry = (slot - first slot of the level) << 12 |
 // tile_a << 6 | tile_b, tiles of 64 (front orders are at most 4096).
 struct LevelTasks {
-    const int32_t* swap;  // (front, column tile) over [0, m)
+    const int32_t* swap;  // (front, column tile of swap_cols) over [0, m); tile index in the low 12 bits
     int32_t nswap;
+    int32_t swap_cols;    // 64, or 16 on levels of few fronts
     const int32_t* g0;    // (front, row tile, column tile) over [0, m)^2 minus the block >= P x >= P
     int32_t ng0;
     const int32_t* g1;    // (front, row tile, column tile) over the contribution block [P, m)^2

@@ -77,6 +77,32 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         }
     }
     const int cb = S.child_ptr[s], ce = S.child_ptr[s + 1];
+    // per child: its FrontNum fields and the child column of each of this block's
+    // columns, computed once per block into LDS (then every row's loads of a child
+    // are independent)
+    constexpr int kMaxKids = 16;
+    __shared__ int cj_s[kMaxKids][kGatherCols];
+    __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids];
+    const int nk = ce - cb;
+    const bool staged = nk <= kMaxKids;
+    if (staged) {
+        if (threadIdx.x == 0) {
+            int dseg = 0;
+            for (int t = 0; t < nk; t++) {
+                const FrontNum dc = fn[S.child_slot[cb + t]];
+                kid_dout[t] = dc.P - dc.k;
+                kid_dseg[t] = dseg;
+                dseg += dc.P - dc.k;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < nk * kGatherCols; q += kThreads) {
+            const int t = q / kGatherCols, jj = q % kGatherCols, j = j0 + jj;
+            const int cs = S.child_slot[cb + t];
+            cj_s[t][jj] = j < m ? child_pos(j, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + S.imap_off[cs]) : -1;
+        }
+        __syncthreads();
+    }
     for (int i = threadIdx.x; i < m; i += kThreads) {
         double acc[kGatherCols];
 #pragma unroll
@@ -90,12 +116,23 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
             const int ci = child_pos(i, d.npiv, d.din, dseg, dout, im);
             if (ci >= 0) {
                 const int64_t rbase = (int64_t)(dc.k + ci);
+                if (staged) {
+                    double val[kGatherCols];
 #pragma unroll
-                for (int jj = 0; jj < kGatherCols; jj++) {
-                    const int j = j0 + jj;
-                    if (j < m) {
-                        const int cj = child_pos(j, d.npiv, d.din, dseg, dout, im);
-                        if (cj >= 0) acc[jj] += load_front(dc, rbase + (int64_t)(dc.k + cj) * dc.m);
+                    for (int jj = 0; jj < kGatherCols; jj++) {
+                        const int cj = cj_s[t - cb][jj];
+                        val[jj] = cj >= 0 ? load_front(dc, rbase + (int64_t)(dc.k + cj) * dc.m) : 0.0;
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < kGatherCols; jj++) acc[jj] += val[jj];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < kGatherCols; jj++) {
+                        const int j = j0 + jj;
+                        if (j < m) {
+                            const int cj = child_pos(j, d.npiv, d.din, dseg, dout, im);
+                            if (cj >= 0) acc[jj] += load_front(dc, rbase + (int64_t)(dc.k + cj) * dc.m);
+                        }
                     }
                 }
             }
@@ -552,10 +589,12 @@ __global__ __launch_bounds__(kPanelSmallThreads) void k_panel_small(FrontNum* fn
 
 // Columns outside the last panel's window: apply its row swaps; for columns
 // ahead of it (>= k, outside the just-delayed block) also form the new U rows
-// with the unit-lower L11 of the panel.  Block (x: kSwapCols-column tile, y: front).
-constexpr int kSwapCols = 64;
+// with the unit-lower L11 of the panel.  One block per (front, tile of sw <= 64
+// columns): 64-column tiles on levels of many fronts, 16-column tiles on levels of
+// few large fronts (more blocks in flight, fewer sequential passes per block).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec, const int32_t* tasks) {
+__global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0, int want_prec, const int32_t* tasks,
+                                                        int sw) {
     __shared__ T L11[kNBMax * kNBMax];
     __shared__ int pd[2 * kNBMax], ps[2 * kNBMax];
     __shared__ T stage[2 * kNBMax * 64];
@@ -566,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     const int m = d.m, P = d.P;
     const int kd0 = d.k0, kd1 = d.k, nb = kd1 - kd0;
     if (nb <= 0) return;
-    const int c0 = (task & 63) * kSwapCols;
+    const int c0 = (task & 4095) * sw, cend = min(c0 + sw, m);
     if (c0 >= m) return;
     T* F = (T*)d.F;
     const int32_t* pairs = iv_pairs(d.iv, P, m);
@@ -581,11 +620,11 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
         ps[q] = pairs[2 + 2 * q];
     }
     __syncthreads();
-    // row swaps of the panel, 64 columns at a time staged through LDS: every source
-    // of a column is read before any destination is written
-    for (int cc = c0; cc < min(c0 + kSwapCols, m); cc += 64) {
-        const int jl = cc + (tid & 63);
-        const bool live = jl < m && !(jl >= kd0 && jl < kd1) && !(jl >= d.x0 && jl < d.x1);
+    // row swaps of the panel, staged through LDS: every source of a column is read
+    // before any destination is written
+    {
+        const int jl = c0 + (tid & 63);
+        const bool live = jl < cend && !(jl >= kd0 && jl < kd1) && !(jl >= d.x0 && jl < d.x1);
         T* cp = F + (int64_t)jl * m;
         for (int q = tid >> 6; q < np; q += kThreads / 64)
             if (live) stage[q * 64 + (tid & 63)] = cp[ps[q]];
@@ -597,9 +636,9 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     // new U rows: unit-lower solve with L11, half a wave per column (lane = row of
     // the panel), the pivot row's value broadcast with readlane at each step
     const int lane = tid & 63, half = lane >> 5, r = lane & 31;
-    for (int jj = c0 + 2 * (tid >> 6); jj < min(c0 + kSwapCols, m); jj += 2 * (kThreads / 64)) {
+    for (int jj = c0 + 2 * (tid >> 6); jj < cend; jj += 2 * (kThreads / 64)) {
         const int j = jj + half;
-        const bool live = j < m && j >= kd1 && !(j >= d.x0 && j < d.x1);
+        const bool live = j < cend && j >= kd1 && !(j >= d.x0 && j < d.x1);
         T* colp = F + (int64_t)j * m + kd0;
         double x = (live && r < nb) ? (double)colp[r] : 0.0;
         for (int a = 0; a < nb - 1; a++) {
@@ -1289,7 +1328,8 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                 hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
             if (e1) (void)hipEventRecord(e1, st);
             if (tk.nswap)
-                hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tk.nswap), dim3(kThreads), 0, st, fn, slot0, prec, tk.swap);
+                hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tk.nswap), dim3(kThreads), 0, st, fn, slot0, prec, tk.swap,
+                                   tk.swap_cols);
             if (tk.ng0) hipLaunchKernelGGL(k_gemm<T>, dim3(tk.ng0), dim3(kThreads), 0, st, fn, slot0, 0, prec, tk.g0);
         }
     }
