@@ -64,6 +64,13 @@ typedef struct {
     int32_t panel_nb;      /* reserved (the panel width is chosen per front from its order) */
     int32_t profile;       /* 1 = time the factorization phases with HIP events on the
                               caller's stream (reported in mf_factor_info; default 0) */
+    int32_t scale;         /* Ruiz equilibration sweeps applied to the values before each
+                              factorization (Ruiz 2001: rows and columns divided by the
+                              square roots of their largest magnitudes, rounded to powers
+                              of two so that scaling is exact); the factors are of
+                              Dr J Dc and mf_solve undoes the scaling around every use of
+                              them, while residuals and omega are of J itself.
+                              0 = none; default 3 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */

@@ -35,7 +35,7 @@ class mf_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("pivot_u", ctypes.c_double), ("leaf_max", ctypes.c_int32),
                 ("target_omega", ctypes.c_double), ("max_outer", ctypes.c_int32), ("gmres_m", ctypes.c_int32),
                 ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("scale", ctypes.c_int32)]
 
 
 class mf_symbolic_view(ctypes.Structure):

@@ -47,6 +47,10 @@ hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const 
                            unsigned long long* omega_bits, hipStream_t st);
 hipError_t launch_axpy(const DevSym& S, int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd,
                        const int32_t* active, int nrhs, hipStream_t st);
+hipError_t launch_ruiz(const DevSym& S, const double* val, int64_t n, int sweeps, double* dr, double* dc,
+                       double* rmax, unsigned long long* cmax, double* out, hipStream_t st);
+hipError_t launch_diag_scale(int64_t n, const double* d, const double* x, int64_t ldx, double* y, int64_t ldy,
+                             int nrhs, hipStream_t st);
 
 namespace {
 thread_local std::string g_err;
@@ -177,6 +181,15 @@ struct mf_num {
     bool factored = false;
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
     std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
+    // equilibration: factors are of Dr J Dc (powers of two); residuals use J itself
+    bool scaled = false;
+    double* d_svals = nullptr;          // Dr J Dc values (nnz)
+    double* d_dr = nullptr;             // n
+    double* d_dc = nullptr;             // n
+    double* d_rmax = nullptr;           // n
+    unsigned long long* d_cmax = nullptr;  // n
+    double* d_sb = nullptr;             // Dr b for the sweeps (n x nrhs)
+    size_t sb_cap = 0;
     int32_t* d_tasks = nullptr;  // per-level tile work lists (LevelTasks)
     int32_t* h_tasks = nullptr;  // pinned staging
     size_t tasks_cap = 0;        // entries
@@ -200,6 +213,12 @@ struct mf_num {
         if (d_cat) (void)hipFree(d_cat);
         if (h_active) (void)hipHostFree(h_active);
         if (d_tasks) (void)hipFree(d_tasks);
+        if (d_svals) (void)hipFree(d_svals);
+        if (d_dr) (void)hipFree(d_dr);
+        if (d_dc) (void)hipFree(d_dc);
+        if (d_rmax) (void)hipFree(d_rmax);
+        if (d_cmax) (void)hipFree(d_cmax);
+        if (d_sb) (void)hipFree(d_sb);
         if (h_tasks) (void)hipHostFree(h_tasks);
     }
 };
@@ -345,6 +364,20 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     } else if (S.nnz) {
         HIPX(hipMemcpyAsync(N->d_vals, values_dev, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, st));
     }
+    // equilibration (values only: the pattern and the analysis are unchanged)
+    const double* fvals = N->d_vals;
+    N->scaled = o.scale > 0 && S.n > 0;
+    if (N->scaled) {
+        if (!N->d_svals) {
+            HIPX(hipMalloc((void**)&N->d_svals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
+            HIPX(hipMalloc((void**)&N->d_dr, sizeof(double) * S.n));
+            HIPX(hipMalloc((void**)&N->d_dc, sizeof(double) * S.n));
+            HIPX(hipMalloc((void**)&N->d_rmax, sizeof(double) * S.n));
+            HIPX(hipMalloc((void**)&N->d_cmax, sizeof(unsigned long long) * S.n));
+        }
+        HIPX(launch_ruiz(D.S, N->d_vals, S.n, o.scale, N->d_dr, N->d_dc, N->d_rmax, N->d_cmax, N->d_svals, st));
+        fvals = N->d_svals;
+    }
     if (N->fronts.chunks.empty()) {
         double tot = 0;
         for (int f = 0; f < nf; f++) tot += (double)S.mnom[f] * S.mnom[f];
@@ -442,14 +475,14 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         if (N->lvl_cnt[0][L]) {
             if (prof) HIPX(hipEventRecord(ev[0][0], st));
             HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
-                                             N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), N->d_vals,
+                                             N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), fvals,
                                              u0, u1, o.pivot_u, 0, tk, st, prof ? &ev[0][1] : nullptr, false,
                                              prof ? &pev : nullptr));
         }
         if (N->lvl_cnt[1][L]) {
             if (prof) HIPX(hipEventRecord(ev[1][0], st));
             HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
-                                            N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), N->d_vals,
+                                            N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), fvals,
                                             u0, u1, o.pivot_u, 1, tk, st, prof ? &ev[1][1] : nullptr,
                                             o.prec == MF_BF16, prof ? &pev : nullptr));
         }
@@ -555,6 +588,19 @@ void ensure_solve_buffers(mf_num* N, int nrhs) {
 void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, hipStream_t st) {
     const Symbolic& S = N->sym->S;
     const DevSym& DS = N->sym->dev->S;
+    // with equilibration the factors are of Dr J Dc: x = Dc (Dr J Dc)^{-1} Dr b
+    if (N->scaled) {
+        const size_t need = (size_t)S.n * nrhs;
+        if (need > N->sb_cap) {
+            if (N->d_sb) HIPX(hipFree(N->d_sb));
+            N->d_sb = nullptr;
+            HIPX(hipMalloc((void**)&N->d_sb, sizeof(double) * need));
+            N->sb_cap = need;
+        }
+        HIPX(launch_diag_scale(S.n, N->d_dr, b, ldb, N->d_sb, S.n, nrhs, st));
+        b = N->d_sb;
+        ldb = S.n;
+    }
     int mm = 1;
     for (int p = 0; p < 2; p++)
         for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
@@ -586,6 +632,7 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
         }
         c0 += nrc;
     }
+    if (N->scaled) HIPX(launch_diag_scale(S.n, N->d_dc, x, ldx, x, ldx, nrhs, st));
 }
 
 double omega_of_bits(unsigned long long b) {
@@ -835,6 +882,7 @@ void mf_default_options(mf_options* o) {
     o->refine = -1;
     o->panel_nb = 32;
     o->profile = 0;
+    o->scale = 3;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -908,10 +956,12 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
         N->opt.refine = opt->refine;
         N->opt.panel_nb = opt->panel_nb;
         N->opt.profile = opt->profile;
+        N->opt.scale = opt->scale;
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");
     if (!(N->opt.pivot_u >= 0.0 && N->opt.pivot_u <= 1.0)) return fail(MF_ERR_ARG, "pivot_u must be in [0, 1]");
+    if (N->opt.scale < 0 || N->opt.scale > 64) return fail(MF_ERR_ARG, "scale must be in [0, 64] sweeps");
     N->factored = false;
     try {
         HIPX(hipGetDevice(&N->device));

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     // per child: its FrontNum fields and the child column of each of this block's
     // columns, computed once per block into LDS (then every row's loads of a child
     // are independent)
-    constexpr int kMaxKids = 16;
+    constexpr int kMaxKids = 64;
     __shared__ int cj_s[kMaxKids][kGatherCols];
     __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids];
     const int nk = ce - cb;
@@ -1390,6 +1390,88 @@ template hipError_t launch_level_bwd<double>(const FrontNum*, int, int, int, dou
                                              int, int, int, hipStream_t);
 template hipError_t launch_level_bwd<float>(const FrontNum*, int, int, int, double*, int64_t, const double*, int,
                                             int, int, int, hipStream_t);
+
+// ------------------------------------------------------------------ equilibration
+// One Ruiz sweep over the CSR values scaled by the current dr, dc: rmax[i] =
+// max_j |dr_i a_ij dc_j| (16 lanes per row) and cmax[j] = the same maximum over
+// column j (atomic max on the bit patterns of non-negative doubles: exact and
+// independent of the order of arrival).
+__global__ __launch_bounds__(kThreads) void k_ruiz_max(const int64_t* rp, const int32_t* ci, const double* val,
+                                                       int64_t n, const double* dr, const double* dc, double* rmax,
+                                                       unsigned long long* cmax) {
+    const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 16;
+    const int sub = threadIdx.x & 15;
+    double mx = 0.0;
+    if (row < n) {
+        const double di = dr[row];
+        for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) {
+            const int j = ci[t];
+            const double a = fabs(di * val[t] * dc[j]);
+            mx = fmax(mx, a);
+            atomicMax(cmax + j, (unsigned long long)__double_as_longlong(a));
+        }
+    }
+    for (int off = 8; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 16));
+    if (row < n && sub == 0) rmax[row] = mx;
+}
+
+// Nearest power of two to 1/sqrt(x) for x > 0 (1 otherwise): the scaled values are
+// then exact multiples of the originals.
+__device__ __forceinline__ double ruiz_factor(double x) {
+    if (!(x > 0.0) || !(x <= DBL_MAX)) return 1.0;
+    return ldexp(1.0, -(int)rint(0.5 * log2(x)));
+}
+
+__global__ __launch_bounds__(kThreads) void k_ruiz_update(int64_t n, double* dr, double* dc, const double* rmax,
+                                                          const unsigned long long* cmax) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        dr[i] *= ruiz_factor(rmax[i]);
+        dc[i] *= ruiz_factor(__longlong_as_double((long long)cmax[i]));
+    }
+}
+
+// out = Dr A Dc, entrywise over the CSR (exact: the factors are powers of two).
+__global__ __launch_bounds__(kThreads) void k_ruiz_apply(const int64_t* rp, const int32_t* ci, const double* val,
+                                                         int64_t n, const double* dr, const double* dc, double* out) {
+    const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 16;
+    const int sub = threadIdx.x & 15;
+    if (row >= n) return;
+    const double di = dr[row];
+    for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) out[t] = di * val[t] * dc[ci[t]];
+}
+
+// y[:, c] = d .* x[:, c] for nrhs columns (y may alias x).
+__global__ __launch_bounds__(kThreads) void k_diag_scale(int64_t n, const double* d, const double* x, int64_t ldx,
+                                                         double* y, int64_t ldy) {
+    const int c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        y[i + c * ldy] = d[i] * x[i + c * ldx];
+}
+
+hipError_t launch_ruiz(const DevSym& S, const double* val, int64_t n, int sweeps, double* dr, double* dc,
+                       double* rmax, unsigned long long* cmax, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned vb = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    const unsigned rb = (unsigned)((n * 16 + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_fill, dim3(vb), dim3(kThreads), 0, st, dr, 1.0, n);
+    hipLaunchKernelGGL(k_fill, dim3(vb), dim3(kThreads), 0, st, dc, 1.0, n);
+    for (int t = 0; t < sweeps; t++) {
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, cmax, (int)n, 0ull);
+        hipLaunchKernelGGL(k_ruiz_max, dim3(rb), dim3(kThreads), 0, st, S.csr_rowptr, S.csr_colind, val, n, dr, dc,
+                           rmax, cmax);
+        hipLaunchKernelGGL(k_ruiz_update, dim3(vb), dim3(kThreads), 0, st, n, dr, dc, rmax, cmax);
+    }
+    hipLaunchKernelGGL(k_ruiz_apply, dim3(rb), dim3(kThreads), 0, st, S.csr_rowptr, S.csr_colind, val, n, dr, dc, out);
+    return MF_CHECK_LAUNCH();
+}
+
+hipError_t launch_diag_scale(int64_t n, const double* d, const double* x, int64_t ldx, double* y, int64_t ldy,
+                             int nrhs, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    const unsigned vb = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_diag_scale, dim3(vb, nrhs), dim3(kThreads), 0, st, n, d, x, ldx, y, ldy);
+    return MF_CHECK_LAUNCH();
+}
 
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,

@@ -221,3 +221,18 @@ def test_pivot_rule(torch_cuda, prec, nx, ny, seed):
             assert fs <= 1.0, (f, t, fs)
             assert cb <= 1.0 / u, (f, t, cb)
     print(f"{prec} {nx}x{ny}: max FS multiplier {worst_fs:.3f}, max u*CB multiplier {worst_cb:.3f}", flush=True)
+
+
+@pytest.mark.parametrize("scale", [0, 1, 3])
+def test_equilibration_parity(torch_cuda, scale):
+    """Ruiz equilibration (power-of-two row and column factors, values only) changes
+    the factors but not the solution: every sweep count meets the FP64 bar against the
+    oracle on the original system."""
+    s = build_2d(32, 16, 5)
+    B = s.b0[0]
+    X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B, scale=scale)
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    print(f"scale={scale}: delayed={num.info().delayed_pivots} omega0={info.omega0:.2e} "
+          f"steps={info.outer_iters}", flush=True)
+    assert_parity(s.to_scipy(), X, Xo, B)
+    assert info.outer_iters <= 2
