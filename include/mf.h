@@ -70,7 +70,8 @@ typedef struct {
                               of two so that scaling is exact); the factors are of
                               Dr J Dc and mf_solve undoes the scaling around every use of
                               them, while residuals and omega are of J itself.
-                              0 = none; default 3 */
+                              With power-of-two factors one sweep already reaches the
+                              fixed point on the Jacobians here. 0 = none; default 1 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */

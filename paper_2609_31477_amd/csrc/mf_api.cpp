@@ -882,7 +882,7 @@ void mf_default_options(mf_options* o) {
     o->refine = -1;
     o->panel_nb = 32;
     o->profile = 0;
-    o->scale = 3;
+    o->scale = 1;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
