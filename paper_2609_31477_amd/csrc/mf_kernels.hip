@@ -576,15 +576,15 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     }
 }
 
-// Levels whose fronts all have order <= 256: the class-0 panel (same window, same
-// arithmetic) on 256 threads, so more fronts share a compute unit.
+// Levels whose fronts all have order <= 512 (class 0): the class-0 panel (same
+// window, same arithmetic) on 256 threads with RS = 1 or 2 rows per thread.
 constexpr int kPanelSmallThreads = 256;
-template <typename T>
+template <typename T, int RS>
 __global__ __launch_bounds__(kPanelSmallThreads) void k_panel_small(FrontNum* fn, int slot0, double u, int want_prec) {
     extern __shared__ int dyn[];
     const int s = slot0 + blockIdx.x;
     if (fn[s].prec != want_prec) return;
-    panel_front<T, 32, 1, kPanelSmallThreads>(fn, s, u, dyn);
+    panel_front<T, 32, RS, kPanelSmallThreads>(fn, s, u, dyn);
 }
 
 // Columns outside the last panel's window: apply its row swaps; for columns
@@ -1321,9 +1321,14 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                 pev->push_back(e0);
                 pev->push_back(e1);
             }
+            // levels of class-0 fronts (order <= 512, window 32): 4 waves per front, one
+            // per SIMD, with one or two rows per lane (same arithmetic as 8 waves)
             if (mmax <= kPanelSmallThreads)
-                hipLaunchKernelGGL(k_panel_small<T>, dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn, slot0, u,
-                                   prec);
+                hipLaunchKernelGGL((k_panel_small<T, 1>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
+                                   slot0, u, prec);
+            else if (mmax <= 2 * kPanelSmallThreads)
+                hipLaunchKernelGGL((k_panel_small<T, 2>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
+                                   slot0, u, prec);
             else
                 hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
             if (e1) (void)hipEventRecord(e1, st);
