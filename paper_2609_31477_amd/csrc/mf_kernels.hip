@@ -240,6 +240,39 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
     const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+// Two-phase wave reduction of a candidate (short dependency chains): first the
+// maxima of aall and afs (independent DPP chains of plain max), then the lowest row
+// among the lanes whose afs equals that maximum (a DPP chain of integer min).  The
+// result is the same as merging the candidates one by one.
+template <int CTRL, int RM>
+__device__ __forceinline__ void dmax_step(double& x) {
+    x = fmax(x, dpp_d<CTRL, RM>(x));
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ void imin_step(int& x) {
+    x = min(x, dpp_i<CTRL, RM>(x));
+}
+__device__ __forceinline__ PivCand cand_wave2(PivCand a) {
+    double ma = a.aall, mf = a.afs;
+    dmax_step<0xB1, 0xF>(ma); dmax_step<0xB1, 0xF>(mf);
+    dmax_step<0x4E, 0xF>(ma); dmax_step<0x4E, 0xF>(mf);
+    dmax_step<0x124, 0xF>(ma); dmax_step<0x124, 0xF>(mf);
+    dmax_step<0x128, 0xF>(ma); dmax_step<0x128, 0xF>(mf);
+    dmax_step<0x142, 0xA>(ma); dmax_step<0x142, 0xA>(mf);
+    dmax_step<0x143, 0xC>(ma); dmax_step<0x143, 0xC>(mf);
+    PivCand r;
+    r.aall = readlane_d(ma, 63);
+    r.afs = readlane_d(mf, 63);
+    int ri = (a.afs == r.afs) ? a.ifs : INT_MAX;
+    imin_step<0xB1, 0xF>(ri);
+    imin_step<0x4E, 0xF>(ri);
+    imin_step<0x124, 0xF>(ri);
+    imin_step<0x128, 0xF>(ri);
+    imin_step<0x142, 0xA>(ri);
+    imin_step<0x143, 0xC>(ri);
+    r.ifs = __builtin_amdgcn_readlane(ri, 63);
+    return r;
+}
 // Wave-wide candidate, all in DPP: within each quad (quad permutations), across
 // the quads of a 16-lane row (row rotations by 4 and 8), then across rows (row 0
 // into row 1 and row 2 into row 3 by the row-15 broadcast, then row 1 into rows 2
@@ -323,7 +356,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
                 }
             }
         }
-        cd = cand_wave(cd);
+        cd = cand_wave2(cd);
         const int par = c & 1;
         // the lane holding the wave's candidate row publishes it with the candidate;
         // LDS writes of one wave land in order, so the zeros follow the row
@@ -349,19 +382,25 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         // the wave candidates are merged lane-parallel: lane l holds candidate
         // l mod kWaves, so after the quad (and, for 8 waves, the row-rotation) DPP
         // steps every lane of row 0 holds the merge of all of them
-        PivCand bc;
+        double ma, mf;
+        int ci;
         {
             const int q = lane & (kWaves - 1);
-            bc.aall = red_a[par][q];
-            bc.afs = red_f[par][q];
-            bc.ifs = red_i[par][q];
+            ma = red_a[par][q];
+            mf = red_f[par][q];
+            ci = red_i[par][q];
         }
-        cand_dpp_step<0xB1, 0xF>(bc);
-        cand_dpp_step<0x4E, 0xF>(bc);
-        if constexpr (kWaves > 4) cand_dpp_step<0x124, 0xF>(bc);
         static_assert(kWaves == 4 || kWaves == 8, "panel blocks of 4 or 8 waves");
-        const double aall = readlane_d(bc.aall, 0), afs = readlane_d(bc.afs, 0);
-        const int ifs = __builtin_amdgcn_readlane(bc.ifs, 0);
+        const double cf = mf;
+        dmax_step<0xB1, 0xF>(ma); dmax_step<0xB1, 0xF>(mf);
+        dmax_step<0x4E, 0xF>(ma); dmax_step<0x4E, 0xF>(mf);
+        if constexpr (kWaves > 4) { dmax_step<0x124, 0xF>(ma); dmax_step<0x124, 0xF>(mf); }
+        const double aall = readlane_d(ma, 0), afs = readlane_d(mf, 0);
+        ci = (cf == afs) ? ci : INT_MAX;
+        imin_step<0xB1, 0xF>(ci);
+        imin_step<0x4E, 0xF>(ci);
+        if constexpr (kWaves > 4) imin_step<0x124, 0xF>(ci);
+        const int ifs = __builtin_amdgcn_readlane(ci, 0);
         const bool accept = (afs > 0.0) && (afs <= DBL_MAX) && (afs >= u * aall);
         if (accept) {
             const int qwin = ((ifs - kd0) % TH) >> 6;  // the wave holding the pivot row
