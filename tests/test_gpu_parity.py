@@ -213,13 +213,16 @@ def test_pivot_rule(torch_cuda, prec, nx, ny, seed):
         m, P, k = meta["m"], meta["P"], meta["k"]
         root = v.front_parent[f] < 0
         u = 1.0 if root else 0.01
+        # multipliers are formed as a * (1/pivot): within a few units in the last
+        # place of the front's precision of the exact ratio
+        eps = np.finfo(np.float32 if meta["prec"] == 1 else np.float64).eps
         for t in range(k):
             fs = np.abs(F[t + 1:P, t]).max(initial=0.0)
             cb = np.abs(F[P:m, t]).max(initial=0.0)
             worst_fs = max(worst_fs, fs)
             worst_cb = max(worst_cb, cb * u)
-            assert fs <= 1.0, (f, t, fs)
-            assert cb <= 1.0 / u, (f, t, cb)
+            assert fs <= 1.0 + 4 * eps, (f, t, fs)
+            assert cb <= (1.0 + 4 * eps) / u, (f, t, cb)
     print(f"{prec} {nx}x{ny}: max FS multiplier {worst_fs:.3f}, max u*CB multiplier {worst_cb:.3f}", flush=True)
 
 
