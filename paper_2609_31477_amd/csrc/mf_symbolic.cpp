@@ -509,37 +509,67 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
     M.seg_row0.clear();
     M.seg_n.clear();
     M.seg_nnz0.clear();
-    int64_t voff = 0, eoff = 0;
-    int32_t foff = 0, poff = 0;
-    M.rowptr.assign(1, 0);
-    M.front_ptr.assign(1, 0);
-    M.rows_ptr.assign(1, 0);
+    // sizes first, then bulk fills with offsets (no per-element growth)
+    int64_t N = 0, NNZ = 0, NROWS = 0, NIMAP = 0, NUE = 0, NSRC = 0, NROOT = 0;
+    int32_t NF = 0;
+    for (const Symbolic* P : parts) {
+        N += P->n;
+        NNZ += P->nnz;
+        NF += P->nf;
+        NROWS += (int64_t)P->rows.size();
+        NIMAP += (int64_t)P->imap.size();
+        NUE += (int64_t)P->ue_front.size();
+        NSRC += (int64_t)P->ue_src.size();
+        NROOT += (int64_t)P->root.size();
+    }
+    if (NNZ > INT32_MAX) throw std::invalid_argument("batch nnz above 2^31-1 is not supported");
+    M.n = N;
+    M.nnz = NNZ;
+    M.nf = NF;
     M.leaf_max = parts.empty() ? 64 : parts[0]->leaf_max;
-    std::vector<int32_t> part_of_front;
-    std::vector<int64_t> imap_len;
+    M.rowptr.resize(N + 1);
+    M.colind.resize(NNZ);
+    M.root.reserve(NROOT);
+    M.perm.resize(N);
+    M.var_etree.resize(N);
+    M.front_ptr.resize(NF + 1);
+    M.front_parent.resize(NF);
+    M.rows_ptr.resize(NF + 1);
+    M.rows.resize(NROWS);
+    M.npiv.resize(NF);
+    M.mnom.resize(NF);
+    M.level.resize(NF);
+    M.imap.resize(NIMAP);
+    M.imap_off.resize(NF + 1);
+    M.rowptr[0] = 0;
+    M.front_ptr[0] = 0;
+    M.rows_ptr[0] = 0;
+    M.imap_off[0] = 0;
+    int64_t voff = 0, eoff = 0, roff = 0, ioff = 0;
+    int32_t foff = 0;
     for (size_t q = 0; q < parts.size(); q++) {
         const Symbolic& P = *parts[q];
         M.seg_row0.push_back(voff);
         M.seg_n.push_back(P.n);
         M.seg_nnz0.push_back(eoff);
-        for (int64_t r = 0; r < P.n; r++) M.rowptr.push_back(P.rowptr[r + 1] + eoff);
-        for (int64_t t = 0; t < P.nnz; t++) M.colind.push_back((int32_t)(P.colind[t] + voff));
-        for (int32_t v : P.root) M.root.push_back((int32_t)(v + voff));
+        const int32_t v32 = (int32_t)voff;
+        for (int64_t r = 0; r < P.n; r++) M.rowptr[voff + r + 1] = P.rowptr[r + 1] + eoff;
+        for (int64_t t = 0; t < P.nnz; t++) M.colind[eoff + t] = P.colind[t] + v32;
+        for (int32_t v : P.root) M.root.push_back(v + v32);
         for (int64_t i = 0; i < P.n; i++) {
-            M.perm.push_back((int32_t)(P.perm[i] + voff));
-            M.var_etree.push_back(P.var_etree[i] < 0 ? -1 : (int32_t)(P.var_etree[i] + voff));
+            M.perm[voff + i] = P.perm[i] + v32;
+            M.var_etree[voff + i] = P.var_etree[i] < 0 ? -1 : P.var_etree[i] + v32;
         }
+        for (size_t t = 0; t < P.rows.size(); t++) M.rows[roff + (int64_t)t] = P.rows[t] + v32;
+        std::copy(P.imap.begin(), P.imap.end(), M.imap.begin() + ioff);
         for (int32_t f = 0; f < P.nf; f++) {
-            M.front_ptr.push_back(P.front_ptr[f + 1] + poff);
-            M.front_parent.push_back(P.front_parent[f] < 0 ? -1 : P.front_parent[f] + foff);
-            for (int64_t t = P.rows_ptr[f]; t < P.rows_ptr[f + 1]; t++) M.rows.push_back((int32_t)(P.rows[t] + voff));
-            M.rows_ptr.push_back((int64_t)M.rows.size());
-            M.npiv.push_back(P.npiv[f]);
-            M.mnom.push_back(P.mnom[f]);
-            M.level.push_back(P.level[f]);
-            part_of_front.push_back((int32_t)q);
-            M.imap.insert(M.imap.end(), P.imap.begin() + P.imap_off[f], P.imap.begin() + P.imap_off[f + 1]);
-            imap_len.push_back(P.imap_off[f + 1] - P.imap_off[f]);
+            M.front_ptr[foff + f + 1] = P.front_ptr[f + 1] + v32;
+            M.front_parent[foff + f] = P.front_parent[f] < 0 ? -1 : P.front_parent[f] + foff;
+            M.rows_ptr[foff + f + 1] = P.rows_ptr[f + 1] + roff;
+            M.imap_off[foff + f + 1] = P.imap_off[f + 1] + ioff;
+            M.npiv[foff + f] = P.npiv[f];
+            M.mnom[foff + f] = P.mnom[f];
+            M.level[foff + f] = P.level[f];
         }
         M.nominal_flops += P.nominal_flops;
         M.nominal_nnz_lu += P.nominal_nnz_lu;
@@ -547,14 +577,10 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
         voff += P.n;
         eoff += P.nnz;
         foff += P.nf;
-        poff += (int32_t)P.n;
+        roff += (int64_t)P.rows.size();
+        ioff += (int64_t)P.imap.size();
     }
-    M.n = voff;
-    M.nnz = eoff;
-    M.nf = foff;
     const int32_t nf = M.nf;
-    M.imap_off.assign(nf + 1, 0);
-    for (int32_t f = 0; f < nf; f++) M.imap_off[f + 1] = M.imap_off[f] + imap_len[f];
     M.child_ptr.assign(nf + 1, 0);
     for (int32_t f = 0; f < nf; f++)
         if (M.front_parent[f] >= 0) M.child_ptr[M.front_parent[f] + 1]++;
@@ -575,23 +601,30 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
     }
     // unique entries in level order, system by system within a level
     M.level_ue_ptr.assign(M.nlevels + 1, 0);
-    M.ue_src_ptr.assign(1, 0);
+    M.ue_front.resize(NUE);
+    M.ue_row.resize(NUE);
+    M.ue_col.resize(NUE);
+    M.ue_src_ptr.resize(NUE + 1);
+    M.ue_src.resize(NSRC);
+    M.ue_src_ptr[0] = 0;
     std::vector<int32_t> foffs(parts.size() + 1, 0);
     for (size_t q = 0; q < parts.size(); q++) foffs[q + 1] = foffs[q] + parts[q]->nf;
+    int64_t uo = 0, so = 0;
     for (int32_t l = 0; l < M.nlevels; l++) {
         for (size_t q = 0; q < parts.size(); q++) {
             const Symbolic& P = *parts[q];
             if (l >= P.nlevels) continue;
-            for (int64_t u = P.level_ue_ptr[l]; u < P.level_ue_ptr[l + 1]; u++) {
-                M.ue_front.push_back(P.ue_front[u] + foffs[q]);
-                M.ue_row.push_back(P.ue_row[u]);
-                M.ue_col.push_back(P.ue_col[u]);
-                for (int64_t t = P.ue_src_ptr[u]; t < P.ue_src_ptr[u + 1]; t++)
-                    M.ue_src.push_back((int32_t)(P.ue_src[t] + M.seg_nnz0[q]));
-                M.ue_src_ptr.push_back((int64_t)M.ue_src.size());
+            const int32_t e32 = (int32_t)M.seg_nnz0[q];
+            const int64_t u0 = P.level_ue_ptr[l], u1 = P.level_ue_ptr[l + 1];
+            for (int64_t u = u0; u < u1; u++, uo++) {
+                M.ue_front[uo] = P.ue_front[u] + foffs[q];
+                M.ue_row[uo] = P.ue_row[u];
+                M.ue_col[uo] = P.ue_col[u];
+                for (int64_t t = P.ue_src_ptr[u]; t < P.ue_src_ptr[u + 1]; t++) M.ue_src[so++] = P.ue_src[t] + e32;
+                M.ue_src_ptr[uo + 1] = so;
             }
         }
-        M.level_ue_ptr[l + 1] = (int64_t)M.ue_front.size();
+        M.level_ue_ptr[l + 1] = uo;
     }
     if (M.nnz > INT32_MAX) throw std::invalid_argument("batch nnz above 2^31-1 is not supported");
 }

@@ -9,12 +9,15 @@ runs ``newton_steps`` factor+solve steps with its symbolic analysis done once
 
 Scheduling (continuous batching, not a queue): requests arrive on a Poisson
 clock; a request is admitted when a slot and its HBM footprint fit; every tick
-takes all admitted requests with a pending Newton step and runs that step for
-all of them in one batched factorization and one batched solve (shared
-launches).  Requests that arrive while others are on the GPU join at the next
-tick; finished requests free their slot and memory immediately.  Because the
-batched kernels keep every system's arithmetic separate, a request's result is
-the same alone and in any mix.
+runs one Newton step of every admitted request.  Requests admitted together form
+a cohort, which shares one batched factorization and one batched solve per step
+(shared launches); the cohort's merged analysis is built once, when it is
+admitted, and reused for all its steps, so no tick pays for re-merging the whole
+active set.  Requests that arrive while others are on the GPU join at the next
+tick as a new cohort; finished requests free their slot and memory immediately.
+Patterns are analyzed once per mesh (the paper's analysis reuse, Sec. 6).
+Because the batched kernels keep every system's arithmetic separate, a request's
+result is the same alone and in any mix.
 
 The scheduler is backend-agnostic: ``MFBackend`` drives libmf on the GPU;
 ``FakeBackend`` simulates durations and footprints for CPU tests of the logic.
@@ -44,6 +47,7 @@ class Request:
     steps_done: int = 0
     step_latency: list = field(default_factory=list)
     footprint: int = 0
+    cohort: int = -1                               # requests admitted together
     results: list = field(default_factory=list)   # per-step info (omega, ...)
     state: object = None                           # backend state
 
@@ -91,11 +95,14 @@ class Scheduler:
         self.done: list[Request] = []
         self.ticks = 0
         self.batch_sizes = []
+        self.cohorts = 0
 
     def submit(self, req: Request):
         heapq.heappush(self.waiting, (req.arrival, req.rid, req))
 
     def _admit(self, now):
+        cohort = self.cohorts
+        admitted = False
         while self.waiting and self.waiting[0][0] <= now and len(self.active) < self.max_slots:
             _, _, req = self.waiting[0]
             if not req.footprint:
@@ -107,7 +114,11 @@ class Scheduler:
             heapq.heappop(self.waiting)
             self.used += req.footprint
             req.admitted = now
+            req.cohort = cohort
+            admitted = True
             self.active.append(req)
+        if admitted:
+            self.cohorts += 1
 
     def run(self, clock=None, idle_sleep=True):
         """Serve until every submitted request is done.  ``clock()`` returns seconds
@@ -184,11 +195,17 @@ class FakeBackend:
 
 
 class MFBackend:
-    """libmf on the GPU: one symbolic handle per request (analysis once), the
-    request's Newton values and right-hand sides resident in HBM, one batched
-    factorization + batched solve per tick."""
+    """libmf on the GPU: one symbolic handle per mesh pattern (analysis once), the
+    request's Newton values and right-hand sides resident in HBM, and per cohort one
+    merged batch (mf_batch_analyze once, its numeric handle reused across steps)
+    driving one batched factorization + batched solve per tick.
 
-    def __init__(self, prec="fp32", target_omega=1e-10, margin=0.5, device="cuda:0"):
+    ``payloads`` (optional) maps a request id to what a server receives with the
+    request: (system, [Newton values per step], [right-hand side per step]) as host
+    arrays; without it the backend assembles the request itself.  ``times`` keeps
+    the host-side wall time spent per phase (prepare, merge, factor+solve)."""
+
+    def __init__(self, prec="fp32", target_omega=1e-10, margin=0.5, device="cuda:0", payloads=None):
         import torch
 
         from . import Symbolic
@@ -199,6 +216,10 @@ class MFBackend:
         self.margin = margin
         self.dev = torch.device(device)
         self.stream = torch.cuda.current_stream(self.dev)
+        self.payloads = payloads or {}
+        self.sym_cache = {}
+        self.times = {"prepare": 0.0, "analyze": 0.0, "merge": 0.0, "factor_solve": 0.0}
+        self.batches = {}       # tuple of request ids -> Batch (one per live cohort)
 
     def build(self, req):
         from vivjac import build_2d, build_3d
@@ -207,32 +228,66 @@ class MFBackend:
         return build_3d(req.mesh[1], req.mesh[2], req.mesh[3], req.seed, nu=req.nu, k=req.k)
 
     def prepare(self, req):
-        from vivjac import newton_rhs, newton_values
-        s = self.build(req)
-        sym = self.Symbolic(s.n, s.rowptr, s.colind, s.root)
-        vals = [self.torch.from_numpy(newton_values(s, t)).to(self.dev) for t in range(req.newton_steps)]
-        rhs = [self.torch.from_numpy(newton_rhs(s, t)[0].copy()).to(self.dev) for t in range(req.newton_steps)]
+        t0 = time.perf_counter()
+        if req.rid in self.payloads:
+            s, hv, hb = self.payloads[req.rid]
+        else:
+            from vivjac import newton_rhs, newton_values
+            s = self.build(req)
+            hv = [newton_values(s, t) for t in range(req.newton_steps)]
+            hb = [newton_rhs(s, t)[0].copy() for t in range(req.newton_steps)]
+        sym = self.sym_cache.get(req.mesh)
+        if sym is None:
+            ta = time.perf_counter()
+            sym = self.sym_cache[req.mesh] = self.Symbolic(s.n, s.rowptr, s.colind, s.root)
+            self.times["analyze"] += time.perf_counter() - ta
+        vals = [self.torch.from_numpy(v).to(self.dev) for v in hv]
+        rhs = [self.torch.from_numpy(b).to(self.dev) for b in hb]
         xs = [self.torch.empty(s.n, dtype=self.torch.float64, device=self.dev) for _ in range(req.newton_steps)]
         req.state = dict(system=s, sym=sym, vals=vals, rhs=rhs, xs=xs)
+        self.times["prepare"] += time.perf_counter() - t0
         return sym.footprint_bytes(self.prec, self.margin) + 8 * (s.nnz + 2 * s.n) * req.newton_steps
 
     def step(self, batch):
         from . import Batch
-        B = Batch([r.state["sym"] for r in batch])
-        vals = [r.state["vals"][r.steps_done] for r in batch]
-        bs = [r.state["rhs"][r.steps_done] for r in batch]
-        xs = [r.state["xs"][r.steps_done] for r in batch]
-        B.factor(vals, stream=self.stream, prec=self.prec, target_omega=self.target)
-        _, infos = B.solve(bs, xs=xs, stream=self.stream)
+        t0 = time.perf_counter()
+        merge0 = self.times["merge"]
+        groups = {}
+        for r in batch:
+            groups.setdefault((r.cohort, r.steps_done), []).append(r)
+        infos = {}
+        live = set()
+        for members in groups.values():
+            key = tuple(r.rid for r in members)
+            live.add(key)
+            B = self.batches.get(key)
+            if B is None:
+                tm = time.perf_counter()
+                B = self.batches[key] = Batch([r.state["sym"] for r in members])
+                self.times["merge"] += time.perf_counter() - tm
+            vals = [r.state["vals"][r.steps_done] for r in members]
+            bs = [r.state["rhs"][r.steps_done] for r in members]
+            xs = [r.state["xs"][r.steps_done] for r in members]
+            B.factor(vals, stream=self.stream, prec=self.prec, target_omega=self.target)
+            _, out = B.solve(bs, xs=xs, stream=self.stream)
+            for r, inf in zip(members, out):
+                infos[r.rid] = {"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters}
         self.torch.cuda.synchronize()
-        B.release()
-        return [{"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters} for inf in infos]
+        self.times["factor_solve"] += time.perf_counter() - t0 - (self.times["merge"] - merge0)
+        for key in [k for k in self.batches if k not in live]:
+            self.batches.pop(key).release()
+        return [infos[r.rid] for r in batch]
 
     def release(self, req):
         st = req.state
         st["sym"] = None
         st["vals"] = None
         st["rhs"] = None
+
+    def close(self):
+        for B in self.batches.values():
+            B.release()
+        self.batches.clear()
 
     def idle_until(self, t, clock):
         dt = t - clock()
