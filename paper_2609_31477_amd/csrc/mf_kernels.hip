@@ -537,24 +537,27 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     //   scratch = [ old rows [0, k0) of the w window columns | whole displaced columns ]
     // then window columns go to col_dst (rows < k0 from scratch, rows >= k0 from
     // registers in final row order) and displaced columns to mv_dst
-    T* Wp = (T*)d.W;
-    T* Wm = Wp + (int64_t)kd0 * w;
-    for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
-        const int c = (int)(q / kd0), i = (int)(q % kd0);
-        Wp[q] = F[i + (int64_t)(kd0 + c) * m];
-    }
-    for (int64_t q = tid; q < (int64_t)m * nmove; q += TH) {
-        const int t = (int)(q / m), i = (int)(q % m);
-        Wm[q] = F[i + (int64_t)mv_src[t] * m];
-    }
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
-        const int c = (int)(q / kd0), i = (int)(q % kd0);
-        F[i + (int64_t)col_dst[c] * m] = Wp[q];
-    }
-    for (int64_t q = tid; q < (int64_t)m * nmove; q += TH) {
-        const int t = (int)(q / m), i = (int)(q % m);
-        F[i + (int64_t)mv_dst[t] * m] = Wm[q];
+    // (with no rejected column every window column stays in place and nothing moves)
+    if (nrej > 0) {
+        T* Wp = (T*)d.W;
+        T* Wm = Wp + (int64_t)kd0 * w;
+        for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
+            const int c = (int)(q / kd0), i = (int)(q % kd0);
+            Wp[q] = F[i + (int64_t)(kd0 + c) * m];
+        }
+        for (int64_t q = tid; q < (int64_t)m * nmove; q += TH) {
+            const int t = (int)(q / m), i = (int)(q % m);
+            Wm[q] = F[i + (int64_t)mv_src[t] * m];
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
+            const int c = (int)(q / kd0), i = (int)(q % kd0);
+            F[i + (int64_t)col_dst[c] * m] = Wp[q];
+        }
+        for (int64_t q = tid; q < (int64_t)m * nmove; q += TH) {
+            const int t = (int)(q / m), i = (int)(q % m);
+            F[i + (int64_t)mv_dst[t] * m] = Wm[q];
+        }
     }
 #pragma unroll
     for (int r = 0; r < RS; r++) {
