@@ -101,3 +101,18 @@ def test_gpu_serving_mix_equals_alone():
             xa = alone.state["xs"][t].cpu().numpy()
             assert np.array_equal(xm, xa), f"request {r.rid} step {t} differs alone vs in the mix"
             assert r.results[t]["omega"] <= 1e-10
+
+
+def test_cohorts_group_requests_admitted_together():
+    # requests admitted in the same admission pass share a cohort id; later arrivals get
+    # new ids, and a cohort's members always run the same Newton step together
+    reqs = poisson_requests(30, rate=300.0, seed=5, allow_3d=False)
+    sch, be, done = run_fake(reqs, budget=10 ** 12)
+    assert sch.cohorts >= 2
+    by_cohort = {}
+    for r in done:
+        assert r.cohort >= 0
+        by_cohort.setdefault(r.cohort, []).append(r)
+    for members in by_cohort.values():
+        assert len({r.admitted for r in members}) == 1
+        assert len({r.finished for r in members}) == 1
