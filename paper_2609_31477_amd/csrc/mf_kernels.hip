@@ -641,7 +641,6 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
                                                         int sw) {
     __shared__ T L11[kNBMax * kNBMax];
     __shared__ int pd[2 * kNBMax], ps[2 * kNBMax];
-    __shared__ T stage[2 * kNBMax * 64];
     const int task = tasks[blockIdx.x];
     const int s = slot0 + (task >> 12);
     const FrontNum d = fn[s];
@@ -664,17 +663,25 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
         ps[q] = pairs[2 + 2 * q];
     }
     __syncthreads();
-    // row swaps of the panel, staged through LDS: every source of a column is read
-    // before any destination is written
+    // row swaps of the panel through registers: every source of a column is read
+    // (all loads of a thread issued together) before any destination is written
     {
+        constexpr int kQ = 2 * kNBMax / (kThreads / 64);
         const int jl = c0 + (tid & 63);
         const bool live = jl < cend && !(jl >= kd0 && jl < kd1) && !(jl >= d.x0 && jl < d.x1);
         T* cp = F + (int64_t)jl * m;
-        for (int q = tid >> 6; q < np; q += kThreads / 64)
-            if (live) stage[q * 64 + (tid & 63)] = cp[ps[q]];
+        T tmp[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; i++) {
+            const int q = (tid >> 6) + i * (kThreads / 64);
+            tmp[i] = (live && q < np) ? cp[ps[q]] : T(0);
+        }
         __syncthreads();
-        for (int q = tid >> 6; q < np; q += kThreads / 64)
-            if (live) cp[pd[q]] = stage[q * 64 + (tid & 63)];
+#pragma unroll
+        for (int i = 0; i < kQ; i++) {
+            const int q = (tid >> 6) + i * (kThreads / 64);
+            if (live && q < np) cp[pd[q]] = tmp[i];
+        }
         __syncthreads();
     }
     // new U rows: unit-lower solve with L11, half a wave per column (lane = row of
@@ -769,17 +776,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = acc_t{0, 0, 0, 0};
+    constexpr int kPer = kKC * kTile / kThreads;  // staged elements per thread and operand
     for (int k0 = ka; k0 < kb; k0 += kKC) {
         const int kc = min(kKC, kb - k0);
-        for (int idx = tid; idx < kKC * kTile; idx += kThreads) {
+        // all global loads of the chunk first, then the LDS stores (a load after an
+        // LDS store could not be hoisted above it, which would serialize the latencies)
+        T ra[kPer], rb[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int idx = tid + q * kThreads;
             const int r = idx % kTile, a = idx / kTile;
             const int row = row0 + r;
-            As[a * kLdsPad + r] = (a < kc && row < m) ? F[row + (int64_t)(k0 + a) * m] : T(0);
+            ra[q] = (a < kc && row < m) ? F[row + (int64_t)(k0 + a) * m] : T(0);
         }
-        for (int idx = tid; idx < kKC * kTile; idx += kThreads) {
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int idx = tid + q * kThreads;
             const int a = idx % kKC, c = idx / kKC;
             const int col = col0 + c;
-            Bs[a * kLdsPad + c] = (a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : T(0);
+            rb[q] = (a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int idx = tid + q * kThreads;
+            As[(idx / kTile) * kLdsPad + idx % kTile] = ra[q];
+            Bs[(idx % kKC) * kLdsPad + idx / kKC] = rb[q];
         }
         __syncthreads();
 #pragma unroll
@@ -808,12 +829,25 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
             }
     __syncthreads();
     T* Fw = (T*)d.F;
-    for (int idx = tid; idx < kTile * kTile; idx += kThreads) {
+    // read every C entry of this thread before the first store, then update
+    constexpr int kOut = kTile * kTile / kThreads;
+    T cold[kOut];
+    bool live[kOut];
+#pragma unroll
+    for (int q = 0; q < kOut; q++) {
+        const int idx = tid + q * kThreads;
         const int i = idx % kTile, j = idx / kTile;
         const int row = row0 + i, col = col0 + j;
-        if (row < rlo || row >= m || col >= m || col < rlo) continue;
-        if (mode == 0 && ((row >= P && col >= P) || (col >= d.x0 && col < d.x1))) continue;
-        Fw[row + (int64_t)col * m] -= Cs[j * kLdsPad + i];
+        bool ok = !(row < rlo || row >= m || col >= m || col < rlo);
+        if (mode == 0 && ((row >= P && col >= P) || (col >= d.x0 && col < d.x1))) ok = false;
+        live[q] = ok;
+        cold[q] = ok ? Fw[row + (int64_t)col * m] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kOut; q++) {
+        const int idx = tid + q * kThreads;
+        const int i = idx % kTile, j = idx / kTile;
+        if (live[q]) Fw[(row0 + i) + (int64_t)(col0 + j) * m] = cold[q] - Cs[j * kLdsPad + i];
     }
 }
 
