@@ -882,17 +882,30 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = flt4{0, 0, 0, 0};
+    constexpr int kPerB = kKB * kTile / kThreads;
     for (int k0 = 0; k0 < kb; k0 += kKB) {
         const int kc = min(kKB, kb - k0);
-        for (int idx = tid; idx < kKB * kTile; idx += kThreads) {
+        // global loads of the chunk first, then the LDS stores (see k_gemm)
+        float ra[kPerB], rb[kPerB];
+#pragma unroll
+        for (int q = 0; q < kPerB; q++) {
+            const int idx = tid + q * kThreads;
             const int r = idx % kTile, a = idx / kTile;
             const int row = row0 + r;
-            As[r * kKBPad + a] = (__bf16)((a < kc && row < m) ? F[row + (int64_t)(k0 + a) * m] : 0.0f);
+            ra[q] = (a < kc && row < m) ? F[row + (int64_t)(k0 + a) * m] : 0.0f;
         }
-        for (int idx = tid; idx < kKB * kTile; idx += kThreads) {
+#pragma unroll
+        for (int q = 0; q < kPerB; q++) {
+            const int idx = tid + q * kThreads;
             const int a = idx % kKB, c = idx / kKB;
             const int col = col0 + c;
-            Bs[c * kKBPad + a] = (__bf16)((a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : 0.0f);
+            rb[q] = (a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kPerB; q++) {
+            const int idx = tid + q * kThreads;
+            As[(idx % kTile) * kKBPad + idx / kTile] = (__bf16)ra[q];
+            Bs[(idx / kKB) * kKBPad + idx % kKB] = (__bf16)rb[q];
         }
         __syncthreads();
         bf16x8 av[2], bv[2];
@@ -921,11 +934,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
             }
     __syncthreads();
     float* Fw = (float*)d.F;
-    for (int idx = tid; idx < kTile * kTile; idx += kThreads) {
+    constexpr int kOutB = kTile * kTile / kThreads;
+    float cold[kOutB];
+#pragma unroll
+    for (int q = 0; q < kOutB; q++) {
+        const int idx = tid + q * kThreads;
+        const int row = row0 + idx % kTile, col = col0 + idx / kTile;
+        cold[q] = (row < m && col < m) ? Fw[row + (int64_t)col * m] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kOutB; q++) {
+        const int idx = tid + q * kThreads;
         const int i = idx % kTile, j = idx / kTile;
         const int row = row0 + i, col = col0 + j;
-        if (row >= m || col >= m) continue;
-        Fw[row + (int64_t)col * m] -= Cs[j * kLdsPad + i];
+        if (row < m && col < m) Fw[row + (int64_t)col * m] = cold[q] - Cs[j * kLdsPad + i];
     }
 }
 
