@@ -72,6 +72,17 @@ typedef struct {
                               them, while residuals and omega are of J itself.
                               With power-of-two factors one sweep already reaches the
                               fixed point on the Jacobians here. 0 = none; default 1 */
+    int32_t plan;          /* 1 = planned schedule: after a factorization that synchronizes
+                              once per tree level, the handle keeps every front's
+                              delayed-in count plus slack as a capacity that fixes its
+                              storage, tile lists and launch shapes, and the following
+                              factorizations on the handle enqueue all levels at once with
+                              a single synchronization at the end; a front that outgrows
+                              its capacity makes that call repeat the factorization level
+                              by level (same result) and enlarges the plan.  On the
+                              256x128 Jacobians it is no faster: the extra empty panel
+                              rounds that capacities add cost about what the per-level
+                              synchronizations do.  0 = synchronize per level; default 0 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */
@@ -143,8 +154,9 @@ mf_status mf_symbolic_export(mf_sym_t sym, mf_symbolic_view* out);
  * with no acceptable pivot among the fully summed rows is delayed to the parent
  * front (the zero pressure and multiplier diagonals of Sec. 3.2 make this
  * common).  The root front always factors in FP64 with partial pivoting.
- * The call synchronizes with `stream` once per tree level (front sizes depend
- * on the delays); factors stay resident on the device.
+ * Front sizes depend on the delays, so a call synchronizes with `stream` once
+ * per tree level, except under options.plan once the handle has a plan: then
+ * it synchronizes once.  Factors stay resident on the device.
  * Errors: MF_ERR_SINGULAR (a root column without a pivot; message names the
  * front and column), MF_ERR_DEVICE, MF_ERR_OOM, MF_ERR_ARG.
  */
@@ -169,6 +181,8 @@ typedef struct {
     double t_panel_kernel_ms;   /* the panel kernel alone (sum over its launches) */
     double panel_flops;         /* nominal panel flops (no delays): per window pivot, scaling + rank-1 update */
     int32_t panel_launches;     /* panel kernel launches timed */
+    int32_t planned;            /* 1 if this factorization ran on the planned schedule */
+    int32_t plan_fallbacks;     /* planned runs on this handle repeated level by level (overflow) */
 } mf_factor_info;
 
 mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);

@@ -42,6 +42,9 @@ hipError_t launch_vadd(const DevSym& S, double* x, const double* V, int64_t ldv,
 hipError_t launch_scale(const DevSym& S, double* y, const double* x, const double* a, int astride, int64_t n,
                         hipStream_t st);
 hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st);
+hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count,
+                              int32_t* overflow, hipStream_t st);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
                            unsigned long long* omega_bits, hipStream_t st);
@@ -195,7 +198,39 @@ struct mf_num {
     size_t tasks_cap = 0;        // entries
     std::vector<int32_t> task_scratch;
     mf_factor_info info{};
+    // Planned schedule.  A factorization that synchronizes once per level learns
+    // every front's delayed-in count; the plan gives each front a capacity (that
+    // count plus slack) and fixes from it all storage, tile lists and launch
+    // shapes, so the next factorizations on this handle enqueue every level at
+    // once and synchronize only at the end.  A front that outgrows its capacity
+    // flags the run, which is then repeated with per-level synchronization.
+    struct Plan {
+        bool valid = false;
+        int32_t prec = -1;
+        std::vector<int32_t> din_cap;  // per slot
+        FrontNum* d_tmpl = nullptr;    // per slot: storage pointers, offsets, din = capacity
+        int32_t* d_tasks = nullptr;    // tile lists of all levels
+        std::vector<LevelTasks> tasks; // per level, pointing into d_tasks
+        std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];
+        std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];
+        int64_t vec_len = 0;
+        int32_t* d_flag = nullptr;  // overflow flag
+        int32_t* h_flag = nullptr;  // pinned mirror
+        void free_device() {
+            if (d_tmpl) (void)hipFree(d_tmpl);
+            if (d_tasks) (void)hipFree(d_tasks);
+            if (d_flag) (void)hipFree(d_flag);
+            if (h_flag) (void)hipHostFree(h_flag);
+            d_tmpl = nullptr;
+            d_tasks = nullptr;
+            d_flag = nullptr;
+            h_flag = nullptr;
+            valid = false;
+        }
+    } plan;
+    int32_t plan_fallbacks = 0;
     ~mf_num() {
+        plan.free_device();
         fronts.release();
         ints.release();
         wsp.release();
@@ -293,32 +328,56 @@ void ensure_device_symbolic(mf_sym* h) {
 
 int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 || is_root) ? 0 : 1; }
 
-// Tile work lists of one level (entries as in LevelTasks), uploaded once per level
-// and shared by both precisions (each kernel skips fronts of the other one).  The
-// previous level has been synchronized, so the pinned staging can be reused.
-LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st) {
-    std::vector<int32_t>& t = N->task_scratch;
-    t.clear();
+// Tile work lists of one level (entries as in LevelTasks, appended to t), shared by
+// both precisions (each kernel skips fronts of the other one).  The result holds
+// the counts and the swap width; place_tasks points it at a device copy.
+LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t) {
+    const size_t base = t.size();
     // few (large) fronts: narrow swap tiles so that more blocks share the latency-bound work
     const int sw = count < 32 ? 16 : 64;
     for (int i = 0; i < count; i++) {
         const int T = (hf[i].m + sw - 1) / sw;
         for (int a = 0; a < T; a++) t.push_back(task_code(i, a >> 6, a & 63));
     }
-    const size_t nswap = t.size();
+    const size_t nswap = t.size() - base;
     for (int i = 0; i < count; i++) {
         const int m = hf[i].m, P = hf[i].P, T = (m + 63) / 64;
         for (int a = 0; a < T; a++)
             for (int b = 0; b < T; b++)
                 if (!(a * 64 >= P && b * 64 >= P)) t.push_back(task_code(i, a, b));
     }
-    const size_t ng0 = t.size() - nswap;
+    const size_t ng0 = t.size() - base - nswap;
     for (int i = 0; i < count; i++) {
         const int T = (hf[i].m - hf[i].P + 63) / 64;
         for (int a = 0; a < T; a++)
             for (int b = 0; b < T; b++) t.push_back(task_code(i, a, b));
     }
-    const size_t ng1 = t.size() - nswap - ng0;
+    const size_t ng1 = t.size() - base - nswap - ng0;
+    LevelTasks tk;
+    tk.swap = nullptr;
+    tk.nswap = (int32_t)nswap;
+    tk.swap_cols = sw;
+    tk.g0 = nullptr;
+    tk.ng0 = (int32_t)ng0;
+    tk.g1 = nullptr;
+    tk.ng1 = (int32_t)ng1;
+    return tk;
+}
+
+// Point a level's lists at their device copy starting at d.
+LevelTasks place_tasks(LevelTasks tk, const int32_t* d) {
+    tk.swap = d;
+    tk.g0 = d + tk.nswap;
+    tk.g1 = d + tk.nswap + tk.ng0;
+    return tk;
+}
+
+// Uploaded once per level by the synchronizing schedule: the previous level has
+// been synchronized, so the pinned staging can be reused.
+LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st) {
+    std::vector<int32_t>& t = N->task_scratch;
+    t.clear();
+    const LevelTasks tk = build_level_tasks(hf, count, t);
     if (t.size() > N->tasks_cap) {
         if (N->d_tasks) HIPX(hipFree(N->d_tasks));
         if (N->h_tasks) HIPX(hipHostFree(N->h_tasks));
@@ -332,15 +391,165 @@ LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStrea
     }
     std::copy(t.begin(), t.end(), N->h_tasks);
     if (!t.empty()) HIPX(hipMemcpyAsync(N->d_tasks, N->h_tasks, sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, st));
-    LevelTasks tk;
-    tk.swap = N->d_tasks;
-    tk.nswap = (int32_t)nswap;
-    tk.swap_cols = sw;
-    tk.g0 = N->d_tasks + nswap;
-    tk.ng0 = (int32_t)ng0;
-    tk.g1 = N->d_tasks + nswap + ng0;
-    tk.ng1 = (int32_t)ng1;
-    return tk;
+    return place_tasks(tk, N->d_tasks);
+}
+
+// Slack of a planned front over the delayed-in count it was planned from.
+int plan_capacity(int din) { return din + 16 + din / 2; }
+
+// Build the plan from the delayed-in counts of the factorization just finished
+// (h_fn).  Capacities never shrink on a handle, so a plan rebuilt after an
+// overflow covers both runs.  Storage is laid out afresh from the arenas' start:
+// the finished factors stay where they are until the next factorization writes.
+void build_plan(mf_num* N) {
+    const Symbolic& S = N->sym->S;
+    const mf_options& o = N->opt;
+    const int nf = S.nf;
+    mf_num::Plan& pl = N->plan;
+    const FrontNum* hf = N->h_fn;
+    const bool grow = pl.prec == o.prec && (int)pl.din_cap.size() == nf;
+    std::vector<int32_t> cap(nf);
+    for (int sl = 0; sl < nf; sl++) {
+        const int c = plan_capacity(hf[sl].din);
+        cap[sl] = grow ? std::max(pl.din_cap[sl], c) : c;
+    }
+    pl.free_device();
+    std::vector<FrontNum> tm(std::max(nf, 1));
+    for (int p = 0; p < 2; p++) {
+        pl.lvl_mmax[p].assign(S.nlevels, 0);
+        pl.lvl_Pmax[p].assign(S.nlevels, 0);
+        pl.lvl_cnt[p].assign(S.nlevels, 0);
+        pl.lvl_cls_mmax[p].assign(S.nlevels, {0, 0, 0, 0});
+        pl.lvl_cls_Pmax[p].assign(S.nlevels, {0, 0, 0, 0});
+    }
+    N->fronts.reset();
+    N->ints.reset();
+    std::vector<int32_t> tasks;
+    std::vector<size_t> toff(S.nlevels);
+    pl.tasks.assign(S.nlevels, LevelTasks{});
+    int64_t voff = 0;
+    for (int L = 0; L < S.nlevels; L++) {
+        const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
+        N->wsp.reset();
+        for (int sl = s0; sl < s1; sl++) {
+            const int f = S.level_fronts[sl];
+            FrontNum& t = tm[sl];
+            t = FrontNum{};
+            t.npiv = S.npiv[f];
+            t.mnom = S.mnom[f];
+            t.din = cap[sl];
+            t.m = t.mnom + cap[sl];  // capacity; the level setup writes the actual order
+            t.P = t.npiv + cap[sl];
+            t.pcur = t.P;
+            t.prec = front_prec(o, S.front_parent[f] < 0);
+            const size_t esz = t.prec ? 4 : 8;
+            t.F = N->fronts.alloc(std::max<size_t>(esz * (size_t)t.m * (size_t)t.m, 8));
+            t.iv = (int32_t*)N->ints.alloc(sizeof(int32_t) * (size_t)iv_size(t.P, t.m));
+            t.voff = voff;
+            voff += t.m;
+            // any class the actual order falls in has a window of at most kNBMax
+            t.W = N->wsp.alloc((size_t)2 * t.m * kNBMax * esz);
+            const int p = t.prec;
+            const int cls = t.m <= 512 ? 0 : (t.m <= 1024 ? 1 : (t.m <= 2048 ? 2 : 3));
+            pl.lvl_cls_mmax[p][L][cls] = std::max(pl.lvl_cls_mmax[p][L][cls], t.m);
+            pl.lvl_cls_Pmax[p][L][cls] = std::max(pl.lvl_cls_Pmax[p][L][cls], t.P);
+            pl.lvl_mmax[p][L] = std::max(pl.lvl_mmax[p][L], t.m);
+            pl.lvl_Pmax[p][L] = std::max(pl.lvl_Pmax[p][L], t.P);
+            pl.lvl_cnt[p][L]++;
+        }
+        for (int p = 0; p < 2; p++)
+            if (pl.lvl_cnt[p][L] &&
+                ((size_t)pl.lvl_Pmax[p][L] * 2 * sizeof(int) > kMaxLds || pl.lvl_mmax[p][L] > 4096))
+                return;  // capacities beyond the kernels' limits: keep synchronizing per level
+        toff[L] = tasks.size();
+        pl.tasks[L] = build_level_tasks(tm.data() + s0, s1 - s0, tasks);
+    }
+    HIPX(hipMalloc((void**)&pl.d_tmpl, sizeof(FrontNum) * tm.size()));
+    HIPX(hipMemcpy(pl.d_tmpl, tm.data(), sizeof(FrontNum) * tm.size(), hipMemcpyHostToDevice));
+    HIPX(hipMalloc((void**)&pl.d_tasks, sizeof(int32_t) * std::max<size_t>(tasks.size(), 1)));
+    if (!tasks.empty())
+        HIPX(hipMemcpy(pl.d_tasks, tasks.data(), sizeof(int32_t) * tasks.size(), hipMemcpyHostToDevice));
+    for (int L = 0; L < S.nlevels; L++) pl.tasks[L] = place_tasks(pl.tasks[L], pl.d_tasks + toff[L]);
+    HIPX(hipMalloc((void**)&pl.d_flag, sizeof(int32_t)));
+    HIPX(hipHostMalloc((void**)&pl.h_flag, sizeof(int32_t), hipHostMallocDefault));
+    pl.vec_len = voff;
+    pl.din_cap = cap;
+    pl.prec = o.prec;
+    pl.valid = true;
+}
+
+// Factor info of a finished run from its fronts' final bookkeeping (h_fn).
+mf_factor_info finished_info(const mf_num* N) {
+    const Symbolic& S = N->sym->S;
+    const FrontNum* hf = N->h_fn;
+    mf_factor_info info{};
+    info.factor_flops = S.nominal_flops;
+    for (int sl = 0; sl < S.nf; sl++) {
+        const FrontNum& fr = hf[sl];
+        const size_t esz = fr.prec ? 4 : 8;
+        info.factor_bytes += (int64_t)(esz * (size_t)fr.m * (size_t)fr.m);
+        info.max_front = std::max(info.max_front, fr.m);
+        const double m = fr.m, pp = fr.P;
+        for (int64_t i = (int64_t)(m - pp); i < (int64_t)m; i++) info.actual_flops += (double)i + 2.0 * (double)i * (double)i;
+        const double cb = (double)(fr.m - fr.P);
+        info.schur_flops += 2.0 * cb * cb * (double)fr.k;
+        const int dout = fr.P - fr.k;
+        info.delayed_pivots += dout;
+        const int f = S.level_fronts[sl];
+        if (S.front_parent[f] < 0) {
+            info.root_order = std::max(info.root_order, fr.m);
+            if (dout > 0)
+                throw Fail{MF_ERR_SINGULAR, "root front " + std::to_string(f) + " (order " + std::to_string(fr.m) +
+                                                "): no acceptable pivot for column position " + std::to_string(fr.k) +
+                                                " (numerically singular or non-finite)"};
+        }
+    }
+    info.levels = S.nlevels;
+    return info;
+}
+
+// The planned schedule: every level enqueued at once, one synchronization at the
+// end.  Returns false (nothing usable) when a front outgrew its capacity.
+bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
+    mf_sym* H = N->sym;
+    const Symbolic& S = H->S;
+    SymDev& D = *H->dev;
+    const mf_options& o = N->opt;
+    mf_num::Plan& pl = N->plan;
+    HIPX(launch_fill_i32(pl.d_flag, 0, st));
+    for (int L = 0; L < S.nlevels; L++) {
+        const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
+        HIPX(launch_level_setup(D.S, N->d_fn, pl.d_tmpl, s0, s1 - s0, pl.d_flag, st));
+        const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
+        if (pl.lvl_cnt[0][L])
+            HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[0][L],
+                                             pl.lvl_cls_mmax[0][L].data(), pl.lvl_cls_Pmax[0][L].data(), fvals, u0,
+                                             u1, o.pivot_u, 0, pl.tasks[L], st, nullptr, false, nullptr));
+        if (pl.lvl_cnt[1][L])
+            HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[1][L],
+                                            pl.lvl_cls_mmax[1][L].data(), pl.lvl_cls_Pmax[1][L].data(), fvals, u0,
+                                            u1, o.pivot_u, 1, pl.tasks[L], st, nullptr, o.prec == MF_BF16, nullptr));
+    }
+    HIPX(hipMemcpyAsync(N->h_fn, N->d_fn, sizeof(FrontNum) * S.nf, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(pl.h_flag, pl.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    if (*pl.h_flag) {
+        N->plan_fallbacks++;
+        return false;
+    }
+    for (int p = 0; p < 2; p++) {
+        N->lvl_mmax[p] = pl.lvl_mmax[p];
+        N->lvl_Pmax[p] = pl.lvl_Pmax[p];
+        N->lvl_cnt[p] = pl.lvl_cnt[p];
+        N->lvl_cls_mmax[p] = pl.lvl_cls_mmax[p];
+        N->lvl_cls_Pmax[p] = pl.lvl_cls_Pmax[p];
+    }
+    N->vec_len = pl.vec_len;
+    N->info = finished_info(N);
+    N->info.planned = 1;
+    N->info.plan_fallbacks = N->plan_fallbacks;
+    N->factored = true;
+    return true;
 }
 
 void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double* const* seg_values = nullptr) {
@@ -378,6 +587,8 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         HIPX(launch_ruiz(D.S, N->d_vals, S.n, o.scale, N->d_dr, N->d_dc, N->d_rmax, N->d_cmax, N->d_svals, st));
         fvals = N->d_svals;
     }
+    const bool use_plan = o.plan != 0 && o.profile == 0 && N->plan.valid && N->plan.prec == o.prec;
+    if (use_plan && factor_planned(N, fvals, st)) return;
     if (N->fronts.chunks.empty()) {
         double tot = 0;
         for (int f = 0; f < nf; f++) tot += (double)S.mnom[f] * S.mnom[f];
@@ -544,8 +755,10 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     }
     N->vec_len = voff;
     info.factor_bytes = front_bytes;
+    info.plan_fallbacks = N->plan_fallbacks;
     N->info = info;
     N->factored = true;
+    if (o.plan != 0) build_plan(N);
 }
 
 void ensure_solve_buffers(mf_num* N, int nrhs) {
@@ -883,6 +1096,7 @@ void mf_default_options(mf_options* o) {
     o->panel_nb = 32;
     o->profile = 0;
     o->scale = 1;
+    o->plan = 0;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -957,6 +1171,7 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
         N->opt.panel_nb = opt->panel_nb;
         N->opt.profile = opt->profile;
         N->opt.scale = opt->scale;
+        N->opt.plan = opt->plan;
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");

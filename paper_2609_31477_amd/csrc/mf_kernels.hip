@@ -34,6 +34,19 @@ constexpr int kTile = 64;         // GEMM tile (rows and columns)
 constexpr int kKC = 32;           // GEMM K chunk staged through LDS
 constexpr int kLdsPad = kTile + 1;
 
+// Pointers read out of a FrontNum are generic to the compiler, so their accesses
+// become flat instructions, which count on the same wait counter as LDS: every
+// LDS access would then wait for all front loads in flight, and the loads would
+// wait for one another.  Front storage is device global memory; casting to the
+// global address space gives global loads and stores with their own in-order
+// counter.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+    return (gptr<T>)p;
+}
+
 // Position of parent (pre-pivot) row i inside child c's contribution block, or -1.
 // dseg: start of c's segment inside the parent's delayed-in block; dout: c's
 // delayed-out count; im: c's inverse nominal map (indexed by parent nominal row).
@@ -161,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(DevSym S, FrontNum* fn, co
     if (c >= d.npiv) c += d.din;
     double v = 0.0;
     for (int64_t q = S.ue_src_ptr[u]; q < S.ue_src_ptr[u + 1]; q++) v += vals[S.ue_src[q]];
-    T* F = (T*)d.F;
+    const gptr<T> F = as_global((T*)d.F);
     const int64_t idx = r + (int64_t)c * d.m;
     F[idx] = (T)((double)F[idx] + v);
 }
@@ -312,7 +325,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         return;
     }
     const int w = min(NB, pc - kd0);
-    T* F = (T*)d.F;
+    const gptr<T> F = as_global((T*)d.F);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int* lmap = dyn;
     int* dstm = dyn + (P - kd0);
@@ -522,8 +535,8 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     }
     __syncthreads();
     // column tags (before any column moves)
-    int32_t* colperm = iv_colperm(d.iv, P, m);
-    int32_t* rowperm = iv_rowperm(d.iv, P, m);
+    const gptr<int32_t> colperm = as_global(iv_colperm(d.iv, P, m));
+    const gptr<int32_t> rowperm = as_global(iv_rowperm(d.iv, P, m));
     if (tid < w) old_tag[tid] = colperm[kd0 + tid];
     if (tid < nmove) mv_tag[tid] = colperm[mv_src[tid]];
     int rtag[RS];  // rows [k0, P) lie within the TH * RS register rows
@@ -539,8 +552,8 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // registers in final row order) and displaced columns to mv_dst
     // (with no rejected column every window column stays in place and nothing moves)
     if (nrej > 0) {
-        T* Wp = (T*)d.W;
-        T* Wm = Wp + (int64_t)kd0 * w;
+        const gptr<T> Wp = as_global((T*)d.W);
+        const gptr<T> Wm = Wp + (int64_t)kd0 * w;
         for (int64_t q = tid; q < (int64_t)kd0 * w; q += TH) {
             const int c = (int)(q / kd0), i = (int)(q % kd0);
             Wp[q] = F[i + (int64_t)(kd0 + c) * m];
@@ -578,7 +591,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // (destination, source) row pairs for the columns outside the window
     if (tid == 0) npairs_s = 0;
     __syncthreads();
-    int32_t* pairs = iv_pairs(d.iv, P, m);
+    const gptr<int32_t> pairs = as_global(iv_pairs(d.iv, P, m));
     for (int i = kd0 + tid; i < P; i += TH) {
         const int src = lmap[i - kd0];
         if (src != i) {
@@ -650,8 +663,8 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     if (nb <= 0) return;
     const int c0 = (task & 4095) * sw, cend = min(c0 + sw, m);
     if (c0 >= m) return;
-    T* F = (T*)d.F;
-    const int32_t* pairs = iv_pairs(d.iv, P, m);
+    const gptr<T> F = as_global((T*)d.F);
+    const gptr<const int32_t> pairs = as_global(iv_pairs(d.iv, P, m));
     const int np = pairs[0];
     const int tid = threadIdx.x;
     for (int idx = tid; idx < nb * nb; idx += kThreads) {
@@ -669,7 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
         constexpr int kQ = 2 * kNBMax / (kThreads / 64);
         const int jl = c0 + (tid & 63);
         const bool live = jl < cend && !(jl >= kd0 && jl < kd1) && !(jl >= d.x0 && jl < d.x1);
-        T* cp = F + (int64_t)jl * m;
+        const gptr<T> cp = F + (int64_t)jl * m;
         T tmp[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; i++) {
@@ -690,7 +703,7 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     for (int jj = c0 + 2 * (tid >> 6); jj < cend; jj += 2 * (kThreads / 64)) {
         const int j = jj + half;
         const bool live = j < cend && j >= kd1 && !(j >= d.x0 && j < d.x1);
-        T* colp = F + (int64_t)j * m + kd0;
+        const gptr<T> colp = F + (int64_t)j * m + kd0;
         double x = (live && r < nb) ? (double)colp[r] : 0.0;
         for (int a = 0; a < nb - 1; a++) {
             const long long xb = __double_as_longlong(x);
@@ -767,7 +780,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
     if (col0 >= m || row0 >= m || row0 + kTile <= rlo || col0 + kTile <= rlo) return;
     if (mode == 0 && row0 >= P && col0 >= P) return;
     if (mode == 0 && col0 >= d.x0 && col0 + kTile <= d.x1) return;
-    const T* F = (const T*)d.F;
+    const gptr<const T> F = as_global((const T*)d.F);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wi = wid & 1, wj = wid >> 1;
     typedef typename Mfma<T>::acc_t acc_t;
@@ -828,7 +841,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
                 Cs[j * kLdsPad + i] = acc[bi][bj][r];
             }
     __syncthreads();
-    T* Fw = (T*)d.F;
+    const gptr<T> Fw = as_global((T*)d.F);
     // read every C entry of this thread before the first store, then update
     constexpr int kOut = kTile * kTile / kThreads;
     T cold[kOut];
@@ -874,7 +887,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
     const int col0 = P + (task & 63) * kTile;
     const int row0 = P + ((task >> 6) & 63) * kTile;
     if (col0 >= m || row0 >= m) return;
-    const float* F = (const float*)d.F;
+    const gptr<const float> F = as_global((const float*)d.F);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wi = wid & 1, wj = wid >> 1;
     flt4 acc[2][2];
@@ -933,7 +946,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
                 Cs[j * kLdsPad + i] = acc[bi][bj][r];
             }
     __syncthreads();
-    float* Fw = (float*)d.F;
+    const gptr<float> Fw = as_global((float*)d.F);
     constexpr int kOutB = kTile * kTile / kThreads;
     float cold[kOutB];
 #pragma unroll
@@ -951,6 +964,44 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
     }
 }
 
+// Start of a tree level in the planned schedule: each front's delayed-in count is
+// the sum of its children's delayed-out counts (P - k), read from the children's
+// finished bookkeeping, and the front's order and fully summed count follow from
+// it.  Everything else (storage, scratch, vector offset) comes from the template,
+// whose din field holds the capacity the storage was sized for.  A front that
+// would outgrow it raises *overflow and is clamped to the capacity, which keeps
+// every later access of the level inside its allocations; the caller discards
+// such a factorization.  One thread per front.
+__global__ __launch_bounds__(kThreads) void k_level_setup(DevSym S, FrontNum* fn, const FrontNum* tmpl, int slot0,
+                                                          int count, int32_t* overflow) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= count) return;
+    const int s = slot0 + q;
+    FrontNum d = tmpl[s];
+    int din = 0;
+    for (int t = S.child_ptr[s]; t < S.child_ptr[s + 1]; t++) {
+        const int cs = S.child_slot[t];
+        din += fn[cs].P - fn[cs].k;
+    }
+    if (din > d.din) {
+        *overflow = 1;
+        din = d.din;
+    }
+    d.din = din;
+    d.m = d.mnom + din;
+    d.P = d.npiv + din;
+    d.k = 0;
+    d.k0 = 0;
+    d.pcur = d.P;
+    d.x0 = 0;
+    d.x1 = 0;
+    fn[s] = d;
+}
+
+__global__ __launch_bounds__(64) void k_fill_i32(int32_t* y, int32_t v) {
+    if (threadIdx.x == 0) *y = v;
+}
+
 // Post-factorization bookkeeping: column variables in final order.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, int slot0, int want_prec) {
@@ -959,8 +1010,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, i
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P;
     const int32_t* rows = S.rows + S.rows_ptr[s];
-    const int32_t* colperm = iv_colperm(d.iv, P, m);
-    int32_t* colvar = iv_colvar(d.iv, P, m);
+    const gptr<const int32_t> colperm = as_global(iv_colperm(d.iv, P, m));
+    const gptr<int32_t> colvar = as_global(iv_colvar(d.iv, P, m));
     const int cb = S.child_ptr[s], ce = S.child_ptr[s + 1];
     for (int i = threadIdx.x; i < m; i += kThreads) {
         const int src = i < P ? colperm[i] : i;
@@ -974,7 +1025,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(DevSym S, FrontNum* fn, i
                 const FrontNum dc = fn[S.child_slot[tt]];
                 const int dout = dc.P - dc.k;
                 if (off < dout) {
-                    v = iv_colvar(dc.iv, dc.P, dc.m)[dc.k + off];
+                    v = as_global(iv_colvar(dc.iv, dc.P, dc.m))[dc.k + off];
                     break;
                 }
                 off -= dout;
@@ -1005,7 +1056,7 @@ constexpr int kGemvRows = 64;    // rows per block of the solve GEMVs
 // stride m) with a vector in LDS.  A full strip is unrolled with 8 accumulators,
 // so all 64 loads of the row are in flight together.
 template <typename T>
-__device__ __forceinline__ double block_dot(const T* Fi, int64_t m, const double* z, int bs) {
+__device__ __forceinline__ double block_dot(gptr<const T> Fi, int64_t m, const double* z, int bs) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (bs == kBS) {
 #pragma unroll
@@ -1025,8 +1076,8 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P, k = d.k;
-    const T* F = (const T*)d.F;
-    const int32_t* rowperm = iv_rowperm(d.iv, P, m);
+    const gptr<const T> F = as_global((const T*)d.F);
+    const gptr<const int32_t> rowperm = as_global(iv_rowperm(d.iv, P, m));
     const int32_t* rows = S.rows + S.rows_ptr[s];
     double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1052,10 +1103,16 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
     for (int j0 = 0; j0 < k; j0 += kBS) {
         const int bs = min(kBS, k - j0);
         if (wid == 0) {
+            // every lane loads an in-range entry (row and column clamped into the
+            // block) and masks it afterwards: the 64 loads are unconditional and all
+            // in flight together instead of one branch (and wait) per column
             double Lr[kBS];
+            const int lr = j0 + min(lane, bs - 1);
 #pragma unroll
-            for (int a = 0; a < kBS; a++)
-                Lr[a] = (lane < bs && a < lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + a) * m] : 0.0;
+            for (int a = 0; a < kBS; a++) {
+                const double t = (double)F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+                Lr[a] = ((lane < bs) & (a < lane)) ? t : 0.0;
+            }
             for (int c = 0; c < nrc; c++) {
                 double x = lane < bs ? zs[j0 + lane + c * m] : 0.0;
 #pragma unroll
@@ -1068,7 +1125,7 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
         }
         __syncthreads();
         for (int i = j0 + bs + tid; i < k; i += TT) {
-            const T* Fi = F + i + (int64_t)j0 * m;
+            const gptr<const T> Fi = F + i + (int64_t)j0 * m;
             for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
         }
         __syncthreads();
@@ -1083,7 +1140,7 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
 // partial sums added in wave order (deterministic).  Returns the row's dot
 // product in wave 0; other waves return 0.
 template <typename T>
-__device__ __forceinline__ double tile_dot(const T* Fcol0, int64_t m, const double* xv, int ncols, double* part) {
+__device__ __forceinline__ double tile_dot(gptr<const T> Fcol0, int64_t m, const double* xv, int ncols, double* part) {
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int j = g;
@@ -1114,7 +1171,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int s
     const int m = d.m, k = d.k;
     const int i0 = k + blockIdx.x * kGemvRows;
     if (i0 >= m || k == 0) return;
-    const T* F = (const T*)d.F;
+    const gptr<const T> F = as_global((const T*)d.F);
     double* v = vec + d.voff * nrhs;
     for (int j = threadIdx.x; j < k; j += kThreads)
         for (int c = 0; c < nrc; c++) ys[j + c * k] = v[j + (int64_t)(c0 + c) * m];
@@ -1138,8 +1195,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
     const int m = d.m, P = d.P, k = d.k;
     const int i0 = blockIdx.x * kGemvRows;
     if (i0 >= k || k == m) return;
-    const T* F = (const T*)d.F;
-    const int32_t* colvar = iv_colvar(d.iv, P, m);
+    const gptr<const T> F = as_global((const T*)d.F);
+    const gptr<const int32_t> colvar = as_global(iv_colvar(d.iv, P, m));
     double* v = vec + d.voff * nrhs;
     const int nc = m - k;
     for (int j = threadIdx.x; j < nc; j += kThreads) {
@@ -1162,8 +1219,8 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m, P = d.P, k = d.k;
-    const T* F = (const T*)d.F;
-    const int32_t* colvar = iv_colvar(d.iv, P, m);
+    const gptr<const T> F = as_global((const T*)d.F);
+    const gptr<const int32_t> colvar = as_global(iv_colvar(d.iv, P, m));
     const double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int i = tid; i < k; i += TT)
@@ -1172,17 +1229,24 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
     for (int j1 = k; j1 > 0; j1 -= kBS) {
         const int j0 = max(0, j1 - kBS), bs = j1 - j0;
         if (wid == 0) {
-            double Ur[kBS];
+            double Ur[kBS];  // clamped unconditional loads, as in the forward sweep
+            const int lr = j0 + min(lane, bs - 1);
 #pragma unroll
-            for (int a = 0; a < kBS; a++)
-                Ur[a] = (lane < bs && a >= lane && a < bs) ? (double)F[(j0 + lane) + (int64_t)(j0 + a) * m] : 0.0;
+            for (int a = 0; a < kBS; a++) {
+                const double t = (double)F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+                Ur[a] = ((lane < bs) & (a >= lane) & (a < bs)) ? t : 0.0;
+            }
+            // each lane's reciprocal of its own diagonal entry, taken in parallel
+            // once per block: the sequential sweep then multiplies instead of
+            // dividing (within 1.5 ulp of the quotient)
+            const double rd = 1.0 / (double)F[lr + (int64_t)lr * m];
             for (int c = 0; c < nrc; c++) {
                 double xl = lane < bs ? ts[j0 + lane + c * k] : 0.0;
 #pragma unroll
                 for (int a = kBS - 1; a >= 0; a--) {
                     if (a < bs) {
-                        // row a's value and diagonal are broadcast from lane a
-                        const double xa = readlane_d(xl, a) / readlane_d(Ur[a], a);
+                        // row a's value and diagonal reciprocal are broadcast from lane a
+                        const double xa = readlane_d(xl, a) * readlane_d(rd, a);
                         if (lane == a) xl = xa;
                         if (lane < a) xl -= Ur[a] * xa;
                     }
@@ -1192,7 +1256,7 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
         }
         __syncthreads();
         for (int i = tid; i < j0; i += TT) {
-            const T* Fi = F + i + (int64_t)j0 * m;
+            const gptr<const T> Fi = F + i + (int64_t)j0 * m;
             for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
         }
         __syncthreads();
@@ -1388,6 +1452,18 @@ hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ launchers
+
+hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count,
+                              int32_t* overflow, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_level_setup, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, st, S, fn, tmpl,
+                       slot0, count, overflow);
+    return MF_CHECK_LAUNCH();
+}
+hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, y, v);
+    return MF_CHECK_LAUNCH();
+}
 
 int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 
