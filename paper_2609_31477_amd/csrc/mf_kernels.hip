@@ -1059,8 +1059,18 @@ template <typename T>
 __device__ __forceinline__ double block_dot(gptr<const T> Fi, int64_t m, const double* z, int bs) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (bs == kBS) {
+        // the strip is loaded in the storage type before any use, a whole strip
+        // (FP32) or half of one (FP64, register budget) at a time
+        constexpr int kChunk = sizeof(T) == 4 ? kBS : kBS / 2;
 #pragma unroll
-        for (int a = 0; a < kBS; a++) acc[a & 7] += (double)Fi[(int64_t)a * m] * z[a];
+        for (int c0 = 0; c0 < kBS; c0 += kChunk) {
+            T raw[kChunk];
+#pragma unroll
+            for (int a = 0; a < kChunk; a++) raw[a] = Fi[(int64_t)(c0 + a) * m];
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the first use
+#pragma unroll
+            for (int a = 0; a < kChunk; a++) acc[a & 7] += (double)raw[a] * z[c0 + a];
+        }
     } else {
         for (int a = 0; a < bs; a++) acc[a & 7] += (double)Fi[(int64_t)a * m] * z[a];
     }
@@ -1106,13 +1116,14 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             // every lane loads an in-range entry (row and column clamped into the
             // block) and masks it afterwards: the 64 loads are unconditional and all
             // in flight together instead of one branch (and wait) per column
-            double Lr[kBS];
+            T raw[kBS];
             const int lr = j0 + min(lane, bs - 1);
 #pragma unroll
-            for (int a = 0; a < kBS; a++) {
-                const double t = (double)F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
-                Lr[a] = ((lane < bs) & (a < lane)) ? t : 0.0;
-            }
+            for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+            double Lr[kBS];
+#pragma unroll
+            for (int a = 0; a < kBS; a++) Lr[a] = ((lane < bs) & (a < lane)) ? (double)raw[a] : 0.0;
             for (int c = 0; c < nrc; c++) {
                 double x = lane < bs ? zs[j0 + lane + c * m] : 0.0;
 #pragma unroll
@@ -1229,13 +1240,14 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
     for (int j1 = k; j1 > 0; j1 -= kBS) {
         const int j0 = max(0, j1 - kBS), bs = j1 - j0;
         if (wid == 0) {
-            double Ur[kBS];  // clamped unconditional loads, as in the forward sweep
+            T raw[kBS];  // clamped unconditional loads, as in the forward sweep
             const int lr = j0 + min(lane, bs - 1);
 #pragma unroll
-            for (int a = 0; a < kBS; a++) {
-                const double t = (double)F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
-                Ur[a] = ((lane < bs) & (a >= lane) & (a < bs)) ? t : 0.0;
-            }
+            for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+            __builtin_amdgcn_sched_barrier(0);
+            double Ur[kBS];
+#pragma unroll
+            for (int a = 0; a < kBS; a++) Ur[a] = ((lane < bs) & (a >= lane) & (a < bs)) ? (double)raw[a] : 0.0;
             // each lane's reciprocal of its own diagonal entry, taken in parallel
             // once per block: the sequential sweep then multiplies instead of
             // dividing (within 1.5 ulp of the quotient)
