@@ -58,7 +58,11 @@ typedef struct {
     double target_omega;   /* componentwise backward-error target of mf_solve (default 1e-12) */
     int32_t max_outer;     /* max refinement steps (default 10) */
     int32_t gmres_m;       /* GMRES restart length / max inner iterations (default 30) */
-    double gmres_tol;      /* inner relative residual tolerance (default 1e-4) */
+    double gmres_tol;      /* inner relative tolerance on the preconditioned residual
+                              (default 1e-12).  The inner iteration also stops as
+                              soon as the refined iterate meets target_omega (its
+                              true FP64 residual is checked after every inner step),
+                              which normally ends it first */
     int32_t refine;        /* 0 = none, 1 = classical FP64 refinement, 2 = GMRES-IR
                               (default: 1 for MF_FP64, 2 otherwise; -1 = by precision) */
     int32_t panel_nb;      /* reserved (the panel width is chosen per front from its order) */

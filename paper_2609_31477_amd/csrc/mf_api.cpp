@@ -181,6 +181,8 @@ struct mf_num {
     std::vector<mf_solve_info> seg_info;    // per system of the last solve
     double* d_cat = nullptr;                // batched solve: concatenated b and x
     size_t cat_cap = 0;
+    int32_t* d_ones = nullptr;              // nseg ones: every system active
+    int ones_cap = 0;
     bool factored = false;
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
     std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
@@ -246,6 +248,7 @@ struct mf_num {
         if (h_omega) (void)hipHostFree(h_omega);
         if (d_active) (void)hipFree(d_active);
         if (d_cat) (void)hipFree(d_cat);
+        if (d_ones) (void)hipFree(d_ones);
         if (h_active) (void)hipHostFree(h_active);
         if (d_tasks) (void)hipFree(d_tasks);
         if (d_svals) (void)hipFree(d_svals);
@@ -870,7 +873,8 @@ void ensure_krylov(mf_num* N, int mres) {
     const Symbolic& S = N->sym->S;
     const int64_t n = S.n;
     const int nseg = (int)S.seg_n.size();
-    size_t need = (size_t)n * (mres + 2) + (size_t)512 * nseg * (mres + 2);
+    // V (mres + 1 vectors) | w | trial x | trial r | reduction scratch
+    size_t need = (size_t)n * (mres + 4) + (size_t)512 * nseg * (mres + 2);
     if (need > N->kry_cap) {
         if (N->d_kry) HIPX(hipFree(N->d_kry));
         N->d_kry = nullptr;
@@ -886,6 +890,14 @@ void ensure_krylov(mf_num* N, int mres) {
         HIPX(hipMalloc((void**)&N->d_small, sizeof(double) * sneed));
         HIPX(hipHostMalloc((void**)&N->h_small, sizeof(double) * sneed, hipHostMallocDefault));
         N->small_cap = sneed;
+    }
+    if (!N->d_ones || N->ones_cap < nseg) {
+        if (N->d_ones) HIPX(hipFree(N->d_ones));
+        N->d_ones = nullptr;
+        HIPX(hipMalloc((void**)&N->d_ones, sizeof(int32_t) * nseg));
+        std::vector<int32_t> ones(nseg, 1);
+        HIPX(hipMemcpy(N->d_ones, ones.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice));
+        N->ones_cap = nseg;
     }
 }
 
@@ -908,12 +920,28 @@ double* put_small(mf_num* N, const std::vector<double>& v, hipStream_t st) {
     return N->d_small + off;
 }
 
+// y = R^{-1} g of the first jq columns of one system's rotated Hessenberg matrix.
+void hessenberg_solve(const std::vector<double>& Hq, const std::vector<double>& gq, int jq, int ldh, double* y) {
+    for (int i = jq - 1; i >= 0; i--) {
+        double t = gq[i];
+        for (int k = i + 1; k < jq; k++) t -= Hq[(size_t)i + (size_t)k * ldh] * y[k];
+        const double rii = Hq[(size_t)i + (size_t)i * ldh];
+        y[i] = rii != 0.0 ? t / rii : 0.0;
+    }
+}
+
 // GMRES(m) on M^{-1} J d = M^{-1} r, one instance per system of the batch, run in
 // lockstep on the concatenated vectors (column c of r and d).  Classical
 // Gram-Schmidt with one reorthogonalization, Givens rotations on the host.  A
-// system's numbers depend only on its own rows.  Returns inner iterations per system.
+// system's numbers depend only on its own rows.  A system stops when its
+// preconditioned residual falls by tol, or, with target > 0, as soon as the
+// refined iterate x + d of the current Krylov space meets the componentwise
+// backward-error target (its true residual against b, one SpMV per iteration:
+// much cheaper than the sweep pair each further iteration or outer step costs).
+// Returns inner iterations per system.
 std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mres, double tol,
-                                  const std::vector<char>& act, hipStream_t st) {
+                                  const std::vector<char>& act, hipStream_t st, const double* b = nullptr,
+                                  const double* x = nullptr, double target = 0.0) {
     const Symbolic& S = N->sym->S;
     const int64_t n = S.n;
     const int nseg = (int)S.seg_n.size();
@@ -921,7 +949,9 @@ std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mre
     const int stride = mres + 2;
     double* V = N->d_kry;
     double* w = V + (size_t)n * (mres + 1);
-    double* part = w + n;
+    double* xt = w + n;
+    double* rt = xt + n;
+    double* part = rt + n;
     std::vector<int> iters(nseg, 0);
     apply_inverse(N, r, n, w, n, 1, st);  // w = M^{-1} r
     std::vector<double> dots, beta(nseg), coef((size_t)nseg * stride, 0.0);
@@ -985,6 +1015,24 @@ std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mre
             jdone[q] = j + 1;
             if (std::fabs(g[q][j + 1]) <= tol * beta[q] || !(hn > 0.0)) running[q] = 0;
         }
+        if (target > 0.0 && b && x) {
+            bool anyr = false;
+            for (int q = 0; q < nseg; q++) anyr = anyr || running[q];
+            if (anyr) {
+                // trial iterate x + V y of every system still running (the others add 0)
+                std::fill(coef.begin(), coef.end(), 0.0);
+                for (int q = 0; q < nseg; q++)
+                    if (running[q]) hessenberg_solve(H[q], g[q], j + 1, mres + 1, coef.data() + (size_t)q * stride);
+                HIPX(launch_fill(d, 0.0, n, st));
+                HIPX(launch_vadd(DS, d, V, n, j + 1, put_small(N, coef, st), stride, n, st));
+                HIPX(hipMemcpyAsync(xt, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+                HIPX(launch_axpy(DS, n, xt, n, d, n, N->d_ones, 1, st));
+                std::vector<double> omt;
+                residual(N, b, n, xt, n, rt, 1, st, omt);
+                for (int q = 0; q < nseg; q++)
+                    if (running[q] && omt[q] <= target) running[q] = 0;
+            }
+        }
     }
     // y = R^{-1} g per system, d = V y
     std::fill(coef.begin(), coef.end(), 0.0);
@@ -994,13 +1042,9 @@ std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mre
         const int jq = jdone[q];
         iters[q] = jq;
         jmax = std::max(jmax, jq);
-        for (int i = jq - 1; i >= 0; i--) {
-            double t = g[q][i];
-            for (int k = i + 1; k < jq; k++) t -= H[q][(size_t)i + (size_t)k * (mres + 1)] * coef[(size_t)q * stride + k];
-            const double rii = H[q][(size_t)i + (size_t)i * (mres + 1)];
-            coef[(size_t)q * stride + i] = rii != 0.0 ? t / rii : 0.0;
-        }
+        hessenberg_solve(H[q], g[q], jq, mres + 1, coef.data() + (size_t)q * stride);
     }
+    HIPX(launch_fill(d, 0.0, n, st));  // (trial iterates left their d behind)
     if (jmax > 0) HIPX(launch_vadd(DS, d, V, n, jmax, put_small(N, coef, st), stride, n, st));
     return iters;
 }
@@ -1047,7 +1091,8 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
                     anyc = anyc || act[q];
                 }
                 if (!anyc) continue;
-                std::vector<int> its = gmres_correction(N, r + (size_t)c * n, dv + (size_t)c * n, mres, o.gmres_tol, act, st);
+                std::vector<int> its = gmres_correction(N, r + (size_t)c * n, dv + (size_t)c * n, mres, o.gmres_tol, act,
+                                                        st, b + (size_t)c * ld, x + (size_t)c * ld, o.target_omega);
                 for (int q = 0; q < nseg; q++) N->seg_info[q].inner_iters += its[q];
             }
         }
@@ -1091,7 +1136,7 @@ void mf_default_options(mf_options* o) {
     o->target_omega = 1e-12;
     o->max_outer = 10;
     o->gmres_m = 30;
-    o->gmres_tol = 1e-4;
+    o->gmres_tol = 1e-12;
     o->refine = -1;
     o->panel_nb = 32;
     o->profile = 0;
