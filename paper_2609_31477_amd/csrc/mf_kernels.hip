@@ -95,16 +95,24 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     // are independent)
     constexpr int kMaxKids = 64;
     __shared__ int cj_s[kMaxKids][kGatherCols];
-    __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids];
+    __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids], kid_k[kMaxKids], kid_m[kMaxKids], kid_prec[kMaxKids];
+    __shared__ int64_t kid_im[kMaxKids];
+    __shared__ const void* kid_F[kMaxKids];
     const int nk = ce - cb;
     const bool staged = nk <= kMaxKids;
     if (staged) {
         if (threadIdx.x == 0) {
             int dseg = 0;
             for (int t = 0; t < nk; t++) {
-                const FrontNum dc = fn[S.child_slot[cb + t]];
+                const int cs = S.child_slot[cb + t];
+                const FrontNum dc = fn[cs];
                 kid_dout[t] = dc.P - dc.k;
                 kid_dseg[t] = dseg;
+                kid_k[t] = dc.k;
+                kid_m[t] = dc.m;
+                kid_prec[t] = dc.prec;
+                kid_im[t] = S.imap_off[cs];
+                kid_F[t] = dc.F;
                 dseg += dc.P - dc.k;
             }
         }
@@ -115,6 +123,47 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
             cj_s[t][jj] = j < m ? child_pos(j, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + S.imap_off[cs]) : -1;
         }
         __syncthreads();
+    }
+    if (staged) {
+        // Each child's 16 values of a row are loaded at once, at clamped in-range
+        // positions (its first contribution-block row or column where the parent
+        // row or column has no counterpart) and masked after: one memory round trip
+        // per child instead of one per value.  Misses add +0.0, which leaves the
+        // sums exactly as skipping them would (they never hold -0.0).
+        for (int i = threadIdx.x; i < m; i += kThreads) {
+            double acc[kGatherCols];
+#pragma unroll
+            for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
+            for (int t = 0; t < nk; t++) {
+                const int ck = kid_k[t], cm = kid_m[t];
+                if (cm == ck) continue;  // empty contribution block
+                const int ci = child_pos(i, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + kid_im[t]);
+                const int64_t rbase = ck + (ci >= 0 ? ci : 0);
+                double val[kGatherCols];
+                if (kid_prec[t]) {
+                    const gptr<const float> Fc = as_global((const float*)kid_F[t]);
+                    float raw[kGatherCols];
+#pragma unroll
+                    for (int jj = 0; jj < kGatherCols; jj++)
+                        raw[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][jj], 0)) * cm];
+#pragma unroll
+                    for (int jj = 0; jj < kGatherCols; jj++) val[jj] = (double)raw[jj];
+                } else {
+                    const gptr<const double> Fc = as_global((const double*)kid_F[t]);
+#pragma unroll
+                    for (int jj = 0; jj < kGatherCols; jj++)
+                        val[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][jj], 0)) * cm];
+                }
+#pragma unroll
+                for (int jj = 0; jj < kGatherCols; jj++) acc[jj] += ((ci >= 0) & (cj_s[t][jj] >= 0)) ? val[jj] : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj < kGatherCols; jj++) {
+                const int j = j0 + jj;
+                if (j < m) F[i + (int64_t)j * m] = (T)acc[jj];
+            }
+        }
+        return;
     }
     for (int i = threadIdx.x; i < m; i += kThreads) {
         double acc[kGatherCols];
@@ -127,25 +176,14 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
             const int dout = dc.P - dc.k;
             const int32_t* im = S.imap + S.imap_off[cs];
             const int ci = child_pos(i, d.npiv, d.din, dseg, dout, im);
-            if (ci >= 0) {
+            if (ci >= 0) {  // (more children than the staging holds: maps looked up per value)
                 const int64_t rbase = (int64_t)(dc.k + ci);
-                if (staged) {
-                    double val[kGatherCols];
 #pragma unroll
-                    for (int jj = 0; jj < kGatherCols; jj++) {
-                        const int cj = cj_s[t - cb][jj];
-                        val[jj] = cj >= 0 ? load_front(dc, rbase + (int64_t)(dc.k + cj) * dc.m) : 0.0;
-                    }
-#pragma unroll
-                    for (int jj = 0; jj < kGatherCols; jj++) acc[jj] += val[jj];
-                } else {
-#pragma unroll
-                    for (int jj = 0; jj < kGatherCols; jj++) {
-                        const int j = j0 + jj;
-                        if (j < m) {
-                            const int cj = child_pos(j, d.npiv, d.din, dseg, dout, im);
-                            if (cj >= 0) acc[jj] += load_front(dc, rbase + (int64_t)(dc.k + cj) * dc.m);
-                        }
+                for (int jj = 0; jj < kGatherCols; jj++) {
+                    const int j = j0 + jj;
+                    if (j < m) {
+                        const int cj = child_pos(j, d.npiv, d.din, dseg, dout, im);
+                        if (cj >= 0) acc[jj] += load_front(dc, rbase + (int64_t)(dc.k + cj) * dc.m);
                     }
                 }
             }
