@@ -736,23 +736,41 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
         __syncthreads();
     }
     // new U rows: unit-lower solve with L11, half a wave per column (lane = row of
-    // the panel), the pivot row's value broadcast with readlane at each step
-    const int lane = tid & 63, half = lane >> 5, r = lane & 31;
-    for (int jj = c0 + 2 * (tid >> 6); jj < cend; jj += 2 * (kThreads / 64)) {
-        const int j = jj + half;
-        const bool live = j < cend && j >= kd1 && !(j >= d.x0 && j < d.x1);
-        const gptr<T> colp = F + (int64_t)j * m + kd0;
-        double x = (live && r < nb) ? (double)colp[r] : 0.0;
-        for (int a = 0; a < nb - 1; a++) {
-            const long long xb = __double_as_longlong(x);
-            const int lo0 = __builtin_amdgcn_readlane((int)xb, a), hi0 = __builtin_amdgcn_readlane((int)(xb >> 32), a);
-            const int lo1 = __builtin_amdgcn_readlane((int)xb, 32 + a),
-                      hi1 = __builtin_amdgcn_readlane((int)(xb >> 32), 32 + a);
-            const int lo = half ? lo1 : lo0, hi = half ? hi1 : hi0;
-            const double xa = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-            if (r > a) x -= (double)L11[r + a * kNBMax] * xa;
+    // the panel), the pivot row's value broadcast with readlane at each step.  A
+    // wave carries kP column pairs through the steps together: independent chains
+    // that fill each other's readlane and FMA latencies.
+    constexpr int kP = 4;
+    const int lane = tid & 63, half = lane >> 5, r = lane & 31, wid = tid >> 6;
+    const int npair = (cend - c0 + 1) / 2;
+    for (int pb = wid; pb < npair; pb += kP * (kThreads / 64)) {
+        double x[kP];
+        bool live[kP];
+        gptr<T> colp[kP];
+#pragma unroll
+        for (int q = 0; q < kP; q++) {
+            const int p = pb + q * (kThreads / 64);
+            const int j = c0 + 2 * p + half;
+            live[q] = p < npair && j < cend && j >= kd1 && !(j >= d.x0 && j < d.x1);
+            colp[q] = F + (int64_t)(live[q] ? j : c0) * m + kd0;
+            x[q] = (live[q] && r < nb) ? (double)colp[q][r] : 0.0;
         }
-        if (live && r < nb) colp[r] = (T)x;
+        for (int a = 0; a < nb - 1; a++) {
+            const double la = (double)L11[r + a * kNBMax];
+#pragma unroll
+            for (int q = 0; q < kP; q++) {
+                const long long xb = __double_as_longlong(x[q]);
+                const int lo0 = __builtin_amdgcn_readlane((int)xb, a),
+                          hi0 = __builtin_amdgcn_readlane((int)(xb >> 32), a);
+                const int lo1 = __builtin_amdgcn_readlane((int)xb, 32 + a),
+                          hi1 = __builtin_amdgcn_readlane((int)(xb >> 32), 32 + a);
+                const int lo = half ? lo1 : lo0, hi = half ? hi1 : hi0;
+                const double xa = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+                if (r > a) x[q] -= la * xa;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kP; q++)
+            if (live[q] && r < nb) colp[q][r] = (T)x[q];
     }
 }
 
