@@ -336,6 +336,14 @@ int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 ||
 // the counts and the swap width; place_tasks points it at a device copy.
 LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t) {
     const size_t base = t.size();
+    {
+        size_t est = 0;
+        for (int i = 0; i < count; i++) {
+            const size_t T = (hf[i].m + 63) / 64;
+            est += 4 * T + 2 * T * T;
+        }
+        t.reserve(base + est);
+    }
     // few (large) fronts: narrow swap tiles so that more blocks share the latency-bound work
     const int sw = count < 32 ? 16 : 64;
     for (int i = 0; i < count; i++) {
@@ -395,6 +403,15 @@ LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStrea
     std::copy(t.begin(), t.end(), N->h_tasks);
     if (!t.empty()) HIPX(hipMemcpyAsync(N->d_tasks, N->h_tasks, sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, st));
     return place_tasks(tk, N->d_tasks);
+}
+
+// Flops of eliminating p pivots from a front of order m: sum over i in [m-p, m)
+// of i + 2 i^2, in closed form (exact in 64-bit integers for orders below 2^20).
+double front_flops(int64_t m, int64_t p) {
+    auto s1 = [](int64_t n) { return n * (n - 1) / 2; };                // sum of i, i < n
+    auto s2 = [](int64_t n) { return (n - 1) * n * (2 * n - 1) / 6; };  // sum of i^2, i < n
+    const int64_t a = m - p;
+    return (double)(s1(m) - s1(a)) + 2.0 * (double)(s2(m) - s2(a));
 }
 
 // Slack of a planned front over the delayed-in count it was planned from.
@@ -492,8 +509,7 @@ mf_factor_info finished_info(const mf_num* N) {
         const size_t esz = fr.prec ? 4 : 8;
         info.factor_bytes += (int64_t)(esz * (size_t)fr.m * (size_t)fr.m);
         info.max_front = std::max(info.max_front, fr.m);
-        const double m = fr.m, pp = fr.P;
-        for (int64_t i = (int64_t)(m - pp); i < (int64_t)m; i++) info.actual_flops += (double)i + 2.0 * (double)i * (double)i;
+        info.actual_flops += front_flops(fr.m, fr.P);
         const double cb = (double)(fr.m - fr.P);
         info.schur_flops += 2.0 * cb * cb * (double)fr.k;
         const int dout = fr.P - fr.k;
@@ -664,8 +680,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             N->lvl_Pmax[p][L] = std::max(N->lvl_Pmax[p][L], fr.P);
             N->lvl_cnt[p][L]++;
             info.max_front = std::max(info.max_front, fr.m);
-            double m = fr.m, pp = fr.P;
-            for (int64_t i = (int64_t)(m - pp); i < (int64_t)m; i++) info.actual_flops += (double)i + 2.0 * (double)i * (double)i;
+            info.actual_flops += front_flops(fr.m, fr.P);
         }
         for (int p = 0; p < 2; p++) {
             if (!N->lvl_cnt[p][L]) continue;
