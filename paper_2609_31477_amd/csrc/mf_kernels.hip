@@ -846,11 +846,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = acc_t{0, 0, 0, 0};
     constexpr int kPer = kKC * kTile / kThreads;  // staged elements per thread and operand
-    for (int k0 = ka; k0 < kb; k0 += kKC) {
+    // K chunks pass through registers: all global loads of a chunk are issued
+    // together (a load after an LDS store could not be hoisted above it, which
+    // would serialize the latencies), and the next chunk's loads are in flight
+    // while the MFMAs of the current one run
+    T ra[kPer], rb[kPer];
+    auto load_chunk = [&](int k0) {
         const int kc = min(kKC, kb - k0);
-        // all global loads of the chunk first, then the LDS stores (a load after an
-        // LDS store could not be hoisted above it, which would serialize the latencies)
-        T ra[kPer], rb[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             const int idx = tid + q * kThreads;
@@ -865,6 +867,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
             const int col = col0 + c;
             rb[q] = (a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : T(0);
         }
+    };
+    load_chunk(ka);
+    for (int k0 = ka; k0 < kb; k0 += kKC) {
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             const int idx = tid + q * kThreads;
@@ -872,6 +877,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int 
             Bs[(idx % kKC) * kLdsPad + idx / kKC] = rb[q];
         }
         __syncthreads();
+        if (k0 + kKC < kb) load_chunk(k0 + kKC);
 #pragma unroll
         for (int kk = 0; kk < kKC; kk += 4) {
             T av[2], bv[2];
