@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -1031,8 +1032,13 @@ std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mre
             if (std::fabs(g[q][j + 1]) <= tol * beta[q] || !(hn > 0.0)) running[q] = 0;
         }
         if (target > 0.0 && b && x) {
+            // the check is worth its SpMV only once some system's preconditioned
+            // residual has fallen to within kCheckGate of the target (on these
+            // Jacobians omega met the target only below that, and a check costs
+            // about a sixth of the sweep pair that one more inner step costs)
+            constexpr double kCheckGate = 1e4;
             bool anyr = false;
-            for (int q = 0; q < nseg; q++) anyr = anyr || running[q];
+            for (int q = 0; q < nseg; q++) anyr = anyr || (running[q] && std::fabs(g[q][j + 1]) <= kCheckGate * target * beta[q]);
             if (anyr) {
                 // trial iterate x + V y of every system still running (the others add 0)
                 std::fill(coef.begin(), coef.end(), 0.0);
@@ -1044,8 +1050,11 @@ std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mre
                 HIPX(launch_axpy(DS, n, xt, n, d, n, N->d_ones, 1, st));
                 std::vector<double> omt;
                 residual(N, b, n, xt, n, rt, 1, st, omt);
+                // each system acts on its own gate only, so that its iterations do
+                // not depend on the systems it is batched with
                 for (int q = 0; q < nseg; q++)
-                    if (running[q] && omt[q] <= target) running[q] = 0;
+                    if (running[q] && std::fabs(g[q][j + 1]) <= kCheckGate * target * beta[q] && omt[q] <= target)
+                        running[q] = 0;
             }
         }
     }

@@ -958,10 +958,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = flt4{0, 0, 0, 0};
     constexpr int kPerB = kKB * kTile / kThreads;
-    for (int k0 = 0; k0 < kb; k0 += kKB) {
+    // K chunks through registers, the next chunk's loads in flight during the
+    // current chunk's MFMAs (as in k_gemm)
+    float ra[kPerB], rb[kPerB];
+    auto load_chunk = [&](int k0) {
         const int kc = min(kKB, kb - k0);
-        // global loads of the chunk first, then the LDS stores (see k_gemm)
-        float ra[kPerB], rb[kPerB];
 #pragma unroll
         for (int q = 0; q < kPerB; q++) {
             const int idx = tid + q * kThreads;
@@ -976,6 +977,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
             const int col = col0 + c;
             rb[q] = (a < kc && col < m) ? F[(k0 + a) + (int64_t)col * m] : 0.0f;
         }
+    };
+    if (kb > 0) load_chunk(0);
+    for (int k0 = 0; k0 < kb; k0 += kKB) {
 #pragma unroll
         for (int q = 0; q < kPerB; q++) {
             const int idx = tid + q * kThreads;
@@ -983,6 +987,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
             Bs[(idx / kKB) * kKBPad + idx % kKB] = (__bf16)rb[q];
         }
         __syncthreads();
+        if (k0 + kKB < kb) load_chunk(k0 + kKB);
         bf16x8 av[2], bv[2];
 #pragma unroll
         for (int bi = 0; bi < 2; bi++)
