@@ -1352,47 +1352,77 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
 // (blockIdx.y) and per system of a batch, 16 lanes per row.  omega is kept as the
 // bit pattern of a non-negative double and combined with an unsigned atomic max
 // (exact and order-independent).
+constexpr int kResRows = 256;  // rows per residual block (16 lanes per row, 16 rows per pass)
+
 __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const int32_t* ci, const double* val,
                                                        int64_t n, const double* x, int64_t ldx, const double* b,
                                                        int64_t ldb, double* r, int64_t ldr,
                                                        unsigned long long* omega_bits, const int32_t* row_seg,
                                                        int nrhs) {
+    // Each block covers kResRows consecutive rows and folds their omegas into one
+    // maximum before touching the shared result: one atomic per block instead of
+    // one per row group (same-address atomics serialize in L2).  In a batch, rows
+    // of one system are contiguous, so only blocks that straddle two systems fall
+    // back to per-thread maxima flushed at each system boundary.
     __shared__ double wmax[kThreads / 64];
     const int c = blockIdx.y;
-    const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 16;
     const int sub = threadIdx.x & 15;
-    double acc = 0.0, den = 0.0;
-    if (row < n) {
-        const double* xc = x + (int64_t)c * ldx;
-        for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) {
-            const double a = val[t];
-            const double xv = xc[ci[t]];
-            acc = fma(a, xv, acc);
-            den = fma(fabs(a), fabs(xv), den);
+    const int64_t r0 = (int64_t)blockIdx.x * kResRows;
+    const int64_t r1 = min(n, r0 + kResRows);
+    const double* xc = x + (int64_t)c * ldx;
+    const bool one_seg = !row_seg || row_seg[r0] == row_seg[r1 - 1];
+    double wm = 0.0;
+    int seg = -1;
+    for (int64_t row0 = r0; row0 < r1; row0 += kThreads / 16) {
+        const int64_t row = row0 + threadIdx.x / 16;
+        double acc = 0.0, den = 0.0;
+        if (row < r1) {
+            for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) {
+                const double a = val[t];
+                const double xv = xc[ci[t]];
+                acc = fma(a, xv, acc);
+                den = fma(fabs(a), fabs(xv), den);
+            }
+        }
+        for (int off = 8; off > 0; off >>= 1) {
+            acc += __shfl_xor(acc, off, 16);
+            den += __shfl_xor(den, off, 16);
+        }
+        if (row < r1 && sub == 0) {
+            const double bi = b[row + (int64_t)c * ldb];
+            const double ri = bi - acc;
+            r[row + (int64_t)c * ldr] = ri;
+            const double dd = den + fabs(bi);
+            double w = dd > 0.0 ? fabs(ri) / dd : (ri == 0.0 ? 0.0 : INFINITY);
+            if (w != w) w = INFINITY;
+            if (one_seg) {
+                wm = fmax(wm, w);
+            } else {
+                const int sg = row_seg[row];
+                if (sg != seg) {
+                    if (seg >= 0)
+                        atomicMax(omega_bits + (int64_t)seg * nrhs + c, (unsigned long long)__double_as_longlong(wm));
+                    seg = sg;
+                    wm = w;
+                } else {
+                    wm = fmax(wm, w);
+                }
+            }
         }
     }
-    for (int off = 8; off > 0; off >>= 1) {
-        acc += __shfl_xor(acc, off, 16);
-        den += __shfl_xor(den, off, 16);
+    if (!one_seg) {
+        if (sub == 0 && seg >= 0)
+            atomicMax(omega_bits + (int64_t)seg * nrhs + c, (unsigned long long)__double_as_longlong(wm));
+        return;
     }
-    double w = 0.0;
-    if (row < n && sub == 0) {
-        const double bi = b[row + (int64_t)c * ldb];
-        const double ri = bi - acc;
-        r[row + (int64_t)c * ldr] = ri;
-        const double dd = den + fabs(bi);
-        w = dd > 0.0 ? fabs(ri) / dd : (ri == 0.0 ? 0.0 : INFINITY);
-        if (w != w) w = INFINITY;
-        if (row_seg) atomicMax(omega_bits + (int64_t)row_seg[row] * nrhs + c, (unsigned long long)__double_as_longlong(w));
-    }
-    if (row_seg) return;
-    for (int off = 32; off > 0; off >>= 1) w = fmax(w, __shfl_xor(w, off));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = w;
+    for (int off = 32; off > 0; off >>= 1) wm = fmax(wm, __shfl_xor(wm, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = wm;
     __syncthreads();
     if (threadIdx.x == 0) {
         double mx = wmax[0];
         for (int i = 1; i < kThreads / 64; i++) mx = fmax(mx, wmax[i]);
-        atomicMax(omega_bits + c, (unsigned long long)__double_as_longlong(mx));
+        const int sg = row_seg ? row_seg[r0] : 0;
+        atomicMax(omega_bits + (int64_t)sg * nrhs + c, (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -1739,7 +1769,7 @@ hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const 
     const int nom = nrhs * S.nseg;
     hipLaunchKernelGGL(k_fill_u64, dim3((nom + 63) / 64), dim3(64), 0, st, omega_bits, nom, 0ull);
     if (n > 0) {
-        const int64_t blocks = (n * 16 + kThreads - 1) / kThreads;
+        const int64_t blocks = (n + kResRows - 1) / kResRows;
         hipLaunchKernelGGL(k_residual, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, st, S.csr_rowptr,
                            S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits, S.row_seg, nrhs);
     }
