@@ -186,7 +186,7 @@ struct mf_num {
     int ones_cap = 0;
     bool factored = false;
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
-    std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
+    std::vector<std::array<int32_t, kNClass>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
     // equilibration: factors are of Dr J Dc (powers of two); residuals use J itself
     bool scaled = false;
     double* d_svals = nullptr;          // Dr J Dc values (nnz)
@@ -215,7 +215,7 @@ struct mf_num {
         int32_t* d_tasks = nullptr;    // tile lists of all levels
         std::vector<LevelTasks> tasks; // per level, pointing into d_tasks
         std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];
-        std::vector<std::array<int32_t, 4>> lvl_cls_mmax[2], lvl_cls_Pmax[2];
+        std::vector<std::array<int32_t, kNClass>> lvl_cls_mmax[2], lvl_cls_Pmax[2];
         int64_t vec_len = 0;
         int32_t* d_flag = nullptr;  // overflow flag
         int32_t* h_flag = nullptr;  // pinned mirror
@@ -440,8 +440,8 @@ void build_plan(mf_num* N) {
         pl.lvl_mmax[p].assign(S.nlevels, 0);
         pl.lvl_Pmax[p].assign(S.nlevels, 0);
         pl.lvl_cnt[p].assign(S.nlevels, 0);
-        pl.lvl_cls_mmax[p].assign(S.nlevels, {0, 0, 0, 0});
-        pl.lvl_cls_Pmax[p].assign(S.nlevels, {0, 0, 0, 0});
+        pl.lvl_cls_mmax[p].assign(S.nlevels, {});
+        pl.lvl_cls_Pmax[p].assign(S.nlevels, {});
     }
     N->fronts.reset();
     N->ints.reset();
@@ -471,7 +471,7 @@ void build_plan(mf_num* N) {
             // any class the actual order falls in has a window of at most kNBMax
             t.W = N->wsp.alloc((size_t)2 * t.m * kNBMax * esz);
             const int p = t.prec;
-            const int cls = t.m <= 512 ? 0 : (t.m <= 1024 ? 1 : (t.m <= 2048 ? 2 : 3));
+            const int cls = front_class(t.m);
             pl.lvl_cls_mmax[p][L][cls] = std::max(pl.lvl_cls_mmax[p][L][cls], t.m);
             pl.lvl_cls_Pmax[p][L][cls] = std::max(pl.lvl_cls_Pmax[p][L][cls], t.P);
             pl.lvl_mmax[p][L] = std::max(pl.lvl_mmax[p][L], t.m);
@@ -623,8 +623,8 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         N->lvl_mmax[p].assign(S.nlevels, 0);
         N->lvl_Pmax[p].assign(S.nlevels, 0);
         N->lvl_cnt[p].assign(S.nlevels, 0);
-        N->lvl_cls_mmax[p].assign(S.nlevels, {0, 0, 0, 0});
-        N->lvl_cls_Pmax[p].assign(S.nlevels, {0, 0, 0, 0});
+        N->lvl_cls_mmax[p].assign(S.nlevels, {});
+        N->lvl_cls_Pmax[p].assign(S.nlevels, {});
     }
     std::vector<int32_t> dout(nf, 0);
     FrontNum* hf = N->h_fn;
@@ -674,7 +674,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             fr.voff = voff;
             voff += fr.m;
             const int p = fr.prec;
-            const int cls = fr.m <= 512 ? 0 : (fr.m <= 1024 ? 1 : (fr.m <= 2048 ? 2 : 3));
+            const int cls = front_class(fr.m);
             N->lvl_cls_mmax[p][L][cls] = std::max(N->lvl_cls_mmax[p][L][cls], fr.m);
             N->lvl_cls_Pmax[p][L][cls] = std::max(N->lvl_cls_Pmax[p][L][cls], fr.P);
             N->lvl_mmax[p][L] = std::max(N->lvl_mmax[p][L], fr.m);
@@ -743,7 +743,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             // for each pivot of a window, scale the column below it and update the rest of the window
             for (int sl = s0; sl < s1; sl++) {
                 const FrontNum& fr = hf[sl];
-                const int cls = fr.m <= 512 ? 0 : (fr.m <= 1024 ? 1 : (fr.m <= 2048 ? 2 : 3));
+                const int cls = front_class(fr.m);
                 const int nbp = panel_nb(fr.prec, fr.m);
                 for (int k0 = 0; k0 < fr.P; k0 += nbp) {
                     const int w = std::min(nbp, fr.P - k0);

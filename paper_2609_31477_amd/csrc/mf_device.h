@@ -10,6 +10,26 @@ namespace mf {
 // Panel width upper bound (options.panel_nb is clamped to it).
 constexpr int kNBMax = 32;
 
+// Panel shape class of a front, from its order and precision: the window width
+// NB and rows per thread RS (of a 512-thread block) are per front (never per
+// launch), so a front's arithmetic does not depend on the other fronts it is
+// batched with.  The widths are the widest windows whose registers fit without
+// spilling in the kernel that holds all classes.
+//   class 0: m <= 512  (NB 32, RS 1)     class 1: m <= 1024 (NB 32, RS 2)
+//   class 2: m <= 1536 (FP64 NB 26, FP32 NB 32; RS 3)
+//   class 3: m <= 2048 (FP64 NB 20, FP32 NB 32; RS 4)
+//   class 4: m <= 4096 (FP64 NB 8, FP32 NB 16; RS 8)
+constexpr int kNClass = 5;
+__host__ __device__ inline int front_class(int m) {
+    return m <= 512 ? 0 : (m <= 1024 ? 1 : (m <= 1536 ? 2 : (m <= 2048 ? 3 : 4)));
+}
+__host__ __device__ inline int class_nb(int cls, int prec) {
+    if (cls <= 1) return 32;
+    if (cls == 2) return prec ? 32 : 26;
+    if (cls == 3) return prec ? 32 : 20;
+    return prec ? 16 : 8;
+}
+
 // Per-front numeric state, indexed by "slot" (fronts in level order, so the
 // fronts of one tree level are contiguous).  Written by the host before a level
 // is assembled; k / k0 are updated by the factorization kernels.

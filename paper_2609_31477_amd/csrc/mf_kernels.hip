@@ -237,16 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(DevSym S, FrontNum* fn, co
 // window.  Columns [x0, x1) (the ones just delayed) are already up to date.
 constexpr int kPanelThreads = 512;
 
-// Panel shape class of a front, from its order and precision: the window width
-// NB and rows per thread RS are per front (never per launch), so a front's
-// arithmetic does not depend on the other fronts it is batched with.
-//   class 0: m <= 512  (NB 32, RS 1)     class 1: m <= 1024 (NB 32, RS 2)
-//   class 2: m <= 2048 (FP64 NB 20, FP32 NB 32; RS 4)
-//   class 3: m <= 4096 (FP64 NB 8, FP32 NB 16; RS 8)
-__host__ __device__ inline int front_class(int m) { return m <= 512 ? 0 : (m <= 1024 ? 1 : (m <= 2048 ? 2 : 3)); }
-__host__ __device__ inline int class_nb(int cls, int prec) {
-    return cls <= 1 ? 32 : (cls == 2 ? (prec ? 32 : 20) : (prec ? 16 : 8));
-}
+// (panel shape classes: front_class / class_nb in mf_device.h)
 
 // Work-group barrier that orders LDS only: global stores issued before it stay in
 // flight (the panel streams its multipliers to scratch while it factors).
@@ -661,6 +652,10 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
         case 0: panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn); break;
         case 1: panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn); break;
         case 2:
+            if constexpr (sizeof(T) == 8) panel_front<T, 26, 3, kPanelThreads>(fn, s, u, dyn);
+            else panel_front<T, 32, 3, kPanelThreads>(fn, s, u, dyn);
+            break;
+        case 3:
             if constexpr (sizeof(T) == 8) panel_front<T, 20, 4, kPanelThreads>(fn, s, u, dyn);
             else panel_front<T, 32, 4, kPanelThreads>(fn, s, u, dyn);
             break;
@@ -1576,7 +1571,7 @@ hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st) {
 
 int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 
-// cls_mmax[4], cls_Pmax[4]: per panel class of this precision in the level (0 = none)
+// cls_mmax[kNClass], cls_Pmax[kNClass]: per panel class of this precision in the level (0 = none)
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
@@ -1591,7 +1586,7 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                            st, S, fn, vals, u0, u1, prec);
     if (ev) (void)hipEventRecord(ev[0], st);
     int rounds = 0, Pmax = 0;
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < kNClass; c++) {
         if (cls_mmax[c] <= 0) continue;
         const int nbc = class_nb(c, prec);
         rounds = std::max(rounds, (cls_Pmax[c] + nbc - 1) / nbc);
