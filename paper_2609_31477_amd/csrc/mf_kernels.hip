@@ -1139,7 +1139,32 @@ __device__ __forceinline__ double block_dot(gptr<const T> Fi, int64_t m, const d
     return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
-template <typename T, int TT>
+// tile_dot's dot product of one row computed by a single lane, with exactly its
+// arithmetic (the four column groups of the block's waves, four accumulators each,
+// combined in the same order), so that the fused small-front sweeps give results
+// bitwise equal to the two-kernel path used on levels of larger fronts.
+template <typename T>
+__device__ __forceinline__ double row_dot_tiled(gptr<const T> Fcol0, int64_t m, const double* xv, int ncols) {
+    double p[4];
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int j = g;
+        for (; j + 12 < ncols; j += 16) {
+            a0 += (double)Fcol0[(int64_t)j * m] * xv[j];
+            a1 += (double)Fcol0[(int64_t)(j + 4) * m] * xv[j + 4];
+            a2 += (double)Fcol0[(int64_t)(j + 8) * m] * xv[j + 8];
+            a3 += (double)Fcol0[(int64_t)(j + 12) * m] * xv[j + 12];
+        }
+        for (; j < ncols; j += 4) a0 += (double)Fcol0[(int64_t)j * m] * xv[j];
+        p[g] = (a0 + a1) + (a2 + a3);
+    }
+    return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// FUSE (one-wave blocks of small-front levels): the same block also forms
+// c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
+template <typename T, int TT, bool FUSE>
 __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
                                                       int nrc) {
@@ -1202,6 +1227,13 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
         }
         __syncthreads();
+    }
+    if constexpr (FUSE) {
+        if (k > 0) {
+            for (int i = k + tid; i < m; i += TT)
+                for (int c = 0; c < nrc; c++) zs[i + c * m] -= row_dot_tiled<T>(F + i, m, zs + c * m, k);
+            __syncthreads();
+        }
     }
     for (int i = tid; i < m; i += TT)
         for (int c = 0; c < nrc; c++) v[i + (int64_t)(c0 + c) * m] = zs[i + c * m];
@@ -1284,7 +1316,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
     }
 }
 
-template <typename T, int TT>
+// FUSE (one-wave blocks of small-front levels): the same block first forms
+// t = y - U12 x[colvar[k:m]], which k_bwd_gemv does otherwise.
+template <typename T, int TT, bool FUSE>
 __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
                                                       int64_t ldx, const double* vec, int nrhs, int c0, int nrc) {
     extern __shared__ double ts[];
@@ -1298,6 +1332,20 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int i = tid; i < k; i += TT)
         for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
+    if constexpr (FUSE) {
+        const int nc = m - k;
+        if (nc > 0 && k > 0) {
+            double* xs = ts + (int64_t)k * nrc;  // the columns' solution values, after ts
+            for (int j = tid; j < nc; j += TT) {
+                const int var = colvar[k + j];
+                for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
+            }
+            __syncthreads();
+            for (int i = tid; i < k; i += TT)
+                for (int c = 0; c < nrc; c++)
+                    ts[i + c * k] -= row_dot_tiled<T>(F + i + (int64_t)k * m, m, xs + c * nc, nc);
+        }
+    }
     __syncthreads();
     for (int j1 = k; j1 > 0; j1 -= kBS) {
         const int j0 = max(0, j1 - kBS), bs = j1 - j0;
@@ -1643,12 +1691,14 @@ hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int 
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     // levels of small fronts: one wave per front (the diagonal sweep is one wave's work anyway)
-    if (mmax <= kTriSmallOrder)
-        hipLaunchKernelGGL((k_fwd_tri<T, 64>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st, S, fn,
-                           slot0, prec, b, ldb, vec, nrhs, c0, nrc);
-    else
-        hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads>), dim3(count), dim3(kTriThreads),
-                           sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+    // (and the L21 product in the same one-wave block)
+    if (mmax <= kTriSmallOrder) {
+        hipLaunchKernelGGL((k_fwd_tri<T, 64, true>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st,
+                           S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+        return MF_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads, false>), dim3(count), dim3(kTriThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc);
     hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
                        sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
@@ -1657,14 +1707,15 @@ template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (mmax <= kTriSmallOrder) {  // U12 product and sweep in one one-wave block
+        hipLaunchKernelGGL((k_bwd_tri<T, 64, true>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st,
+                           fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc);
+        return MF_CHECK_LAUNCH();
+    }
     hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
                        sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc);
-    if (mmax <= kTriSmallOrder)
-        hipLaunchKernelGGL((k_bwd_tri<T, 64>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st, fn,
-                           slot0, prec, x, ldx, vec, nrhs, c0, nrc);
-    else
-        hipLaunchKernelGGL((k_bwd_tri<T, kTriThreads>), dim3(count), dim3(kTriThreads),
-                           sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc);
+    hipLaunchKernelGGL((k_bwd_tri<T, kTriThreads, false>), dim3(count), dim3(kTriThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc);
     return MF_CHECK_LAUNCH();
 }
 template hipError_t launch_level_fwd<double>(const DevSym&, const FrontNum*, int, int, int, const double*, int64_t,
