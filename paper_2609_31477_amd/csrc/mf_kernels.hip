@@ -254,14 +254,6 @@ struct PivCand {
     double aall, afs;
     int ifs;
 };
-__device__ __forceinline__ void cand_merge(PivCand& a, double oa, double of, int oi) {
-    // branch-free: aall and afs are never NaN (a NaN entry counts as +inf in aall
-    // and never wins afs), so plain comparisons are exact
-    a.aall = (oa > a.aall) ? oa : a.aall;
-    const bool take = (of > a.afs) | ((of == a.afs) & (oi < a.ifs));
-    a.afs = take ? of : a.afs;
-    a.ifs = take ? oi : a.ifs;
-}
 template <int CTRL, int RM>
 __device__ __forceinline__ int dpp_i(int x) {
     return __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xf, false);
@@ -272,11 +264,6 @@ __device__ __forceinline__ double dpp_d(double x) {
     const int lo = dpp_i<CTRL, RM>((int)b), hi = dpp_i<CTRL, RM>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-// Lanes outside the row mask keep their own value, which merging leaves unchanged.
-template <int CTRL, int RM>
-__device__ __forceinline__ void cand_dpp_step(PivCand& a) {
-    cand_merge(a, dpp_d<CTRL, RM>(a.aall), dpp_d<CTRL, RM>(a.afs), dpp_i<CTRL, RM>(a.ifs));
-}
 __device__ __forceinline__ double readlane_d(double x, int l) {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
@@ -284,8 +271,13 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 }
 // Two-phase wave reduction of a candidate (short dependency chains): first the
 // maxima of aall and afs (independent DPP chains of plain max), then the lowest row
-// among the lanes whose afs equals that maximum (a DPP chain of integer min).  The
-// result is the same as merging the candidates one by one.
+// among the lanes whose afs equals that maximum (a DPP chain of integer min).  Each
+// chain runs within each quad (quad permutations), across the quads of a 16-lane
+// row (row rotations by 4 and 8), then across rows (row 0 into row 1 and row 2 into
+// row 3 by the row-15 broadcast, then row 1 into rows 2 and 3 by the lane-31
+// broadcast), so lane 63 holds the result and is read out uniformly.  Lanes
+// outside a step's row mask keep their own value.  The result is the same as
+// merging the candidates one by one in any order.
 template <int CTRL, int RM>
 __device__ __forceinline__ void dmax_step(double& x) {
     x = fmax(x, dpp_d<CTRL, RM>(x));
@@ -313,24 +305,6 @@ __device__ __forceinline__ PivCand cand_wave2(PivCand a) {
     imin_step<0x142, 0xA>(ri);
     imin_step<0x143, 0xC>(ri);
     r.ifs = __builtin_amdgcn_readlane(ri, 63);
-    return r;
-}
-// Wave-wide candidate, all in DPP: within each quad (quad permutations), across
-// the quads of a 16-lane row (row rotations by 4 and 8), then across rows (row 0
-// into row 1 and row 2 into row 3 by the row-15 broadcast, then row 1 into rows 2
-// and 3 by the lane-31 broadcast), so lane 63 holds the merge of all 64 lanes and
-// is read out uniformly.  Merging is commutative and associative.
-__device__ __forceinline__ PivCand cand_wave(PivCand a) {
-    cand_dpp_step<0xB1, 0xF>(a);   // quad_perm [1,0,3,2]
-    cand_dpp_step<0x4E, 0xF>(a);   // quad_perm [2,3,0,1]
-    cand_dpp_step<0x124, 0xF>(a);  // row_ror:4
-    cand_dpp_step<0x128, 0xF>(a);  // row_ror:8
-    cand_dpp_step<0x142, 0xA>(a);  // row_bcast:15 into rows 1 and 3
-    cand_dpp_step<0x143, 0xC>(a);  // row_bcast:31 into rows 2 and 3
-    PivCand r;
-    r.aall = readlane_d(a.aall, 63);
-    r.afs = readlane_d(a.afs, 63);
-    r.ifs = __builtin_amdgcn_readlane(a.ifs, 63);
     return r;
 }
 
