@@ -58,3 +58,34 @@ def test_newton_256x128_sampled(torch_cuda):
         assert om <= 1e-12
         assert info.outer_iters <= 2
         num.release()
+
+
+@pytest.mark.timeout(900)
+def test_newton_256x128_mixed(torch_cuda):
+    """The mixed path at full size (FP32 fronts, FP64 root, FP64 GMRES-IR): the
+    componentwise backward error of every step's solution, recomputed on the CPU
+    from the generator's matrix, meets the mixed target 1e-10, and the sampled
+    entries agree with the oracle's FP64 solution to the plain FP64 path's bar
+    (1e-8 relative to the largest entry; observed about 1e-14)."""
+    torch = torch_cuda
+    g = json.load(open(GOLDEN))
+    s = build_2d(*g["mesh"], g["seed"])
+    idx = np.asarray(g["index"], dtype=np.int64)
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    num = None
+    for st in g["steps"]:
+        t = st["step"]
+        v = newton_values(s, t)
+        b = newton_rhs(s, t)[0]
+        num = S.factor(torch.from_numpy(v).to(dev), numeric=num, prec="fp32", target_omega=1e-10)
+        x, info = num.solve(torch.from_numpy(b.copy()).to(dev))
+        torch.cuda.synchronize()
+        x = x.cpu().numpy()
+        err = np.abs(x[idx] - np.asarray(st["x"])).max() / st["xinf"]
+        om = check.omega_fast(s.to_scipy(v), x, b)
+        print(f"mixed step {t}: sampled rel err={err:.2e} omega={om:.2e} (device {info.omega:.2e}, "
+              f"outer {info.outer_iters}, inner {info.inner_iters})", flush=True)
+        assert om <= 1e-10
+        assert err <= 1e-8
+    num.release()
