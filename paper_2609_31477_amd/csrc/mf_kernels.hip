@@ -674,13 +674,27 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
     const gptr<const int32_t> pairs = as_global(iv_pairs(d.iv, P, m));
     const int np = pairs[0];
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < nb * nb; idx += kThreads) {
-        const int a = idx % nb, b = idx / nb;
-        L11[a + b * kNBMax] = F[(kd0 + a) + (int64_t)(kd0 + b) * m];
-    }
-    for (int q = tid; q < np; q += kThreads) {
-        pd[q] = pairs[1 + 2 * q];
-        ps[q] = pairs[2 + 2 * q];
+    {
+        // L11 and the pair list: every global load issued before the first LDS
+        // store (a store could alias a later load and would serialize them)
+        constexpr int kL = kNBMax * kNBMax / kThreads;
+        T l11[kL];
+#pragma unroll
+        for (int q = 0; q < kL; q++) {
+            const int idx = tid + q * kThreads;
+            const int a = idx % nb, b = idx / nb;
+            l11[q] = idx < nb * nb ? F[(kd0 + a) + (int64_t)(kd0 + b) * m] : T(0);
+        }
+        const int pdv = tid < np ? pairs[1 + 2 * tid] : 0, psv = tid < np ? pairs[2 + 2 * tid] : 0;
+#pragma unroll
+        for (int q = 0; q < kL; q++) {
+            const int idx = tid + q * kThreads;
+            if (idx < nb * nb) L11[idx % nb + (idx / nb) * kNBMax] = l11[q];
+        }
+        if (tid < np) {
+            pd[tid] = pdv;
+            ps[tid] = psv;
+        }
     }
     __syncthreads();
     // row swaps of the panel through registers: every source of a column is read
