@@ -86,7 +86,11 @@ typedef struct {
                               by level (same result) and enlarges the plan.  On the
                               256x128 Jacobians it is no faster: the extra empty panel
                               rounds that capacities add cost about what the per-level
-                              synchronizations do.  0 = synchronize per level; default 0 */
+                              synchronizations do.  2 = the same, with the planned
+                              launches captured once into a HIP graph (on a private
+                              stream) and replayed on `stream`; recaptured when the
+                              plan, the pivot threshold or the scaling mode changes.
+                              0 = synchronize per level; default 0 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */
@@ -185,7 +189,7 @@ typedef struct {
     double t_panel_kernel_ms;   /* the panel kernel alone (sum over its launches) */
     double panel_flops;         /* nominal panel flops (no delays): per window pivot, scaling + rank-1 update */
     int32_t panel_launches;     /* panel kernel launches timed */
-    int32_t planned;            /* 1 if this factorization ran on the planned schedule */
+    int32_t planned;            /* 1 if this factorization ran on the planned schedule, 2 as a graph replay */
     int32_t plan_fallbacks;     /* planned runs on this handle repeated level by level (overflow) */
 } mf_factor_info;
 

@@ -219,7 +219,22 @@ struct mf_num {
         int64_t vec_len = 0;
         int32_t* d_flag = nullptr;  // overflow flag
         int32_t* h_flag = nullptr;  // pinned mirror
+        // plan = 2: the planned launches captured once into a graph and replayed;
+        // the capture bakes in the values buffer and the pivot threshold
+        hipGraphExec_t graph = nullptr;
+        hipStream_t cap_stream = nullptr;  // private stream to capture on (the caller's may be the null stream)
+        const double* graph_vals = nullptr;
+        double graph_u = -1.0;
+        void drop_graph() {
+            if (graph) (void)hipGraphExecDestroy(graph);
+            graph = nullptr;
+            graph_vals = nullptr;
+            graph_u = -1.0;
+        }
         void free_device() {
+            drop_graph();
+            if (cap_stream) (void)hipStreamDestroy(cap_stream);
+            cap_stream = nullptr;
             if (d_tmpl) (void)hipFree(d_tmpl);
             if (d_tasks) (void)hipFree(d_tasks);
             if (d_flag) (void)hipFree(d_flag);
@@ -536,19 +551,46 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     SymDev& D = *H->dev;
     const mf_options& o = N->opt;
     mf_num::Plan& pl = N->plan;
-    HIPX(launch_fill_i32(pl.d_flag, 0, st));
-    for (int L = 0; L < S.nlevels; L++) {
-        const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
-        HIPX(launch_level_setup(D.S, N->d_fn, pl.d_tmpl, s0, s1 - s0, pl.d_flag, st));
-        const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
-        if (pl.lvl_cnt[0][L])
-            HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[0][L],
-                                             pl.lvl_cls_mmax[0][L].data(), pl.lvl_cls_Pmax[0][L].data(), fvals, u0,
-                                             u1, o.pivot_u, 0, pl.tasks[L], st, nullptr, false, nullptr));
-        if (pl.lvl_cnt[1][L])
-            HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[1][L],
-                                            pl.lvl_cls_mmax[1][L].data(), pl.lvl_cls_Pmax[1][L].data(), fvals, u0,
-                                            u1, o.pivot_u, 1, pl.tasks[L], st, nullptr, o.prec == MF_BF16, nullptr));
+    auto enqueue = [&](hipStream_t q) {
+        HIPX(launch_fill_i32(pl.d_flag, 0, q));
+        for (int L = 0; L < S.nlevels; L++) {
+            const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
+            HIPX(launch_level_setup(D.S, N->d_fn, pl.d_tmpl, s0, s1 - s0, pl.d_flag, q));
+            const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
+            if (pl.lvl_cnt[0][L])
+                HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[0][L],
+                                                 pl.lvl_cls_mmax[0][L].data(), pl.lvl_cls_Pmax[0][L].data(), fvals,
+                                                 u0, u1, o.pivot_u, 0, pl.tasks[L], q, nullptr, false, nullptr));
+            if (pl.lvl_cnt[1][L])
+                HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[1][L],
+                                                pl.lvl_cls_mmax[1][L].data(), pl.lvl_cls_Pmax[1][L].data(), fvals,
+                                                u0, u1, o.pivot_u, 1, pl.tasks[L], q, nullptr, o.prec == MF_BF16,
+                                                nullptr));
+        }
+    };
+    if (o.plan == 2) {
+        if (!pl.graph || pl.graph_vals != fvals || pl.graph_u != o.pivot_u) {
+            pl.drop_graph();
+            if (!pl.cap_stream) HIPX(hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            HIPX(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue(pl.cap_stream);
+            } catch (...) {
+                (void)hipStreamEndCapture(pl.cap_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIPX(hipStreamEndCapture(pl.cap_stream, &g));
+            const hipError_t ie = hipGraphInstantiate(&pl.graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPX(ie);
+            pl.graph_vals = fvals;
+            pl.graph_u = o.pivot_u;
+        }
+        HIPX(hipGraphLaunch(pl.graph, st));
+    } else {
+        enqueue(st);
     }
     HIPX(hipMemcpyAsync(N->h_fn, N->d_fn, sizeof(FrontNum) * S.nf, hipMemcpyDeviceToHost, st));
     HIPX(hipMemcpyAsync(pl.h_flag, pl.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -566,7 +608,7 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     }
     N->vec_len = pl.vec_len;
     N->info = finished_info(N);
-    N->info.planned = 1;
+    N->info.planned = o.plan == 2 ? 2 : 1;
     N->info.plan_fallbacks = N->plan_fallbacks;
     N->factored = true;
     return true;

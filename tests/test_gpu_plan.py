@@ -1,6 +1,6 @@
-"""Planned schedule (options.plan): once a handle has factored once level by
-level, the next factorizations reuse its front capacities and enqueue every tree
-level at once.  They must produce exactly the factors of the level-by-level
+"""Planned schedule (options.plan = 1, and 2 with graph replay): once a handle
+has factored once level by level, the next factorizations reuse its front
+capacities and enqueue every tree level at once.  They must produce exactly the factors of the level-by-level
 schedule (same arithmetic in every kernel, only storage and launch shapes
 differ), and a front that outgrows its capacity must make the call repeat the
 factorization level by level, again with the same result."""
@@ -29,20 +29,22 @@ def run(torch, S, vals, b, num=None, **opts):
     return num, x.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_planned_equals_levelwise(torch_cuda, prec):
+@pytest.mark.parametrize("prec,plan", [("fp64", 1), ("fp32", 1), ("fp64", 2), ("fp32", 2)])
+def test_planned_equals_levelwise(torch_cuda, prec, plan):
+    """plan = 2 replays the captured graph on steps 1-3, with the solves' own
+    work and synchronizations between the replays; every replay is checked."""
     s = build_2d(32, 16, 1)
     S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
     num_p = num_l = None
     for t in range(4):
         v, b = newton_values(s, t), newton_rhs(s, t)[0]
         num_l, x_l, _ = run(torch_cuda, S, v, b, num_l, prec=prec, plan=0)
-        num_p, x_p, _ = run(torch_cuda, S, v, b, num_p, prec=prec, plan=1)
+        num_p, x_p, _ = run(torch_cuda, S, v, b, num_p, prec=prec, plan=plan)
         fl, fp = num_l.info(), num_p.info()
         print(f"{prec} step {t}: planned={fp.planned} fallbacks={fp.plan_fallbacks} "
               f"delayed {fp.delayed_pivots} (level-wise {fl.delayed_pivots})", flush=True)
         assert fl.planned == 0
-        assert fp.planned == (1 if t > 0 else 0)
+        assert fp.planned == (plan if t > 0 else 0)
         assert fp.delayed_pivots == fl.delayed_pivots
         assert fp.max_front == fl.max_front
         assert np.array_equal(x_p, x_l)
