@@ -91,6 +91,12 @@ typedef struct {
                               stream) and replayed on `stream`; recaptured when the
                               plan, the pivot threshold or the scaling mode changes.
                               0 = synchronize per level; default 0 */
+    int32_t tune;          /* 1 = launch-shape tuner: the first 4 factorizations on a handle
+                              (level by level, not profiled) each run one combination of
+                              panel block (4 or 8 waves, for fronts of order <= 512) and
+                              swap tile width (16 or 64 columns) on every tree level and
+                              time each level; later ones use each level's fastest.  The
+                              shapes never change a result.  0 = fixed heuristics; default 0 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */
@@ -191,6 +197,7 @@ typedef struct {
     int32_t panel_launches;     /* panel kernel launches timed */
     int32_t planned;            /* 1 if this factorization ran on the planned schedule, 2 as a graph replay */
     int32_t plan_fallbacks;     /* planned runs on this handle repeated level by level (overflow) */
+    int32_t tuned;              /* 1 if this factorization used the tuner's chosen shapes */
 } mf_factor_info;
 
 mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);

@@ -35,7 +35,8 @@ class mf_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("pivot_u", ctypes.c_double), ("leaf_max", ctypes.c_int32),
                 ("target_omega", ctypes.c_double), ("max_outer", ctypes.c_int32), ("gmres_m", ctypes.c_int32),
                 ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("scale", ctypes.c_int32), ("plan", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("scale", ctypes.c_int32), ("plan", ctypes.c_int32),
+                ("tune", ctypes.c_int32)]
 
 
 class mf_symbolic_view(ctypes.Structure):
@@ -55,7 +56,7 @@ class mf_factor_info(ctypes.Structure):
                 ("schur_flops", ctypes.c_double), ("schur_launches", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("t_panel_kernel_ms", ctypes.c_double), ("panel_flops", ctypes.c_double),
                 ("panel_launches", ctypes.c_int32), ("planned", ctypes.c_int32),
-                ("plan_fallbacks", ctypes.c_int32)]
+                ("plan_fallbacks", ctypes.c_int32), ("tuned", ctypes.c_int32)]
 
 
 class mf_solve_info(ctypes.Structure):

@@ -25,7 +25,7 @@ template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
                                const LevelTasks& tk, hipStream_t st, hipEvent_t* ev, bool bf16_schur,
-                               std::vector<hipEvent_t>* pev);
+                               std::vector<hipEvent_t>* pev, bool panel_full = false);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
@@ -247,7 +247,29 @@ struct mf_num {
         }
     } plan;
     int32_t plan_fallbacks = 0;
+    // Launch-shape tuner (options.tune): per tree level, the panel block (4 or 8
+    // waves for fronts of order <= 512) and the swap tile width (16 or 64
+    // columns).  Neither changes any result.  Trial factorization c runs shape c
+    // on every level and times each level with events; after the last trial each
+    // level keeps its fastest shape.
+    struct Tuner {
+        static constexpr int kShapes = 4;  // bit 0: 8-wave panel; bit 1: 16-column swap tiles
+        int32_t prec = -1;
+        int trials = 0;
+        std::vector<std::array<float, kShapes>> ms;  // per level and shape
+        std::vector<int8_t> pick;                    // per level, once done
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool done() const { return trials >= kShapes; }
+        void reset(int nlevels, int p) {
+            prec = p;
+            trials = 0;
+            ms.assign(nlevels, {});
+            pick.assign(nlevels, -1);
+        }
+    } tuner;
     ~mf_num() {
+        if (tuner.e0) (void)hipEventDestroy(tuner.e0);
+        if (tuner.e1) (void)hipEventDestroy(tuner.e1);
         plan.free_device();
         fronts.release();
         ints.release();
@@ -350,7 +372,7 @@ int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 ||
 // Tile work lists of one level (entries as in LevelTasks, appended to t), shared by
 // both precisions (each kernel skips fronts of the other one).  The result holds
 // the counts and the swap width; place_tasks points it at a device copy.
-LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t) {
+LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t, int sw_force = 0) {
     const size_t base = t.size();
     {
         size_t est = 0;
@@ -361,7 +383,7 @@ LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>
         t.reserve(base + est);
     }
     // few (large) fronts: narrow swap tiles so that more blocks share the latency-bound work
-    const int sw = count < 32 ? 16 : 64;
+    const int sw = sw_force ? sw_force : (count < 32 ? 16 : 64);
     for (int i = 0; i < count; i++) {
         const int T = (hf[i].m + sw - 1) / sw;
         for (int a = 0; a < T; a++) t.push_back(task_code(i, a >> 6, a & 63));
@@ -401,10 +423,10 @@ LevelTasks place_tasks(LevelTasks tk, const int32_t* d) {
 
 // Uploaded once per level by the synchronizing schedule: the previous level has
 // been synchronized, so the pinned staging can be reused.
-LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st) {
+LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st, int sw_force = 0) {
     std::vector<int32_t>& t = N->task_scratch;
     t.clear();
-    const LevelTasks tk = build_level_tasks(hf, count, t);
+    const LevelTasks tk = build_level_tasks(hf, count, t, sw_force);
     if (t.size() > N->tasks_cap) {
         if (N->d_tasks) HIPX(hipFree(N->d_tasks));
         if (N->h_tasks) HIPX(hipHostFree(N->h_tasks));
@@ -498,7 +520,8 @@ void build_plan(mf_num* N) {
                 ((size_t)pl.lvl_Pmax[p][L] * 2 * sizeof(int) > kMaxLds || pl.lvl_mmax[p][L] > 4096))
                 return;  // capacities beyond the kernels' limits: keep synchronizing per level
         toff[L] = tasks.size();
-        pl.tasks[L] = build_level_tasks(tm.data() + s0, s1 - s0, tasks);
+        const int shape = (o.tune && N->tuner.done()) ? N->tuner.pick[L] : -1;
+        pl.tasks[L] = build_level_tasks(tm.data() + s0, s1 - s0, tasks, shape < 0 ? 0 : ((shape & 2) ? 16 : 64));
     }
     HIPX(hipMalloc((void**)&pl.d_tmpl, sizeof(FrontNum) * tm.size()));
     HIPX(hipMemcpy(pl.d_tmpl, tm.data(), sizeof(FrontNum) * tm.size(), hipMemcpyHostToDevice));
@@ -555,17 +578,18 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
         HIPX(launch_fill_i32(pl.d_flag, 0, q));
         for (int L = 0; L < S.nlevels; L++) {
             const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
+            const bool full = o.tune && N->tuner.done() && (N->tuner.pick[L] & 1);
             HIPX(launch_level_setup(D.S, N->d_fn, pl.d_tmpl, s0, s1 - s0, pl.d_flag, q));
             const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
             if (pl.lvl_cnt[0][L])
                 HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[0][L],
                                                  pl.lvl_cls_mmax[0][L].data(), pl.lvl_cls_Pmax[0][L].data(), fvals,
-                                                 u0, u1, o.pivot_u, 0, pl.tasks[L], q, nullptr, false, nullptr));
+                                                 u0, u1, o.pivot_u, 0, pl.tasks[L], q, nullptr, false, nullptr, full));
             if (pl.lvl_cnt[1][L])
                 HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[1][L],
                                                 pl.lvl_cls_mmax[1][L].data(), pl.lvl_cls_Pmax[1][L].data(), fvals,
                                                 u0, u1, o.pivot_u, 1, pl.tasks[L], q, nullptr, o.prec == MF_BF16,
-                                                nullptr));
+                                                nullptr, full));
         }
     };
     if (o.plan == 2) {
@@ -609,6 +633,7 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     N->vec_len = pl.vec_len;
     N->info = finished_info(N);
     N->info.planned = o.plan == 2 ? 2 : 1;
+    N->info.tuned = (o.tune && N->tuner.done()) ? 1 : 0;
     N->info.plan_fallbacks = N->plan_fallbacks;
     N->factored = true;
     return true;
@@ -649,7 +674,8 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         HIPX(launch_ruiz(D.S, N->d_vals, S.n, o.scale, N->d_dr, N->d_dc, N->d_rmax, N->d_cmax, N->d_svals, st));
         fvals = N->d_svals;
     }
-    const bool use_plan = o.plan != 0 && o.profile == 0 && N->plan.valid && N->plan.prec == o.prec;
+    const bool use_plan = o.plan != 0 && o.profile == 0 && N->plan.valid && N->plan.prec == o.prec &&
+                          !(o.tune && !N->tuner.done());  // tuner trials run level by level
     if (use_plan && factor_planned(N, fvals, st)) return;
     if (N->fronts.chunks.empty()) {
         double tot = 0;
@@ -685,6 +711,15 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         }
     } evg{ev, prof};
     std::vector<hipEvent_t> pev;  // (start, end) of every panel launch (profile mode)
+    // launch-shape tuner: trials run on this (level by level) schedule only
+    if (o.tune && (N->tuner.prec != o.prec || (int)N->tuner.pick.size() != S.nlevels))
+        N->tuner.reset(S.nlevels, o.prec);
+    const bool tuning = o.tune && !prof && !N->tuner.done();
+    const bool tuned = o.tune && N->tuner.done();
+    if (tuning && !N->tuner.e0) {
+        HIPX(hipEventCreate(&N->tuner.e0));
+        HIPX(hipEventCreate(&N->tuner.e1));
+    }
     int64_t voff = 0;
     mf_factor_info info{};
     info.factor_flops = S.nominal_flops;
@@ -741,25 +776,30 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
             fr.W = N->wsp.alloc((size_t)2 * fr.m * nbp * (fr.prec ? 4 : 8));
         }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
-        const LevelTasks tk = upload_level_tasks(N, hf + s0, s1 - s0, st);
+        const int shape = tuning ? N->tuner.trials : (tuned ? N->tuner.pick[L] : -1);
+        const LevelTasks tk = upload_level_tasks(N, hf + s0, s1 - s0, st, shape < 0 ? 0 : ((shape & 2) ? 16 : 64));
+        const bool full = shape >= 0 && (shape & 1);
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
+        if (tuning) HIPX(hipEventRecord(N->tuner.e0, st));
         // fronts of both precisions may share a level; each kernel skips the other kind
         if (N->lvl_cnt[0][L]) {
             if (prof) HIPX(hipEventRecord(ev[0][0], st));
             HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
                                              N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), fvals,
                                              u0, u1, o.pivot_u, 0, tk, st, prof ? &ev[0][1] : nullptr, false,
-                                             prof ? &pev : nullptr));
+                                             prof ? &pev : nullptr, full));
         }
         if (N->lvl_cnt[1][L]) {
             if (prof) HIPX(hipEventRecord(ev[1][0], st));
             HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
                                             N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), fvals,
                                             u0, u1, o.pivot_u, 1, tk, st, prof ? &ev[1][1] : nullptr,
-                                            o.prec == MF_BF16, prof ? &pev : nullptr));
+                                            o.prec == MF_BF16, prof ? &pev : nullptr, full));
         }
+        if (tuning) HIPX(hipEventRecord(N->tuner.e1, st));
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));
+        if (tuning) HIPX(hipEventElapsedTime(&N->tuner.ms[L][N->tuner.trials], N->tuner.e0, N->tuner.e1));
         info.levels++;
         if (prof)
             for (int p = 0; p < 2; p++) {
@@ -817,6 +857,14 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     N->vec_len = voff;
     info.factor_bytes = front_bytes;
     info.plan_fallbacks = N->plan_fallbacks;
+    info.tuned = tuned ? 1 : 0;
+    if (tuning && ++N->tuner.trials == mf_num::Tuner::kShapes)
+        for (int L = 0; L < S.nlevels; L++) {
+            int best = 0;
+            for (int c = 1; c < mf_num::Tuner::kShapes; c++)
+                if (N->tuner.ms[L][c] < N->tuner.ms[L][best]) best = c;
+            N->tuner.pick[L] = (int8_t)best;
+        }
     N->info = info;
     N->factored = true;
     if (o.plan != 0) build_plan(N);
@@ -1208,6 +1256,7 @@ void mf_default_options(mf_options* o) {
     o->profile = 0;
     o->scale = 1;
     o->plan = 0;
+    o->tune = 0;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -1283,6 +1332,7 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
         N->opt.profile = opt->profile;
         N->opt.scale = opt->scale;
         N->opt.plan = opt->plan;
+        N->opt.tune = opt->tune;
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");

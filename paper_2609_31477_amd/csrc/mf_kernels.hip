@@ -1612,7 +1612,7 @@ template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
                                const LevelTasks& tk, hipStream_t st, hipEvent_t* ev, bool bf16_schur,
-                               std::vector<hipEvent_t>* pev) {
+                               std::vector<hipEvent_t>* pev, bool panel_full) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
@@ -1638,8 +1638,11 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                 pev->push_back(e1);
             }
             // levels of class-0 fronts (order <= 512, window 32): 4 waves per front, one
-            // per SIMD, with one or two rows per lane (same arithmetic as 8 waves)
-            if (mmax <= kPanelSmallThreads)
+            // per SIMD, with one or two rows per lane (same arithmetic as 8 waves),
+            // unless panel_full asks for the 8-wave kernel
+            if (panel_full)
+                hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+            else if (mmax <= kPanelSmallThreads)
                 hipLaunchKernelGGL((k_panel_small<T, 1>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
                                    slot0, u, prec);
             else if (mmax <= 2 * kPanelSmallThreads)
@@ -1669,10 +1672,10 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
 
 template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
                                                 const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
-                                                hipEvent_t*, bool, std::vector<hipEvent_t>*);
+                                                hipEvent_t*, bool, std::vector<hipEvent_t>*, bool);
 template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
                                                const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
-                                               hipEvent_t*, bool, std::vector<hipEvent_t>*);
+                                               hipEvent_t*, bool, std::vector<hipEvent_t>*, bool);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,

@@ -72,3 +72,21 @@ def test_plan_overflow_falls_back(torch_cuda):
     f2 = num.info()
     assert f2.planned == 1 and f2.plan_fallbacks == 1
     assert np.array_equal(x2, x_ref)
+
+
+@pytest.mark.parametrize("plan", [0, 1])
+def test_tuner_keeps_results(torch_cuda, plan):
+    """options.tune: the four trial factorizations (each launch shape on every
+    level) and the tuned ones after them give exactly the results of the fixed
+    heuristic shapes."""
+    s = build_2d(32, 16, 1)
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    num_t = num_f = None
+    for t in range(7):
+        v, b = newton_values(s, t % 5), newton_rhs(s, t % 5)[0]
+        num_f, x_f, _ = run(torch_cuda, S, v, b, num_f, plan=0, tune=0)
+        num_t, x_t, _ = run(torch_cuda, S, v, b, num_t, plan=plan, tune=1)
+        fi = num_t.info()
+        print(f"factorization {t}: tuned={fi.tuned} planned={fi.planned}", flush=True)
+        assert fi.tuned == (1 if t >= 4 else 0)
+        assert np.array_equal(x_t, x_f)
