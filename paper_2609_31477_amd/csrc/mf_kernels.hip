@@ -101,19 +101,25 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     const int nk = ce - cb;
     const bool staged = nk <= kMaxKids;
     if (staged) {
+        // one thread per child reads its fields (no chain of dependent loads),
+        // then one thread forms the delayed-segment offsets in child order
+        if (threadIdx.x < nk) {
+            const int t = threadIdx.x;
+            const int cs = S.child_slot[cb + t];
+            const FrontNum dc = fn[cs];
+            kid_dout[t] = dc.P - dc.k;
+            kid_k[t] = dc.k;
+            kid_m[t] = dc.m;
+            kid_prec[t] = dc.prec;
+            kid_im[t] = S.imap_off[cs];
+            kid_F[t] = dc.F;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
             int dseg = 0;
             for (int t = 0; t < nk; t++) {
-                const int cs = S.child_slot[cb + t];
-                const FrontNum dc = fn[cs];
-                kid_dout[t] = dc.P - dc.k;
                 kid_dseg[t] = dseg;
-                kid_k[t] = dc.k;
-                kid_m[t] = dc.m;
-                kid_prec[t] = dc.prec;
-                kid_im[t] = S.imap_off[cs];
-                kid_F[t] = dc.F;
-                dseg += dc.P - dc.k;
+                dseg += kid_dout[t];
             }
         }
         __syncthreads();
