@@ -98,6 +98,8 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids], kid_k[kMaxKids], kid_m[kMaxKids], kid_prec[kMaxKids];
     __shared__ int64_t kid_im[kMaxKids];
     __shared__ const void* kid_F[kMaxKids];
+    __shared__ int act_s[kMaxKids];
+    __shared__ int nact_s;
     const int nk = ce - cb;
     const bool staged = nk <= kMaxKids;
     if (staged) {
@@ -129,6 +131,21 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
             cj_s[t][jj] = j < m ? child_pos(j, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + S.imap_off[cs]) : -1;
         }
         __syncthreads();
+        // children that reach none of this block's columns (or have an empty
+        // contribution block) add only zeros: the first wave lists the others,
+        // in child order, with one ballot
+        if (threadIdx.x < kMaxKids) {
+            const int t = threadIdx.x;
+            bool act = false;
+            if (t < nk && kid_m[t] != kid_k[t]) {
+#pragma unroll
+                for (int jj = 0; jj < kGatherCols; jj++) act |= cj_s[t][jj] >= 0;
+            }
+            const uint64_t mask = __ballot(act);
+            if (act) act_s[__popcll(mask & ((1ull << t) - 1))] = t;
+            if (t == 0) nact_s = __popcll(mask);
+        }
+        __syncthreads();
     }
     if (staged) {
         // Each child's 16 values of a row are loaded at once, at clamped in-range
@@ -140,9 +157,10 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
             double acc[kGatherCols];
 #pragma unroll
             for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
-            for (int t = 0; t < nk; t++) {
+            const int nact = nact_s;
+            for (int a = 0; a < nact; a++) {
+                const int t = act_s[a];
                 const int ck = kid_k[t], cm = kid_m[t];
-                if (cm == ck) continue;  // empty contribution block
                 const int ci = child_pos(i, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + kid_im[t]);
                 const int64_t rbase = ck + (ci >= 0 ? ci : 0);
                 double val[kGatherCols];
