@@ -378,7 +378,7 @@ LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>
         size_t est = 0;
         for (int i = 0; i < count; i++) {
             const size_t T = (hf[i].m + 63) / 64;
-            est += 4 * T + 2 * T * T;
+            est += 4 * T + 2 * T * T + (hf[i].m + kGatherTileCols - 1) / kGatherTileCols;
         }
         t.reserve(base + est);
     }
@@ -402,6 +402,12 @@ LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>
             for (int b = 0; b < T; b++) t.push_back(task_code(i, a, b));
     }
     const size_t ng1 = t.size() - base - nswap - ng0;
+    // extend-add: 16-column tiles, 4 (order <= 64) or 2 (<= 128) of them per block
+    for (int i = 0; i < count; i++) {
+        const int m = hf[i].m, lg = gather_lg(m), T = (m + kGatherTileCols - 1) / kGatherTileCols;
+        for (int a = 0; a < T; a += 1 << lg) t.push_back(gather_task(i, lg, a));
+    }
+    const size_t ngather = t.size() - base - nswap - ng0 - ng1;
     LevelTasks tk;
     tk.swap = nullptr;
     tk.nswap = (int32_t)nswap;
@@ -410,6 +416,8 @@ LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>
     tk.ng0 = (int32_t)ng0;
     tk.g1 = nullptr;
     tk.ng1 = (int32_t)ng1;
+    tk.gather = nullptr;
+    tk.ngather = (int32_t)ngather;
     return tk;
 }
 
@@ -418,6 +426,7 @@ LevelTasks place_tasks(LevelTasks tk, const int32_t* d) {
     tk.swap = d;
     tk.g0 = d + tk.nswap;
     tk.g1 = d + tk.nswap + tk.ng0;
+    tk.gather = d + tk.nswap + tk.ng0 + tk.ng1;
     return tk;
 }
 

@@ -63,8 +63,18 @@ struct LevelTasks {
     int32_t ng0;
     const int32_t* g1;    // (front, row tile, column tile) over the contribution block [P, m)^2
     int32_t ng1;
+    const int32_t* gather;  // (front, group size, first column tile): see gather_task
+    int32_t ngather;
 };
 __host__ __device__ inline int32_t task_code(int rel, int a, int b) { return (rel << 12) | (a << 6) | b; }
+
+// Extend-add tasks: kGatherCols-column tiles (16), 1 << lg of them per block;
+// tile index below 512 (orders up to 8192), lg in {0, 1, 2}.
+constexpr int kGatherTileCols = 16;
+__host__ __device__ inline int gather_lg(int m) { return m <= 64 ? 2 : (m <= 128 ? 1 : 0); }
+__host__ __device__ inline int32_t gather_task(int rel, int lg, int tile) { return (rel << 12) | (lg << 9) | tile; }
+__host__ __device__ inline int gather_task_lg(int32_t code) { return (code >> 9) & 3; }
+__host__ __device__ inline int gather_task_tile(int32_t code) { return code & 511; }
 
 // Pattern data (slot-indexed), uploaded once per symbolic handle.
 struct DevSym {

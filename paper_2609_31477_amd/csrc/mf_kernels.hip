@@ -29,7 +29,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kGatherCols = 16;   // columns per gather work-group
+constexpr int kGatherCols = kGatherTileCols;  // columns per gather tile
+static_assert(kGatherCols == 16, "gather column decoding assumes 16-column tiles");
 constexpr int kTile = 64;         // GEMM tile (rows and columns)
 constexpr int kKC = 32;           // GEMM K chunk staged through LDS
 constexpr int kLdsPad = kTile + 1;
@@ -70,18 +71,29 @@ __device__ __forceinline__ double load_front(const FrontNum& d, int64_t idx) {
 
 // ------------------------------------------------------------------ assembly
 // Owner-computes extend-add: every entry of the front is written exactly once,
-// as the sum over children (in child order) of the matching CB entries.  Block
-// (x: column tile, y: front).  Also resets the front's pivot bookkeeping.
+// as the sum over children (in child order) of the matching CB entries.  One
+// block per task (front, first column tile); the block covers G = 1, 2 or 4
+// consecutive tiles of kGatherCols columns, one per group of 256/G threads (the
+// host picks G = 4 for fronts of order <= 64 and 2 up to 128, so that small
+// fronts keep every lane busy).  Also resets the front's pivot bookkeeping.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int slot0, int want_prec) {
-    const int s = slot0 + blockIdx.y;
+__global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int slot0, int want_prec,
+                                                     const int32_t* tasks) {
+    const int32_t code = tasks[blockIdx.x];
+    const int s = slot0 + (code >> 12);
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m;
-    const int j0 = blockIdx.x * kGatherCols;
-    if (j0 >= m) return;
+    const int lg = gather_task_lg(code);
+    const int jb = gather_task_tile(code) * kGatherCols;  // first column of the block
+    if (jb >= m) return;
+    const int rstep = kThreads >> lg;                 // rows per pass of a group
+    const int g = threadIdx.x >> (8 - lg);
+    const int r = threadIdx.x & (rstep - 1);
+    const int bc = kGatherCols << lg;                 // columns of the block
+    const int j0 = jb + g * kGatherCols;              // first column of this group
     T* F = (T*)d.F;
-    if (blockIdx.x == 0) {
+    if (jb == 0) {
         int32_t* colperm = iv_colperm(d.iv, d.P, m);
         int32_t* rowperm = iv_rowperm(d.iv, d.P, m);
         for (int i = threadIdx.x; i < d.P; i += kThreads) {
@@ -94,7 +106,8 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     // columns, computed once per block into LDS (then every row's loads of a child
     // are independent)
     constexpr int kMaxKids = 64;
-    __shared__ int cj_s[kMaxKids][kGatherCols];
+    constexpr int kMaxCols = 4 * kGatherCols;
+    __shared__ int cj_s[kMaxKids][kMaxCols];
     __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids], kid_k[kMaxKids], kid_m[kMaxKids], kid_prec[kMaxKids];
     __shared__ int64_t kid_im[kMaxKids];
     __shared__ const void* kid_F[kMaxKids];
@@ -125,10 +138,9 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < nk * kGatherCols; q += kThreads) {
-            const int t = q / kGatherCols, jj = q % kGatherCols, j = j0 + jj;
-            const int cs = S.child_slot[cb + t];
-            cj_s[t][jj] = j < m ? child_pos(j, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + S.imap_off[cs]) : -1;
+        for (int q = threadIdx.x; q < nk * bc; q += kThreads) {
+            const int t = q >> (4 + lg), c = q & (bc - 1), j = jb + c;
+            cj_s[t][c] = j < m ? child_pos(j, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + kid_im[t]) : -1;
         }
         __syncthreads();
         // children that reach none of this block's columns (or have an empty
@@ -137,31 +149,35 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         if (threadIdx.x < kMaxKids) {
             const int t = threadIdx.x;
             bool act = false;
-            if (t < nk && kid_m[t] != kid_k[t]) {
-#pragma unroll
-                for (int jj = 0; jj < kGatherCols; jj++) act |= cj_s[t][jj] >= 0;
-            }
+            if (t < nk && kid_m[t] != kid_k[t])
+                for (int c = 0; c < bc; c++) act |= cj_s[t][c] >= 0;
             const uint64_t mask = __ballot(act);
             if (act) act_s[__popcll(mask & ((1ull << t) - 1))] = t;
             if (t == 0) nact_s = __popcll(mask);
         }
         __syncthreads();
-    }
-    if (staged) {
+        if (j0 >= m) return;  // (no barrier follows)
+        const int gc = g * kGatherCols;
+        const int nact = nact_s;
         // Each child's 16 values of a row are loaded at once, at clamped in-range
         // positions (its first contribution-block row or column where the parent
         // row or column has no counterpart) and masked after: one memory round trip
-        // per child instead of one per value.  Misses add +0.0, which leaves the
-        // sums exactly as skipping them would (they never hold -0.0).
-        for (int i = threadIdx.x; i < m; i += kThreads) {
+        // per child instead of one per value; the next child's row position is
+        // looked up while these loads are in flight.  Misses add +0.0, which leaves
+        // the sums exactly as skipping them would (they never hold -0.0).
+        for (int i = r; i < m; i += rstep) {
             double acc[kGatherCols];
 #pragma unroll
             for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
-            const int nact = nact_s;
+            int ci_next = 0;
+            if (nact > 0) {
+                const int t = act_s[0];
+                ci_next = child_pos(i, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + kid_im[t]);
+            }
             for (int a = 0; a < nact; a++) {
                 const int t = act_s[a];
                 const int ck = kid_k[t], cm = kid_m[t];
-                const int ci = child_pos(i, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + kid_im[t]);
+                const int ci = ci_next;
                 const int64_t rbase = ck + (ci >= 0 ? ci : 0);
                 double val[kGatherCols];
                 if (kid_prec[t]) {
@@ -169,17 +185,22 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
                     float raw[kGatherCols];
 #pragma unroll
                     for (int jj = 0; jj < kGatherCols; jj++)
-                        raw[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][jj], 0)) * cm];
+                        raw[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][gc + jj], 0)) * cm];
 #pragma unroll
                     for (int jj = 0; jj < kGatherCols; jj++) val[jj] = (double)raw[jj];
                 } else {
                     const gptr<const double> Fc = as_global((const double*)kid_F[t]);
 #pragma unroll
                     for (int jj = 0; jj < kGatherCols; jj++)
-                        val[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][jj], 0)) * cm];
+                        val[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][gc + jj], 0)) * cm];
+                }
+                if (a + 1 < nact) {
+                    const int tn = act_s[a + 1];
+                    ci_next = child_pos(i, d.npiv, d.din, kid_dseg[tn], kid_dout[tn], S.imap + kid_im[tn]);
                 }
 #pragma unroll
-                for (int jj = 0; jj < kGatherCols; jj++) acc[jj] += ((ci >= 0) & (cj_s[t][jj] >= 0)) ? val[jj] : 0.0;
+                for (int jj = 0; jj < kGatherCols; jj++)
+                    acc[jj] += ((ci >= 0) & (cj_s[t][gc + jj] >= 0)) ? val[jj] : 0.0;
             }
 #pragma unroll
             for (int jj = 0; jj < kGatherCols; jj++) {
@@ -189,7 +210,8 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         }
         return;
     }
-    for (int i = threadIdx.x; i < m; i += kThreads) {
+    if (j0 >= m) return;
+    for (int i = r; i < m; i += rstep) {
         double acc[kGatherCols];
 #pragma unroll
         for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
@@ -1639,8 +1661,8 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                                std::vector<hipEvent_t>* pev, bool panel_full) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gather<T>, dim3((mmax + kGatherCols - 1) / kGatherCols, count), dim3(kThreads), 0, st, S,
-                       fn, slot0, prec);
+    if (tk.ngather)
+        hipLaunchKernelGGL(k_gather<T>, dim3(tk.ngather), dim3(kThreads), 0, st, S, fn, slot0, prec, tk.gather);
     if (u1 > u0)
         hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                            st, S, fn, vals, u0, u1, prec);
