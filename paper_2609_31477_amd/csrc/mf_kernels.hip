@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     const int jb = gather_task_tile(code) * kGatherCols;  // first column of the block
     if (jb >= m) return;
     const int rstep = kThreads >> lg;                 // rows per pass of a group
-    const int g = threadIdx.x >> (8 - lg);
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> (8 - lg));  // (uniform per wave)
     const int r = threadIdx.x & (rstep - 1);
     const int bc = kGatherCols << lg;                 // columns of the block
     const int j0 = jb + g * kGatherCols;              // first column of this group
@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
     // columns, computed once per block into LDS (then every row's loads of a child
     // are independent)
     constexpr int kMaxKids = 64;
+    constexpr int kFewKids = 8;
     constexpr int kMaxCols = 4 * kGatherCols;
     __shared__ int cj_s[kMaxKids][kMaxCols];
     __shared__ int kid_dout[kMaxKids], kid_dseg[kMaxKids], kid_k[kMaxKids], kid_m[kMaxKids], kid_prec[kMaxKids];
@@ -159,6 +160,58 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         if (j0 >= m) return;  // (no barrier follows)
         const int gc = g * kGatherCols;
         const int nact = nact_s;
+        // Many children (a front whose columns every child reaches, such as the
+        // ones tied to all multipliers): row positions are looked up for kCiBatch
+        // children at once, and a child none of whose rows meets the wave's rows
+        // is skipped (wave-uniform test).
+        if (nact > kFewKids) {
+            constexpr int kCiBatch = 4;
+            for (int i = r; i < m; i += rstep) {
+                double acc[kGatherCols];
+#pragma unroll
+                for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
+                for (int a0 = 0; a0 < nact; a0 += kCiBatch) {
+                    int ci[kCiBatch];
+#pragma unroll
+                    for (int b = 0; b < kCiBatch; b++) {
+                        const int t = act_s[min(a0 + b, nact - 1)];
+                        ci[b] = child_pos(i, d.npiv, d.din, kid_dseg[t], kid_dout[t], S.imap + kid_im[t]);
+                    }
+#pragma unroll
+                    for (int b = 0; b < kCiBatch; b++) {
+                        if (a0 + b >= nact) break;
+                        if (!__any(ci[b] >= 0)) continue;
+                        const int t = act_s[a0 + b];
+                        const int ck = kid_k[t], cm = kid_m[t];
+                        const int64_t rbase = ck + (ci[b] >= 0 ? ci[b] : 0);
+                        double val[kGatherCols];
+                        if (kid_prec[t]) {
+                            const gptr<const float> Fc = as_global((const float*)kid_F[t]);
+                            float raw[kGatherCols];
+#pragma unroll
+                            for (int jj = 0; jj < kGatherCols; jj++)
+                                raw[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][gc + jj], 0)) * cm];
+#pragma unroll
+                            for (int jj = 0; jj < kGatherCols; jj++) val[jj] = (double)raw[jj];
+                        } else {
+                            const gptr<const double> Fc = as_global((const double*)kid_F[t]);
+#pragma unroll
+                            for (int jj = 0; jj < kGatherCols; jj++)
+                                val[jj] = Fc[rbase + (int64_t)(ck + max(cj_s[t][gc + jj], 0)) * cm];
+                        }
+#pragma unroll
+                        for (int jj = 0; jj < kGatherCols; jj++)
+                            acc[jj] += ((ci[b] >= 0) & (cj_s[t][gc + jj] >= 0)) ? val[jj] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < kGatherCols; jj++) {
+                    const int j = j0 + jj;
+                    if (j < m) F[i + (int64_t)j * m] = (T)acc[jj];
+                }
+            }
+            return;
+        }
         // Each child's 16 values of a row are loaded at once, at clamped in-range
         // positions (its first contribution-block row or column where the parent
         // row or column has no counterpart) and masked after: one memory round trip
