@@ -750,6 +750,42 @@ __global__ __launch_bounds__(kPanelSmallThreads, (RS == 1 ? 5 : 1)) void k_panel
     panel_front<T, 32, RS, kPanelSmallThreads>(fn, s, u, dyn);
 }
 
+// Forward substitution x <- L11^-1 x for the columns [c0, cend) of the tile that
+// lie ahead of the panel (>= kd1) and outside the just-delayed block [x0, x1),
+// one column per lane of the calling wave (so cend - c0 <= 64), on rows
+// [kd0, kd0 + nb).  L11 is unit lower, column-major with leading dimension
+// kNBMax, in LDS.  Each row is updated in step order with one fused multiply-add
+// per step, in double precision, and rounded to T once at the end.
+template <typename T, int N>
+__device__ __forceinline__ void trsm_lane_cols(const gptr<T> F, const T* L11, int m, int kd0, int kd1, int x0,
+                                               int x1, int nb, int c0, int cend) {
+    const int lane = threadIdx.x & 63;
+    const int j = c0 + lane;
+    const bool live = j < cend && j >= kd1 && !(j >= x0 && j < x1);
+    if (!__any(live)) return;
+    const gptr<T> colp = F + (int64_t)(live ? j : c0) * m + kd0;
+    double x[N];
+#pragma unroll
+    for (int r = 0; r < N; r++) x[r] = (double)colp[min(r, nb - 1)];
+#pragma unroll
+    for (int a = 0; a < N - 1; a++) {
+        const double xa = x[a];
+        // a zero the compiler cannot see through, computed from x[a]: step a's L11
+        // reads wait for x[a] instead of all being hoisted to the start, which
+        // would hold every entry of L11 in registers at once
+        int z;
+        asm("v_mov_b32 %0, 0" : "=v"(z) : "v"((int)(__double_as_longlong(xa) >> 32)));
+        const T* Lc = L11 + a * kNBMax + z;
+#pragma unroll
+        for (int r = a + 1; r < N; r++) x[r] -= (double)Lc[r] * xa;
+    }
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < N; r++)
+            if (r < nb) colp[r] = (T)x[r];
+    }
+}
+
 // Columns outside the last panel's window: apply its row swaps; for columns
 // ahead of it (>= k, outside the just-delayed block) also form the new U rows
 // with the unit-lower L11 of the panel.  One block per (front, tile of sw <= 64
@@ -817,42 +853,16 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
         }
         __syncthreads();
     }
-    // new U rows: unit-lower solve with L11, half a wave per column (lane = row of
-    // the panel), the pivot row's value broadcast with readlane at each step.  A
-    // wave carries kP column pairs through the steps together: independent chains
-    // that fill each other's readlane and FMA latencies.
-    constexpr int kP = 4;
-    const int lane = tid & 63, half = lane >> 5, r = lane & 31, wid = tid >> 6;
-    const int npair = (cend - c0 + 1) / 2;
-    for (int pb = wid; pb < npair; pb += kP * (kThreads / 64)) {
-        double x[kP];
-        bool live[kP];
-        gptr<T> colp[kP];
-#pragma unroll
-        for (int q = 0; q < kP; q++) {
-            const int p = pb + q * (kThreads / 64);
-            const int j = c0 + 2 * p + half;
-            live[q] = p < npair && j < cend && j >= kd1 && !(j >= d.x0 && j < d.x1);
-            colp[q] = F + (int64_t)(live[q] ? j : c0) * m + kd0;
-            x[q] = (live[q] && r < nb) ? (double)colp[q][r] : 0.0;
-        }
-        for (int a = 0; a < nb - 1; a++) {
-            const double la = (double)L11[r + a * kNBMax];
-#pragma unroll
-            for (int q = 0; q < kP; q++) {
-                const long long xb = __double_as_longlong(x[q]);
-                const int lo0 = __builtin_amdgcn_readlane((int)xb, a),
-                          hi0 = __builtin_amdgcn_readlane((int)(xb >> 32), a);
-                const int lo1 = __builtin_amdgcn_readlane((int)xb, 32 + a),
-                          hi1 = __builtin_amdgcn_readlane((int)(xb >> 32), 32 + a);
-                const int lo = half ? lo1 : lo0, hi = half ? hi1 : hi0;
-                const double xa = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-                if (r > a) x[q] -= la * xa;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kP; q++)
-            if (live[q] && r < nb) colp[q][r] = (T)x[q];
+    // new U rows: unit-lower solve with L11, one lane per column with the column's
+    // rows in registers and L11's entries read as wave-uniform LDS broadcasts, so
+    // a step needs no cross-lane traffic.  N >= nb is a compile-time row count:
+    // rows [nb, N) and steps [nb - 1, N - 1) only touch rows that are not stored.
+    if (tid < 64) {
+        if (nb <= 8) trsm_lane_cols<T, 8>(F, L11, m, kd0, kd1, d.x0, d.x1, nb, c0, cend);
+        else if (nb <= 16) trsm_lane_cols<T, 16>(F, L11, m, kd0, kd1, d.x0, d.x1, nb, c0, cend);
+        else if (nb <= 20) trsm_lane_cols<T, 20>(F, L11, m, kd0, kd1, d.x0, d.x1, nb, c0, cend);
+        else if (nb <= 26) trsm_lane_cols<T, 26>(F, L11, m, kd0, kd1, d.x0, d.x1, nb, c0, cend);
+        else trsm_lane_cols<T, kNBMax>(F, L11, m, kd0, kd1, d.x0, d.x1, nb, c0, cend);
     }
 }
 
