@@ -558,19 +558,39 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         // other parity, and this parity is rewritten only after every wave has
         // passed the next step's barrier (so all of this step's reads are done)
     };
+    // A wave whose rows all lie beyond the front (its first row is >= m) has no
+    // candidate, no update and no row to publish: it posts "no candidate" once for
+    // both parities and only keeps the block's barrier count, one per column.
+    // Its registers are never stored, and nb reaches it through LDS below.
+    __shared__ int nb_s;
+    if (kd0 + (__builtin_amdgcn_readfirstlane(wid) << 6) >= m) {
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                red_a[q][wid] = 0.0;
+                red_f[q][wid] = -1.0;
+                red_i[q][wid] = INT_MAX;
+            }
+        }
+        for (int c = 0; c < w; c++) lds_barrier();
+    } else {
 #pragma unroll 1
-    for (int c0 = 0; c0 < NB; c0 += 2) {
-        step(c0, std::integral_constant<int, 0>());
-        step(c0, std::integral_constant<int, 1>());
+        for (int c0 = 0; c0 < NB; c0 += 2) {
+            step(c0, std::integral_constant<int, 0>());
+            step(c0, std::integral_constant<int, 1>());
 #pragma unroll
-        for (int r = 0; r < RS; r++) {
-            const T t0 = v[r][0], t1 = v[r][1];
+            for (int r = 0; r < RS; r++) {
+                const T t0 = v[r][0], t1 = v[r][1];
 #pragma unroll
-            for (int j = 0; j + 2 < NB; j++) v[r][j] = v[r][j + 2];
-            v[r][NB - 2] = t0;
-            v[r][NB - 1] = t1;
+                for (int j = 0; j + 2 < NB; j++) v[r][j] = v[r][j + 2];
+                v[r][NB - 2] = t0;
+                v[r][NB - 1] = t1;
+            }
         }
     }
+    if (tid == 0) nb_s = nb;
+    __syncthreads();
+    nb = nb_s;
 
     // ---- final column and row positions
     const int nrej = w - nb;
