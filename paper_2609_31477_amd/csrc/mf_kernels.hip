@@ -766,8 +766,12 @@ template <typename T, int RS>
 __global__ __launch_bounds__(kPanelSmallThreads, (RS == 1 ? 5 : 1)) void k_panel_small(FrontNum* fn, int slot0, double u, int want_prec) {
     extern __shared__ int dyn[];
     const int s = slot0 + blockIdx.x;
-    if (fn[s].prec != want_prec) return;
-    panel_front<T, 32, RS, kPanelSmallThreads>(fn, s, u, dyn);
+    const FrontNum d = fn[s];
+    if (d.prec != want_prec) return;
+    // two rows per thread only where the front's remaining rows need them (the
+    // arithmetic of the two variants is the same)
+    if (RS == 1 || d.m - d.k <= kPanelSmallThreads) panel_front<T, 32, 1, kPanelSmallThreads>(fn, s, u, dyn);
+    else panel_front<T, 32, RS, kPanelSmallThreads>(fn, s, u, dyn);
 }
 
 // Forward substitution x <- L11^-1 x for the columns [c0, cend) of the tile that
