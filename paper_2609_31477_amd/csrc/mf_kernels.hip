@@ -741,16 +741,35 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
     const int s = slot0 + blockIdx.x;
     const int prec = fn[s].prec;
     if (prec != want_prec) return;
-    switch (front_class(fn[s].m)) {
+    // The window width follows the front's class (its order); the rows per thread
+    // follow the rows still to factor, [k, m), which shrink round by round (the
+    // arithmetic does not depend on how rows are spread over threads).
+    const int m = fn[s].m, rem = m - fn[s].k;
+    switch (front_class(m)) {
         case 0: panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn); break;
-        case 1: panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn); break;
+        case 1:
+            if (rem <= kPanelThreads) panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn);
+            else panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn);
+            break;
         case 2:
-            if constexpr (sizeof(T) == 8) panel_front<T, 26, 3, kPanelThreads>(fn, s, u, dyn);
-            else panel_front<T, 32, 3, kPanelThreads>(fn, s, u, dyn);
+            if constexpr (sizeof(T) == 8) {
+                if (rem <= kPanelThreads) panel_front<T, 26, 1, kPanelThreads>(fn, s, u, dyn);
+                else if (rem <= 2 * kPanelThreads) panel_front<T, 26, 2, kPanelThreads>(fn, s, u, dyn);
+                else panel_front<T, 26, 3, kPanelThreads>(fn, s, u, dyn);
+            } else {
+                if (rem <= kPanelThreads) panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn);
+                else if (rem <= 2 * kPanelThreads) panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn);
+                else panel_front<T, 32, 3, kPanelThreads>(fn, s, u, dyn);
+            }
             break;
         case 3:
             if constexpr (sizeof(T) == 8) panel_front<T, 20, 4, kPanelThreads>(fn, s, u, dyn);
-            else panel_front<T, 32, 4, kPanelThreads>(fn, s, u, dyn);
+            else {
+                if (rem <= kPanelThreads) panel_front<T, 32, 1, kPanelThreads>(fn, s, u, dyn);
+                else if (rem <= 2 * kPanelThreads) panel_front<T, 32, 2, kPanelThreads>(fn, s, u, dyn);
+                else if (rem <= 3 * kPanelThreads) panel_front<T, 32, 3, kPanelThreads>(fn, s, u, dyn);
+                else panel_front<T, 32, 4, kPanelThreads>(fn, s, u, dyn);
+            }
             break;
         default:
             if constexpr (sizeof(T) == 8) panel_front<T, 8, 8, kPanelThreads>(fn, s, u, dyn);
