@@ -355,7 +355,10 @@ struct PivCand {
 };
 template <int CTRL, int RM>
 __device__ __forceinline__ int dpp_i(int x) {
-    return __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xf, false);
+    // all rows enabled (quad permutations, row rotations): every lane has a valid
+    // source, so no old value needs to be kept and the move needs no copy first
+    if constexpr (RM == 0xF) return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+    else return __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xf, false);
 }
 template <int CTRL, int RM>
 __device__ __forceinline__ double dpp_d(double x) {
