@@ -73,6 +73,7 @@ struct Fail {
     } while (0)
 
 constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kSweepStaticLds = 36 * 1024;  // static LDS of the sweep kernels, with margin
 
 template <typename V>
 void upload(V** dst, const std::vector<V>& src) {
@@ -935,8 +936,13 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
     int mm = 1;
     for (int p = 0; p < 2; p++)
         for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
-    // vectors of the largest front per right-hand side, beside 2 KB of static LDS
-    const size_t budget = kMaxLds - 4096;
+    // vectors of the largest front per right-hand side in dynamic LDS, beside the
+    // sweep kernels' static LDS (the staged 64 x 64 diagonal block, at most 32 KB,
+    // and small buffers), within the device's limit per block
+    int lds_block = 0;
+    HIPX(hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, N->device));
+    if ((size_t)lds_block <= kSweepStaticLds) throw Fail{MF_ERR_DEVICE, "device LDS per block too small for the sweeps"};
+    const size_t budget = (size_t)lds_block - kSweepStaticLds;
     if ((size_t)mm * sizeof(double) > budget)
         throw Fail{MF_ERR_ARG, "front of order " + std::to_string(mm) + " exceeds the solve kernel's LDS budget"};
     for (int c0 = 0; c0 < nrhs;) {

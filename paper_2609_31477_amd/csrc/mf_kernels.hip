@@ -1307,6 +1307,35 @@ __device__ __forceinline__ double row_dot_tiled(gptr<const T> Fcol0, int64_t m, 
 
 // FUSE (one-wave blocks of small-front levels): the same block also forms
 // c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
+// Diagonal blocks of the sweeps staged through LDS (blocks of more than one
+// wave): while the block's threads form the dot products of one diagonal block,
+// waves 1.. load the next block into registers and store it to LDS after their
+// dot products, so the wave that solves the next block reads LDS instead of
+// waiting for global memory.  Column a, row r of the block at a * kBS + r, with
+// rows and columns clamped into the block exactly as the direct loads are.
+template <typename T, int TT>
+struct DiagStage {
+    static constexpr int kN = (kBS * kBS + TT - 64 - 1) / (TT - 64);  // entries per thread of waves 1..
+    T pre[kN];
+    __device__ __forceinline__ void load(const gptr<const T> F, int64_t m, int jb0, int jbs) {
+        const int t = (int)threadIdx.x - 64;
+#pragma unroll
+        for (int q = 0; q < kN; q++) {
+            const int e = min(t + q * (TT - 64), kBS * kBS - 1);
+            const int a = e / kBS, r = e % kBS;
+            pre[q] = F[(jb0 + min(r, jbs - 1)) + (int64_t)(jb0 + min(a, jbs - 1)) * m];
+        }
+    }
+    __device__ __forceinline__ void store(T* blk) const {
+        const int t = (int)threadIdx.x - 64;
+#pragma unroll
+        for (int q = 0; q < kN; q++) {
+            const int e = t + q * (TT - 64);
+            if (e < kBS * kBS) blk[e] = pre[q];
+        }
+    }
+};
+
 template <typename T, int TT, bool FUSE>
 __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
@@ -1322,6 +1351,15 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
     double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int cb = S.child_ptr[s], ce = S.child_ptr[s + 1];
+    constexpr bool kStage = TT > 64;
+    __shared__ T dblk[kStage ? kBS * kBS : 1];
+    if constexpr (kStage) {
+        if (wid > 0 && k > 0) {
+            DiagStage<T, TT> st0;
+            st0.load(F, m, 0, min(kBS, k));
+            st0.store(dblk);
+        }
+    }
     for (int i = tid; i < m; i += TT) {
         const int src = i < P ? rowperm[i] : i;
         for (int c = 0; c < nrc; c++)
@@ -1348,8 +1386,13 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             // in flight together instead of one branch (and wait) per column
             T raw[kBS];
             const int lr = j0 + min(lane, bs - 1);
+            if constexpr (kStage) {
 #pragma unroll
-            for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+                for (int a = 0; a < kBS; a++) raw[a] = dblk[a * kBS + lane];
+            } else {
+#pragma unroll
+                for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+            }
             if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
             double Lr[kBS];
 #pragma unroll
@@ -1365,9 +1408,20 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             }
         }
         __syncthreads();
-        for (int i = j0 + bs + tid; i < k; i += TT) {
-            const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-            for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
+        if constexpr (kStage) {
+            const bool nxt = wid > 0 && j0 + kBS < k;
+            DiagStage<T, TT> st1;
+            if (nxt) st1.load(F, m, j0 + kBS, min(kBS, k - j0 - kBS));
+            for (int i = j0 + bs + tid; i < k; i += TT) {
+                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
+            }
+            if (nxt) st1.store(dblk);
+        } else {
+            for (int i = j0 + bs + tid; i < k; i += TT) {
+                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
+            }
         }
         __syncthreads();
     }
@@ -1473,6 +1527,16 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
     const gptr<const int32_t> colvar = as_global(iv_colvar(d.iv, P, m));
     const double* v = vec + d.voff * nrhs;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr bool kStage = TT > 64;
+    __shared__ T dblk[kStage ? kBS * kBS : 1];
+    if constexpr (kStage) {
+        if (wid > 0 && k > 0) {
+            DiagStage<T, TT> st0;
+            const int jb0 = max(0, k - kBS);
+            st0.load(F, m, jb0, k - jb0);
+            st0.store(dblk);
+        }
+    }
     for (int i = tid; i < k; i += TT)
         for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
     if constexpr (FUSE) {
@@ -1495,8 +1559,13 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
         if (wid == 0) {
             T raw[kBS];  // clamped unconditional loads, as in the forward sweep
             const int lr = j0 + min(lane, bs - 1);
+            if constexpr (kStage) {
 #pragma unroll
-            for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+                for (int a = 0; a < kBS; a++) raw[a] = dblk[a * kBS + lane];
+            } else {
+#pragma unroll
+                for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+            }
             __builtin_amdgcn_sched_barrier(0);
             double Ur[kBS];
 #pragma unroll
@@ -1504,7 +1573,8 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
             // each lane's reciprocal of its own diagonal entry, taken in parallel
             // once per block: the sequential sweep then multiplies instead of
             // dividing (within 1.5 ulp of the quotient)
-            const double rd = 1.0 / (double)F[lr + (int64_t)lr * m];
+            const int ld = min(lane, bs - 1);
+            const double rd = 1.0 / (double)(kStage ? dblk[ld * kBS + ld] : F[lr + (int64_t)lr * m]);
             for (int c = 0; c < nrc; c++) {
                 double xl = lane < bs ? ts[j0 + lane + c * k] : 0.0;
 #pragma unroll
@@ -1520,9 +1590,20 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
             }
         }
         __syncthreads();
-        for (int i = tid; i < j0; i += TT) {
-            const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-            for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
+        if constexpr (kStage) {
+            const bool nxt = wid > 0 && j0 > 0;
+            DiagStage<T, TT> st1;
+            if (nxt) st1.load(F, m, max(0, j0 - kBS), j0 - max(0, j0 - kBS));
+            for (int i = tid; i < j0; i += TT) {
+                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
+            }
+            if (nxt) st1.store(dblk);
+        } else {
+            for (int i = tid; i < j0; i += TT) {
+                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
+            }
         }
         __syncthreads();
     }
