@@ -1305,8 +1305,6 @@ __device__ __forceinline__ double row_dot_tiled(gptr<const T> Fcol0, int64_t m, 
     return (p[0] + p[1]) + (p[2] + p[3]);
 }
 
-// FUSE (one-wave blocks of small-front levels): the same block also forms
-// c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
 // Diagonal blocks of the sweeps staged through LDS (blocks of more than one
 // wave): while the block's threads form the dot products of one diagonal block,
 // waves 1.. load the next block into registers and store it to LDS after their
@@ -1336,6 +1334,8 @@ struct DiagStage {
     }
 };
 
+// FUSE (one-wave blocks of small-front levels): the same block also forms
+// c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
 template <typename T, int TT, bool FUSE>
 __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
