@@ -785,7 +785,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(FrontNum* fn, int slot0
 // window, same arithmetic) on 256 threads with RS = 1 or 2 rows per thread.
 constexpr int kPanelSmallThreads = 256;
 template <typename T, int RS>
-__global__ __launch_bounds__(kPanelSmallThreads, (RS == 1 ? 5 : 1)) void k_panel_small(FrontNum* fn, int slot0, double u, int want_prec) {
+__global__ __launch_bounds__(kPanelSmallThreads, (RS == 1 ? (sizeof(T) == 8 ? 4 : 5) : 1)) void k_panel_small(FrontNum* fn, int slot0, double u, int want_prec) {
     extern __shared__ int dyn[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
