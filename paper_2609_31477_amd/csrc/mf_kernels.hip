@@ -943,7 +943,7 @@ struct Mfma<float> {
 // Block (x: column tile, y: row tile, z: front).  4 waves, each a 32x32 quarter
 // made of 2x2 MFMA 16x16 blocks; K staged through LDS in chunks of 32.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec,
+__global__ __launch_bounds__(kThreads, 4) void k_gemm(FrontNum* fn, int slot0, int mode, int want_prec,
                                                    const int32_t* tasks) {
     // A and B chunks, then (aliased) the C tile for the transposed epilogue
     __shared__ T smem_ab[2 * kKC * kLdsPad];
