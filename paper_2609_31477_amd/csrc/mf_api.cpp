@@ -198,6 +198,7 @@ struct mf_num {
     double* d_sb = nullptr;             // Dr b for the sweeps (n x nrhs)
     size_t sb_cap = 0;
     int32_t* d_tasks = nullptr;  // per-level tile work lists (LevelTasks)
+    std::vector<int32_t> kid_scratch;  // children per front of the level being set up
     int32_t* h_tasks = nullptr;  // pinned staging
     size_t tasks_cap = 0;        // entries
     std::vector<int32_t> task_scratch;
@@ -373,7 +374,18 @@ int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 ||
 // Tile work lists of one level (entries as in LevelTasks, appended to t), shared by
 // both precisions (each kernel skips fronts of the other one).  The result holds
 // the counts and the swap width; place_tasks points it at a device copy.
-LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t, int sw_force = 0) {
+// Children of each front of the level [s0, s1) (slot order).
+void level_kids(const Symbolic& S, int s0, int s1, std::vector<int32_t>& out) {
+    out.resize((size_t)std::max(s1 - s0, 0));
+    for (int sl = s0; sl < s1; sl++) {
+        const int f = S.level_fronts[sl];
+        out[sl - s0] = S.child_ptr[f + 1] - S.child_ptr[f];
+    }
+}
+
+// nkid (optional): children per front of the level, for the extend-add row chunks.
+LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t, int sw_force = 0,
+                             const int32_t* nkid = nullptr) {
     const size_t base = t.size();
     {
         size_t est = 0;
@@ -403,10 +415,18 @@ LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>
             for (int b = 0; b < T; b++) t.push_back(task_code(i, a, b));
     }
     const size_t ng1 = t.size() - base - nswap - ng0;
-    // extend-add: 16-column tiles, 4 (order <= 64) or 2 (<= 128) of them per block
+    // extend-add: 16-column tiles, 4 (order <= 64) or 2 (<= 128) of them per block;
+    // fronts with many children split their rows into chunks as well
     for (int i = 0; i < count; i++) {
         const int m = hf[i].m, lg = gather_lg(m), T = (m + kGatherTileCols - 1) / kGatherTileCols;
-        for (int a = 0; a < T; a += 1 << lg) t.push_back(gather_task(i, lg, a));
+        const bool split = nkid && nkid[i] > kGatherChunkKids && m > kGatherChunkRows;
+        const int nch = split ? (m + kGatherChunkRows - 1) / kGatherChunkRows : 0;
+        for (int a = 0; a < T; a += 1 << lg) {
+            if (split)
+                for (int c = 0; c < nch; c++) t.push_back(gather_task(i, lg, a, c));
+            else
+                t.push_back(gather_task(i, lg, a));
+        }
     }
     const size_t ngather = t.size() - base - nswap - ng0 - ng1;
     LevelTasks tk;
@@ -433,10 +453,11 @@ LevelTasks place_tasks(LevelTasks tk, const int32_t* d) {
 
 // Uploaded once per level by the synchronizing schedule: the previous level has
 // been synchronized, so the pinned staging can be reused.
-LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st, int sw_force = 0) {
+LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st, int sw_force = 0,
+                              const int32_t* nkid = nullptr) {
     std::vector<int32_t>& t = N->task_scratch;
     t.clear();
-    const LevelTasks tk = build_level_tasks(hf, count, t, sw_force);
+    const LevelTasks tk = build_level_tasks(hf, count, t, sw_force, nkid);
     if (t.size() > N->tasks_cap) {
         if (N->d_tasks) HIPX(hipFree(N->d_tasks));
         if (N->h_tasks) HIPX(hipHostFree(N->h_tasks));
@@ -531,7 +552,10 @@ void build_plan(mf_num* N) {
                 return;  // capacities beyond the kernels' limits: keep synchronizing per level
         toff[L] = tasks.size();
         const int shape = (o.tune && N->tuner.done()) ? N->tuner.pick[L] : -1;
-        pl.tasks[L] = build_level_tasks(tm.data() + s0, s1 - s0, tasks, shape < 0 ? 0 : ((shape & 2) ? 16 : 64));
+        std::vector<int32_t> kids;
+        level_kids(S, s0, s1, kids);
+        pl.tasks[L] = build_level_tasks(tm.data() + s0, s1 - s0, tasks, shape < 0 ? 0 : ((shape & 2) ? 16 : 64),
+                                        kids.data());
     }
     HIPX(hipMalloc((void**)&pl.d_tmpl, sizeof(FrontNum) * tm.size()));
     HIPX(hipMemcpy(pl.d_tmpl, tm.data(), sizeof(FrontNum) * tm.size(), hipMemcpyHostToDevice));
@@ -787,7 +811,9 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         }
         HIPX(hipMemcpyAsync(N->d_fn + s0, hf + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyHostToDevice, st));
         const int shape = tuning ? N->tuner.trials : (tuned ? N->tuner.pick[L] : -1);
-        const LevelTasks tk = upload_level_tasks(N, hf + s0, s1 - s0, st, shape < 0 ? 0 : ((shape & 2) ? 16 : 64));
+        level_kids(S, s0, s1, N->kid_scratch);
+        const LevelTasks tk = upload_level_tasks(N, hf + s0, s1 - s0, st, shape < 0 ? 0 : ((shape & 2) ? 16 : 64),
+                                                 N->kid_scratch.data());
         const bool full = shape >= 0 && (shape & 1);
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
         if (tuning) HIPX(hipEventRecord(N->tuner.e0, st));

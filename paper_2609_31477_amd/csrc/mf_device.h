@@ -69,12 +69,22 @@ struct LevelTasks {
 __host__ __device__ inline int32_t task_code(int rel, int a, int b) { return (rel << 12) | (a << 6) | b; }
 
 // Extend-add tasks: kGatherCols-column tiles (16), 1 << lg of them per block;
-// tile index below 512 (orders up to 8192), lg in {0, 1, 2}.
+// tile index below 512 (orders up to 8192), lg in {0, 1, 2}.  Fronts with many
+// children can also split their rows into chunks of kGatherChunkRows (one task
+// per tile and chunk), so that no single block walks all rows past every child.
+// Bits: tile 0-8, lg 9-10, chunked 11, chunk 12-15, front 16-31 (unsigned).
 constexpr int kGatherTileCols = 16;
+constexpr int kGatherChunkRows = 256;
+constexpr int kGatherChunkKids = 8;  // fronts with more children than this are split by rows
 __host__ __device__ inline int gather_lg(int m) { return m <= 64 ? 2 : (m <= 128 ? 1 : 0); }
-__host__ __device__ inline int32_t gather_task(int rel, int lg, int tile) { return (rel << 12) | (lg << 9) | tile; }
+__host__ __device__ inline int32_t gather_task(int rel, int lg, int tile, int chunk = -1) {
+    const uint32_t c = chunk < 0 ? 0u : ((1u | ((uint32_t)chunk << 1)) << 11);
+    return (int32_t)(((uint32_t)rel << 16) | c | ((uint32_t)lg << 9) | (uint32_t)tile);
+}
+__host__ __device__ inline int gather_task_rel(int32_t code) { return (int)((uint32_t)code >> 16); }
 __host__ __device__ inline int gather_task_lg(int32_t code) { return (code >> 9) & 3; }
 __host__ __device__ inline int gather_task_tile(int32_t code) { return code & 511; }
+__host__ __device__ inline int gather_task_chunk(int32_t code) { return ((code >> 11) & 1) ? ((code >> 12) & 15) : -1; }
 
 // Pattern data (slot-indexed), uploaded once per symbolic handle.
 struct DevSym {

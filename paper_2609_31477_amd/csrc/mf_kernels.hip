@@ -80,20 +80,23 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int slot0, int want_prec,
                                                      const int32_t* tasks) {
     const int32_t code = tasks[blockIdx.x];
-    const int s = slot0 + (code >> 12);
+    const int s = slot0 + gather_task_rel(code);
     const FrontNum d = fn[s];
     if (d.prec != want_prec) return;
     const int m = d.m;
     const int lg = gather_task_lg(code);
     const int jb = gather_task_tile(code) * kGatherCols;  // first column of the block
-    if (jb >= m) return;
+    const int ch = gather_task_chunk(code);
+    const int i_lo = ch < 0 ? 0 : ch * kGatherChunkRows;  // rows [i_lo, i_hi) of this block
+    const int i_hi = ch < 0 ? m : min(m, i_lo + kGatherChunkRows);
+    if (jb >= m || i_lo >= m) return;
     const int rstep = kThreads >> lg;                 // rows per pass of a group
     const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> (8 - lg));  // (uniform per wave)
     const int r = threadIdx.x & (rstep - 1);
     const int bc = kGatherCols << lg;                 // columns of the block
     const int j0 = jb + g * kGatherCols;              // first column of this group
     T* F = (T*)d.F;
-    if (jb == 0) {
+    if (jb == 0 && i_lo == 0) {
         int32_t* colperm = iv_colperm(d.iv, d.P, m);
         int32_t* rowperm = iv_rowperm(d.iv, d.P, m);
         for (int i = threadIdx.x; i < d.P; i += kThreads) {
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         // is skipped (wave-uniform test).
         if (nact > kFewKids) {
             constexpr int kCiBatch = 4;
-            for (int i = r; i < m; i += rstep) {
+            for (int i = i_lo + r; i < i_hi; i += rstep) {
                 double acc[kGatherCols];
 #pragma unroll
                 for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         // per child instead of one per value; the next child's row position is
         // looked up while these loads are in flight.  Misses add +0.0, which leaves
         // the sums exactly as skipping them would (they never hold -0.0).
-        for (int i = r; i < m; i += rstep) {
+        for (int i = i_lo + r; i < i_hi; i += rstep) {
             double acc[kGatherCols];
 #pragma unroll
             for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(DevSym S, FrontNum* fn, int
         return;
     }
     if (j0 >= m) return;
-    for (int i = r; i < m; i += rstep) {
+    for (int i = i_lo + r; i < i_hi; i += rstep) {
         double acc[kGatherCols];
 #pragma unroll
         for (int jj = 0; jj < kGatherCols; jj++) acc[jj] = 0.0;
