@@ -123,3 +123,32 @@ def test_newton_256x128_eight_rhs(torch_cuda):
         assert om <= 1e-12
         assert d <= 1e-12
     num.release()
+
+
+@pytest.mark.timeout(900)
+def test_newton_256x128_planned_bitwise(torch_cuda):
+    """The planned schedule with graph replay at full size, over four Newton
+    steps: fronts are stored at planned capacities above their orders, the front
+    with 57 children is gathered in row chunks, and capacity overflows repeat the
+    factorization level by level.  Every step's solution equals the
+    level-by-level one bitwise."""
+    torch = torch_cuda
+    g = json.load(open(GOLDEN))
+    s = build_2d(*g["mesh"], g["seed"])
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    num_l = num_p = None
+    for t in range(4):
+        v = torch.from_numpy(newton_values(s, t)).to(dev)
+        b = torch.from_numpy(newton_rhs(s, t)[0].copy()).to(dev)
+        num_l = S.factor(v, numeric=num_l, plan=0)
+        xl, _ = num_l.solve(b)
+        num_p = S.factor(v, numeric=num_p, plan=2)
+        xp, _ = num_p.solve(b)
+        torch.cuda.synchronize()
+        fi = num_p.info()
+        same = bool(torch.equal(xl, xp))
+        print(f"step {t}: planned={fi.planned} fallbacks={fi.plan_fallbacks} bitwise equal={same}", flush=True)
+        assert same
+    num_l.release()
+    num_p.release()
