@@ -201,7 +201,6 @@ struct mf_num {
     std::vector<int32_t> kid_scratch;  // children per front of the level being set up
     int32_t* h_tasks = nullptr;  // pinned staging
     size_t tasks_cap = 0;        // entries
-    std::vector<int32_t> task_scratch;
     mf_factor_info info{};
     // Planned schedule.  A factorization that synchronizes once per level learns
     // every front's delayed-in count; the plan gives each front a capacity (that
@@ -383,52 +382,30 @@ void level_kids(const Symbolic& S, int s0, int s1, std::vector<int32_t>& out) {
     }
 }
 
+// Tile work lists of one level, written to o (room for level_task_count
+// entries): swap tiles, eager GEMM tiles, Schur GEMM tiles, extend-add tasks.
 // nkid (optional): children per front of the level, for the extend-add row chunks.
-LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t, int sw_force = 0,
-                             const int32_t* nkid = nullptr) {
-    const size_t base = t.size();
-    {
-        size_t est = 0;
-        for (int i = 0; i < count; i++) {
-            const size_t T = (hf[i].m + 63) / 64;
-            est += 4 * T + 2 * T * T + (hf[i].m + kGatherTileCols - 1) / kGatherTileCols;
-        }
-        t.reserve(base + est);
-    }
+int swap_tile_cols(int count, int sw_force) {
     // few (large) fronts: narrow swap tiles so that more blocks share the latency-bound work
-    const int sw = sw_force ? sw_force : (count < 32 ? 16 : 64);
-    for (int i = 0; i < count; i++) {
-        const int T = (hf[i].m + sw - 1) / sw;
-        for (int a = 0; a < T; a++) t.push_back(task_code(i, a >> 6, a & 63));
-    }
-    const size_t nswap = t.size() - base;
+    return sw_force ? sw_force : (count < 32 ? 16 : 64);
+}
+bool gather_split(const FrontNum& f, const int32_t* nkid, int i) {
+    return nkid && nkid[i] > kGatherChunkKids && f.m > kGatherChunkRows;
+}
+LevelTasks level_task_count(const FrontNum* hf, int count, int sw_force, const int32_t* nkid) {
+    const int sw = swap_tile_cols(count, sw_force);
+    size_t nswap = 0, ng0 = 0, ng1 = 0, ngather = 0;
     for (int i = 0; i < count; i++) {
         const int m = hf[i].m, P = hf[i].P, T = (m + 63) / 64;
-        for (int a = 0; a < T; a++)
-            for (int b = 0; b < T; b++)
-                if (!(a * 64 >= P && b * 64 >= P)) t.push_back(task_code(i, a, b));
+        nswap += (size_t)((m + sw - 1) / sw);
+        const int tcb = std::max(0, T - (P + 63) / 64);  // tiles at or beyond P
+        ng0 += (size_t)T * T - (size_t)tcb * tcb;
+        const int T1 = (m - P + 63) / 64;
+        ng1 += (size_t)T1 * T1;
+        const int lg = gather_lg(m), TG = (m + kGatherTileCols - 1) / kGatherTileCols;
+        const size_t nt = (size_t)((TG + (1 << lg) - 1) >> lg);
+        ngather += gather_split(hf[i], nkid, i) ? nt * (size_t)((m + kGatherChunkRows - 1) / kGatherChunkRows) : nt;
     }
-    const size_t ng0 = t.size() - base - nswap;
-    for (int i = 0; i < count; i++) {
-        const int T = (hf[i].m - hf[i].P + 63) / 64;
-        for (int a = 0; a < T; a++)
-            for (int b = 0; b < T; b++) t.push_back(task_code(i, a, b));
-    }
-    const size_t ng1 = t.size() - base - nswap - ng0;
-    // extend-add: 16-column tiles, 4 (order <= 64) or 2 (<= 128) of them per block;
-    // fronts with many children split their rows into chunks as well
-    for (int i = 0; i < count; i++) {
-        const int m = hf[i].m, lg = gather_lg(m), T = (m + kGatherTileCols - 1) / kGatherTileCols;
-        const bool split = nkid && nkid[i] > kGatherChunkKids && m > kGatherChunkRows;
-        const int nch = split ? (m + kGatherChunkRows - 1) / kGatherChunkRows : 0;
-        for (int a = 0; a < T; a += 1 << lg) {
-            if (split)
-                for (int c = 0; c < nch; c++) t.push_back(gather_task(i, lg, a, c));
-            else
-                t.push_back(gather_task(i, lg, a));
-        }
-    }
-    const size_t ngather = t.size() - base - nswap - ng0 - ng1;
     LevelTasks tk;
     tk.swap = nullptr;
     tk.nswap = (int32_t)nswap;
@@ -439,6 +416,49 @@ LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>
     tk.ng1 = (int32_t)ng1;
     tk.gather = nullptr;
     tk.ngather = (int32_t)ngather;
+    return tk;
+}
+size_t level_task_total(const LevelTasks& tk) { return (size_t)tk.nswap + tk.ng0 + tk.ng1 + tk.ngather; }
+size_t fill_level_tasks(const FrontNum* hf, int count, const LevelTasks& tk, const int32_t* nkid, int32_t* o) {
+    int32_t* const o0 = o;
+    const int sw = tk.swap_cols;
+    for (int i = 0; i < count; i++) {
+        const int T = (hf[i].m + sw - 1) / sw;
+        for (int a = 0; a < T; a++) *o++ = task_code(i, a >> 6, a & 63);
+    }
+    for (int i = 0; i < count; i++) {
+        const int m = hf[i].m, P = hf[i].P, T = (m + 63) / 64;
+        for (int a = 0; a < T; a++)
+            for (int b = 0; b < T; b++)
+                if (!(a * 64 >= P && b * 64 >= P)) *o++ = task_code(i, a, b);
+    }
+    for (int i = 0; i < count; i++) {
+        const int T = (hf[i].m - hf[i].P + 63) / 64;
+        for (int a = 0; a < T; a++)
+            for (int b = 0; b < T; b++) *o++ = task_code(i, a, b);
+    }
+    // extend-add: 16-column tiles, 4 (order <= 64) or 2 (<= 128) of them per block;
+    // fronts with many children split their rows into chunks as well
+    for (int i = 0; i < count; i++) {
+        const int m = hf[i].m, lg = gather_lg(m), T = (m + kGatherTileCols - 1) / kGatherTileCols;
+        const int nch = gather_split(hf[i], nkid, i) ? (m + kGatherChunkRows - 1) / kGatherChunkRows : 0;
+        for (int a = 0; a < T; a += 1 << lg) {
+            if (nch)
+                for (int c = 0; c < nch; c++) *o++ = gather_task(i, lg, a, c);
+            else
+                *o++ = gather_task(i, lg, a);
+        }
+    }
+    return (size_t)(o - o0);
+}
+// Appended to t (the planned schedule collects every level's lists).
+LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t, int sw_force = 0,
+                             const int32_t* nkid = nullptr) {
+    const LevelTasks tk = level_task_count(hf, count, sw_force, nkid);
+    const size_t base = t.size();
+    t.resize(base + level_task_total(tk));
+    if (fill_level_tasks(hf, count, tk, nkid, t.data() + base) != level_task_total(tk))
+        throw Fail{MF_ERR_STATE, "internal: task list count mismatch"};
     return tk;
 }
 
@@ -455,22 +475,23 @@ LevelTasks place_tasks(LevelTasks tk, const int32_t* d) {
 // been synchronized, so the pinned staging can be reused.
 LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStream_t st, int sw_force = 0,
                               const int32_t* nkid = nullptr) {
-    std::vector<int32_t>& t = N->task_scratch;
-    t.clear();
-    const LevelTasks tk = build_level_tasks(hf, count, t, sw_force, nkid);
-    if (t.size() > N->tasks_cap) {
+    // written straight into the pinned staging buffer, then one copy
+    const LevelTasks tk = level_task_count(hf, count, sw_force, nkid);
+    const size_t total = level_task_total(tk);
+    if (total > N->tasks_cap) {
         if (N->d_tasks) HIPX(hipFree(N->d_tasks));
         if (N->h_tasks) HIPX(hipHostFree(N->h_tasks));
         N->d_tasks = nullptr;
         N->h_tasks = nullptr;
         N->tasks_cap = 0;
-        const size_t cap = t.size() + t.size() / 2 + 1024;
+        const size_t cap = total + total / 2 + 1024;
         HIPX(hipMalloc((void**)&N->d_tasks, sizeof(int32_t) * cap));
         HIPX(hipHostMalloc((void**)&N->h_tasks, sizeof(int32_t) * cap, hipHostMallocDefault));
         N->tasks_cap = cap;
     }
-    std::copy(t.begin(), t.end(), N->h_tasks);
-    if (!t.empty()) HIPX(hipMemcpyAsync(N->d_tasks, N->h_tasks, sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, st));
+    if (fill_level_tasks(hf, count, tk, nkid, N->h_tasks) != total)
+        throw Fail{MF_ERR_STATE, "internal: task list count mismatch"};
+    if (total) HIPX(hipMemcpyAsync(N->d_tasks, N->h_tasks, sizeof(int32_t) * total, hipMemcpyHostToDevice, st));
     return place_tasks(tk, N->d_tasks);
 }
 
