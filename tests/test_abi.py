@@ -99,3 +99,15 @@ def test_footprint_positive(config0):
     s = config0
     sy = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
     assert sy.footprint_bytes("fp64") > sy.footprint_bytes("fp32") > 0
+
+
+@pytest.mark.slow
+def test_symbolic_bit_exact_256x128():
+    """The benchmark's own pattern (256x128 cells, n = 540,606): the library's
+    analysis equals the oracle's bit for bit, at the size where it is timed."""
+    from vivjac import build_2d
+    s = build_2d(256, 128, 1)
+    v = mf.Symbolic(s.n, s.rowptr, s.colind, s.root).export()
+    S = osym.analyze(s.n, s.rowptr, s.colind, s.root)
+    assert v.nfronts == S.nfronts
+    assert_same(v, S)

@@ -162,3 +162,84 @@ def test_planted_mistake_is_caught(config0):
     bad = x.copy()
     bad[s.blocks["p"][0]] = 0.0
     assert check.omega(A, bad, s.b0[0]) > 1e-6
+
+
+# ---- pins of the backward-error measures themselves (hand-worked, not restated)
+#
+# A = [[2, -1], [1, 3]], x = [1, 2], b = [-1, 8]:
+#   A x = [0, 7], so r = b - A x = [-1, 1];
+#   |A||x| = [2*1 + 1*2, 1*1 + 3*2] = [4, 7], plus |b| = [1, 8] gives [5, 15];
+#   omega = max(|-1| / 5, |1| / 15) = 0.2   (the first row decides).
+#   ||r||_inf = 1, ||A||_inf = max(2 + 1, 1 + 3) = 4, ||x||_inf = 2, ||b||_inf = 8;
+#   eta = 1 / (4 * 2 + 8) = 1 / 16.
+# A dropped absolute value on A gives |A x| + |b| = [1, 15] and omega = 1; a
+# dropped |b| gives omega = 0.25; a signed residual gives max(-0.2, 1/15); a
+# column-sum norm of A (3 instead of 4) gives eta = 1/14.
+HAND_A = np.array([[2.0, -1.0], [1.0, 3.0]])
+HAND_X = np.array([1.0, 2.0])
+HAND_B = np.array([-1.0, 8.0])
+
+
+@pytest.mark.parametrize("fn", [check.omega, check.omega_fast])
+def test_omega_hand_worked(fn):
+    A = sp.csr_matrix(HAND_A)
+    assert fn(A, HAND_X, HAND_B) == 0.2
+
+
+def test_eta_hand_worked():
+    assert check.eta(sp.csr_matrix(HAND_A), HAND_X, HAND_B) == 1.0 / 16.0
+
+
+@pytest.mark.parametrize("fn", [check.omega, check.omega_fast])
+def test_omega_zero_over_zero_and_inf(fn):
+    # row 0 of A is empty and b_0 = 0: 0/0 counts as 0 (an exactly satisfied empty
+    # row); row 1: 3 * 1 = 3 = b_1, exact.  With b_0 = 1 the empty row cannot be
+    # satisfied by any x: its denominator |A||x| + |b| is 1, residual 1, omega 1.
+    A = sp.csr_matrix(np.array([[0.0, 0.0], [0.0, 3.0]]))
+    x = np.array([5.0, 1.0])
+    assert fn(A, x, np.array([0.0, 3.0])) == 0.0
+    assert fn(A, x, np.array([1.0, 3.0])) == 1.0
+    # a zero denominator with a nonzero residual is not a backward-stable answer
+    A = sp.csr_matrix(np.array([[1.0, 0.0], [0.0, 3.0]]))
+    assert fn(A, np.array([0.0, 1.0]), np.array([0.0, 3.0])) == 0.0
+
+
+def _gamma(k):
+    # Higham's gamma_k = k u / (1 - k u), u the unit roundoff of binary64
+    u = np.finfo(np.float64).eps / 2
+    return k * u / (1 - k * u)
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(16, 8, 0), (32, 16, 3)])
+def test_omega_fast_within_summation_bound(nx, ny, seed):
+    """omega_fast sums each residual row in ordinary floating point; omega sums it
+    exactly.  Recursive summation of k terms errs by at most gamma_{k} times the
+    sum of the magnitudes (Higham, Accuracy and Stability, Sec. 3.1), and the
+    products by one rounding each, so |r_fast - r|_i <= gamma_{k+1} (|A||x| + |b|)_i
+    with k the row's entry count, hence |omega_fast - omega| <= gamma_{k+1}.
+    Checked on an accurate solution (omega near u) and a perturbed one (omega near
+    1e-9, where the two must agree to about 1e-6 relative)."""
+    s = build_2d(nx, ny, seed)
+    A = s.to_scipy()
+    S = sym.analyze(s.n, s.rowptr, s.colind, s.root)
+    x, _, _ = splu.SparseLU(s.n, s.rowptr, s.colind, s.values, S.perm).solve(s.b0[0])
+    k = int(np.diff(A.indptr).max()) + 1
+    bound = _gamma(k + 1)
+    rng = np.random.default_rng(11)
+    xp = x * (1 + 1e-9 * rng.standard_normal(s.n))
+    for xx in (x, xp):
+        w, wf = check.omega(A, xx, s.b0[0]), check.omega_fast(A, xx, s.b0[0])
+        assert abs(wf - w) <= bound, (w, wf, bound)
+    wp = check.omega(A, xp, s.b0[0])
+    assert wp > 1e-11
+    assert abs(check.omega_fast(A, xp, s.b0[0]) - wp) <= 1e-5 * wp
+
+
+def test_eta_scales_with_residual():
+    # eta is homogeneous of degree 1 in the residual at fixed x: doubling r by
+    # moving b away from A x doubles the numerator only (the denominator changes by
+    # |b|, worked out here): A = I, x = [1, 1]; b = [1 + t, 1] gives
+    # eta = t / (1 + 1 + t) for t >= 0.
+    A = sp.csr_matrix(np.eye(2))
+    for t in (0.5, 1.0, 3.0):
+        assert check.eta(A, np.ones(2), np.array([1.0 + t, 1.0])) == pytest.approx(t / (2.0 + t), rel=1e-15)

@@ -171,7 +171,18 @@ def test_config0_invariants(config0):
     assert S.perm[-2:].tolist() == s.root.tolist()
     assert S.front_parent[-1] == -1 and np.sum(S.front_parent == -1) == 1
     npiv = np.diff(S.front_ptr)
-    assert npiv.max() <= max(64, npiv[-1]) or True
+    # leaves are components of at most leaf_max vertices (this mesh has no
+    # component of eccentricity below 2 that would be a larger leaf), and the root
+    # front holds exactly the two position unknowns
+    has_kid = np.zeros(S.nfronts, dtype=bool)
+    has_kid[S.front_parent[S.front_parent >= 0]] = True
+    assert npiv[~has_kid].max() <= 64
+    assert npiv[-1] == 2
+    # every separator is a proper separator: smaller than the subtree it splits
+    sub = npiv.astype(np.int64).copy()
+    for f in range(S.nfronts - 1):
+        sub[S.front_parent[f]] += sub[f]
+    assert np.all(npiv[has_kid] < sub[has_kid])
     for f in range(S.nfronts - 1):
         p = S.front_parent[f]
         rows = S.front_rows(f)
