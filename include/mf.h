@@ -24,6 +24,18 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *   - Handles are not thread-safe: one call at a time per handle.
  *   - Values at the boundary are always FP64; reduced precision is internal.
+ *   - Device buffers are plain pointers: the library cannot check their sizes.
+ *     A buffer shorter than documented is read or written out of range, so the
+ *     caller (e.g. the Python binding) checks lengths before the call.
+ *
+ * Hard limits (MF_ERR_ARG when exceeded, before any kernel runs on the level):
+ *   - front order (nominal rows plus delayed-in columns) <= 4096: the tile work
+ *     lists hold 64-row tile indices in 6 bits;
+ *   - fully summed variables per front <= 8192 (the panel's row maps in 64 KB of
+ *     LDS);
+ *   - fronts per tree level <= 65535 (16 bits of the extend-add task code); a
+ *     batch of many systems adds their levels' front counts, so batches are
+ *     sized to stay below it (the serving loop splits cohorts for this).
  */
 #ifndef MF_H
 #define MF_H
@@ -97,6 +109,11 @@ typedef struct {
                               swap tile width (16 or 64 columns) on every tree level and
                               time each level; later ones use each level's fastest.  The
                               shapes never change a result.  0 = fixed heuristics; default 0 */
+    int32_t fallback;      /* 1 = when GMRES-IR on FP32/BF16 factors stops above target_omega,
+                              mf_solve factors the handle again in FP64 (from its own copy of
+                              the values) and solves with FP64 refinement; the handle then
+                              holds FP64 factors and mf_solve_info.fp64_fallback is 1.
+                              0 = return MF_ERR_NOT_CONVERGED.  Default 1 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */
@@ -131,6 +148,9 @@ mf_status mf_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
 
 /* Read-only view of the symbolic result; arrays are owned by the handle and
  * valid until it is released.  Fronts are numbered in completion (post)order.
+ * This is the analysis the paper computes once per mesh and reuses for every
+ * factorization of the run (Sec. 6, "Scaling"); exporting it lets an
+ * independent implementation of the same specification be compared bit for bit.
  *   perm[n]            new position -> original variable
  *   front_ptr[nf+1]    pivot ranges of each front in the new numbering
  *   front_parent[nf]   parent front, -1 for a root
@@ -203,19 +223,29 @@ typedef struct {
 mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);
 
 /*
- * Solve J X = B with the factors and refine in FP64 until the componentwise
- * backward error omega = max_i |B - J X|_i / (|J||X| + |B|)_i <= target_omega.
+ * Solve J X = B with the factors: the Newton correction of eq. NR_iteration
+ * (Sec. 3.4), which the paper obtains from a direct solver (Sec. 4.3).  The
+ * solution is refined in FP64 until the componentwise backward error
+ *     omega = max_i |B - J X|_i / (|J||X| + |B|)_i  <=  target_omega.
  *   b_dev, x_dev   device FP64, n x nrhs column-major with leading dimension ld >= n
- *                  (b_dev == x_dev is not allowed)
+ *                  (b_dev == x_dev is not allowed); read / written on `stream`
+ *   info           may be NULL
  * Refinement: classical (x += M^{-1} r) for FP64 factors, GMRES-IR
- * (left-preconditioned GMRES on M^{-1} J d = M^{-1} r, FP64 vectors) for
- * reduced-precision factors.  MF_ERR_NOT_CONVERGED leaves the best x written.
+ * (left-preconditioned GMRES on M^{-1} J d = M^{-1} r, FP64 vectors, all
+ * right-hand sides in lockstep) for reduced-precision factors, with the FP64
+ * fallback of mf_options.fallback.  MF_ERR_NOT_CONVERGED leaves the best x
+ * written.  Errors: MF_ERR_STATE (no successful mf_factor), MF_ERR_ARG,
+ * MF_ERR_DEVICE, MF_ERR_OOM.
  */
 typedef struct {
     double omega;               /* max over right-hand sides of the final omega */
     double omega0;              /* omega of the unrefined solution */
     int32_t outer_iters;        /* refinement steps (max over right-hand sides) */
     int32_t inner_iters;        /* total GMRES iterations */
+    double eta;                 /* normwise backward error of the final x, max over right-hand
+                                   sides: ||B - J X||_inf / (||J||_inf ||X||_inf + ||B||_inf) */
+    int64_t delayed_pivots;     /* delayed columns of the factorization the solve used */
+    int32_t fp64_fallback;      /* 1 if the solve refactored in FP64 (mf_options.fallback) */
 } mf_solve_info;
 
 mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld,
@@ -224,6 +254,8 @@ mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrh
 /*
  * Batches of independent systems (many uneven small Newton systems, or
  * concurrent requests of a serving loop) factor and solve in the same launches.
+ * Batching is this library's extension for many concurrent parametric solves;
+ * the paper factors one system at a time (its method per system is unchanged).
  *
  * mf_batch_analyze merges already-analyzed systems into one block-diagonal plan
  * (a symbolic handle of its own; the inputs may be released afterwards).  Each
@@ -241,15 +273,20 @@ mf_status mf_batch_analyze(int32_t count, const mf_sym_t* syms, mf_sym_t* out);
 mf_status mf_factor_batched(mf_sym_t batch, const double* const* values_dev, const mf_options* opt,
                             void* stream, mf_num_t* inout);
 
-/* Solve every system of a factored batch: b_dev[i], x_dev[i] are n_i x nrhs
- * column-major with leading dimension n_i.  info (may be NULL) receives one
- * mf_solve_info per system.  MF_ERR_NOT_CONVERGED if any system stopped above
- * the target (all x are written). */
-mf_status mf_solve_batched(mf_num_t num, const double* const* b_dev, double* const* x_dev, int32_t nrhs,
+/* Solve every system of a factored batch: b_dev[i], x_dev[i] are n_i x nrhs[i]
+ * column-major with leading dimension n_i (nrhs[i] >= 0; nrhs == NULL means one
+ * right-hand side each).  Systems with fewer right-hand sides than the batch's
+ * largest count are padded with zero columns internally (their solution is 0 and
+ * needs no refinement), so every system's columns are solved exactly as alone.
+ * info (may be NULL) receives one mf_solve_info per system.  MF_ERR_NOT_CONVERGED
+ * if any system stopped above the target (all x are written). */
+mf_status mf_solve_batched(mf_num_t num, const double* const* b_dev, double* const* x_dev, const int32_t* nrhs,
                            void* stream, mf_solve_info* info);
 
 /* Device bytes a factorization of this pattern needs at nominal front sizes,
- * times (1 + margin) for delayed-pivot growth (admission estimate). */
+ * times (1 + margin) for delayed-pivot growth: the admission estimate of the
+ * serving loop (a library extension; the paper's direct solver is instead given
+ * a fixed relative workspace increase, 200 % in its Appendix A job settings). */
 int64_t mf_footprint_bytes(mf_sym_t sym, const mf_options* opt, double margin);
 
 /* Introspection of one factored front (for tests and debugging): copies the

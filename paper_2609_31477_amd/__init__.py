@@ -36,7 +36,7 @@ class mf_options(ctypes.Structure):
                 ("target_omega", ctypes.c_double), ("max_outer", ctypes.c_int32), ("gmres_m", ctypes.c_int32),
                 ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("scale", ctypes.c_int32), ("plan", ctypes.c_int32),
-                ("tune", ctypes.c_int32)]
+                ("tune", ctypes.c_int32), ("fallback", ctypes.c_int32)]
 
 
 class mf_symbolic_view(ctypes.Structure):
@@ -61,7 +61,8 @@ class mf_factor_info(ctypes.Structure):
 
 class mf_solve_info(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("omega0", ctypes.c_double), ("outer_iters", ctypes.c_int32),
-                ("inner_iters", ctypes.c_int32)]
+                ("inner_iters", ctypes.c_int32), ("eta", ctypes.c_double), ("delayed_pivots", ctypes.c_int64),
+                ("fp64_fallback", ctypes.c_int32)]
 
 
 class MFError(RuntimeError):
@@ -102,7 +103,7 @@ def lib():
         L.mf_factor_batched.argtypes = [ctypes.c_void_p, P, ctypes.POINTER(mf_options), P,
                                         ctypes.POINTER(ctypes.c_void_p)]
         L.mf_factor_batched.restype = ctypes.c_int
-        L.mf_solve_batched.argtypes = [ctypes.c_void_p, P, P, ctypes.c_int32, P, ctypes.POINTER(mf_solve_info)]
+        L.mf_solve_batched.argtypes = [ctypes.c_void_p, P, P, P, P, ctypes.POINTER(mf_solve_info)]
         L.mf_solve_batched.restype = ctypes.c_int
         L.mf_debug_front.argtypes = [ctypes.c_void_p, ctypes.c_int32, P, P, P]
         L.mf_debug_front.restype = ctypes.c_int
@@ -127,6 +128,25 @@ def default_options(**kw) -> mf_options:
             v = PRECISIONS[v]
         setattr(o, k, v)
     return o
+
+
+def check_vectors(t, n, name, nrhs=None, require_cuda=True):
+    """Validate a right-hand-side or solution tensor before its pointer crosses the
+    ABI (the library cannot check device buffer sizes): float64, contiguous, on
+    the GPU, shaped (n,) or (nrhs, n).  Returns its number of columns."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if require_cuda and not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if t.dim() not in (1, 2) or t.shape[-1] != n:
+        raise ValueError(f"{name} must have shape ({n},) or (nrhs, {n}), got {tuple(t.shape)}")
+    cols = 1 if t.dim() == 1 else int(t.shape[0])
+    if nrhs is not None and cols != nrhs:
+        raise ValueError(f"{name} has {cols} columns, expected {nrhs}")
+    return cols
 
 
 def _stream_ptr(stream):
@@ -238,14 +258,16 @@ class Numeric:
         """b: float64 CUDA tensor (n,) or (nrhs, n) -- row r is right-hand side r
         (i.e. column-major n x nrhs with ld = n).  Returns (x, mf_solve_info)."""
         import torch
-        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()):
-            raise TypeError("b must be a contiguous float64 CUDA tensor")
         n = self.sym.n
-        if b.shape[-1] != n:
-            raise ValueError("b has the wrong length")
-        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        nrhs = check_vectors(b, n, "b")
         if x is None:
             x = torch.empty_like(b)
+        else:
+            check_vectors(x, n, "x", nrhs=nrhs)
+            if x.shape != b.shape:
+                raise ValueError("x must have the shape of b")
+            if x.numel() > 0 and x.data_ptr() == b.data_ptr():
+                raise ValueError("x and b must be distinct buffers")
         inf = mf_solve_info()
         st = lib().mf_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), nrhs, n,
                             _stream_ptr(stream), ctypes.byref(inf))
@@ -318,16 +340,30 @@ class Batch:
         return inf
 
     def solve(self, bs, xs=None, stream=None, check=True):
-        """bs: list of float64 CUDA tensors (n_i,) or (nrhs, n_i).  Returns (xs, [mf_solve_info])."""
+        """bs: list of float64 CUDA tensors, system i's shaped (n_i,) or (nrhs_i, n_i);
+        the systems may have different numbers of right-hand sides.  Returns
+        (xs, [mf_solve_info])."""
         import torch
+        if len(bs) != len(self.syms):
+            raise ValueError("one right-hand-side tensor per system")
+        nrhs = [check_vectors(b, n, f"bs[{i}]") for i, (b, n) in enumerate(zip(bs, self.ns))]
         if xs is None:
             xs = [torch.empty_like(b) for b in bs]
-        nrhs = 1 if bs[0].dim() == 1 else bs[0].shape[0]
+        else:
+            if len(xs) != len(bs):
+                raise ValueError("one solution tensor per system")
+            for i, (x, b, n, k) in enumerate(zip(xs, bs, self.ns, nrhs)):
+                check_vectors(x, n, f"xs[{i}]", nrhs=k)
+                if x.shape != b.shape:
+                    raise ValueError(f"xs[{i}] must have the shape of bs[{i}]")
+                if x.numel() > 0 and x.data_ptr() == b.data_ptr():
+                    raise ValueError(f"xs[{i}] and bs[{i}] must be distinct buffers")
         bp = (ctypes.c_void_p * len(bs))(*[b.data_ptr() for b in bs])
         xp = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        nr = (ctypes.c_int32 * len(bs))(*nrhs)
         infos = (mf_solve_info * len(bs))()
         st = lib().mf_solve_batched(self._num, ctypes.cast(bp, ctypes.c_void_p), ctypes.cast(xp, ctypes.c_void_p),
-                                    nrhs, _stream_ptr(stream), infos)
+                                    ctypes.cast(nr, ctypes.c_void_p), _stream_ptr(stream), infos)
         if check or st != MF_ERR_NOT_CONVERGED:
             _check(st)
         return xs, list(infos)

@@ -16,6 +16,7 @@
 
 #include "mf_device.h"
 #include "mf_internal.h"
+#include "mf_tasks.h"
 
 namespace mf {
 
@@ -33,7 +34,8 @@ template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
 int panel_nb(int prec, int mmax);
-hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, double* y, hipStream_t st);
+hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx, double* y,
+                       int64_t ldy, int ncol, hipStream_t st);
 hipError_t launch_mdot(const DevSym& S, const double* V, int64_t ldv, int nv, const double* w, double* part,
                        double* out, int ostride, hipStream_t st);
 hipError_t launch_vsub(const DevSym& S, double* w, const double* V, int64_t ldv, int nv, const double* h, int hstride,
@@ -44,6 +46,7 @@ hipError_t launch_scale(const DevSym& S, double* y, const double* x, const doubl
                         hipStream_t st);
 hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st);
+hipError_t launch_nonfinite(const double* v, int64_t nnz, unsigned long long* first, hipStream_t st);
 hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count,
                               int32_t* overflow, hipStream_t st);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
@@ -181,6 +184,13 @@ struct mf_num {
     int omega_cap = 0;
     size_t small_cap = 0;
     std::vector<mf_solve_info> seg_info;    // per system of the last solve
+    std::vector<int64_t> seg_delayed;       // per system: delayed columns of the last factorization
+    // Krylov vectors of several right-hand sides as one segmented vector (krylov_view)
+    int kv_nrhs = 0;
+    DevSym kv{};
+    std::vector<void*> kv_alloc;
+    unsigned long long* d_bad = nullptr;    // first CSR position of a non-finite value
+    unsigned long long* h_bad = nullptr;    // pinned mirror
     double* d_cat = nullptr;                // batched solve: concatenated b and x
     size_t cat_cap = 0;
     int32_t* d_ones = nullptr;              // nseg ones: every system active
@@ -269,6 +279,9 @@ struct mf_num {
         }
     } tuner;
     ~mf_num() {
+        for (void* p : kv_alloc) (void)hipFree(p);
+        if (d_bad) (void)hipFree(d_bad);
+        if (h_bad) (void)hipHostFree(h_bad);
         if (tuner.e0) (void)hipEventDestroy(tuner.e0);
         if (tuner.e1) (void)hipEventDestroy(tuner.e1);
         plan.free_device();
@@ -370,9 +383,6 @@ void ensure_device_symbolic(mf_sym* h) {
 
 int front_prec(const mf_options& o, bool is_root) { return (o.prec == MF_FP64 || is_root) ? 0 : 1; }
 
-// Tile work lists of one level (entries as in LevelTasks, appended to t), shared by
-// both precisions (each kernel skips fronts of the other one).  The result holds
-// the counts and the swap width; place_tasks points it at a device copy.
 // Children of each front of the level [s0, s1) (slot order).
 void level_kids(const Symbolic& S, int s0, int s1, std::vector<int32_t>& out) {
     out.resize((size_t)std::max(s1 - s0, 0));
@@ -382,82 +392,13 @@ void level_kids(const Symbolic& S, int s0, int s1, std::vector<int32_t>& out) {
     }
 }
 
-// Tile work lists of one level, written to o (room for level_task_count
-// entries): swap tiles, eager GEMM tiles, Schur GEMM tiles, extend-add tasks.
-// nkid (optional): children per front of the level, for the extend-add row chunks.
-int swap_tile_cols(int count, int sw_force) {
-    // few (large) fronts: narrow swap tiles so that more blocks share the latency-bound work
-    return sw_force ? sw_force : (count < 32 ? 16 : 64);
-}
-bool gather_split(const FrontNum& f, const int32_t* nkid, int i) {
-    return nkid && nkid[i] > kGatherChunkKids && f.m > kGatherChunkRows;
-}
-LevelTasks level_task_count(const FrontNum* hf, int count, int sw_force, const int32_t* nkid) {
-    const int sw = swap_tile_cols(count, sw_force);
-    size_t nswap = 0, ng0 = 0, ng1 = 0, ngather = 0;
-    for (int i = 0; i < count; i++) {
-        const int m = hf[i].m, P = hf[i].P, T = (m + 63) / 64;
-        nswap += (size_t)((m + sw - 1) / sw);
-        const int tcb = std::max(0, T - (P + 63) / 64);  // tiles at or beyond P
-        ng0 += (size_t)T * T - (size_t)tcb * tcb;
-        const int T1 = (m - P + 63) / 64;
-        ng1 += (size_t)T1 * T1;
-        const int lg = gather_lg(m), TG = (m + kGatherTileCols - 1) / kGatherTileCols;
-        const size_t nt = (size_t)((TG + (1 << lg) - 1) >> lg);
-        ngather += gather_split(hf[i], nkid, i) ? nt * (size_t)((m + kGatherChunkRows - 1) / kGatherChunkRows) : nt;
-    }
-    LevelTasks tk;
-    tk.swap = nullptr;
-    tk.nswap = (int32_t)nswap;
-    tk.swap_cols = sw;
-    tk.g0 = nullptr;
-    tk.ng0 = (int32_t)ng0;
-    tk.g1 = nullptr;
-    tk.ng1 = (int32_t)ng1;
-    tk.gather = nullptr;
-    tk.ngather = (int32_t)ngather;
-    return tk;
-}
-size_t level_task_total(const LevelTasks& tk) { return (size_t)tk.nswap + tk.ng0 + tk.ng1 + tk.ngather; }
-size_t fill_level_tasks(const FrontNum* hf, int count, const LevelTasks& tk, const int32_t* nkid, int32_t* o) {
-    int32_t* const o0 = o;
-    const int sw = tk.swap_cols;
-    for (int i = 0; i < count; i++) {
-        const int T = (hf[i].m + sw - 1) / sw;
-        for (int a = 0; a < T; a++) *o++ = task_code(i, a >> 6, a & 63);
-    }
-    for (int i = 0; i < count; i++) {
-        const int m = hf[i].m, P = hf[i].P, T = (m + 63) / 64;
-        for (int a = 0; a < T; a++)
-            for (int b = 0; b < T; b++)
-                if (!(a * 64 >= P && b * 64 >= P)) *o++ = task_code(i, a, b);
-    }
-    for (int i = 0; i < count; i++) {
-        const int T = (hf[i].m - hf[i].P + 63) / 64;
-        for (int a = 0; a < T; a++)
-            for (int b = 0; b < T; b++) *o++ = task_code(i, a, b);
-    }
-    // extend-add: 16-column tiles, 4 (order <= 64) or 2 (<= 128) of them per block;
-    // fronts with many children split their rows into chunks as well
-    for (int i = 0; i < count; i++) {
-        const int m = hf[i].m, lg = gather_lg(m), T = (m + kGatherTileCols - 1) / kGatherTileCols;
-        const int nch = gather_split(hf[i], nkid, i) ? (m + kGatherChunkRows - 1) / kGatherChunkRows : 0;
-        for (int a = 0; a < T; a += 1 << lg) {
-            if (nch)
-                for (int c = 0; c < nch; c++) *o++ = gather_task(i, lg, a, c);
-            else
-                *o++ = gather_task(i, lg, a);
-        }
-    }
-    return (size_t)(o - o0);
-}
 // Appended to t (the planned schedule collects every level's lists).
 LevelTasks build_level_tasks(const FrontNum* hf, int count, std::vector<int32_t>& t, int sw_force = 0,
                              const int32_t* nkid = nullptr) {
     const LevelTasks tk = level_task_count(hf, count, sw_force, nkid);
     const size_t base = t.size();
     t.resize(base + level_task_total(tk));
-    if (fill_level_tasks(hf, count, tk, nkid, t.data() + base) != level_task_total(tk))
+    if (fill_level_tasks(hf, count, tk, nkid, t.data() + base, level_task_total(tk)) != level_task_total(tk))
         throw Fail{MF_ERR_STATE, "internal: task list count mismatch"};
     return tk;
 }
@@ -489,7 +430,7 @@ LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStrea
         HIPX(hipHostMalloc((void**)&N->h_tasks, sizeof(int32_t) * cap, hipHostMallocDefault));
         N->tasks_cap = cap;
     }
-    if (fill_level_tasks(hf, count, tk, nkid, N->h_tasks) != total)
+    if (fill_level_tasks(hf, count, tk, nkid, N->h_tasks, N->tasks_cap) != total)
         throw Fail{MF_ERR_STATE, "internal: task list count mismatch"};
     if (total) HIPX(hipMemcpyAsync(N->d_tasks, N->h_tasks, sizeof(int32_t) * total, hipMemcpyHostToDevice, st));
     return place_tasks(tk, N->d_tasks);
@@ -569,7 +510,7 @@ void build_plan(mf_num* N) {
         }
         for (int p = 0; p < 2; p++)
             if (pl.lvl_cnt[p][L] &&
-                ((size_t)pl.lvl_Pmax[p][L] * 2 * sizeof(int) > kMaxLds || pl.lvl_mmax[p][L] > 4096))
+                ((size_t)pl.lvl_Pmax[p][L] * 2 * sizeof(int) > kMaxLds || pl.lvl_mmax[p][L] > kMaxFrontOrder))
                 return;  // capacities beyond the kernels' limits: keep synchronizing per level
         toff[L] = tasks.size();
         const int shape = (o.tune && N->tuner.done()) ? N->tuner.pick[L] : -1;
@@ -619,6 +560,30 @@ mf_factor_info finished_info(const mf_num* N) {
     }
     info.levels = S.nlevels;
     return info;
+}
+
+// Delayed columns per system of a batch (one entry for a single system), from the
+// finished factorization's bookkeeping (h_fn).
+void seg_delays(mf_num* N) {
+    const Symbolic& S = N->sym->S;
+    const int nseg = (int)S.seg_n.size();
+    N->seg_delayed.assign(nseg, 0);
+    for (int sl = 0; sl < S.nf; sl++) {
+        const int f = S.level_fronts[sl];
+        if (S.rows_ptr[f + 1] == S.rows_ptr[f]) continue;
+        const int64_t var = S.rows[S.rows_ptr[f]];
+        const int q = nseg == 1 ? 0
+                                : (int)(std::upper_bound(S.seg_row0.begin(), S.seg_row0.end(), var) -
+                                        S.seg_row0.begin()) - 1;
+        N->seg_delayed[q] += N->h_fn[sl].P - N->h_fn[sl].k;
+    }
+}
+
+// Values are scanned for NaN and Inf before any front is built; the position of
+// the first one is read back with the first synchronization of the factorization.
+void check_finite(const mf_num* N) {
+    if (*N->h_bad != ~0ull)
+        throw Fail{MF_ERR_ARG, "values_dev[" + std::to_string(*N->h_bad) + "] is NaN or Inf"};
 }
 
 // The planned schedule: every level enqueued at once, one synchronization at the
@@ -674,6 +639,7 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     HIPX(hipMemcpyAsync(N->h_fn, N->d_fn, sizeof(FrontNum) * S.nf, hipMemcpyDeviceToHost, st));
     HIPX(hipMemcpyAsync(pl.h_flag, pl.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
+    check_finite(N);
     if (*pl.h_flag) {
         N->plan_fallbacks++;
         return false;
@@ -687,6 +653,7 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     }
     N->vec_len = pl.vec_len;
     N->info = finished_info(N);
+    seg_delays(N);
     N->info.planned = o.plan == 2 ? 2 : 1;
     N->info.tuned = (o.tune && N->tuner.done()) ? 1 : 0;
     N->info.plan_fallbacks = N->plan_fallbacks;
@@ -706,15 +673,21 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         HIPX(hipHostMalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
     }
     if (!N->d_vals) HIPX(hipMalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
+    if (!N->d_bad) {
+        HIPX(hipMalloc((void**)&N->d_bad, sizeof(unsigned long long)));
+        HIPX(hipHostMalloc((void**)&N->h_bad, sizeof(unsigned long long), hipHostMallocDefault));
+    }
     if (seg_values) {
         for (size_t q = 0; q < S.seg_n.size(); q++) {
             const int64_t nz = (q + 1 < S.seg_n.size() ? S.seg_nnz0[q + 1] : S.nnz) - S.seg_nnz0[q];
             if (nz) HIPX(hipMemcpyAsync(N->d_vals + S.seg_nnz0[q], seg_values[q], sizeof(double) * nz,
                                         hipMemcpyDeviceToDevice, st));
         }
-    } else if (S.nnz) {
+    } else if (S.nnz && values_dev != N->d_vals) {
         HIPX(hipMemcpyAsync(N->d_vals, values_dev, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, st));
     }
+    HIPX(launch_nonfinite(N->d_vals, S.nnz, N->d_bad, st));
+    HIPX(hipMemcpyAsync(N->h_bad, N->d_bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     // equilibration (values only: the pattern and the analysis are unchanged)
     const double* fvals = N->d_vals;
     N->scaled = o.scale > 0 && S.n > 0;
@@ -818,11 +791,17 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         for (int p = 0; p < 2; p++) {
             if (!N->lvl_cnt[p][L]) continue;
             size_t lds = (size_t)N->lvl_Pmax[p][L] * 2 * sizeof(int);
-            if (lds > kMaxLds || N->lvl_mmax[p][L] > 4096)
+            if (N->lvl_mmax[p][L] > kMaxFrontOrder)
+                throw Fail{MF_ERR_ARG, "front of order " + std::to_string(N->lvl_mmax[p][L]) +
+                                           " (nominal plus delayed-in) exceeds the limit of " +
+                                           std::to_string(kMaxFrontOrder)};
+            if (lds > kMaxLds)
                 throw Fail{MF_ERR_ARG, "front with " + std::to_string(N->lvl_Pmax[p][L]) +
                                            " fully summed variables exceeds the panel kernel's LDS budget"};
         }
-        if (s1 - s0 > 65535) throw Fail{MF_ERR_ARG, "tree level with more than 65535 fronts"};
+        if (s1 - s0 > kMaxLevelFronts)
+            throw Fail{MF_ERR_ARG, "tree level with " + std::to_string(s1 - s0) + " fronts (limit " +
+                                       std::to_string(kMaxLevelFronts) + "; split the batch)"};
         // panel scratch (reused level by level): m x NB entries per front
         N->wsp.reset();
         for (int sl = s0; sl < s1; sl++) {
@@ -856,6 +835,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         if (tuning) HIPX(hipEventRecord(N->tuner.e1, st));
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));
+        if (L == 0) check_finite(N);
         if (tuning) HIPX(hipEventElapsedTime(&N->tuner.ms[L][N->tuner.trials], N->tuner.e0, N->tuner.e1));
         info.levels++;
         if (prof)
@@ -922,7 +902,12 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
                 if (N->tuner.ms[L][c] < N->tuner.ms[L][best]) best = c;
             N->tuner.pick[L] = (int8_t)best;
         }
+    if (S.nlevels == 0) {
+        HIPX(hipStreamSynchronize(st));
+        check_finite(N);
+    }
     N->info = info;
+    seg_delays(N);
     N->factored = true;
     if (o.plan != 0) build_plan(N);
 }
@@ -955,8 +940,8 @@ void ensure_solve_buffers(mf_num* N, int nrhs) {
         N->d_active = nullptr;
         N->h_active = nullptr;
         const int cnt = nrhs * nseg;
-        HIPX(hipMalloc((void**)&N->d_omega, sizeof(unsigned long long) * cnt));
-        HIPX(hipHostMalloc((void**)&N->h_omega, sizeof(unsigned long long) * cnt, hipHostMallocDefault));
+        HIPX(hipMalloc((void**)&N->d_omega, sizeof(unsigned long long) * kResQ * cnt));
+        HIPX(hipHostMalloc((void**)&N->h_omega, sizeof(unsigned long long) * kResQ * cnt, hipHostMallocDefault));
         HIPX(hipMalloc((void**)&N->d_active, sizeof(int32_t) * cnt));
         HIPX(hipHostMalloc((void**)&N->h_active, sizeof(int32_t) * cnt, hipHostMallocDefault));
         N->omega_cap = cnt;
@@ -1025,31 +1010,85 @@ double omega_of_bits(unsigned long long b) {
     return w;
 }
 
-// r = b - J x; om[seg * nrhs + c] = omega of system seg, right-hand side c.
+// r = b - J x; om[seg * nrhs + c] = omega of system seg, right-hand side c, and
+// (if eta is given) the normwise backward error
+// eta = ||r||_inf / (||J||_inf ||x||_inf + ||b||_inf) at the same positions.
 void residual(mf_num* N, const double* b, int64_t ldb, const double* x, int64_t ldx, double* r, int nrhs,
-              hipStream_t st, std::vector<double>& om) {
+              hipStream_t st, std::vector<double>& om, std::vector<double>* eta = nullptr) {
     const Symbolic& S = N->sym->S;
     const int nseg = (int)S.seg_n.size();
+    const int cnt = nrhs * nseg;
     HIPX(launch_residual(N->sym->dev->S, N->d_vals, S.n, x, ldx, b, ldb, r, S.n, nrhs, N->d_omega, st));
-    HIPX(hipMemcpyAsync(N->h_omega, N->d_omega, sizeof(unsigned long long) * nrhs * nseg, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(N->h_omega, N->d_omega, sizeof(unsigned long long) * (eta ? kResQ : 1) * cnt,
+                        hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
-    om.resize((size_t)nrhs * nseg);
-    for (int q = 0; q < nrhs * nseg; q++) om[q] = omega_of_bits(N->h_omega[q]);
+    om.resize((size_t)cnt);
+    for (int q = 0; q < cnt; q++) om[q] = omega_of_bits(N->h_omega[q]);
+    if (eta) {
+        eta->resize((size_t)cnt);
+        for (int q = 0; q < cnt; q++) {
+            const double rm = omega_of_bits(N->h_omega[cnt + q]), xm = omega_of_bits(N->h_omega[2 * cnt + q]);
+            const double bm = omega_of_bits(N->h_omega[3 * cnt + q]), jm = omega_of_bits(N->h_omega[4 * cnt + q]);
+            const double den = jm * xm + bm;
+            (*eta)[q] = den > 0.0 ? rm / den : (rm == 0.0 ? 0.0 : INFINITY);
+        }
+    }
 }
 
-void ensure_krylov(mf_num* N, int mres) {
+// Krylov vectors of nrhs columns: the n x nrhs block (leading dimension n) is
+// treated as one long vector whose segment v = c * nseg + s holds system s's rows
+// of column c.  Every (system, column) pair is then an independent GMRES
+// instance, and the segmented vector kernels run all of them in lockstep.
+const DevSym& krylov_view(mf_num* N, int nrhs) {
+    const DevSym& DS = N->sym->dev->S;
+    if (nrhs == 1) return DS;
+    if (N->kv_nrhs == nrhs) return N->kv;
+    for (void* p : N->kv_alloc) HIPX(hipFree(p));
+    N->kv_alloc.clear();
+    N->kv_nrhs = 0;
     const Symbolic& S = N->sym->S;
     const int64_t n = S.n;
     const int nseg = (int)S.seg_n.size();
+    std::vector<int64_t> r0((size_t)nseg * nrhs), nn((size_t)nseg * nrhs);
+    std::vector<int32_t> rs((size_t)n * nrhs);
+    for (int c = 0; c < nrhs; c++)
+        for (int s = 0; s < nseg; s++) {
+            const int v = c * nseg + s;
+            r0[v] = (int64_t)c * n + S.seg_row0[s];
+            nn[v] = S.seg_n[s];
+            std::fill(rs.begin() + r0[v], rs.begin() + r0[v] + nn[v], v);
+        }
+    int64_t* d_r0 = nullptr;
+    int64_t* d_nn = nullptr;
+    int32_t* d_rs = nullptr;
+    upload(&d_r0, r0);
+    N->kv_alloc.push_back(d_r0);
+    upload(&d_nn, nn);
+    N->kv_alloc.push_back(d_nn);
+    upload(&d_rs, rs);
+    N->kv_alloc.push_back(d_rs);
+    N->kv = DS;
+    N->kv.nseg = nseg * nrhs;
+    N->kv.seg_row0 = d_r0;
+    N->kv.seg_n = d_nn;
+    N->kv.row_seg = d_rs;
+    N->kv_nrhs = nrhs;
+    return N->kv;
+}
+
+void ensure_krylov(mf_num* N, int mres, int nrhs) {
+    const Symbolic& S = N->sym->S;
+    const int64_t len = S.n * nrhs;
+    const int nq = (int)S.seg_n.size() * nrhs;
     // V (mres + 1 vectors) | w | trial x | trial r | reduction scratch
-    size_t need = (size_t)n * (mres + 4) + (size_t)512 * nseg * (mres + 2);
+    size_t need = (size_t)len * (mres + 4) + (size_t)512 * nq * (mres + 2);
     if (need > N->kry_cap) {
         if (N->d_kry) HIPX(hipFree(N->d_kry));
         N->d_kry = nullptr;
         HIPX(hipMalloc((void**)&N->d_kry, sizeof(double) * need));
         N->kry_cap = need;
     }
-    size_t sneed = (size_t)2 * nseg * (mres + 2);
+    size_t sneed = (size_t)2 * nq * (mres + 2);
     if (sneed > N->small_cap) {
         if (N->d_small) HIPX(hipFree(N->d_small));
         if (N->h_small) HIPX(hipHostFree(N->h_small));
@@ -1059,25 +1098,24 @@ void ensure_krylov(mf_num* N, int mres) {
         HIPX(hipHostMalloc((void**)&N->h_small, sizeof(double) * sneed, hipHostMallocDefault));
         N->small_cap = sneed;
     }
-    if (!N->d_ones || N->ones_cap < nseg) {
+    if (!N->d_ones || N->ones_cap < nq) {
         if (N->d_ones) HIPX(hipFree(N->d_ones));
         N->d_ones = nullptr;
-        HIPX(hipMalloc((void**)&N->d_ones, sizeof(int32_t) * nseg));
-        std::vector<int32_t> ones(nseg, 1);
-        HIPX(hipMemcpy(N->d_ones, ones.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice));
-        N->ones_cap = nseg;
+        HIPX(hipMalloc((void**)&N->d_ones, sizeof(int32_t) * nq));
+        std::vector<int32_t> ones(nq, 1);
+        HIPX(hipMemcpy(N->d_ones, ones.data(), sizeof(int32_t) * nq, hipMemcpyHostToDevice));
+        N->ones_cap = nq;
     }
 }
 
-// Per-system dots of V[:, 0:nv] with w, returned on the host: out[seg * stride + i].
-void mdot_host(mf_num* N, const double* V, int nv, const double* w, double* part, int stride, std::vector<double>& out,
-               hipStream_t st) {
-    const Symbolic& S = N->sym->S;
-    const int nseg = (int)S.seg_n.size();
-    HIPX(launch_mdot(N->sym->dev->S, V, S.n, nv, w, part, N->d_small, stride, st));
-    HIPX(hipMemcpyAsync(N->h_small, N->d_small, sizeof(double) * nseg * stride, hipMemcpyDeviceToHost, st));
+// Per-segment dots of V[:, 0:nv] with w (segments of VS), returned on the host:
+// out[seg * stride + i].
+void mdot_host(mf_num* N, const DevSym& VS, const double* V, int64_t ldv, int nv, const double* w, double* part,
+               int stride, std::vector<double>& out, hipStream_t st) {
+    HIPX(launch_mdot(VS, V, ldv, nv, w, part, N->d_small, stride, st));
+    HIPX(hipMemcpyAsync(N->h_small, N->d_small, sizeof(double) * VS.nseg * stride, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
-    out.assign(N->h_small, N->h_small + (size_t)nseg * stride);
+    out.assign(N->h_small, N->h_small + (size_t)VS.nseg * stride);
 }
 
 // per-system coefficients to the device (second half of the small buffer)
@@ -1098,72 +1136,78 @@ void hessenberg_solve(const std::vector<double>& Hq, const std::vector<double>& 
     }
 }
 
-// GMRES(m) on M^{-1} J d = M^{-1} r, one instance per system of the batch, run in
-// lockstep on the concatenated vectors (column c of r and d).  Classical
-// Gram-Schmidt with one reorthogonalization, Givens rotations on the host.  A
-// system's numbers depend only on its own rows.  A system stops when its
-// preconditioned residual falls by tol, or, with target > 0, as soon as the
-// refined iterate x + d of the current Krylov space meets the componentwise
-// backward-error target (its true residual against b, one SpMV per iteration:
-// much cheaper than the sweep pair each further iteration or outer step costs).
-// Returns inner iterations per system.
-std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mres, double tol,
-                                  const std::vector<char>& act, hipStream_t st, const double* b = nullptr,
-                                  const double* x = nullptr, double target = 0.0) {
+// GMRES(m) on M^{-1} J d = M^{-1} r, one instance per (system, right-hand side)
+// of the batch, all run in lockstep on the concatenated n x nrhs vectors (ld n):
+// one multi-column sweep pair and one multi-column SpMV per inner step serve every
+// instance.  Classical Gram-Schmidt with one reorthogonalization, Givens
+// rotations on the host.  An instance's numbers depend only on its own rows and
+// column.  It stops when its preconditioned residual falls by tol, or, with
+// target > 0, as soon as the refined iterate x + d of the current Krylov space
+// meets the componentwise backward-error target (its true residual against b, one
+// SpMV per check: much cheaper than the sweep pair each further iteration or
+// outer step costs).  act and the result are in residual order (seg * nrhs + c);
+// returns the inner iterations per instance.
+std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int nrhs, int mres, double tol,
+                                  const std::vector<char>& act, hipStream_t st, const double* b, int64_t ldb,
+                                  const double* x, int64_t ldx, double target) {
     const Symbolic& S = N->sym->S;
     const int64_t n = S.n;
     const int nseg = (int)S.seg_n.size();
+    const int nq = nseg * nrhs;
+    const int64_t len = n * nrhs;
     const DevSym& DS = N->sym->dev->S;
+    const DevSym& VS = krylov_view(N, nrhs);
     const int stride = mres + 2;
     double* V = N->d_kry;
-    double* w = V + (size_t)n * (mres + 1);
-    double* xt = w + n;
-    double* rt = xt + n;
-    double* part = rt + n;
-    std::vector<int> iters(nseg, 0);
-    apply_inverse(N, r, n, w, n, 1, st);  // w = M^{-1} r
-    std::vector<double> dots, beta(nseg), coef((size_t)nseg * stride, 0.0);
-    mdot_host(N, w, 1, w, part, stride, dots, st);
-    std::vector<char> live(nseg, 0);
-    for (int q = 0; q < nseg; q++) {
+    double* w = V + (size_t)len * (mres + 1);
+    double* xt = w + len;
+    double* rt = xt + len;
+    double* part = rt + len;
+    auto ro = [&](int v) { return (v % nseg) * nrhs + v / nseg; };  // instance -> residual order
+    std::vector<int> iters(nq, 0);
+    apply_inverse(N, r, n, w, n, nrhs, st);  // w = M^{-1} r
+    std::vector<double> dots, beta(nq), coef((size_t)nq * stride, 0.0);
+    mdot_host(N, VS, w, len, 1, w, part, stride, dots, st);
+    std::vector<char> live(nq, 0);
+    for (int q = 0; q < nq; q++) {
         beta[q] = std::sqrt(dots[(size_t)q * stride]);
-        live[q] = act[q] && beta[q] > 0.0 && std::isfinite(beta[q]);
+        live[q] = act[ro(q)] && beta[q] > 0.0 && std::isfinite(beta[q]);
         coef[(size_t)q * stride] = live[q] ? 1.0 / beta[q] : 0.0;
     }
-    HIPX(launch_fill(d, 0.0, n, st));
-    HIPX(launch_scale(DS, V, w, put_small(N, coef, st), stride, n, st));
-    std::vector<std::vector<double>> H(nseg, std::vector<double>((size_t)(mres + 1) * mres, 0.0)), cs(nseg),
-        sn(nseg), g(nseg);
-    std::vector<int> jdone(nseg, 0);
-    for (int q = 0; q < nseg; q++) {
+    HIPX(launch_fill(d, 0.0, len, st));
+    HIPX(launch_scale(VS, V, w, put_small(N, coef, st), stride, len, st));
+    std::vector<std::vector<double>> H(nq, std::vector<double>((size_t)(mres + 1) * mres, 0.0)), cs(nq), sn(nq),
+        g(nq);
+    std::vector<int> jdone(nq, 0);
+    for (int q = 0; q < nq; q++) {
         cs[q].assign(mres, 0.0);
         sn[q].assign(mres, 0.0);
         g[q].assign(mres + 1, 0.0);
         g[q][0] = beta[q];
     }
     std::vector<char> running = live;
-    std::vector<double> h((size_t)nseg * stride), h2;
+    std::vector<double> h((size_t)nq * stride), h2;
     for (int j = 0; j < mres; j++) {
         bool any = false;
-        for (int q = 0; q < nseg; q++) any = any || running[q];
+        for (int q = 0; q < nq; q++) any = any || running[q];
         if (!any) break;
-        double* vj = V + (size_t)n * j;
-        double* vj1 = V + (size_t)n * (j + 1);
-        HIPX(launch_spmv(DS, N->d_vals, n, vj, vj1, st));  // vj1 = J vj (temporary)
-        apply_inverse(N, vj1, n, w, n, 1, st);              // w = M^{-1} J vj
-        mdot_host(N, V, j + 1, w, part, stride, h, st);
-        HIPX(launch_vsub(DS, w, V, n, j + 1, put_small(N, h, st), stride, n, st));
-        mdot_host(N, V, j + 1, w, part, stride, h2, st);  // reorthogonalize
-        HIPX(launch_vsub(DS, w, V, n, j + 1, put_small(N, h2, st), stride, n, st));
+        double* vj = V + (size_t)len * j;
+        double* vj1 = V + (size_t)len * (j + 1);
+        HIPX(launch_spmv(DS, N->d_vals, n, vj, n, vj1, n, nrhs, st));  // vj1 = J vj (temporary)
+        apply_inverse(N, vj1, n, w, n, nrhs, st);                       // w = M^{-1} J vj
+        mdot_host(N, VS, V, len, j + 1, w, part, stride, h, st);
+        HIPX(launch_vsub(VS, w, V, len, j + 1, put_small(N, h, st), stride, len, st));
+        mdot_host(N, VS, V, len, j + 1, w, part, stride, h2, st);  // reorthogonalize
+        HIPX(launch_vsub(VS, w, V, len, j + 1, put_small(N, h2, st), stride, len, st));
         for (size_t i = 0; i < h.size(); i++) h[i] += h2[i];
-        mdot_host(N, w, 1, w, part, stride, dots, st);
-        for (int q = 0; q < nseg; q++) {
+        mdot_host(N, VS, w, len, 1, w, part, stride, dots, st);
+        for (int q = 0; q < nq; q++) {
             const double hn = std::sqrt(dots[(size_t)q * stride]);
             h[(size_t)q * stride + j + 1] = hn;
             coef[(size_t)q * stride] = hn > 0.0 ? 1.0 / hn : 0.0;
         }
-        HIPX(launch_scale(DS, vj1, w, put_small(N, coef, st), stride, n, st));
-        for (int q = 0; q < nseg; q++) {
+        HIPX(launch_scale(VS, vj1, w, put_small(N, coef, st), stride, len, st));
+        for (int q = 0; q < nq; q++) {
             if (!running[q]) continue;
             double* hq = h.data() + (size_t)q * stride;
             const double hn = hq[j + 1];
@@ -1184,45 +1228,48 @@ std::vector<int> gmres_correction(mf_num* N, const double* r, double* d, int mre
             if (std::fabs(g[q][j + 1]) <= tol * beta[q] || !(hn > 0.0)) running[q] = 0;
         }
         if (target > 0.0 && b && x) {
-            // the check is worth its SpMV only once some system's preconditioned
+            // the check is worth its SpMV only once some instance's preconditioned
             // residual has fallen to within kCheckGate of the target (on these
             // Jacobians omega met the target only below that, and a check costs
             // about a sixth of the sweep pair that one more inner step costs)
             constexpr double kCheckGate = 1e4;
             bool anyr = false;
-            for (int q = 0; q < nseg; q++) anyr = anyr || (running[q] && std::fabs(g[q][j + 1]) <= kCheckGate * target * beta[q]);
+            for (int q = 0; q < nq; q++)
+                anyr = anyr || (running[q] && std::fabs(g[q][j + 1]) <= kCheckGate * target * beta[q]);
             if (anyr) {
-                // trial iterate x + V y of every system still running (the others add 0)
+                // trial iterate x + V y of every instance still running (the others add 0)
                 std::fill(coef.begin(), coef.end(), 0.0);
-                for (int q = 0; q < nseg; q++)
+                for (int q = 0; q < nq; q++)
                     if (running[q]) hessenberg_solve(H[q], g[q], j + 1, mres + 1, coef.data() + (size_t)q * stride);
-                HIPX(launch_fill(d, 0.0, n, st));
-                HIPX(launch_vadd(DS, d, V, n, j + 1, put_small(N, coef, st), stride, n, st));
-                HIPX(hipMemcpyAsync(xt, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-                HIPX(launch_axpy(DS, n, xt, n, d, n, N->d_ones, 1, st));
+                HIPX(launch_fill(d, 0.0, len, st));
+                HIPX(launch_vadd(VS, d, V, len, j + 1, put_small(N, coef, st), stride, len, st));
+                HIPX(hipMemcpy2DAsync(xt, sizeof(double) * n, x, sizeof(double) * ldx, sizeof(double) * n, nrhs,
+                                      hipMemcpyDeviceToDevice, st));
+                HIPX(launch_axpy(DS, n, xt, n, d, n, N->d_ones, nrhs, st));
                 std::vector<double> omt;
-                residual(N, b, n, xt, n, rt, 1, st, omt);
-                // each system acts on its own gate only, so that its iterations do
-                // not depend on the systems it is batched with
-                for (int q = 0; q < nseg; q++)
-                    if (running[q] && std::fabs(g[q][j + 1]) <= kCheckGate * target * beta[q] && omt[q] <= target)
+                residual(N, b, ldb, xt, n, rt, nrhs, st, omt);
+                // each instance acts on its own gate only, so that its iterations do
+                // not depend on the systems or columns it runs beside
+                for (int q = 0; q < nq; q++)
+                    if (running[q] && std::fabs(g[q][j + 1]) <= kCheckGate * target * beta[q] && omt[ro(q)] <= target)
                         running[q] = 0;
             }
         }
     }
-    // y = R^{-1} g per system, d = V y
+    // y = R^{-1} g per instance, d = V y
     std::fill(coef.begin(), coef.end(), 0.0);
     int jmax = 0;
-    for (int q = 0; q < nseg; q++) {
+    std::vector<int> out(nq, 0);
+    for (int q = 0; q < nq; q++) {
         if (!live[q]) continue;
         const int jq = jdone[q];
-        iters[q] = jq;
+        out[ro(q)] = jq;
         jmax = std::max(jmax, jq);
         hessenberg_solve(H[q], g[q], jq, mres + 1, coef.data() + (size_t)q * stride);
     }
-    HIPX(launch_fill(d, 0.0, n, st));  // (trial iterates left their d behind)
-    if (jmax > 0) HIPX(launch_vadd(DS, d, V, n, jmax, put_small(N, coef, st), stride, n, st));
-    return iters;
+    HIPX(launch_fill(d, 0.0, len, st));  // (trial iterates left their d behind)
+    if (jmax > 0) HIPX(launch_vadd(VS, d, V, len, jmax, put_small(N, coef, st), stride, len, st));
+    return out;
 }
 
 // Solve and refine.  b, x: n x nrhs (ld) over the whole (possibly batched) system.
@@ -1237,14 +1284,18 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
     double* r = N->d_work;
     double* dv = N->d_work + (size_t)n * nrhs;
     apply_inverse(N, b, ld, x, ld, nrhs, st);
-    std::vector<double> om;
-    residual(N, b, ld, x, ld, r, nrhs, st, om);
+    std::vector<double> om, et;
+    residual(N, b, ld, x, ld, r, nrhs, st, om, &et);
     N->seg_info.assign(nseg, mf_solve_info{});
-    for (int q = 0; q < nseg; q++)
+    for (int q = 0; q < nseg; q++) {
+        mf_solve_info& si = N->seg_info[q];
         for (int c = 0; c < nrhs; c++) {
-            N->seg_info[q].omega0 = std::max(N->seg_info[q].omega0, om[(size_t)q * nrhs + c]);
-            N->seg_info[q].omega = N->seg_info[q].omega0;
+            si.omega0 = std::max(si.omega0, om[(size_t)q * nrhs + c]);
+            si.eta = std::max(si.eta, et[(size_t)q * nrhs + c]);
         }
+        si.omega = si.omega0;
+        si.delayed_pivots = q < (int)N->seg_delayed.size() ? N->seg_delayed[q] : 0;
+    }
     std::vector<char> active((size_t)nseg * nrhs);
     int it = 0;
     while (o.refine > 0 && it < o.max_outer) {
@@ -1258,46 +1309,64 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
             apply_inverse(N, r, n, dv, n, nrhs, st);
         } else {
             const int mres = std::max(1, std::min(o.gmres_m, 200));
-            ensure_krylov(N, mres);
-            for (int c = 0; c < nrhs; c++) {
-                std::vector<char> act(nseg);
-                bool anyc = false;
-                for (int q = 0; q < nseg; q++) {
-                    act[q] = active[(size_t)q * nrhs + c];
-                    anyc = anyc || act[q];
-                }
-                if (!anyc) continue;
-                std::vector<int> its = gmres_correction(N, r + (size_t)c * n, dv + (size_t)c * n, mres, o.gmres_tol, act,
-                                                        st, b + (size_t)c * ld, x + (size_t)c * ld, o.target_omega);
-                for (int q = 0; q < nseg; q++) N->seg_info[q].inner_iters += its[q];
-            }
+            ensure_krylov(N, mres, nrhs);
+            const std::vector<int> its = gmres_correction(N, r, dv, nrhs, mres, o.gmres_tol, active, st, b, ld, x, ld,
+                                                          o.target_omega);
+            for (int q = 0; q < nseg; q++)
+                for (int c = 0; c < nrhs; c++) N->seg_info[q].inner_iters += its[(size_t)q * nrhs + c];
         }
         for (size_t q = 0; q < active.size(); q++) N->h_active[q] = active[q];
         HIPX(hipMemcpyAsync(N->d_active, N->h_active, sizeof(int32_t) * active.size(), hipMemcpyHostToDevice, st));
         HIPX(launch_axpy(N->sym->dev->S, n, x, ld, dv, n, N->d_active, nrhs, st));
-        residual(N, b, ld, x, ld, r, nrhs, st, om);
+        residual(N, b, ld, x, ld, r, nrhs, st, om, &et);
         it++;
         for (int q = 0; q < nseg; q++) {
             bool stepped = false;
-            double wq = 0.0;
+            double wq = 0.0, eq = 0.0;
             for (int c = 0; c < nrhs; c++) {
                 stepped = stepped || active[(size_t)q * nrhs + c];
                 wq = std::max(wq, om[(size_t)q * nrhs + c]);
+                eq = std::max(eq, et[(size_t)q * nrhs + c]);
             }
             if (stepped) N->seg_info[q].outer_iters++;
             N->seg_info[q].omega = wq;
+            N->seg_info[q].eta = eq;
         }
     }
     mf_solve_info inf{};
     for (int q = 0; q < nseg; q++) {
         inf.omega = std::max(inf.omega, N->seg_info[q].omega);
         inf.omega0 = std::max(inf.omega0, N->seg_info[q].omega0);
+        inf.eta = std::max(inf.eta, N->seg_info[q].eta);
         inf.outer_iters = std::max(inf.outer_iters, N->seg_info[q].outer_iters);
         inf.inner_iters += N->seg_info[q].inner_iters;
+        inf.delayed_pivots += N->seg_info[q].delayed_pivots;
     }
     if (info) *info = inf;
     if (!(inf.omega <= o.target_omega) && o.refine > 0)
         throw Fail{MF_ERR_NOT_CONVERGED, "refinement stopped at omega = " + std::to_string(inf.omega)};
+}
+
+// Solve with the fallback of the reduced-precision path: when GMRES-IR on FP32 or
+// BF16 factors stops above the target, the handle is factored again in FP64 (from
+// its own copy of the values) and the system solved with FP64 refinement.
+void solve_with_fallback(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipStream_t st,
+                         mf_solve_info* info) {
+    try {
+        do_solve(N, b, x, nrhs, ld, st, info);
+        return;
+    } catch (const Fail& f) {
+        if (f.st != MF_ERR_NOT_CONVERGED || !N->opt.fallback || N->opt.prec == MF_FP64) throw;
+    }
+    N->opt.prec = MF_FP64;
+    N->opt.refine = 1;
+    N->opt.plan = 0;
+    N->opt.tune = 0;
+    N->factored = false;
+    do_factor(N, N->d_vals, st);
+    do_solve(N, b, x, nrhs, ld, st, info);
+    for (auto& si : N->seg_info) si.fp64_fallback = 1;
+    if (info) info->fp64_fallback = 1;
 }
 
 }  // namespace
@@ -1319,6 +1388,7 @@ void mf_default_options(mf_options* o) {
     o->scale = 1;
     o->plan = 0;
     o->tune = 0;
+    o->fallback = 1;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -1395,6 +1465,7 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
         N->opt.scale = opt->scale;
         N->opt.plan = opt->plan;
         N->opt.tune = opt->tune;
+        N->opt.fallback = opt->fallback;
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");
@@ -1468,7 +1539,7 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
     if (ld < n) return fail(MF_ERR_ARG, "ld < n");
     if (!b_dev || !x_dev || b_dev == x_dev) return fail(MF_ERR_ARG, "b_dev and x_dev must be distinct device buffers");
     try {
-        do_solve(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
+        solve_with_fallback(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
     } catch (const Fail& f) {
         return fail(f.st, f.msg);
     } catch (const std::bad_alloc&) {
@@ -1477,20 +1548,29 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
     return MF_OK;
 }
 
-mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const* x_dev, int32_t nrhs, void* stream,
-                           mf_solve_info* info) {
+mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const* x_dev, const int32_t* nrhs,
+                           void* stream, mf_solve_info* info) {
     if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
     if (!N->factored) return fail(MF_ERR_STATE, "mf_solve_batched before a successful mf_factor_batched");
-    if (!b_dev || !x_dev || nrhs < 0) return fail(MF_ERR_ARG, "bad arguments");
+    if (!b_dev || !x_dev) return fail(MF_ERR_ARG, "bad arguments");
     const Symbolic& S = N->sym->S;
     const int nseg = (int)S.seg_n.size();
-    for (int q = 0; q < nseg; q++)
-        if (S.seg_n[q] > 0 && (!b_dev[q] || !x_dev[q] || b_dev[q] == x_dev[q]))
+    int nmax = 0;
+    bool ragged = false;
+    for (int q = 0; q < nseg; q++) {
+        const int nr = nrhs ? nrhs[q] : 1;
+        if (nr < 0) return fail(MF_ERR_ARG, "nrhs[" + std::to_string(q) + "] < 0");
+        ragged = ragged || (q > 0 && nr != (nrhs ? nrhs[0] : 1));
+        nmax = std::max(nmax, nr);
+        if (S.seg_n[q] > 0 && nr > 0 && (!b_dev[q] || !x_dev[q] || b_dev[q] == x_dev[q]))
             return fail(MF_ERR_ARG, "b_dev[i] and x_dev[i] must be distinct device buffers");
-    if (nrhs == 0 || S.n == 0) return MF_OK;
+    }
+    if (info)
+        for (int q = 0; q < nseg; q++) info[q] = mf_solve_info{};
+    if (nmax == 0 || S.n == 0) return MF_OK;
     hipStream_t st = (hipStream_t)stream;
     try {
-        const size_t need = (size_t)S.n * nrhs * 2;
+        const size_t need = (size_t)S.n * nmax * 2;
         if (need > N->cat_cap) {
             if (N->d_cat) HIPX(hipFree(N->d_cat));
             N->d_cat = nullptr;
@@ -1498,25 +1578,30 @@ mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const
             N->cat_cap = need;
         }
         double* B = N->d_cat;
-        double* X = N->d_cat + (size_t)S.n * nrhs;
+        double* X = N->d_cat + (size_t)S.n * nmax;
+        // systems with fewer right-hand sides get zero columns: their solution is
+        // exactly zero with omega 0, so they never refine
+        if (ragged) HIPX(launch_fill(B, 0.0, S.n * nmax, st));
         for (int q = 0; q < nseg; q++) {
-            if (!S.seg_n[q]) continue;
+            const int nr = nrhs ? nrhs[q] : 1;
+            if (!S.seg_n[q] || !nr) continue;
             HIPX(hipMemcpy2DAsync(B + S.seg_row0[q], sizeof(double) * S.n, b_dev[q], sizeof(double) * S.seg_n[q],
-                                  sizeof(double) * S.seg_n[q], nrhs, hipMemcpyDeviceToDevice, st));
+                                  sizeof(double) * S.seg_n[q], nr, hipMemcpyDeviceToDevice, st));
         }
         mf_status rc = MF_OK;
         std::string msg;
         try {
-            do_solve(N, B, X, nrhs, S.n, st, nullptr);
+            solve_with_fallback(N, B, X, nmax, S.n, st, nullptr);
         } catch (const Fail& f) {
             if (f.st != MF_ERR_NOT_CONVERGED) throw;
             rc = f.st;
             msg = f.msg;
         }
         for (int q = 0; q < nseg; q++) {
-            if (!S.seg_n[q]) continue;
+            const int nr = nrhs ? nrhs[q] : 1;
+            if (!S.seg_n[q] || !nr) continue;
             HIPX(hipMemcpy2DAsync(x_dev[q], sizeof(double) * S.seg_n[q], X + S.seg_row0[q], sizeof(double) * S.n,
-                                  sizeof(double) * S.seg_n[q], nrhs, hipMemcpyDeviceToDevice, st));
+                                  sizeof(double) * S.seg_n[q], nr, hipMemcpyDeviceToDevice, st));
         }
         if (info)
             for (int q = 0; q < nseg; q++) info[q] = N->seg_info[q];

@@ -9,6 +9,10 @@ namespace mf {
 
 // Panel width upper bound (options.panel_nb is clamped to it).
 constexpr int kNBMax = 32;
+// Largest front order: the tile work lists keep 64-row tile indices in 6 bits.
+constexpr int kMaxFrontOrder = 4096;
+// Most fronts in one tree level: the extend-add task code keeps the front in 16 bits.
+constexpr int kMaxLevelFronts = 65535;
 
 // Panel shape class of a front, from its order and precision: the window width
 // NB and rows per thread RS (of a 512-thread block) are per front (never per
@@ -85,6 +89,11 @@ __host__ __device__ inline int gather_task_rel(int32_t code) { return (int)((uin
 __host__ __device__ inline int gather_task_lg(int32_t code) { return (code >> 9) & 3; }
 __host__ __device__ inline int gather_task_tile(int32_t code) { return code & 511; }
 __host__ __device__ inline int gather_task_chunk(int32_t code) { return ((code >> 11) & 1) ? ((code >> 12) & 15) : -1; }
+
+// Quantities of one residual pass, per (system, right-hand side): the
+// componentwise backward error omega, then max |r_i|, max |x_i|, max |b_i| and
+// the largest row sum of |J| (the pieces of the normwise backward error eta).
+constexpr int kResQ = 5;
 
 // Pattern data (slot-indexed), uploaded once per symbolic handle.
 struct DevSym {

@@ -1618,45 +1618,55 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
 }
 
 // ------------------------------------------------------------------ residual
-// r = b - J x and omega = max_i |r_i| / (|J||x| + |b|)_i per right-hand side
-// (blockIdx.y) and per system of a batch, 16 lanes per row.  omega is kept as the
-// bit pattern of a non-negative double and combined with an unsigned atomic max
-// (exact and order-independent).
+// r = b - J x and, per right-hand side (blockIdx.y) and per system of a batch,
+// the componentwise backward error omega = max_i |r_i| / (|J||x| + |b|)_i
+// together with the four maxima of the normwise one (max |r_i|, max |x_i|,
+// max |b_i| and max_i sum_j |J_ij|), 16 lanes per row.  Each quantity is a
+// non-negative double kept as its bit pattern and combined with an unsigned
+// atomic max (exact and order-independent); quantity q of (system, rhs) s sits at
+// out[q * cnt + s].
 constexpr int kResRows = 256;  // rows per residual block (16 lanes per row, 16 rows per pass)
+
+__device__ __forceinline__ void res_flush(unsigned long long* out, int64_t cnt, int64_t s, const double* q) {
+#pragma unroll
+    for (int k = 0; k < kResQ; k++) atomicMax(out + k * cnt + s, (unsigned long long)__double_as_longlong(q[k]));
+}
 
 __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const int32_t* ci, const double* val,
                                                        int64_t n, const double* x, int64_t ldx, const double* b,
                                                        int64_t ldb, double* r, int64_t ldr,
-                                                       unsigned long long* omega_bits, const int32_t* row_seg,
+                                                       unsigned long long* out, int64_t cnt, const int32_t* row_seg,
                                                        int nrhs) {
-    // Each block covers kResRows consecutive rows and folds their omegas into one
-    // maximum before touching the shared result: one atomic per block instead of
+    // Each block covers kResRows consecutive rows and folds their maxima before
+    // touching the shared result: one atomic per quantity and block instead of
     // one per row group (same-address atomics serialize in L2).  In a batch, rows
     // of one system are contiguous, so only blocks that straddle two systems fall
     // back to per-thread maxima flushed at each system boundary.
-    __shared__ double wmax[kThreads / 64];
+    __shared__ double wmax[kResQ][kThreads / 64];
     const int c = blockIdx.y;
     const int sub = threadIdx.x & 15;
     const int64_t r0 = (int64_t)blockIdx.x * kResRows;
     const int64_t r1 = min(n, r0 + kResRows);
     const double* xc = x + (int64_t)c * ldx;
     const bool one_seg = !row_seg || row_seg[r0] == row_seg[r1 - 1];
-    double wm = 0.0;
+    double q[kResQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int seg = -1;
     for (int64_t row0 = r0; row0 < r1; row0 += kThreads / 16) {
         const int64_t row = row0 + threadIdx.x / 16;
-        double acc = 0.0, den = 0.0;
+        double acc = 0.0, den = 0.0, asum = 0.0;
         if (row < r1) {
             for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) {
                 const double a = val[t];
                 const double xv = xc[ci[t]];
                 acc = fma(a, xv, acc);
                 den = fma(fabs(a), fabs(xv), den);
+                asum += fabs(a);
             }
         }
         for (int off = 8; off > 0; off >>= 1) {
             acc += __shfl_xor(acc, off, 16);
             den += __shfl_xor(den, off, 16);
+            asum += __shfl_xor(asum, off, 16);
         }
         if (row < r1 && sub == 0) {
             const double bi = b[row + (int64_t)c * ldb];
@@ -1665,34 +1675,43 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
             const double dd = den + fabs(bi);
             double w = dd > 0.0 ? fabs(ri) / dd : (ri == 0.0 ? 0.0 : INFINITY);
             if (w != w) w = INFINITY;
-            if (one_seg) {
-                wm = fmax(wm, w);
-            } else {
+            double v[kResQ] = {w, fabs(ri), fabs(xc[row]), fabs(bi), asum};
+#pragma unroll
+            for (int k = 1; k < kResQ; k++)
+                if (v[k] != v[k]) v[k] = INFINITY;
+            if (!one_seg) {
                 const int sg = row_seg[row];
                 if (sg != seg) {
-                    if (seg >= 0)
-                        atomicMax(omega_bits + (int64_t)seg * nrhs + c, (unsigned long long)__double_as_longlong(wm));
+                    if (seg >= 0) res_flush(out, cnt, (int64_t)seg * nrhs + c, q);
                     seg = sg;
-                    wm = w;
-                } else {
-                    wm = fmax(wm, w);
+#pragma unroll
+                    for (int k = 0; k < kResQ; k++) q[k] = v[k];
+                    continue;
                 }
             }
+#pragma unroll
+            for (int k = 0; k < kResQ; k++) q[k] = fmax(q[k], v[k]);
         }
     }
     if (!one_seg) {
-        if (sub == 0 && seg >= 0)
-            atomicMax(omega_bits + (int64_t)seg * nrhs + c, (unsigned long long)__double_as_longlong(wm));
+        if (sub == 0 && seg >= 0) res_flush(out, cnt, (int64_t)seg * nrhs + c, q);
         return;
     }
-    for (int off = 32; off > 0; off >>= 1) wm = fmax(wm, __shfl_xor(wm, off));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = wm;
+#pragma unroll
+    for (int k = 0; k < kResQ; k++) {
+        for (int off = 32; off > 0; off >>= 1) q[k] = fmax(q[k], __shfl_xor(q[k], off));
+        if ((threadIdx.x & 63) == 0) wmax[k][threadIdx.x >> 6] = q[k];
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double mx = wmax[0];
-        for (int i = 1; i < kThreads / 64; i++) mx = fmax(mx, wmax[i]);
+        double mx[kResQ];
+#pragma unroll
+        for (int k = 0; k < kResQ; k++) {
+            mx[k] = wmax[k][0];
+            for (int i = 1; i < kThreads / 64; i++) mx[k] = fmax(mx[k], wmax[k][i]);
+        }
         const int sg = row_seg ? row_seg[r0] : 0;
-        atomicMax(omega_bits + (int64_t)sg * nrhs + c, (unsigned long long)__double_as_longlong(mx));
+        res_flush(out, cnt, (int64_t)sg * nrhs + c, mx);
     }
 }
 
@@ -1715,16 +1734,17 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, double* x, int64_t
 #define MF_CHECK_LAUNCH() (hipGetLastError())
 
 // ------------------------------------------------------------------ Krylov vectors (FP64)
-// y = J x (one vector), 16 lanes per row
+// y[:, c] = J x[:, c] (column c = blockIdx.y), 16 lanes per row
 __global__ __launch_bounds__(kThreads) void k_spmv(const int64_t* rp, const int32_t* ci, const double* val, int64_t n,
-                                                   const double* x, double* y) {
+                                                   const double* x, int64_t ldx, double* y, int64_t ldy) {
     const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 16;
     const int sub = threadIdx.x & 15;
+    const double* xc = x + (int64_t)blockIdx.y * ldx;
     double acc = 0.0;
     if (row < n)
-        for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) acc = fma(val[t], x[ci[t]], acc);
+        for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) acc = fma(val[t], xc[ci[t]], acc);
     for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-    if (row < n && sub == 0) y[row] = acc;
+    if (row < n && sub == 0) y[row + (int64_t)blockIdx.y * ldy] = acc;
 }
 
 // Deterministic segmented multi-dot, stage 1: block (b, s) reduces chunk b of
@@ -1794,10 +1814,11 @@ __global__ __launch_bounds__(kThreads) void k_fill(double* y, double v, int64_t 
 
 static unsigned vec_blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 2048); }
 
-hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, double* y, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n * 16 + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-                       S.csr_rowptr, S.csr_colind, val, n, x, y);
+hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx, double* y,
+                       int64_t ldy, int ncol, hipStream_t st) {
+    if (n <= 0 || ncol <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n * 16 + kThreads - 1) / kThreads), (unsigned)ncol), dim3(kThreads), 0,
+                       st, S.csr_rowptr, S.csr_colind, val, n, x, ldx, y, ldy);
     return MF_CHECK_LAUNCH();
 }
 // out[s * ostride + i] (device) = V_s[:, 0:nv]^T w_s per system; part: kDotBlocks * nseg * nv doubles
@@ -1837,6 +1858,18 @@ hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmp
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_level_setup, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, st, S, fn, tmpl,
                        slot0, count, overflow);
+    return MF_CHECK_LAUNCH();
+}
+// first[0] = smallest CSR position holding NaN or Inf (left at ~0 if none)
+__global__ __launch_bounds__(kThreads) void k_nonfinite(const double* v, int64_t nnz, unsigned long long* first) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kThreads)
+        if (!isfinite(v[i])) atomicMin(first, (unsigned long long)i);
+}
+hipError_t launch_nonfinite(const double* v, int64_t nnz, unsigned long long* first, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, first, 1, ~0ull);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min<int64_t>((nnz + kThreads - 1) / kThreads, 4096)),
+                           dim3(kThreads), 0, st, v, nnz, first);
     return MF_CHECK_LAUNCH();
 }
 hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st) {
@@ -2042,12 +2075,13 @@ hipError_t launch_diag_scale(int64_t n, const double* d, const double* x, int64_
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
                            unsigned long long* omega_bits, hipStream_t st) {
+    // omega_bits holds kResQ blocks of nrhs * nseg entries (see k_residual)
     const int nom = nrhs * S.nseg;
-    hipLaunchKernelGGL(k_fill_u64, dim3((nom + 63) / 64), dim3(64), 0, st, omega_bits, nom, 0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3((kResQ * nom + 63) / 64), dim3(64), 0, st, omega_bits, kResQ * nom, 0ull);
     if (n > 0) {
         const int64_t blocks = (n + kResRows - 1) / kResRows;
         hipLaunchKernelGGL(k_residual, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, st, S.csr_rowptr,
-                           S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits, S.row_seg, nrhs);
+                           S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits, (int64_t)nom, S.row_seg, nrhs);
     }
     return MF_CHECK_LAUNCH();
 }

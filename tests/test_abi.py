@@ -111,3 +111,19 @@ def test_symbolic_bit_exact_256x128():
     S = osym.analyze(s.n, s.rowptr, s.colind, s.root)
     assert v.nfronts == S.nfronts
     assert_same(v, S)
+
+
+def test_level_task_lists_count_equals_fill(tmp_path):
+    """The per-level tile work lists are counted exactly before they are written
+    into a fixed buffer (pinned host memory in the driver): a C++ check over random
+    levels that the count equals the fill and that a short buffer is detected
+    without a write past its end."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    exe = str(tmp_path / "test_tasks")
+    src = os.path.join(ROOT, "tests", "csrc", "test_tasks.cpp")
+    subprocess.check_call([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-std=c++17", src, "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.startswith("OK")

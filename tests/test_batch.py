@@ -69,3 +69,40 @@ def test_batch_equals_alone_bitwise(prec, target):
               f"max|batch-alone|={np.abs(xb - xa).max():.1e}", flush=True)
         assert np.array_equal(xb, xa), "batched result must equal the system solved alone"
         assert om <= target
+
+
+@pytest.mark.gpu
+def test_batch_ragged_right_hand_sides_equal_alone():
+    """Systems of one batch with different numbers of right-hand sides (1, 3, 0,
+    2): each system's columns equal the same system solved alone, bitwise, and the
+    system with none is left untouched."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda:0")
+    systems = batch_systems(4, seed0=140)
+    counts = [1, 3, 0, 2]
+    syms = [mf.Symbolic(s.n, s.rowptr, s.colind, s.root) for s in systems]
+    vals = [torch.from_numpy(s.values).to(dev) for s in systems]
+    rng = np.random.default_rng(9)
+    bs = [torch.from_numpy(rng.standard_normal((k, s.n)) if k != 1 else rng.standard_normal(s.n)).to(dev)
+          for s, k in zip(systems, counts)]
+    alone = []
+    for S, v, b, k in zip(syms, vals, bs, counts):
+        num = S.factor(v, prec="fp32", target_omega=1e-10)
+        alone.append(num.solve(b)[0].cpu().numpy() if k else None)
+    B = mf.Batch(syms)
+    B.factor(vals, prec="fp32", target_omega=1e-10)
+    sentinel = torch.full_like(bs[2], 7.0)
+    xs = [torch.empty_like(b) for b in bs]
+    xs[2] = sentinel
+    xs, infos = B.solve(bs, xs=xs)
+    torch.cuda.synchronize()
+    for i, (s, k) in enumerate(zip(systems, counts)):
+        print(f"system {i}: n={s.n} nrhs={k} omega={infos[i].omega:.1e} eta={infos[i].eta:.1e} "
+              f"inner={infos[i].inner_iters}", flush=True)
+        if k == 0:
+            assert xs[i].numel() == 0
+            continue
+        assert np.array_equal(xs[i].cpu().numpy(), alone[i])
+        assert infos[i].omega <= 1e-10

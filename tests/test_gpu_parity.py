@@ -142,18 +142,6 @@ def test_singular_reported(torch_cuda):
     assert e.value.status == mf.MF_ERR_SINGULAR
 
 
-def test_nan_values_reported(torch_cuda):
-    torch = torch_cuda
-    s = build_2d(16, 8, 0)
-    v = s.values.copy()
-    v[100] = np.nan
-    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
-    with pytest.raises(mf.MFError) as e:
-        num = S.factor(torch.from_numpy(v).cuda())
-        num.solve(torch.from_numpy(s.b0[0].copy()).cuda())
-    assert e.value.status in (mf.MF_ERR_SINGULAR, mf.MF_ERR_NOT_CONVERGED)
-
-
 def test_empty_system(torch_cuda):
     torch = torch_cuda
     S = mf.Symbolic(0, np.zeros(1, np.int64), np.zeros(0, np.int32), [])
@@ -239,3 +227,59 @@ def test_equilibration_parity(torch_cuda, scale):
           f"steps={info.outer_iters}", flush=True)
     assert_parity(s.to_scipy(), X, Xo, B)
     assert info.outer_iters <= 2
+
+
+def _gamma(k):
+    u = np.finfo(np.float64).eps / 2
+    return k * u / (1 - k * u)
+
+
+def test_solve_info_eta_and_delays(torch_cuda):
+    """The solve reports the normwise backward error eta of its final x (device
+    residual with ordinary summation) within the summation error bound of the
+    oracle's exact-residual eta, and the delayed-pivot count of its factors."""
+    s = build_2d(32, 16, 6)
+    X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, s.b0[0])
+    A = s.to_scipy()
+    e = check.eta(A, X, s.b0[0])
+    k = int(np.diff(A.indptr).max()) + 1
+    print(f"eta device {info.eta:.3e} oracle {e:.3e}; delayed {info.delayed_pivots}", flush=True)
+    assert abs(info.eta - e) <= _gamma(k + 1)
+    assert info.delayed_pivots == num.info().delayed_pivots
+
+
+def test_nonfinite_values_refused_up_front(torch_cuda):
+    torch = torch_cuda
+    s = build_2d(16, 8, 0)
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    for bad in (np.nan, np.inf):
+        v = s.values.copy()
+        v[100] = bad
+        with pytest.raises(mf.MFError) as e:
+            S.factor(torch.from_numpy(v).cuda())
+        assert e.value.status == mf.MF_ERR_ARG
+        assert "values_dev[100]" in str(e.value)
+
+
+def test_fp64_fallback_when_gmres_ir_stalls(torch_cuda):
+    """GMRES-IR on BF16 factors limited to one inner and one outer step cannot
+    reach 1e-12; with the fallback on, the handle is refactored in FP64 and the
+    solve meets the target (the FP64 bar against the oracle); with it off, the
+    solve reports MF_ERR_NOT_CONVERGED."""
+    torch = torch_cuda
+    s = build_2d(32, 16, 8)
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    v = torch.from_numpy(s.values).to(dev)
+    b = torch.from_numpy(s.b0[0].copy()).to(dev)
+    num = S.factor(v, prec="bf16", target_omega=1e-12, gmres_m=1, max_outer=1, fallback=0)
+    with pytest.raises(mf.MFError) as e:
+        num.solve(b)
+    assert e.value.status == mf.MF_ERR_NOT_CONVERGED
+    num = S.factor(v, prec="bf16", target_omega=1e-12, gmres_m=1, max_outer=1, fallback=1)
+    x, info = num.solve(b)
+    torch.cuda.synchronize()
+    print(f"fallback={info.fp64_fallback} omega={info.omega:.2e} outer={info.outer_iters}", flush=True)
+    assert info.fp64_fallback == 1
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, s.b0[0])
+    assert_parity(s.to_scipy(), x.cpu().numpy(), Xo, s.b0[0])
