@@ -114,6 +114,12 @@ typedef struct {
                               the values) and solves with FP64 refinement; the handle then
                               holds FP64 factors and mf_solve_info.fp64_fallback is 1.
                               0 = return MF_ERR_NOT_CONVERGED.  Default 1 */
+    int32_t sweep;         /* triangular sweeps of mf_solve: 1 = one persistent launch per direction
+                              over a device task list (fronts in dependency order, tickets
+                              from one counter, per-front ready counts with bounded waits;
+                              large fronts split into 64-row blocks run by many work-groups);
+                              0 = two launches per tree level and direction.  The two give
+                              different rounding; each is deterministic.  Default 1 */
 } mf_options;
 
 /* Fill *opt with the defaults above. */

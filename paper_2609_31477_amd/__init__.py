@@ -36,7 +36,7 @@ class mf_options(ctypes.Structure):
                 ("target_omega", ctypes.c_double), ("max_outer", ctypes.c_int32), ("gmres_m", ctypes.c_int32),
                 ("gmres_tol", ctypes.c_double), ("refine", ctypes.c_int32), ("panel_nb", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("scale", ctypes.c_int32), ("plan", ctypes.c_int32),
-                ("tune", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+                ("tune", ctypes.c_int32), ("fallback", ctypes.c_int32), ("sweep", ctypes.c_int32)]
 
 
 class mf_symbolic_view(ctypes.Structure):

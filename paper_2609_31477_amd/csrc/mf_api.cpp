@@ -29,10 +29,12 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
                                std::vector<hipEvent_t>* pev, bool panel_full = false);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
-                            int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
+                            int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
+                            const uint8_t* skip = nullptr);
 template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
-                            const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st);
+                            const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
+                            const uint8_t* skip = nullptr);
 int panel_nb(int prec, int mmax);
 hipError_t launch_spmv(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx, double* y,
                        int64_t ldy, int ncol, hipStream_t st);
@@ -51,7 +53,13 @@ hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmp
                               int32_t* overflow, hipStream_t st);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
-                           unsigned long long* omega_bits, hipStream_t st);
+                           unsigned long long* omega_bits, double* part, hipStream_t st);
+size_t residual_part_size(int64_t n, int nrhs);
+hipError_t launch_sweep_persist(bool forward, const DevSym& S, const FrontNum* fn, const int32_t* tasks,
+                                const int32_t* bptr, int nbund, const int32_t* ntask, const int32_t* need,
+                                int32_t* ctr,
+                                const double* b, int64_t ldb, double* x, int64_t ldx, double* vec, int nrhs, int c0,
+                                int nrc, int grid, int cap, hipStream_t st);
 hipError_t launch_axpy(const DevSym& S, int64_t n, double* x, int64_t ldx, const double* d, int64_t ldd,
                        const int32_t* active, int nrhs, hipStream_t st);
 hipError_t launch_ruiz(const DevSym& S, const double* val, int64_t n, int sweeps, double* dr, double* dc,
@@ -178,6 +186,8 @@ struct mf_num {
     double* d_small = nullptr;  // device coefficients (dots, combination weights)
     double* h_small = nullptr;  // pinned mirror
     unsigned long long* d_omega = nullptr;
+    double* d_respart = nullptr;            // residual per-block maxima
+    size_t respart_cap = 0;
     unsigned long long* h_omega = nullptr;  // pinned
     int32_t* d_active = nullptr;            // per (system, rhs): still refining
     int32_t* h_active = nullptr;            // pinned
@@ -189,6 +199,35 @@ struct mf_num {
     int kv_nrhs = 0;
     DevSym kv{};
     std::vector<void*> kv_alloc;
+    // Persistent sweeps: per direction (0 forward, 1 backward) the ticket-ordered
+    // task list of the current factors, built at the first solve after a factorization.
+    struct SweepPlan {
+        bool valid = false;
+        int32_t* d_buf = nullptr;  // tasks | bundle pointers | per-slot task counts, both directions
+        const int32_t* tasks[2] = {nullptr, nullptr};
+        const int32_t* bptr[2] = {nullptr, nullptr};
+        const int32_t* ntask[2] = {nullptr, nullptr};
+        const int32_t* need = nullptr;  // forward: children of each slot inside the lists
+        const uint8_t* d_listed = nullptr;  // per slot: run by the lists (skipped by the level launches)
+        std::vector<int32_t> level_rest;    // per level: fronts left to the level launches
+        bool any = false;                   // the lists are not empty
+        int32_t nbund[2] = {0, 0};
+        int64_t ntasks[2] = {0, 0};
+        size_t cap = 0;            // ints of d_buf
+        int32_t* d_ctr = nullptr;  // counters of both directions (2 + 3 nslots each)
+        int32_t* h_err = nullptr;  // pinned: the two error words
+        void free_device() {
+            if (d_buf) (void)hipFree(d_buf);
+            if (d_ctr) (void)hipFree(d_ctr);
+            if (h_err) (void)hipHostFree(h_err);
+            d_buf = nullptr;
+            d_ctr = nullptr;
+            h_err = nullptr;
+            cap = 0;
+            valid = false;
+        }
+    } sweep;
+    int sweep_grid = 0;
     unsigned long long* d_bad = nullptr;    // first CSR position of a non-finite value
     unsigned long long* h_bad = nullptr;    // pinned mirror
     double* d_cat = nullptr;                // batched solve: concatenated b and x
@@ -280,6 +319,7 @@ struct mf_num {
     } tuner;
     ~mf_num() {
         for (void* p : kv_alloc) (void)hipFree(p);
+        sweep.free_device();
         if (d_bad) (void)hipFree(d_bad);
         if (h_bad) (void)hipHostFree(h_bad);
         if (tuner.e0) (void)hipEventDestroy(tuner.e0);
@@ -297,6 +337,7 @@ struct mf_num {
         if (d_small) (void)hipFree(d_small);
         if (h_small) (void)hipHostFree(h_small);
         if (d_omega) (void)hipFree(d_omega);
+        if (d_respart) (void)hipFree(d_respart);
         if (h_omega) (void)hipHostFree(h_omega);
         if (d_active) (void)hipFree(d_active);
         if (d_cat) (void)hipFree(d_cat);
@@ -662,6 +703,7 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
 }
 
 void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double* const* seg_values = nullptr) {
+    N->sweep.valid = false;
     mf_sym* H = N->sym;
     const Symbolic& S = H->S;
     ensure_device_symbolic(H);
@@ -948,6 +990,122 @@ void ensure_solve_buffers(mf_num* N, int nrhs) {
     }
 }
 
+// Task lists of the persistent sweeps for the current factors (h_fn): the
+// forward list goes up the tree level by level, the backward list down; a front
+// of order <= kSwWhole is one task (runs of them share a ticket, kSwBundle at
+// most), a larger one is its fully summed 64-row blocks (forward: in order, then
+// its contribution tiles; backward: last block first).  A front with nothing to
+// eliminate still gets one task, which releases its dependants.
+void build_sweep_plan(mf_num* N) {
+    const Symbolic& S = N->sym->S;
+    const FrontNum* hf = N->h_fn;
+    const int ns = S.nf;
+    std::vector<int32_t> tk[2], bp[2], nt[2], hm(std::max(ns, 1)), hk(std::max(ns, 1));
+    for (int sl = 0; sl < ns; sl++) {
+        hm[sl] = hf[sl].m;
+        hk[sl] = hf[sl].k;
+    }
+    // Each system of a batch lists its own upper tree: the levels, from the top
+    // down, where it has at most kSwTopFronts fronts.  The choice depends only on
+    // the system, so its arithmetic is the same alone and in any batch.
+    const int nseg = (int)S.seg_n.size();
+    std::vector<int32_t> seg_of(std::max(ns, 1), 0);
+    for (int sl = 0; sl < ns; sl++) {
+        const int f = S.level_fronts[sl];
+        if (nseg > 1 && S.rows_ptr[f + 1] > S.rows_ptr[f]) {
+            const int64_t var = S.rows[S.rows_ptr[f]];
+            seg_of[sl] = (int)(std::upper_bound(S.seg_row0.begin(), S.seg_row0.end(), var) - S.seg_row0.begin()) - 1;
+        }
+    }
+    std::vector<int32_t> cnt((size_t)nseg * (S.nlevels + 1), 0), first(nseg, S.nlevels);
+    for (int L = 0; L < S.nlevels; L++)
+        for (int sl = S.level_ptr[L]; sl < S.level_ptr[L + 1]; sl++) cnt[(size_t)seg_of[sl] * (S.nlevels + 1) + L]++;
+    for (int q = 0; q < nseg; q++) {
+        const int32_t* c = cnt.data() + (size_t)q * (S.nlevels + 1);
+        int T = S.nlevels;
+        while (T > 0 && c[T - 1] <= kSwTopFronts) T--;
+        first[q] = T;
+    }
+    std::vector<uint8_t> listed(std::max(ns, 1), 0);
+    mf_num::SweepPlan& P0 = N->sweep;
+    P0.level_rest.assign(S.nlevels, 0);
+    P0.any = false;
+    for (int L = 0; L < S.nlevels; L++)
+        for (int sl = S.level_ptr[L]; sl < S.level_ptr[L + 1]; sl++) {
+            listed[sl] = L >= first[seg_of[sl]] ? 1 : 0;
+            if (listed[sl]) P0.any = true;
+            else P0.level_rest[L]++;
+        }
+    if (!sweep_lists(S.nlevels, S.level_ptr.data(), hm.data(), hk.data(), ns, tk, bp, nt, listed.data()))
+        throw Fail{MF_ERR_ARG, "front too large for the sweep task code"};
+    // forward: a listed front waits for its listed children only (the others
+    // finished in the level launches before the list)
+    std::vector<int32_t> need(std::max(ns, 1), 0);
+    for (int sl = 0; sl < ns; sl++) {
+        if (!listed[sl]) continue;
+        const int f = S.level_fronts[sl];
+        for (int q = S.child_ptr[f]; q < S.child_ptr[f + 1]; q++)
+            if (listed[N->sym->dev->slot_of[S.child_idx[q]]]) need[sl]++;
+    }
+    mf_num::SweepPlan& P = N->sweep;
+    size_t need_ints = 0;
+    for (int dir = 0; dir < 2; dir++) need_ints += tk[dir].size() + bp[dir].size() + nt[dir].size();
+    need_ints += need.size() + (listed.size() + 3) / 4;
+    if (need_ints > P.cap) {
+        if (P.d_buf) HIPX(hipFree(P.d_buf));
+        P.d_buf = nullptr;
+        P.cap = 0;
+        HIPX(hipMalloc((void**)&P.d_buf, sizeof(int32_t) * need_ints));
+        P.cap = need_ints;
+    }
+    if (!P.d_ctr) {
+        HIPX(hipMalloc((void**)&P.d_ctr, sizeof(int32_t) * 2 * (2 + 3 * (size_t)std::max(ns, 1))));
+        HIPX(hipHostMalloc((void**)&P.h_err, sizeof(int32_t) * 2, hipHostMallocDefault));
+        P.h_err[0] = P.h_err[1] = 0;
+    }
+    std::vector<int32_t> host;
+    host.reserve(need_ints);
+    size_t off[2][3];
+    for (int dir = 0; dir < 2; dir++) {
+        off[dir][0] = host.size();
+        host.insert(host.end(), tk[dir].begin(), tk[dir].end());
+        off[dir][1] = host.size();
+        host.insert(host.end(), bp[dir].begin(), bp[dir].end());
+        off[dir][2] = host.size();
+        host.insert(host.end(), nt[dir].begin(), nt[dir].end());
+        P.nbund[dir] = (int32_t)bp[dir].size() - 1;
+        P.ntasks[dir] = (int64_t)tk[dir].size() / 2;
+    }
+    const size_t need_off = host.size();
+    host.insert(host.end(), need.begin(), need.end());
+    const size_t listed_off = host.size();
+    host.resize(host.size() + (listed.size() + 3) / 4, 0);
+    std::memcpy(host.data() + listed_off, listed.data(), listed.size());
+    HIPX(hipMemcpy(P.d_buf, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice));
+    for (int dir = 0; dir < 2; dir++) {
+        P.tasks[dir] = P.d_buf + off[dir][0];
+        P.bptr[dir] = P.d_buf + off[dir][1];
+        P.ntask[dir] = P.d_buf + off[dir][2];
+    }
+    P.need = P.d_buf + need_off;
+    P.d_listed = (const uint8_t*)(P.d_buf + listed_off);
+    if (!N->sweep_grid) {
+        int cus = 0;
+        HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, N->device));
+        N->sweep_grid = std::max(1, cus) * 3;  // about 48 KB of LDS per work-group: 3 per CU
+    }
+    P.valid = true;
+}
+
+// A persistent sweep that ran into its wait limit (never expected: every wait is
+// for a task taken earlier by a running work-group) leaves wrong vectors.
+void check_sweep_errors(const mf_num* N) {
+    const mf_num::SweepPlan& P = N->sweep;
+    if (P.h_err && (P.h_err[0] || P.h_err[1]))
+        throw Fail{MF_ERR_DEVICE, "persistent sweep wait limit reached (forward " + std::to_string(P.h_err[0]) +
+                                      ", backward " + std::to_string(P.h_err[1]) + ")"};
+}
+
 // x = M^{-1} b with the multifrontal factors (forward then backward sweep).
 void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, hipStream_t st) {
     const Symbolic& S = N->sym->S;
@@ -965,6 +1123,24 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
         b = N->d_sb;
         ldb = S.n;
     }
+    // persistent sweeps for the upper tree (levels >= T), one launch per level and
+    // direction below it
+    bool hybrid = false;
+    if (N->opt.sweep == 1 && S.nlevels > 0) {
+        if (!N->sweep.valid) build_sweep_plan(N);
+        hybrid = N->sweep.any;
+    }
+    mf_num::SweepPlan& P = N->sweep;
+    const uint8_t* skip = hybrid ? P.d_listed : nullptr;
+    auto level_runs = [&](int L) { return !hybrid || P.level_rest[L] > 0; };
+    const size_t cstride = 2 + 3 * (size_t)std::max(S.nf, 1);
+    int32_t* cf = P.d_ctr;
+    int32_t* cb = P.d_ctr ? P.d_ctr + cstride : nullptr;
+    constexpr int kCap = 1 << 20;  // polls of one wait (a device-coherent load and a short sleep each): about a second
+    if (hybrid) {
+        HIPX(launch_fill_i32(cf + 1, 0, st));  // error words (the launches clear everything else)
+        HIPX(launch_fill_i32(cb + 1, 0, st));
+    }
     int mm = 1;
     for (int p = 0; p < 2; p++)
         for (int L = 0; L < S.nlevels; L++) mm = std::max(mm, N->lvl_mmax[p][L]);
@@ -981,25 +1157,38 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
         // right-hand-side chunk so that the largest front's vectors fit in LDS
         int nrc = (int)std::max<size_t>(1, budget / (sizeof(double) * (size_t)mm));
         nrc = std::min(nrc, nrhs - c0);
+        if (hybrid) nrc = std::min(nrc, kSwRhs);
         for (int L = 0; L < S.nlevels; L++) {
+            if (!level_runs(L)) continue;
             const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;
             if (N->lvl_cnt[0][L])
                 HIPX(launch_level_fwd<double>(DS, N->d_fn, s0, cnt, 0, b, ldb, N->d_vec, nrhs, c0, nrc,
-                                              N->lvl_mmax[0][L], st));
+                                              N->lvl_mmax[0][L], st, skip));
             if (N->lvl_cnt[1][L])
                 HIPX(launch_level_fwd<float>(DS, N->d_fn, s0, cnt, 1, b, ldb, N->d_vec, nrhs, c0, nrc,
-                                             N->lvl_mmax[1][L], st));
+                                             N->lvl_mmax[1][L], st, skip));
+        }
+        if (hybrid) {
+            HIPX(launch_sweep_persist(true, DS, N->d_fn, P.tasks[0], P.bptr[0], P.nbund[0], P.ntask[0], P.need, cf,
+                                      b, ldb, x, ldx, N->d_vec, nrhs, c0, nrc, N->sweep_grid, kCap, st));
+            HIPX(launch_sweep_persist(false, DS, N->d_fn, P.tasks[1], P.bptr[1], P.nbund[1], P.ntask[1], P.need, cb,
+                                      b, ldb, x, ldx, N->d_vec, nrhs, c0, nrc, N->sweep_grid, kCap, st));
         }
         for (int L = S.nlevels - 1; L >= 0; L--) {
+            if (!level_runs(L)) continue;
             const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;
             if (N->lvl_cnt[0][L])
                 HIPX(launch_level_bwd<double>(N->d_fn, s0, cnt, 0, x, ldx, N->d_vec, nrhs, c0, nrc,
-                                              N->lvl_mmax[0][L], st));
+                                              N->lvl_mmax[0][L], st, skip));
             if (N->lvl_cnt[1][L])
                 HIPX(launch_level_bwd<float>(N->d_fn, s0, cnt, 1, x, ldx, N->d_vec, nrhs, c0, nrc,
-                                             N->lvl_mmax[1][L], st));
+                                             N->lvl_mmax[1][L], st, skip));
         }
         c0 += nrc;
+    }
+    if (hybrid) {
+        HIPX(hipMemcpyAsync(P.h_err, cf + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPX(hipMemcpyAsync(P.h_err + 1, cb + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
     if (N->scaled) HIPX(launch_diag_scale(S.n, N->d_dc, x, ldx, x, ldx, nrhs, st));
 }
@@ -1018,10 +1207,18 @@ void residual(mf_num* N, const double* b, int64_t ldb, const double* x, int64_t 
     const Symbolic& S = N->sym->S;
     const int nseg = (int)S.seg_n.size();
     const int cnt = nrhs * nseg;
-    HIPX(launch_residual(N->sym->dev->S, N->d_vals, S.n, x, ldx, b, ldb, r, S.n, nrhs, N->d_omega, st));
+    const size_t pneed = residual_part_size(S.n, nrhs);
+    if (pneed > N->respart_cap) {
+        if (N->d_respart) HIPX(hipFree(N->d_respart));
+        N->d_respart = nullptr;
+        HIPX(hipMalloc((void**)&N->d_respart, sizeof(double) * pneed));
+        N->respart_cap = pneed;
+    }
+    HIPX(launch_residual(N->sym->dev->S, N->d_vals, S.n, x, ldx, b, ldb, r, S.n, nrhs, N->d_omega, N->d_respart, st));
     HIPX(hipMemcpyAsync(N->h_omega, N->d_omega, sizeof(unsigned long long) * (eta ? kResQ : 1) * cnt,
                         hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
+    check_sweep_errors(N);
     om.resize((size_t)cnt);
     for (int q = 0; q < cnt; q++) om[q] = omega_of_bits(N->h_omega[q]);
     if (eta) {
@@ -1115,6 +1312,7 @@ void mdot_host(mf_num* N, const DevSym& VS, const double* V, int64_t ldv, int nv
     HIPX(launch_mdot(VS, V, ldv, nv, w, part, N->d_small, stride, st));
     HIPX(hipMemcpyAsync(N->h_small, N->d_small, sizeof(double) * VS.nseg * stride, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
+    check_sweep_errors(N);
     out.assign(N->h_small, N->h_small + (size_t)VS.nseg * stride);
 }
 
@@ -1389,6 +1587,7 @@ void mf_default_options(mf_options* o) {
     o->plan = 0;
     o->tune = 0;
     o->fallback = 1;
+    o->sweep = 1;
 }
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -1466,11 +1665,13 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
         N->opt.plan = opt->plan;
         N->opt.tune = opt->tune;
         N->opt.fallback = opt->fallback;
+        N->opt.sweep = opt->sweep;
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");
     if (!(N->opt.pivot_u >= 0.0 && N->opt.pivot_u <= 1.0)) return fail(MF_ERR_ARG, "pivot_u must be in [0, 1]");
     if (N->opt.scale < 0 || N->opt.scale > 64) return fail(MF_ERR_ARG, "scale must be in [0, 64] sweeps");
+    if (N->opt.sweep < 0 || N->opt.sweep > 1) return fail(MF_ERR_ARG, "sweep must be 0 or 1");
     N->factored = false;
     try {
         HIPX(hipGetDevice(&N->device));

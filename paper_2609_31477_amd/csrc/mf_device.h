@@ -118,6 +118,20 @@ struct DevSym {
     const int64_t* seg_n;        // nseg: rows of each segment
 };
 
+// Persistent sweeps (k_fwd_persist / k_bwd_persist): one launch per direction
+// runs every front of every system from a ticket-ordered list of tasks.  Fronts
+// of order <= kSwWhole are one task; larger fronts split into 64-row blocks of
+// the fully summed part (forward and backward) and 64-row tiles of the
+// contribution rows (forward).  Task = (slot, kind << 8 | block).
+constexpr int kSwWhole = 256;
+constexpr int kSwRhs = 8;       // right-hand sides per sweep launch
+constexpr int kSwBundle = 8;    // consecutive whole-front tasks taken with one ticket
+constexpr int kSwTopFronts = 64;  // levels with at most this many fronts (and all above) run persistently
+enum SweepKind { kSwKindWhole = 0, kSwKindFs = 1, kSwKindCb = 2 };
+__host__ __device__ inline int32_t sweep_code(int kind, int blk) { return (kind << 8) | blk; }
+__host__ __device__ inline int sweep_kind(int32_t code) { return code >> 8; }
+__host__ __device__ inline int sweep_blk(int32_t code) { return code & 255; }
+
 __host__ __device__ inline int32_t* iv_rowpiv(int32_t* iv, int P, int m) { (void)m; return iv; }
 __host__ __device__ inline int32_t* iv_colperm(int32_t* iv, int P, int m) { (void)m; return iv + P; }
 __host__ __device__ inline int32_t* iv_rowperm(int32_t* iv, int P, int m) { (void)m; return iv + 2 * P; }

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "mf_device.h"
+#include "mf_kutil.h"
 
 namespace mf {
 
@@ -34,36 +35,6 @@ static_assert(kGatherCols == 16, "gather column decoding assumes 16-column tiles
 constexpr int kTile = 64;         // GEMM tile (rows and columns)
 constexpr int kKC = 32;           // GEMM K chunk staged through LDS
 constexpr int kLdsPad = kTile + 1;
-
-// Pointers read out of a FrontNum are generic to the compiler, so their accesses
-// become flat instructions, which count on the same wait counter as LDS: every
-// LDS access would then wait for all front loads in flight, and the loads would
-// wait for one another.  Front storage is device global memory; casting to the
-// global address space gives global loads and stores with their own in-order
-// counter.
-template <typename T>
-using gptr = __attribute__((address_space(1))) T*;
-template <typename T>
-__device__ __forceinline__ gptr<T> as_global(T* p) {
-    return (gptr<T>)p;
-}
-
-// Position of parent (pre-pivot) row i inside child c's contribution block, or -1.
-// dseg: start of c's segment inside the parent's delayed-in block; dout: c's
-// delayed-out count; im: c's inverse nominal map (indexed by parent nominal row).
-__device__ __forceinline__ int child_pos(int i, int npiv_p, int din_p, int dseg, int dout, const int32_t* im) {
-    if (i < npiv_p) {
-        int t = im[i];
-        return t >= 0 ? dout + t : -1;
-    }
-    int d = i - npiv_p;
-    if (d < din_p) {
-        d -= dseg;
-        return (d >= 0 && d < dout) ? d : -1;
-    }
-    int t = im[i - din_p];
-    return t >= 0 ? dout + t : -1;
-}
 
 __device__ __forceinline__ double load_front(const FrontNum& d, int64_t idx) {
     return d.prec ? (double)((const float*)d.F)[idx] : ((const double*)d.F)[idx];
@@ -367,11 +338,6 @@ template <int CTRL, int RM>
 __device__ __forceinline__ double dpp_d(double x) {
     const long long b = __double_as_longlong(x);
     const int lo = dpp_i<CTRL, RM>((int)b), hi = dpp_i<CTRL, RM>((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double readlane_d(double x, int l) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 // Two-phase wave reduction of a candidate (short dependency chains): first the
@@ -1342,11 +1308,11 @@ struct DiagStage {
 template <typename T, int TT, bool FUSE>
 __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
-                                                      int nrc) {
+                                                      int nrc, const uint8_t* skip) {
     extern __shared__ double zs[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || (skip && skip[s])) return;
     const int m = d.m, P = d.P, k = d.k;
     const gptr<const T> F = as_global((const T*)d.F);
     const gptr<const int32_t> rowperm = as_global(iv_rowperm(d.iv, P, m));
@@ -1467,12 +1433,12 @@ __device__ __forceinline__ double tile_dot(gptr<const T> Fcol0, int64_t m, const
 // c[i] = z[i] - sum_{j<k} L[i, j] y[j] for rows i in [k, m); block (x: 64-row tile, y: front)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int slot0, int want_prec, double* vec,
-                                                       int nrhs, int c0, int nrc) {
+                                                       int nrhs, int c0, int nrc, const uint8_t* skip) {
     extern __shared__ double ys[];
     __shared__ double part[kThreads];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || (skip && skip[s])) return;
     const int m = d.m, k = d.k;
     const int i0 = k + blockIdx.x * kGemvRows;
     if (i0 >= m || k == 0) return;
@@ -1491,12 +1457,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int s
 // t[i] = y[i] - sum_{j in [k,m)} U[i, j] x[colvar[j]] for rows i < k, in place in vec
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int slot0, int want_prec, const double* x,
-                                                       int64_t ldx, double* vec, int nrhs, int c0, int nrc) {
+                                                       int64_t ldx, double* vec, int nrhs, int c0, int nrc,
+                                                       const uint8_t* skip) {
     extern __shared__ double xs[];
     __shared__ double part[kThreads];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || (skip && skip[s])) return;
     const int m = d.m, P = d.P, k = d.k;
     const int i0 = blockIdx.x * kGemvRows;
     if (i0 >= k || k == m) return;
@@ -1520,11 +1487,12 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
 // t = y - U12 x[colvar[k:m]], which k_bwd_gemv does otherwise.
 template <typename T, int TT, bool FUSE>
 __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
-                                                      int64_t ldx, const double* vec, int nrhs, int c0, int nrc) {
+                                                      int64_t ldx, const double* vec, int nrhs, int c0, int nrc,
+                                                      const uint8_t* skip) {
     extern __shared__ double ts[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
-    if (d.prec != want_prec) return;
+    if (d.prec != want_prec || (skip && skip[s])) return;
     const int m = d.m, P = d.P, k = d.k;
     const gptr<const T> F = as_global((const T*)d.F);
     const gptr<const int32_t> colvar = as_global(iv_colvar(d.iv, P, m));
@@ -1636,12 +1604,13 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
                                                        int64_t n, const double* x, int64_t ldx, const double* b,
                                                        int64_t ldb, double* r, int64_t ldr,
                                                        unsigned long long* out, int64_t cnt, const int32_t* row_seg,
-                                                       int nrhs) {
-    // Each block covers kResRows consecutive rows and folds their maxima before
-    // touching the shared result: one atomic per quantity and block instead of
-    // one per row group (same-address atomics serialize in L2).  In a batch, rows
-    // of one system are contiguous, so only blocks that straddle two systems fall
-    // back to per-thread maxima flushed at each system boundary.
+                                                       int nrhs, double* part) {
+    // Each block covers kResRows consecutive rows and folds their maxima into
+    // part[(c * gridDim.x + block) * kResQ + q]; k_residual_fold then reduces the
+    // blocks of each system, so no two blocks update one address (same-address
+    // atomics serialize in L2).  In a batch, rows of one system are contiguous,
+    // so only blocks that straddle two systems post zeros there and fall back to
+    // per-thread maxima flushed with atomics at each system boundary.
     __shared__ double wmax[kResQ][kThreads / 64];
     const int c = blockIdx.y;
     const int sub = threadIdx.x & 15;
@@ -1693,8 +1662,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
             for (int k = 0; k < kResQ; k++) q[k] = fmax(q[k], v[k]);
         }
     }
+    double* pb = part + ((int64_t)c * gridDim.x + blockIdx.x) * kResQ;
     if (!one_seg) {
         if (sub == 0 && seg >= 0) res_flush(out, cnt, (int64_t)seg * nrhs + c, q);
+        if (threadIdx.x < kResQ) pb[threadIdx.x] = 0.0;
         return;
     }
 #pragma unroll
@@ -1703,15 +1674,40 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
         if ((threadIdx.x & 63) == 0) wmax[k][threadIdx.x >> 6] = q[k];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double mx[kResQ];
+    if (threadIdx.x < kResQ) {
+        double mx = wmax[threadIdx.x][0];
+        for (int i = 1; i < kThreads / 64; i++) mx = fmax(mx, wmax[threadIdx.x][i]);
+        pb[threadIdx.x] = mx;
+    }
+}
+
+// Second stage: block (s, c) folds the per-block maxima of system s's row blocks
+// for right-hand side c and posts them with one atomic max per quantity (blocks
+// that straddle two systems posted zeros and their own atomics).
+__global__ __launch_bounds__(kThreads) void k_residual_fold(const double* part, int nblk, const int64_t* seg_row0,
+                                                            const int64_t* seg_n, int nrhs,
+                                                            unsigned long long* out, int64_t cnt) {
+    __shared__ double red[kResQ][kThreads / 64];
+    const int s = blockIdx.x, c = blockIdx.y;
+    const int64_t ns = seg_n[s];
+    if (ns <= 0) return;
+    const int b0 = (int)(seg_row0[s] / kResRows), b1 = (int)((seg_row0[s] + ns - 1) / kResRows);
+    double q[kResQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = b0 + (int)threadIdx.x; b <= b1; b += kThreads) {
+        const double* pb = part + ((int64_t)c * nblk + b) * kResQ;
 #pragma unroll
-        for (int k = 0; k < kResQ; k++) {
-            mx[k] = wmax[k][0];
-            for (int i = 1; i < kThreads / 64; i++) mx[k] = fmax(mx[k], wmax[k][i]);
-        }
-        const int sg = row_seg ? row_seg[r0] : 0;
-        res_flush(out, cnt, (int64_t)sg * nrhs + c, mx);
+        for (int k = 0; k < kResQ; k++) q[k] = fmax(q[k], pb[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kResQ; k++) {
+        for (int off = 32; off > 0; off >>= 1) q[k] = fmax(q[k], __shfl_xor(q[k], off));
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = q[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kResQ) {
+        double mx = red[threadIdx.x][0];
+        for (int i = 1; i < kThreads / 64; i++) mx = fmax(mx, red[threadIdx.x][i]);
+        atomicMax(out + threadIdx.x * cnt + (int64_t)s * nrhs + c, (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -1951,44 +1947,47 @@ template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, in
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
-                            int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
+                            int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
+                            const uint8_t* skip) {
     if (count <= 0) return hipSuccess;
     // levels of small fronts: one wave per front (the diagonal sweep is one wave's work anyway)
     // (and the L21 product in the same one-wave block)
     if (mmax <= kTriSmallOrder) {
         hipLaunchKernelGGL((k_fwd_tri<T, 64, true>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st,
-                           S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+                           S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
         return MF_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads, false>), dim3(count), dim3(kTriThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc);
+                       sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
     hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc);
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc, skip);
     return MF_CHECK_LAUNCH();
 }
 template <typename T>
 hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx,
-                            const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st) {
+                            const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
+                            const uint8_t* skip) {
     if (count <= 0) return hipSuccess;
     if (mmax <= kTriSmallOrder) {  // U12 product and sweep in one one-wave block
         hipLaunchKernelGGL((k_bwd_tri<T, 64, true>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st,
-                           fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc);
+                           fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
         return MF_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc);
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc,
+                       skip);
     hipLaunchKernelGGL((k_bwd_tri<T, kTriThreads, false>), dim3(count), dim3(kTriThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc);
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
     return MF_CHECK_LAUNCH();
 }
 template hipError_t launch_level_fwd<double>(const DevSym&, const FrontNum*, int, int, int, const double*, int64_t,
-                                             double*, int, int, int, int, hipStream_t);
+                                             double*, int, int, int, int, hipStream_t, const uint8_t*);
 template hipError_t launch_level_fwd<float>(const DevSym&, const FrontNum*, int, int, int, const double*, int64_t,
-                                            double*, int, int, int, int, hipStream_t);
+                                            double*, int, int, int, int, hipStream_t, const uint8_t*);
 template hipError_t launch_level_bwd<double>(const FrontNum*, int, int, int, double*, int64_t, const double*, int,
-                                             int, int, int, hipStream_t);
+                                             int, int, int, hipStream_t, const uint8_t*);
 template hipError_t launch_level_bwd<float>(const FrontNum*, int, int, int, double*, int64_t, const double*, int,
-                                            int, int, int, hipStream_t);
+                                            int, int, int, hipStream_t, const uint8_t*);
 
 // ------------------------------------------------------------------ equilibration
 // One Ruiz sweep over the CSR values scaled by the current dr, dc: rmax[i] =
@@ -2072,16 +2071,23 @@ hipError_t launch_diag_scale(int64_t n, const double* d, const double* x, int64_
     return MF_CHECK_LAUNCH();
 }
 
+// doubles of residual scratch (per-block maxima) for n rows and nrhs columns
+size_t residual_part_size(int64_t n, int nrhs) {
+    return (size_t)std::max<int64_t>((n + kResRows - 1) / kResRows, 1) * nrhs * kResQ;
+}
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
-                           unsigned long long* omega_bits, hipStream_t st) {
+                           unsigned long long* omega_bits, double* part, hipStream_t st) {
     // omega_bits holds kResQ blocks of nrhs * nseg entries (see k_residual)
     const int nom = nrhs * S.nseg;
     hipLaunchKernelGGL(k_fill_u64, dim3((kResQ * nom + 63) / 64), dim3(64), 0, st, omega_bits, kResQ * nom, 0ull);
     if (n > 0) {
         const int64_t blocks = (n + kResRows - 1) / kResRows;
         hipLaunchKernelGGL(k_residual, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, st, S.csr_rowptr,
-                           S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits, (int64_t)nom, S.row_seg, nrhs);
+                           S.csr_colind, val, n, x, ldx, b, ldb, r, ldr, omega_bits, (int64_t)nom, S.row_seg, nrhs,
+                           part);
+        hipLaunchKernelGGL(k_residual_fold, dim3((unsigned)S.nseg, nrhs), dim3(kThreads), 0, st, part, (int)blocks,
+                           S.seg_row0, S.seg_n, nrhs, omega_bits, (int64_t)nom);
     }
     return MF_CHECK_LAUNCH();
 }

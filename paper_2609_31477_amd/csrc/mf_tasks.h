@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "mf_device.h"
 
@@ -92,6 +93,77 @@ inline size_t fill_level_tasks(const FrontNum* hf, int count, const LevelTasks& 
         }
     }
     return over ? SIZE_MAX : (size_t)(o - o0);
+}
+
+// First level of the persistent part of the sweeps: the lowest level from which
+// every level has at most max_fronts fronts (the upper tree, where few large
+// fronts leave most of the GPU idle in a launch per level); nlevels if none.
+inline int sweep_first_level(int nlevels, const int32_t* level_ptr, int max_fronts) {
+    int T = nlevels;
+    while (T > 0 && level_ptr[T] - level_ptr[T - 1] <= max_fronts) T--;
+    return T;
+}
+
+// Task lists of the persistent sweeps (direction 0 forward, 1 backward), from
+// the slots' actual orders m and eliminated counts k and the level ranges
+// level_ptr[0..nlevels].  Per direction: tk = (slot, code) pairs in ticket
+// order, bp = bundle pointers into the pairs, nt = tasks per slot.  The forward
+// list goes up the tree level by level, the backward list down; a front of
+// order <= kSwWhole is one task (runs of them share a bundle, kSwBundle at most),
+// a larger one is its fully summed 64-row blocks (forward: in order, then its
+// contribution tiles; backward: last block first).  A front with nothing to
+// eliminate still gets one task, which releases its dependants.  Returns false
+// if a front needs more than 255 blocks of either kind.
+// Only slots with listed[slot] != 0 are listed (nullptr: all); the others run
+// as one launch per level and direction, before the forward list and after the
+// backward list, so a listed front's unlisted children are finished before the
+// forward list starts and its unlisted descendants wait for the backward list.
+inline bool sweep_lists(int nlevels, const int32_t* level_ptr, const int32_t* m_of, const int32_t* k_of, int ns,
+                        std::vector<int32_t> tk[2], std::vector<int32_t> bp[2], std::vector<int32_t> nt[2],
+                        const uint8_t* listed = nullptr) {
+    for (int dir = 0; dir < 2; dir++) {
+        tk[dir].clear();
+        bp[dir].assign(1, 0);
+        nt[dir].assign(std::max(ns, 1), 0);
+        int open = 0;  // whole-front tasks in the open bundle
+        auto close = [&]() {
+            if (open) bp[dir].push_back((int32_t)(tk[dir].size() / 2));
+            open = 0;
+        };
+        auto single = [&](int sl, int kind, int blk) {
+            close();
+            tk[dir].push_back(sl);
+            tk[dir].push_back(sweep_code(kind, blk));
+            bp[dir].push_back((int32_t)(tk[dir].size() / 2));
+            nt[dir][sl]++;
+        };
+        for (int q = 0; q < nlevels; q++) {
+            const int L = dir == 0 ? q : nlevels - 1 - q;
+            for (int sl = level_ptr[L]; sl < level_ptr[L + 1]; sl++) {
+                if (listed && !listed[sl]) continue;
+                const int m = m_of[sl], k = k_of[sl];
+                if (m <= kSwWhole) {
+                    if (open == kSwBundle) close();
+                    tk[dir].push_back(sl);
+                    tk[dir].push_back(sweep_code(kSwKindWhole, 0));
+                    open++;
+                    nt[dir][sl]++;
+                    continue;
+                }
+                const int nfs = (k + 63) / 64, ncb = (m - k + 63) / 64;
+                if (nfs > 255 || ncb > 255) return false;
+                if (dir == 0) {
+                    for (int i = 0; i < nfs; i++) single(sl, kSwKindFs, i);
+                    for (int r = 0; r < ncb; r++) single(sl, kSwKindCb, r);
+                } else {
+                    for (int i = nfs - 1; i >= 0; i--) single(sl, kSwKindFs, i);
+                    if (nfs == 0) single(sl, kSwKindFs, 0);
+                }
+            }
+        }
+        close();
+    }
+    return true;
 }
 
 }  // namespace mf

@@ -127,3 +127,19 @@ def test_level_task_lists_count_equals_fill(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.startswith("OK")
+
+
+def test_sweep_work_list_protocol(tmp_path):
+    """The persistent sweeps' work-list protocol, emulated on the CPU over random
+    front forests and random interleavings of 1..64 work-groups: tickets,
+    per-front counts and waits as in the kernels; no deadlock, every task runs
+    once, and only after the tasks whose results it reads."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    exe = str(tmp_path / "test_sweep_protocol")
+    src = os.path.join(ROOT, "tests", "csrc", "test_sweep_protocol.cpp")
+    subprocess.check_call([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-std=c++17", src, "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.startswith("OK")

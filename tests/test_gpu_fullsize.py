@@ -24,9 +24,10 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "newton_256x128_seed1.json")
 BLOCKS = ("u", "p", "d", "lam", "s")
-# The mixed paths' target bounds the backward error (1e-10), not the forward
-# error of each block: their per-block errors are printed and held to 1e-6.
-MIXED_BLOCK_TOL = 1e-6
+# The mixed paths' target bounds the backward error (1e-10) rather than the
+# forward error of each block; observed per-block errors stay below 1e-10, and
+# they are held to the FP64 path's bar.
+MIXED_BLOCK_TOL = 1e-8
 
 
 def block_errors(g, idx, x_sampled, ref):

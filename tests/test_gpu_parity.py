@@ -283,3 +283,35 @@ def test_fp64_fallback_when_gmres_ir_stalls(torch_cuda):
     assert info.fp64_fallback == 1
     Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, s.b0[0])
     assert_parity(s.to_scipy(), x.cpu().numpy(), Xo, s.b0[0])
+
+
+@pytest.mark.parametrize("prec,nx,ny,seed,nrhs", [("fp64", 16, 8, 0, 1), ("fp64", 32, 16, 3, 3),
+                                                   ("fp32", 64, 32, 0, 2), ("fp64", 64, 32, 2, 9)])
+def test_persistent_sweeps_match_level_sweeps(torch_cuda, prec, nx, ny, seed, nrhs):
+    """The persistent sweeps (one launch per direction over the task list) and
+    the level-by-level sweeps apply the same factors: without refinement their
+    solutions agree to rounding (relative 1e-10), and each meets the FP64 bar
+    against the oracle after refinement (nine right-hand sides span two launch
+    chunks of eight)."""
+    torch = torch_cuda
+    s = build_2d(nx, ny, seed, nrhs=nrhs)
+    B = s.b0
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    v = torch.from_numpy(s.values).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    raw = {}
+    for sw in (0, 1):
+        num = S.factor(v, prec=prec, refine=0, sweep=sw)
+        x, _ = num.solve(b)
+        raw[sw] = x.cpu().numpy()
+    d = np.abs(raw[0] - raw[1]).max() / np.abs(raw[0]).max()
+    print(f"{prec} {nx}x{ny} nrhs={nrhs}: persistent vs level sweeps {d:.2e}", flush=True)
+    assert d <= 1e-10
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    target = 1e-12 if prec == "fp64" else 1e-10
+    for sw in (0, 1):
+        num = S.factor(v, prec=prec, sweep=sw, target_omega=target)
+        x, info = num.solve(b)
+        assert_parity(s.to_scipy(), x.cpu().numpy(), Xo, B, omega_tol=target,
+                      rel_tol=1e-8 if prec == "fp64" else 1e-6)
