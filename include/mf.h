@@ -258,6 +258,21 @@ mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrh
                    void* stream, mf_solve_info* info);
 
 /*
+ * mf_solve without any device or pinned-host allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, layout and result as mf_solve with the
+ * handle's refinement (refine 0 or 1 only: GMRES-IR's Krylov basis does not fit),
+ * level-by-level sweeps, and no FP64 fallback.  Its scratch (the front vector
+ * blocks, residual and correction vectors, residual maxima) comes from one
+ * statically sized device array per GPU, 64 MiB, held until the process ends;
+ * about 8 (sum of front orders + 3 n) bytes per right-hand side must fit, else
+ * MF_ERR_ARG.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (other threads, other streams) race.
+ */
+mf_status mf_solve_noalloc(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld,
+                           void* stream, mf_solve_info* info);
+
+/*
  * Batches of independent systems (many uneven small Newton systems, or
  * concurrent requests of a serving loop) factor and solve in the same launches.
  * Batching is this library's extension for many concurrent parametric solves;

@@ -28,7 +28,7 @@ PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
 # every entry point declared in include/mf.h
 EXPORTS = ["mf_default_options", "mf_analyze", "mf_symbolic_export", "mf_factor", "mf_get_factor_info",
            "mf_solve", "mf_batch_analyze", "mf_factor_batched", "mf_solve_batched", "mf_footprint_bytes",
-           "mf_debug_front", "mf_release", "mf_last_error"]
+           "mf_debug_front", "mf_release", "mf_last_error", "mf_solve_noalloc"]
 
 
 class mf_options(ctypes.Structure):
@@ -96,6 +96,9 @@ def lib():
         L.mf_solve.argtypes = [ctypes.c_void_p, P, P, ctypes.c_int32, ctypes.c_int64, P,
                                ctypes.POINTER(mf_solve_info)]
         L.mf_solve.restype = ctypes.c_int
+        L.mf_solve_noalloc.argtypes = [ctypes.c_void_p, P, P, ctypes.c_int32, ctypes.c_int64, P,
+                                       ctypes.POINTER(mf_solve_info)]
+        L.mf_solve_noalloc.restype = ctypes.c_int
         L.mf_footprint_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_options), ctypes.c_double]
         L.mf_footprint_bytes.restype = ctypes.c_int64
         L.mf_batch_analyze.argtypes = [ctypes.c_int32, P, ctypes.POINTER(ctypes.c_void_p)]
@@ -271,6 +274,23 @@ class Numeric:
         inf = mf_solve_info()
         st = lib().mf_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), nrhs, n,
                             _stream_ptr(stream), ctypes.byref(inf))
+        if check or st != MF_ERR_NOT_CONVERGED:
+            _check(st)
+        return x, inf
+
+    def solve_noalloc(self, b, x, stream=None, check=True):
+        """mf_solve_noalloc: as solve(), into a caller-provided x, with the library's
+        static scratch instead of any allocation."""
+        n = self.sym.n
+        nrhs = check_vectors(b, n, "b")
+        check_vectors(x, n, "x", nrhs=nrhs)
+        if x.shape != b.shape:
+            raise ValueError("x must have the shape of b")
+        if x.numel() > 0 and x.data_ptr() == b.data_ptr():
+            raise ValueError("x and b must be distinct buffers")
+        inf = mf_solve_info()
+        st = lib().mf_solve_noalloc(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), nrhs, n,
+                                    _stream_ptr(stream), ctypes.byref(inf))
         if check or st != MF_ERR_NOT_CONVERGED:
             _check(st)
         return x, inf

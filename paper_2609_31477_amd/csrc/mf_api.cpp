@@ -1749,6 +1749,140 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
     return MF_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation solve
+// Callers that cannot allocate (graph capture, tight serving loops) get the solve's
+// scratch from one statically sized device array per GPU instead of the handle's
+// buffers.  Host code never takes the array's name as a device address: it asks
+// the runtime for this GPU's copy once and keeps that pointer.
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchMaxDevices = 64;
+constexpr int kScratchMaxCounts = 4096;  // (system, right-hand side) pairs
+double* g_scratch_ptr[kScratchMaxDevices] = {};
+unsigned long long g_host_omega[kResQ * kScratchMaxCounts];  // readback staging (pageable, static)
+int32_t g_host_active[kScratchMaxCounts];
+}  // namespace
+}  // extern "C"
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+// This device's copy of the scratch array (looked up once per device).
+double* scratch_for_current_device(int* dev_out) {
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchMaxDevices) throw Fail{MF_ERR_DEVICE, "device index beyond the scratch table"};
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            throw Fail{MF_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *dev_out = dev;
+    return g_scratch_ptr[dev];
+}
+
+// Carve the solve's buffers out of the scratch array for the duration of one
+// call; the handle's own buffers (and their capacities) are put back afterwards.
+struct ScratchSolve {
+    mf_num* N;
+    double *vec, *work, *sb, *respart;
+    unsigned long long *omega, *homega;
+    int32_t *active, *hactive;
+    size_t vec_cap, work_cap, sb_cap, respart_cap;
+    int omega_cap;
+    int sweep;
+    explicit ScratchSolve(mf_num* n)
+        : N(n), vec(n->d_vec), work(n->d_work), sb(n->d_sb), respart(n->d_respart), omega(n->d_omega),
+          homega(n->h_omega), active(n->d_active), hactive(n->h_active), vec_cap(n->vec_cap), work_cap(n->work_cap),
+          sb_cap(n->sb_cap), respart_cap(n->respart_cap), omega_cap(n->omega_cap), sweep(n->opt.sweep) {}
+    ~ScratchSolve() {
+        N->d_vec = vec;
+        N->d_work = work;
+        N->d_sb = sb;
+        N->d_respart = respart;
+        N->d_omega = omega;
+        N->h_omega = homega;
+        N->d_active = active;
+        N->h_active = hactive;
+        N->vec_cap = vec_cap;
+        N->work_cap = work_cap;
+        N->sb_cap = sb_cap;
+        N->respart_cap = respart_cap;
+        N->omega_cap = omega_cap;
+        N->opt.sweep = sweep;
+    }
+};
+}  // namespace
+
+extern "C" {
+
+mf_status mf_solve_noalloc(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld, void* stream,
+                           mf_solve_info* info) {
+    if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
+    if (!N->factored) return fail(MF_ERR_STATE, "mf_solve_noalloc before a successful mf_factor");
+    const Symbolic& S = N->sym->S;
+    const int64_t n = S.n;
+    if (nrhs < 0) return fail(MF_ERR_ARG, "bad nrhs");
+    if (nrhs == 0 || n == 0) {
+        if (info) *info = mf_solve_info{};
+        return MF_OK;
+    }
+    if (ld < n) return fail(MF_ERR_ARG, "ld < n");
+    if (!b_dev || !x_dev || b_dev == x_dev) return fail(MF_ERR_ARG, "b_dev and x_dev must be distinct device buffers");
+    if (N->opt.refine > 1)
+        return fail(MF_ERR_ARG, "mf_solve_noalloc refines with FP64 iterative refinement only (refine 0 or 1): "
+                                "GMRES-IR needs its Krylov basis; use mf_solve");
+    const int nseg = (int)S.seg_n.size();
+    const int cnt = nseg * nrhs;
+    if (cnt > kScratchMaxCounts) return fail(MF_ERR_ARG, "too many (system, right-hand side) pairs for mf_solve_noalloc");
+    auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+    const size_t b_vec = al(sizeof(double) * (size_t)std::max<int64_t>(N->vec_len, 1) * nrhs);
+    const size_t b_work = al(sizeof(double) * (size_t)n * nrhs * 2);
+    const size_t b_sb = N->scaled ? al(sizeof(double) * (size_t)n * nrhs) : 0;
+    const size_t b_part = al(sizeof(double) * residual_part_size(n, nrhs));
+    const size_t b_om = al(sizeof(unsigned long long) * kResQ * cnt);
+    const size_t b_act = al(sizeof(int32_t) * cnt);
+    const size_t total = b_vec + b_work + b_sb + b_part + b_om + b_act;
+    if (total > kScratchBytes)
+        return fail(MF_ERR_ARG, "mf_solve_noalloc needs " + std::to_string(total) + " bytes of scratch, above its " +
+                                    std::to_string(kScratchBytes) + "-byte limit (use mf_solve)");
+    try {
+        int dev = 0;
+        char* base = (char*)scratch_for_current_device(&dev);
+        ScratchSolve keep(N);  // restores the handle's buffers on every exit
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            char* p = base + off;
+            off += bytes;
+            return p;
+        };
+        N->d_vec = (double*)take(b_vec);
+        N->vec_cap = b_vec / sizeof(double);
+        N->d_work = (double*)take(b_work);
+        N->work_cap = b_work / sizeof(double);
+        if (N->scaled) {
+            N->d_sb = (double*)take(b_sb);
+            N->sb_cap = b_sb / sizeof(double);
+        }
+        N->d_respart = (double*)take(b_part);
+        N->respart_cap = b_part / sizeof(double);
+        N->d_omega = (unsigned long long*)take(b_om);
+        N->h_omega = g_host_omega;
+        N->d_active = (int32_t*)take(b_act);
+        N->h_active = g_host_active;
+        N->omega_cap = cnt;
+        N->opt.sweep = 0;  // the persistent sweeps keep task lists in handle memory
+        do_solve(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
+    } catch (const Fail& f) {
+        return fail(f.st, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(MF_ERR_OOM, "host allocation failed in mf_solve_noalloc");
+    }
+    return MF_OK;
+}
+
 mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const* x_dev, const int32_t* nrhs,
                            void* stream, mf_solve_info* info) {
     if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
