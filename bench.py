@@ -8,6 +8,13 @@ to a componentwise backward error <= 1e-10.  Workload: the 2D construction at
 1 % relative N(0,1) noise each (cycled), one N(0,1) right-hand side per step.
 All inputs are resident in HBM before the timed region.
 
+Beside the headline it reports, on the same line: the mixed path on the same
+workload (FP32 fronts, FP64 root, FP64 GMRES-IR); the same matrix with eight
+right-hand sides in FP64, FP32 and BF16 (the precision comparison); the
+dominant kernel against its roofline and the Schur GEMM, solve sweeps and
+extend-add against theirs; a large-K Schur GEMM on one dense front in each
+precision; the 64-system batch; and the CPU oracle on a bounded sample.
+
 Prints ONE JSON line (rank 0).  --gpus above 1 is refused: this build measures
 one GPU.
 """
@@ -33,26 +40,86 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds_cap=60.0):
-    """The oracle (left-looking sparse LU + FP64 refinement, single thread) on a
-    bounded sample: one Newton step of the same construction at 128x64 cells,
-    scaled to the 256x128 workload by the ratio of nominal front flops."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_step(nx, ny, seed=1):
+    """One Newton step of the oracle (nested-dissection order, left-looking sparse
+    LU with threshold tau = 0.1, FP64 refinement to 1e-10), single-threaded C.
+    Returns (seconds, nominal front flops of the same order, omega)."""
     import numpy as np
     from oracle import splu, sym
     from vivjac import build_2d
-    s = build_2d(128, 64, 1)
+    s = build_2d(nx, ny, seed)
     S = sym.analyze(s.n, s.rowptr, s.colind, s.root)
+    npiv = np.diff(S.front_ptr).astype(np.float64)
+    m = np.diff(S.rows_ptr).astype(np.float64)
+    flops = float(sum(((a := np.arange(mm - pp, mm)) + 2 * a * a).sum() for mm, pp in zip(m, npiv)))
     t0 = time.perf_counter()
     F = splu.SparseLU(s.n, s.rowptr, s.colind, s.values, S.perm, tau=0.1)
     x, om, st = F.solve(s.b0[0], tol=1e-10, max_steps=3)
-    dt = time.perf_counter() - t0
-    npiv = np.diff(S.front_ptr).astype(np.float64)
-    m = np.diff(S.rows_ptr).astype(np.float64)
-    flops_sample = float(sum(((a := np.arange(mm - pp, mm)) + 2 * a * a).sum() for mm, pp in zip(m, npiv)))
-    return dt, flops_sample, float(om[0])
+    return time.perf_counter() - t0, flops, float(om[0])
 
 
-def bench_batch(args):
+def cpu_baseline(target_flops, full=True, nx=256, ny=128):
+    """The oracle on this host's cores, single-threaded.  Default (full): one Newton
+    step of the workload itself (step 0 at nx x ny: analysis untimed, then the
+    factorization, solve and refinement), about 20-30 s.  full=False: a bounded
+    sample instead, one step at 64x32 and at 128x64 cells of the same construction,
+    with the full-size time extrapolated by the power law in nominal front flops
+    fitted through the two (on the GPU host it came out 19% below the measured
+    full-size step)."""
+    import math
+    if full:
+        dt, fl, om = _oracle_step(nx, ny)
+        return {"value": round(1.0 / dt, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"one full Newton step of the {nx}x{ny} workload (factor+solve+refinement, omega {om:.1e}) "
+                          f"took {dt:.1f}s single-threaded",
+                "cpu": _cpu_model(), "nproc": os.cpu_count()}
+    t1, f1, _ = _oracle_step(64, 32)
+    t2, f2, om = _oracle_step(128, 64)
+    alpha = math.log(t2 / t1) / math.log(f2 / f1)
+    est = t2 * (target_flops / f2) ** alpha
+    return {"value": round(1.0 / est, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one Newton step at 64x32 ({t1:.2f}s) and 128x64 ({t2:.2f}s, omega {om:.1e}) of the same "
+                      f"construction, single-threaded; time taken as a power of nominal front flops fitted through "
+                      f"the two (exponent {alpha:.2f}) and evaluated at the workload's {target_flops:.3e} flops: "
+                      f"{est:.1f}s per step",
+            "cpu": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def gemm_micro(prec, N=4096, nroot=2048):
+    """Large-K Schur GEMM: one dense front of order N whose last nroot variables are
+    the root list, so the front eliminates N - nroot pivots and updates an nroot x
+    nroot contribution block with K = N - nroot (k_gemm / k_gemm_bf16 through a
+    profiled factorization).  Returns achieved TFLOP/s of the Schur phase."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    import paper_2609_31477_amd as mf
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((N, N)) + np.sqrt(N) * np.eye(N)
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    S = mf.Symbolic(N, M.indptr, M.indices, np.arange(N - nroot, N, dtype=np.int32), leaf_max=N)
+    v = torch.from_numpy(M.data.copy()).cuda()
+    num = S.factor(v, prec=prec, profile=1)
+    num = S.factor(v, numeric=num, prec=prec, profile=1)
+    torch.cuda.synchronize()
+    fi = num.info()
+    num.release()
+    return fi.schur_flops / (fi.t_schur_ms * 1e-3) / 1e12, fi.schur_flops
+
+
+def bench_batch(args, summary_only=False):
     """64 independent 2D systems (seeds 100-163, nx = 16 + 4 U{0..12}, ny = nx/2) factored
     and solved together, FP32 fronts (FP64 roots) with FP64 GMRES-IR to omega <= 1e-10."""
     import numpy as np
@@ -88,6 +155,13 @@ def bench_batch(args):
         infos = step()
         ts.append(time.perf_counter() - t1)
     el = time.perf_counter() - t0
+    if summary_only:
+        B.release()
+        return {"workload": "64 uneven 2D systems (16x8..64x32 cells), one batched factor+solve per step, FP32 fronts, "
+                            "FP64 roots, GMRES-IR to omega<=1e-10",
+                "value": round(64 * args.steps / el, 3), "unit": "solves/s",
+                "ms_per_step": round(1e3 * el / args.steps, 3), "p99_ms": round(1e3 * float(np.percentile(ts, 99)), 3),
+                "omega_max": float(max(i.omega for i in infos)), "steps": args.steps}
     res = {"metric": METRIC, "value": round(64 * args.steps / el, 3), "unit": "solves/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -155,6 +229,11 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fit", action="store_true",
+                    help="estimate the oracle's time from one step at 64x32 and 128x64 cells (power law in nominal "
+                         "front flops) instead of timing the full-size step (about 20-30 s on one core)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the eight-right-hand-side precision comparison, GEMM microbenchmark and batch line")
     ap.add_argument("--no-profile", action="store_true", help="skip the separate event-timed profiling pass")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 fronts) comparison")
     args = ap.parse_args()
@@ -189,6 +268,11 @@ def main():
     rhs = [torch.from_numpy(newton_rhs(s, k)[0].copy()).to(dev) for k in range(nsteps_newton)]
     x = torch.empty(s.n, dtype=torch.float64, device=dev)
     x.zero_()
+    # the precision comparison: the same matrices with eight right-hand sides
+    # (the first eight rows of each step's seeded stream)
+    rhs8 = [] if args.no_extras else [torch.from_numpy(newton_rhs(s, k, nrhs=8).copy()).to(dev)
+                                      for k in range(nsteps_newton)]
+    x8 = torch.empty(8, s.n, dtype=torch.float64, device=dev) if rhs8 else None
     t = time.perf_counter()
     S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
     t_analyze = time.perf_counter() - t
@@ -197,17 +281,21 @@ def main():
         f"nominal flops={view.nominal_flops:.3e} nnz(L+U)={view.nominal_nnz_lu:.3e}")
     stream = torch.cuda.current_stream()
 
-    def run_path(prec):
-        """Time args.steps Newton-step solves (factor + solve + refinement) in one precision."""
+    def run_path(prec, nrhs=1, steps=None, warmup=None, profile=True):
+        """Time Newton-step solves (factor + solve + refinement) in one precision."""
+        steps = args.steps if steps is None else steps
+        warmup = args.warmup if warmup is None else warmup
         opts = dict(prec=prec, target_omega=args.target_omega)
         state = {"num": None}
         step_ms, omegas, iters, inner = [], [], [], []
+        rr = rhs if nrhs == 1 else rhs8
+        xx = x if nrhs == 1 else x8
 
         def step(i, timed):
             k = i % nsteps_newton
             t0 = time.perf_counter()
             state["num"] = S.factor(vals[k], numeric=state["num"], stream=stream, **opts)
-            _, info = state["num"].solve(rhs[k], x=x, stream=stream)
+            _, info = state["num"].solve(rr[k], x=xx, stream=stream)
             torch.cuda.synchronize()
             if timed:
                 step_ms.append(1e3 * (time.perf_counter() - t0))
@@ -215,18 +303,18 @@ def main():
                 iters.append(info.outer_iters)
                 inner.append(info.inner_iters)
 
-        for i in range(args.warmup):
+        for i in range(warmup):
             step(i, False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             step(i, True)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        log(f"{prec}: timed {args.steps} steps in {elapsed:.3f}s")
+        log(f"{prec} ({nrhs} rhs): timed {steps} steps in {elapsed:.3f}s")
         num = state["num"]
         finfo = None
-        if not args.no_profile:
+        if profile and not args.no_profile:
             num = S.factor(vals[0], numeric=num, stream=stream, profile=1, **opts)
             torch.cuda.synchronize()
             finfo = num.info()
@@ -238,12 +326,28 @@ def main():
         t_factor = (time.perf_counter() - t_f0) / nf_rep
         if finfo is None:
             finfo = num.info()
+        # one sweep pair alone (no refinement), timed with events on the stream
+        t_sweep = None
+        if profile and not args.no_profile:
+            num = S.factor(vals[0], numeric=num, stream=stream, prec=prec, refine=0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            num.solve(rr[0], x=xx, stream=stream)
+            e0.record(stream)
+            for _ in range(3):
+                num.solve(rr[0], x=xx, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_sweep = e0.elapsed_time(e1) / 3
         num.release()
         return dict(elapsed=elapsed, step_ms=step_ms, omegas=omegas, iters=iters, inner=inner, finfo=finfo,
-                    t_factor=t_factor)
+                    t_factor=t_factor, t_sweep=t_sweep, steps=steps)
 
     main = run_path(args.prec)
     mixed = None if args.no_mixed or args.prec != "fp64" else run_path("fp32")
+    eight = {}
+    if rhs8 and args.prec == "fp64" and not args.no_mixed:
+        for pr in ("fp64", "fp32", "bf16"):
+            eight[pr] = run_path(pr, nrhs=8, steps=3, warmup=1, profile=False)
     elapsed, step_ms, omegas, iters, finfo, t_factor = (main["elapsed"], main["step_ms"], main["omegas"],
                                                          main["iters"], main["finfo"], main["t_factor"])
 
@@ -288,6 +392,17 @@ def main():
                         "omega_max": float(max(mixed["omegas"])), "outer_max": int(max(mixed["iters"])),
                         "inner_total": int(sum(mixed["inner"])),
                         "speedup_vs_fp64": round(mv / value, 4)}
+    if eight:
+        base = eight["fp64"]["steps"] / eight["fp64"]["elapsed"]
+        res["eight_rhs"] = {"workload": "the same 256x128 Newton steps with 8 right-hand sides N(0,1) per step; "
+                                        "mixed paths: FP64 root, FP64 residual, GMRES-IR over the 8 in lockstep",
+                            "unit": "solves/s (one solve = factor + 8-column solve)"}
+        for pr, r in eight.items():
+            v = r["steps"] / r["elapsed"]
+            res["eight_rhs"][pr] = {"value": round(v, 4), "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 3),
+                                    "omega_max": float(max(r["omegas"])), "outer_max": int(max(r["iters"])),
+                                    "inner_per_step": round(sum(r["inner"]) / len(r["inner"]), 1),
+                                    "speedup_vs_fp64": round(v / base, 4)}
     if finfo is not None and finfo.schur_launches:
         res["phases_ms"] = {"assemble": round(finfo.t_assemble_ms, 3), "panel_loop": round(finfo.t_panel_ms, 3),
                             "panel_kernel": round(finfo.t_panel_kernel_ms, 3), "schur": round(finfo.t_schur_ms, 3),
@@ -307,19 +422,49 @@ def main():
                            "avg_launch_ms": round(avg_ms, 4), "launches": int(finfo.panel_launches),
                            "per_launch": "nominal window flops of one panel round over a tree level: "
                                          f"{finfo.panel_flops / max(1, finfo.panel_launches):.3e} flops"}
+        # front TFLOP/s of the whole factorization against the MFMA peak of its precision
+        res["front_tflops_frac"] = round(view.nominal_flops / t_factor / 1e12 / PEAK[dtype], 5)
+        # extend-add and scatter (assembly phase): every contribution-block entry read
+        # once and added into the parent (read-modify-write), every original entry
+        # read once and added into its front
+        import numpy as _np
+        mm = _np.diff(view.rows_ptr).astype(_np.float64)
+        pp = _np.diff(view.front_ptr).astype(_np.float64)
+        cb = (mm - pp)[view.front_parent >= 0]
+        sf = 8.0 if args.prec == "fp64" else 4.0
+        asm_bytes = 3.0 * sf * float((cb * cb).sum()) + s.nnz * (8.0 + 2.0 * sf)
+        res["roofline_assembly"] = {"bound": "hbm", "kernel": "k_gather + k_scatter (extend-add and value scatter)",
+                                    "achieved": round(asm_bytes / (finfo.t_assemble_ms * 1e-3) / 1e9, 2),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(asm_bytes / (finfo.t_assemble_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                                    "per_factorization_bytes": asm_bytes}
+        if main["t_sweep"]:
+            sw_bytes = view.nominal_nnz_lu * sf
+            res["roofline_sweeps"] = {"bound": "hbm", "kernel": "forward + backward sweep pair (persistent upper tree, "
+                                                                "level launches below) plus one residual",
+                                      "achieved": round(sw_bytes / (main["t_sweep"] * 1e-3) / 1e9, 2),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(sw_bytes / (main["t_sweep"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                                      "ms": round(main["t_sweep"], 4), "bytes": sw_bytes}
         sch = finfo.schur_flops / (finfo.t_schur_ms * 1e-3) / 1e12
         res["roofline_schur"] = {"bound": "mfma", "kernel": "k_gemm mode 1 (contribution-block Schur update)",
                                  "achieved": round(sch, 4), "peak": PEAK[dtype], "unit": "TFLOP/s",
                                  "frac": round(sch / PEAK[dtype], 5),
                                  "per_launch": f"sum over a level's fronts of 2 (m-P)^2 k flops; "
                                                f"{finfo.schur_flops / max(1, finfo.schur_launches):.3e} flops"}
+    if not args.no_extras and args.prec == "fp64":
+        gm = {}
+        for pr in ("fp64", "fp32", "bf16"):
+            tf, fl = gemm_micro(pr)
+            pk = PEAK[{"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[pr]]
+            gm[pr] = {"achieved": round(tf, 3), "peak": pk, "unit": "TFLOP/s", "frac": round(tf / pk, 5)}
+        gm["workload"] = ("one dense front of order 4096 eliminating 2048 pivots: Schur GEMM of a 2048 x 2048 "
+                          f"contribution block with K = 2048 ({fl:.3e} flops), timed with events")
+        res["gemm_large_k"] = gm
+        res["batch"] = bench_batch(argparse.Namespace(steps=5, warmup=1, prec="fp32", target_omega=args.target_omega),
+                                   summary_only=True)
     if not args.no_cpu_baseline:
-        dt, fl_sample, om = cpu_baseline()
-        scaled = dt * view.nominal_flops / fl_sample
-        res["cpu_baseline"] = {"value": round(1.0 / scaled, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one Newton step (factor+solve+refinement, omega {om:.1e}) of the 128x64 "
-                                         f"mesh of the same construction took {dt:.2f}s single-threaded; scaled by "
-                                         f"nominal front flops ({fl_sample:.3e} -> {view.nominal_flops:.3e})"}
+        res["cpu_baseline"] = cpu_baseline(view.nominal_flops, full=not args.cpu_fit, nx=args.nx, ny=args.ny)
     print(json.dumps(res), flush=True)
 
 

@@ -1017,10 +1017,17 @@ void build_sweep_plan(mf_num* N) {
             seg_of[sl] = (int)(std::upper_bound(S.seg_row0.begin(), S.seg_row0.end(), var) - S.seg_row0.begin()) - 1;
         }
     }
-    std::vector<int32_t> cnt((size_t)nseg * (S.nlevels + 1), 0), first(nseg, S.nlevels);
+    std::vector<int32_t> cnt((size_t)nseg * (S.nlevels + 1), 0), first(nseg, S.nlevels), mmax(nseg, 0);
     for (int L = 0; L < S.nlevels; L++)
-        for (int sl = S.level_ptr[L]; sl < S.level_ptr[L + 1]; sl++) cnt[(size_t)seg_of[sl] * (S.nlevels + 1) + L]++;
+        for (int sl = S.level_ptr[L]; sl < S.level_ptr[L + 1]; sl++) {
+            cnt[(size_t)seg_of[sl] * (S.nlevels + 1) + L]++;
+            mmax[seg_of[sl]] = std::max(mmax[seg_of[sl]], hm[sl]);
+        }
     for (int q = 0; q < nseg; q++) {
+        // only systems with fronts large enough for several work-groups per front to
+        // pay for the cross-group waits (measured: the 64-system batch of small
+        // meshes sweeps faster level by level)
+        if (mmax[q] < kSwListedMinOrder) continue;
         const int32_t* c = cnt.data() + (size_t)q * (S.nlevels + 1);
         int T = S.nlevels;
         while (T > 0 && c[T - 1] <= kSwTopFronts) T--;

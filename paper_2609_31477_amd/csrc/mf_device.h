@@ -127,6 +127,7 @@ constexpr int kSwWhole = 256;
 constexpr int kSwRhs = 8;       // right-hand sides per sweep launch
 constexpr int kSwBundle = 8;    // consecutive whole-front tasks taken with one ticket
 constexpr int kSwTopFronts = 64;  // levels with at most this many fronts (and all above) run persistently
+constexpr int kSwListedMinOrder = 1024;  // ... in systems whose largest front has at least this order
 enum SweepKind { kSwKindWhole = 0, kSwKindFs = 1, kSwKindCb = 2 };
 __host__ __device__ inline int32_t sweep_code(int kind, int blk) { return (kind << 8) | blk; }
 __host__ __device__ inline int sweep_kind(int32_t code) { return code >> 8; }

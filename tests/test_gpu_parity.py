@@ -315,3 +315,37 @@ def test_persistent_sweeps_match_level_sweeps(torch_cuda, prec, nx, ny, seed, nr
         x, info = num.solve(b)
         assert_parity(s.to_scipy(), x.cpu().numpy(), Xo, B, omega_tol=target,
                       rel_tol=1e-8 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp32", 3), ("fp64", 9)])
+def test_persistent_sweeps_match_level_sweeps_256x128(torch_cuda, prec, nrhs):
+    """At 256x128 the upper tree (levels of at most 64 fronts, fronts up to order
+    1,464) runs in the persistent sweeps with its large fronts split over many
+    work-groups: without refinement the solution agrees with the level-by-level
+    sweeps to rounding (relative 1e-10), and with refinement each meets its
+    backward-error target (recomputed on the CPU)."""
+    torch = torch_cuda
+    s = build_2d(256, 128, 1, nrhs=nrhs)
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    v = torch.from_numpy(s.values).to(dev)
+    B = s.b0 if nrhs > 1 else s.b0[0]
+    b = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    raw = {}
+    for sw in (0, 1):
+        num = S.factor(v, prec=prec, refine=0, sweep=sw)
+        x, _ = num.solve(b)
+        raw[sw] = x.cpu().numpy()
+        num.release()
+    d = np.abs(raw[0] - raw[1]).max() / np.abs(raw[0]).max()
+    print(f"256x128 {prec} nrhs={nrhs}: persistent vs level sweeps {d:.2e}", flush=True)
+    assert d <= 1e-10
+    target = 1e-12 if prec == "fp64" else 1e-10
+    A = s.to_scipy()
+    num = S.factor(v, prec=prec, target_omega=target)
+    x, info = num.solve(b)
+    X = np.atleast_2d(x.cpu().numpy())
+    for c in range(nrhs):
+        assert check.omega_fast(A, X[c], np.atleast_2d(B)[c]) <= target
+    num.release()
