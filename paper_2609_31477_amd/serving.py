@@ -8,16 +8,21 @@ runs ``newton_steps`` factor+solve steps with its symbolic analysis done once
 (Sec. 6, "Scaling").
 
 Scheduling (continuous batching, not a queue): requests arrive on a Poisson
-clock; a request is admitted when a slot and its HBM footprint fit; every tick
-runs one Newton step of every admitted request.  Requests admitted together form
-a cohort, which shares one batched factorization and one batched solve per step
-(shared launches); the cohort's merged analysis is built once, when it is
-admitted, and reused for all its steps, so no tick pays for re-merging the whole
-active set.  Requests that arrive while others are on the GPU join at the next
-tick as a new cohort; finished requests free their slot and memory immediately.
-Patterns are analyzed once per mesh (the paper's analysis reuse, Sec. 6).
-Because the batched kernels keep every system's arithmetic separate, a request's
-result is the same alone and in any mix.
+clock; each arrival's preparation (its mesh's pattern analysis, done once per
+mesh: the paper's analysis reuse, Sec. 6) starts at once on a host thread pool,
+off the tick path; a prepared request is admitted when a slot and its HBM
+footprint fit; every tick runs one Newton step of every admitted request.
+Requests admitted together form a cohort, which shares one batched
+factorization and one batched solve per step (shared launches); the cohort's
+merged analysis is built once, when it is admitted, and reused for all its
+steps.  A cohort is closed before its merged tree would pass the library's
+limit of fronts per level.  The cohorts of a tick run at the same time, each
+from its own host thread on its own stream (up to four), so work admitted at
+different times overlaps on the device.  Requests that arrive while others are
+on the GPU join at the next tick as a new cohort; finished requests free their
+slot and memory immediately, and the analyses cached per mesh are counted
+against the same HBM budget.  Because the batched kernels keep every system's
+arithmetic separate, a request's result is the same alone and in any mix.
 
 The scheduler is backend-agnostic: ``MFBackend`` drives libmf on the GPU;
 ``FakeBackend`` simulates durations and footprints for CPU tests of the logic.
@@ -26,7 +31,9 @@ from __future__ import annotations
 
 import heapq
 import math
+import threading
 import time
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -50,6 +57,8 @@ class Request:
     cohort: int = -1                               # requests admitted together
     results: list = field(default_factory=list)   # per-step info (omega, ...)
     state: object = None                           # backend state
+    prepared: object = None                        # Future of the backend's preparation (footprint)
+    level_fronts: tuple = ()                       # fronts per tree level of its pattern
 
     @property
     def nu(self) -> float:
@@ -82,6 +91,9 @@ def poisson_requests(n, rate, seed=0, mix_3d=0.3, newton_steps=5, mesh_2d=range(
     return out
 
 
+MAX_LEVEL_FRONTS = 65535  # fronts per tree level of one batch (library limit)
+
+
 class Scheduler:
     """Admission by footprint + continuous batching over Newton steps."""
 
@@ -100,25 +112,43 @@ class Scheduler:
     def submit(self, req: Request):
         heapq.heappush(self.waiting, (req.arrival, req.rid, req))
 
+    def _start_preparation(self, now):
+        # every request that has arrived starts its preparation at once (in the
+        # background), whether or not a slot is free
+        for _, _, req in self.waiting:
+            if req.arrival <= now and req.prepared is None:
+                req.prepared = self.backend.prepare_async(req)
+
     def _admit(self, now):
+        self._start_preparation(now)
         cohort = self.cohorts
-        admitted = False
+        admitted = 0
+        levels = []
         while self.waiting and self.waiting[0][0] <= now and len(self.active) < self.max_slots:
             _, _, req = self.waiting[0]
-            if not req.footprint:
-                req.footprint = self.backend.prepare(req)
+            if not req.prepared.done():
+                break                  # FIFO: the head is still being analyzed
+            req.footprint = req.prepared.result()
             if req.footprint > self.budget:
                 raise MemoryError(f"request {req.rid} needs {req.footprint} B, above the whole budget")
-            if self.used + req.footprint > self.budget:
+            if self.used + self.backend.resident_bytes() + req.footprint > self.budget:
                 break                  # wait until memory frees up (FIFO admission)
+            lf = list(req.level_fronts)
+            merged = [a + b for a, b in zip(levels + [0] * len(lf), lf + [0] * len(levels))]
+            if admitted and max(merged, default=0) > MAX_LEVEL_FRONTS:
+                cohort += 1            # close the cohort before it passes the fronts-per-level limit
+                admitted = 0
+                merged = lf
             heapq.heappop(self.waiting)
             self.used += req.footprint
             req.admitted = now
             req.cohort = cohort
-            admitted = True
+            admitted += 1
+            levels = merged
             self.active.append(req)
         if admitted:
-            self.cohorts += 1
+            cohort += 1
+        self.cohorts = cohort
 
     def run(self, clock=None, idle_sleep=True):
         """Serve until every submitted request is done.  ``clock()`` returns seconds
@@ -130,7 +160,9 @@ class Scheduler:
             self._admit(now)
             if not self.active:
                 nxt = self.waiting[0][0]
-                if idle_sleep:
+                if nxt <= now:         # the head has arrived: its analysis is still running
+                    self.waiting[0][2].prepared.result()
+                elif idle_sleep:
                     self.backend.idle_until(nxt, clock)
                 continue
             batch = list(self.active)
@@ -180,7 +212,22 @@ class FakeBackend:
         return self.now
 
     def prepare(self, req):
+        # a synthetic tree: leaves hold about 64 dofs, each level above half as many fronts
+        f = max(1, self.dofs(req) // 64)
+        lv = []
+        while f >= 1:
+            lv.append(f)
+            f //= 2
+        req.level_fronts = tuple(lv)
         return self.dofs(req) * self.bytes_per_dof
+
+    def prepare_async(self, req):
+        fut = Future()
+        fut.set_result(self.prepare(req))
+        return fut
+
+    def resident_bytes(self):
+        return 0
 
     def step(self, batch):
         self.calls.append([r.rid for r in batch])
@@ -205,7 +252,8 @@ class MFBackend:
     arrays; without it the backend assembles the request itself.  ``times`` keeps
     the host-side wall time spent per phase (prepare, merge, factor+solve)."""
 
-    def __init__(self, prec="fp32", target_omega=1e-10, margin=0.5, device="cuda:0", payloads=None):
+    def __init__(self, prec="fp32", target_omega=1e-10, margin=0.5, device="cuda:0", payloads=None,
+                 streams=4, prep_threads=4):
         import torch
 
         from . import Symbolic
@@ -216,8 +264,15 @@ class MFBackend:
         self.margin = margin
         self.dev = torch.device(device)
         self.stream = torch.cuda.current_stream(self.dev)
+        # cohorts of a tick run concurrently, each from its own thread and stream
+        # (all streams at the default priority)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, streams))]
+        self.pool = ThreadPoolExecutor(max_workers=len(self.streams))
+        self.prep_pool = ThreadPoolExecutor(max_workers=max(1, prep_threads))
+        self.lock = threading.Lock()
         self.payloads = payloads or {}
-        self.sym_cache = {}
+        self.sym_cache = {}     # mesh -> Future of its analysis (Symbolic, level fronts)
+        self.sym_bytes = {}     # mesh -> device bytes of its pattern data (charged to the budget)
         self.times = {"prepare": 0.0, "analyze": 0.0, "merge": 0.0, "factor_solve": 0.0}
         self.batches = {}       # tuple of request ids -> Batch (one per live cohort)
 
@@ -226,6 +281,24 @@ class MFBackend:
         if req.mesh[0] == "2d":
             return build_2d(req.mesh[1], req.mesh[2], req.seed, nu=req.nu, k=req.k)
         return build_3d(req.mesh[1], req.mesh[2], req.mesh[3], req.seed, nu=req.nu, k=req.k)
+
+    def _analyze(self, s, mesh):
+        ta = time.perf_counter()
+        sym = self.Symbolic(s.n, s.rowptr, s.colind, s.root)
+        v = sym.export()
+        h = [0] * v.nfronts
+        for f in range(v.nfronts):  # front heights (postorder: children first)
+            p = int(v.front_parent[f])
+            if p >= 0:
+                h[p] = max(h[p], h[f] + 1)
+        lf = [0] * (max(h) + 1 if h else 0)
+        for x in h:
+            lf[x] += 1
+        with self.lock:
+            self.times["analyze"] += time.perf_counter() - ta
+            # pattern data resident on the device once the first factorization uploads it
+            self.sym_bytes[mesh] = 4 * (v.rows_ptr[-1] * 3 + 8 * v.nfronts) + 12 * s.nnz + 16 * s.n
+        return sym, tuple(lf)
 
     def prepare(self, req):
         t0 = time.perf_counter()
@@ -236,20 +309,55 @@ class MFBackend:
             s = self.build(req)
             hv = [newton_values(s, t) for t in range(req.newton_steps)]
             hb = [newton_rhs(s, t)[0].copy() for t in range(req.newton_steps)]
-        sym = self.sym_cache.get(req.mesh)
-        if sym is None:
-            ta = time.perf_counter()
-            sym = self.sym_cache[req.mesh] = self.Symbolic(s.n, s.rowptr, s.colind, s.root)
-            self.times["analyze"] += time.perf_counter() - ta
+        with self.lock:
+            fut = self.sym_cache.get(req.mesh)
+            mine = fut is None
+            if mine:
+                fut = self.sym_cache[req.mesh] = Future()
+        if mine:
+            try:
+                fut.set_result(self._analyze(s, req.mesh))
+            except BaseException as e:  # hand the failure to every waiter
+                fut.set_exception(e)
+                raise
+        sym, lf = fut.result()
+        req.level_fronts = lf
         vals = [self.torch.from_numpy(v).to(self.dev) for v in hv]
         rhs = [self.torch.from_numpy(b).to(self.dev) for b in hb]
         xs = [self.torch.empty(s.n, dtype=self.torch.float64, device=self.dev) for _ in range(req.newton_steps)]
+        self.torch.cuda.synchronize(self.dev)
         req.state = dict(system=s, sym=sym, vals=vals, rhs=rhs, xs=xs)
-        self.times["prepare"] += time.perf_counter() - t0
+        with self.lock:
+            self.times["prepare"] += time.perf_counter() - t0
         return sym.footprint_bytes(self.prec, self.margin) + 8 * (s.nnz + 2 * s.n) * req.newton_steps
 
-    def step(self, batch):
+    def prepare_async(self, req):
+        return self.prep_pool.submit(self.prepare, req)
+
+    def resident_bytes(self):
+        with self.lock:
+            return int(sum(self.sym_bytes.values()))
+
+    def _run_cohort(self, key, members, stream):
         from . import Batch
+        B = self.batches.get(key)
+        if B is None:
+            tm = time.perf_counter()
+            B = Batch([r.state["sym"] for r in members])
+            with self.lock:
+                self.batches[key] = B
+                self.times["merge"] += time.perf_counter() - tm
+        vals = [r.state["vals"][r.steps_done] for r in members]
+        bs = [r.state["rhs"][r.steps_done] for r in members]
+        xs = [r.state["xs"][r.steps_done] for r in members]
+        with self.torch.cuda.stream(stream):
+            B.factor(vals, stream=stream, prec=self.prec, target_omega=self.target)
+            _, out = B.solve(bs, xs=xs, stream=stream)
+        stream.synchronize()
+        return {r.rid: {"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters}
+                for r, inf in zip(members, out)}
+
+    def step(self, batch):
         t0 = time.perf_counter()
         merge0 = self.times["merge"]
         groups = {}
@@ -257,21 +365,13 @@ class MFBackend:
             groups.setdefault((r.cohort, r.steps_done), []).append(r)
         infos = {}
         live = set()
-        for members in groups.values():
+        futs = []
+        for i, members in enumerate(groups.values()):
             key = tuple(r.rid for r in members)
             live.add(key)
-            B = self.batches.get(key)
-            if B is None:
-                tm = time.perf_counter()
-                B = self.batches[key] = Batch([r.state["sym"] for r in members])
-                self.times["merge"] += time.perf_counter() - tm
-            vals = [r.state["vals"][r.steps_done] for r in members]
-            bs = [r.state["rhs"][r.steps_done] for r in members]
-            xs = [r.state["xs"][r.steps_done] for r in members]
-            B.factor(vals, stream=self.stream, prec=self.prec, target_omega=self.target)
-            _, out = B.solve(bs, xs=xs, stream=self.stream)
-            for r, inf in zip(members, out):
-                infos[r.rid] = {"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters}
+            futs.append(self.pool.submit(self._run_cohort, key, members, self.streams[i % len(self.streams)]))
+        for f in futs:
+            infos.update(f.result())
         self.torch.cuda.synchronize()
         self.times["factor_solve"] += time.perf_counter() - t0 - (self.times["merge"] - merge0)
         for key in [k for k in self.batches if k not in live]:
@@ -285,6 +385,8 @@ class MFBackend:
         st["rhs"] = None
 
     def close(self):
+        self.pool.shutdown(wait=True)
+        self.prep_pool.shutdown(wait=True)
         for B in self.batches.values():
             B.release()
         self.batches.clear()

@@ -88,6 +88,7 @@ def test_gpu_serving_mix_equals_alone():
     for r in reqs:
         sch.submit(r)
     done = sch.run()
+    be.close()
     assert max(sch.batch_sizes) > 1
     for r in done:
         for t in range(r.newton_steps):
@@ -99,6 +100,7 @@ def test_gpu_serving_mix_equals_alone():
             alone.steps_done = t
             be1.step([alone])
             xa = alone.state["xs"][t].cpu().numpy()
+            be1.close()
             assert np.array_equal(xm, xa), f"request {r.rid} step {t} differs alone vs in the mix"
             assert r.results[t]["omega"] <= 1e-10
 
@@ -116,3 +118,60 @@ def test_cohorts_group_requests_admitted_together():
     for members in by_cohort.values():
         assert len({r.admitted for r in members}) == 1
         assert len({r.finished for r in members}) == 1
+
+
+def test_cohort_closed_before_level_limit():
+    # patterns whose widest level holds 40,000 fronts: two of them would pass the
+    # library's 65,535 fronts per level, so each admission pass splits them into
+    # separate cohorts (and separate batched launches)
+    class Wide(FakeBackend):
+        def prepare(self, req):
+            fp = super().prepare(req)
+            req.level_fronts = (40000, 20000, 1)
+            return fp
+    be = Wide()
+    sch = Scheduler(be, hbm_budget=10 ** 12)
+    reqs = poisson_requests(6, rate=1e6, seed=9, allow_3d=False)
+    for r in reqs:
+        sch.submit(r)
+    done = sch.run(clock=be.clock)
+    assert len(done) == 6
+    for call in be.calls:
+        by = {}
+        for rid in call:
+            c = next(r.cohort for r in done if r.rid == rid)
+            by[c] = by.get(c, 0) + 1
+        assert max(by.values()) == 1
+
+
+def test_preparation_runs_off_the_tick_path():
+    # a request whose analysis is still running does not block the ticks of the
+    # requests already admitted; it is admitted once its preparation completes
+    from concurrent.futures import Future
+    pending = {}
+
+    class Slow(FakeBackend):
+        def prepare_async(self, req):
+            fut = Future()
+            if req.rid == 1:
+                pending[1] = (fut, self.prepare(req))
+            else:
+                fut.set_result(self.prepare(req))
+            return fut
+
+        def step(self, batch):
+            out = super().step(batch)
+            if 1 in pending and len(self.calls) == 3:   # the analysis finishes during the third tick
+                fut, fp = pending.pop(1)
+                fut.set_result(fp)
+            return out
+    be = Slow()
+    sch = Scheduler(be, hbm_budget=10 ** 12)
+    r0 = Request(rid=0, arrival=0.0, mesh=("2d", 32, 16), reynolds=150, reduced_velocity=5, seed=1)
+    r1 = Request(rid=1, arrival=0.0, mesh=("2d", 64, 32), reynolds=150, reduced_velocity=5, seed=2)
+    sch.submit(r0)
+    sch.submit(r1)
+    sch.run(clock=be.clock)
+    assert be.calls[0] == [0] and be.calls[1] == [0] and be.calls[2] == [0]
+    assert 1 in be.calls[3]
+    assert r1.admitted is not None and r1.admitted > r0.admitted

@@ -14,6 +14,6 @@ force-position coupling of Sec. 4.2 (eq. coupling_constraint) in its single
 global-master form, and the spring balance of Sec. 2 (eq. solid_balance).
 """
 from .gen2d import System, build_2d, newton_values, newton_rhs
-from .gen3d import build_3d
+from .gen3d import build_3d, p2_tet
 
 __all__ = ["System", "build_2d", "build_3d", "newton_values", "newton_rhs"]
