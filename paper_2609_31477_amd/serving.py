@@ -150,9 +150,10 @@ class Scheduler:
             cohort += 1
         self.cohorts = cohort
 
-    def run(self, clock=None, idle_sleep=True):
+    def run(self, clock=None, idle_sleep=True, on_tick=None):
         """Serve until every submitted request is done.  ``clock()`` returns seconds
-        since the start (wall clock by default; the fake backend advances its own)."""
+        since the start (wall clock by default; the fake backend advances its own);
+        ``on_tick(scheduler)``, if given, is called after every tick."""
         t0 = time.perf_counter()
         clock = clock or (lambda: time.perf_counter() - t0)
         while self.waiting or self.active:
@@ -181,6 +182,8 @@ class Scheduler:
                     self.used -= req.footprint
                     self.backend.release(req)
                     self.done.append(req)
+            if on_tick is not None:
+                on_tick(self)
         return self.done
 
 
@@ -247,10 +250,12 @@ class MFBackend:
     merged batch (mf_batch_analyze once, its numeric handle reused across steps)
     driving one batched factorization + batched solve per tick.
 
-    ``payloads`` (optional) maps a request id to what a server receives with the
-    request: (system, [Newton values per step], [right-hand side per step]) as host
-    arrays; without it the backend assembles the request itself.  ``times`` keeps
-    the host-side wall time spent per phase (prepare, merge, factor+solve)."""
+    ``payloads`` (optional) gives what a server receives with the request: either a
+    dict from request id to (system, [Newton values per step], [right-hand side per
+    step]) as host arrays, or a callable ``payloads(req, device)`` returning the same
+    triple with the values and right-hand sides already as device tensors; without
+    it the backend assembles the request itself.  ``times`` keeps the host-side wall
+    time spent per phase (prepare, merge, factor+solve)."""
 
     def __init__(self, prec="fp32", target_omega=1e-10, margin=0.5, device="cuda:0", payloads=None,
                  streams=4, prep_threads=4):
@@ -270,7 +275,8 @@ class MFBackend:
         self.pool = ThreadPoolExecutor(max_workers=len(self.streams))
         self.prep_pool = ThreadPoolExecutor(max_workers=max(1, prep_threads))
         self.lock = threading.Lock()
-        self.payloads = payloads or {}
+        self.tls = threading.local()    # per preparation thread: its upload stream
+        self.payloads = payloads if payloads is not None else {}
         self.sym_cache = {}     # mesh -> Future of its analysis (Symbolic, level fronts)
         self.sym_bytes = {}     # mesh -> device bytes of its pattern data (charged to the budget)
         self.times = {"prepare": 0.0, "analyze": 0.0, "merge": 0.0, "factor_solve": 0.0}
@@ -302,7 +308,19 @@ class MFBackend:
 
     def prepare(self, req):
         t0 = time.perf_counter()
-        if req.rid in self.payloads:
+        # each preparation thread uploads on a stream of its own and waits for that
+        # stream alone, so it never waits for the cohorts running on the device
+        ps = getattr(self.tls, "stream", None)
+        if ps is None:
+            ps = self.tls.stream = self.torch.cuda.Stream(device=self.dev)
+        with self.torch.cuda.stream(ps):
+            return self._prepare_on(req, ps, t0)
+
+    def _prepare_on(self, req, ps, t0):
+        on_device = callable(self.payloads)
+        if on_device:
+            s, vals, rhs = self.payloads(req, self.dev)
+        elif req.rid in self.payloads:
             s, hv, hb = self.payloads[req.rid]
         else:
             from vivjac import newton_rhs, newton_values
@@ -322,10 +340,13 @@ class MFBackend:
                 raise
         sym, lf = fut.result()
         req.level_fronts = lf
-        vals = [self.torch.from_numpy(v).to(self.dev) for v in hv]
-        rhs = [self.torch.from_numpy(b).to(self.dev) for b in hb]
+        if not on_device:
+            vals = [self.torch.from_numpy(v).to(self.dev) for v in hv]
+            rhs = [self.torch.from_numpy(b).to(self.dev) for b in hb]
+        if len(vals) < req.newton_steps or len(rhs) < req.newton_steps:
+            raise ValueError(f"request {req.rid}: payload holds fewer than {req.newton_steps} Newton steps")
         xs = [self.torch.empty(s.n, dtype=self.torch.float64, device=self.dev) for _ in range(req.newton_steps)]
-        self.torch.cuda.synchronize(self.dev)
+        ps.synchronize()
         req.state = dict(system=s, sym=sym, vals=vals, rhs=rhs, xs=xs)
         with self.lock:
             self.times["prepare"] += time.perf_counter() - t0
@@ -370,9 +391,8 @@ class MFBackend:
             key = tuple(r.rid for r in members)
             live.add(key)
             futs.append(self.pool.submit(self._run_cohort, key, members, self.streams[i % len(self.streams)]))
-        for f in futs:
+        for f in futs:                 # each cohort waits for its own stream
             infos.update(f.result())
-        self.torch.cuda.synchronize()
         self.times["factor_solve"] += time.perf_counter() - t0 - (self.times["merge"] - merge0)
         for key in [k for k in self.batches if k not in live]:
             self.batches.pop(key).release()

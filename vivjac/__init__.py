@@ -15,5 +15,6 @@ global-master form, and the spring balance of Sec. 2 (eq. solid_balance).
 """
 from .gen2d import System, build_2d, newton_values, newton_rhs
 from .gen3d import build_3d, p2_tet
+from .parts import build_mesh, value_parts
 
-__all__ = ["System", "build_2d", "build_3d", "newton_values", "newton_rhs"]
+__all__ = ["System", "build_2d", "build_3d", "build_mesh", "value_parts", "newton_values", "newton_rhs"]
