@@ -425,6 +425,25 @@ def main():
         return dict(elapsed=elapsed, step_ms=step_ms, omegas=omegas, iters=iters, inner=inner, finfo=finfo,
                     t_factor=t_factor, t_sweep=t_sweep, steps=steps)
 
+    def run_reuse(prec, seq=None, repeats=2):
+        """The Newton sequence with one reduced-precision factorization kept as the
+        GMRES-IR preconditioner across steps (refreshed by the reuse policy)."""
+        from paper_2609_31477_amd.newton import ReusedFactorNewton
+        seq = vals if seq is None else seq
+        out = None
+        for rep in range(repeats):
+            solver = ReusedFactorNewton(S, prec=prec, target_omega=args.target_omega, stream=stream)
+            ms = []
+            for k in range(nsteps_newton):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info, rec = solver.step(seq[k], rhs[k], x=x)
+                torch.cuda.synchronize()
+                ms.append(1e3 * (time.perf_counter() - t0))
+            out = dict(step_ms=ms, history=solver.history)
+            solver.release()
+        return out
+
     main = run_path(args.prec)
     mixed = None if args.no_mixed or args.prec != "fp64" else run_path("fp32")
     eight = {}
@@ -535,6 +554,35 @@ def main():
                                  "frac": round(sch / PEAK[dtype], 5),
                                  "per_launch": f"sum over a level's fronts of 2 (m-P)^2 k flops; "
                                                f"{finfo.schur_flops / max(1, finfo.schur_launches):.3e} flops"}
+    if not args.no_extras and args.prec == "fp64" and not args.no_mixed:
+        ru = run_reuse("fp32")
+        tot = sum(ru["step_ms"])
+        res["reuse"] = {"workload": f"the {nsteps_newton} Newton steps once, FP32 factors kept as the FP64 GMRES-IR "
+                                    "preconditioner across steps (a reuse is capped at 20 GMRES iterations; "
+                                    "refresh after > 10, back-off after a failed reuse)",
+                        "ms_per_step": round(tot / nsteps_newton, 3),
+                        "speedup_vs_fp64": round(1e3 * elapsed / args.steps / (tot / nsteps_newton), 4),
+                        "steps": [{"ms": round(m, 3), "refactored": h.refactored, "retried": h.retried,
+                                   "inner": h.inner_iters, "omega": h.omega}
+                                  for m, h in zip(ru["step_ms"], ru["history"])]}
+        log(f"reuse: {json.dumps(res['reuse'])}")
+        # the same policy on Newton streams that change less per step (eps N(0,1)
+        # relative, drawn on the device): where reuse starts to pay
+        sens = {}
+        for eps in (1e-3, 1e-4):
+            g = torch.Generator(device=dev)
+            g.manual_seed(17)
+            seq = [vals[0]]
+            for k in range(1, nsteps_newton):
+                seq.append(seq[-1] * (1.0 + eps * torch.randn(s.nnz, generator=g, dtype=torch.float64, device=dev)))
+            r = run_reuse("fp32", seq)
+            t = sum(r["step_ms"]) / nsteps_newton
+            sens[f"{eps:g}"] = {"ms_per_step": round(t, 3), "speedup_vs_fp64": round(1e3 * elapsed / args.steps / t, 4),
+                                "refactored_steps": sum(h.refactored for h in r["history"]),
+                                "inner": [h.inner_iters for h in r["history"]],
+                                "omega_max": max(h.omega for h in r["history"])}
+        res["reuse"]["smaller_changes"] = sens
+        log(f"reuse with smaller changes per step: {json.dumps(sens)}")
     if not args.no_extras and args.prec == "fp64":
         gm = {}
         for pr in ("fp64", "fp32", "bf16"):

@@ -258,6 +258,36 @@ mf_status mf_solve(mf_num_t num, const double* b_dev, double* x_dev, int32_t nrh
                    void* stream, mf_solve_info* info);
 
 /*
+ * Replace the operator of a factored handle without factoring it again: later
+ * solves (mf_solve, mf_solve_batched) solve J' X = B for the new values J' (same
+ * pattern and CSR order as the factored values) by GMRES-IR, with the existing
+ * factors, of the earlier values and in their own precision, kept only as the
+ * preconditioner.  This is the iterative solver with a multifrontal
+ * preconditioner that the paper names as the way past its direct solver (Sec.
+ * 4.3, Sec. 7): here the preconditioner is a reduced-precision factorization
+ * reused across the Newton iterations of eq. NR_iteration (Sec. 3.4), whose
+ * Jacobian changes from one iteration to the next.
+ *   values_dev   device FP64, nnz entries (mf_set_operator) or one array per
+ *                system of a batch handle (mf_set_operator_batched); copied on
+ *                `stream`, which the call synchronizes
+ *   opt          NULL keeps the factorization's refinement settings; otherwise
+ *                its target_omega, max_outer, gmres_m, gmres_tol, fallback and
+ *                (if >= 0) refine replace them for the following solves (a cap
+ *                on the iterations a reuse may spend); other fields are ignored
+ * The refinement of a replaced operator is always the Krylov one (refine 1 is
+ * taken as GMRES-IR; refine 0 returns the preconditioner applied once): when
+ * GMRES-IR stops above the target, the fallback (if enabled) factors the new
+ * values in FP64.  The next mf_factor ends the reuse and restores its own
+ * options.  mf_solve_noalloc refuses a replaced operator.
+ * Errors: MF_ERR_STATE (no successful factorization), MF_ERR_ARG (null values,
+ * bad options, the wrong call for the handle's kind, or NaN / Inf in the values: the handle
+ * must then be factored again before it solves), MF_ERR_DEVICE, MF_ERR_OOM.
+ */
+mf_status mf_set_operator(mf_num_t num, const double* values_dev, const mf_options* opt, void* stream);
+mf_status mf_set_operator_batched(mf_num_t num, const double* const* values_dev, const mf_options* opt,
+                                  void* stream);
+
+/*
  * mf_solve without any device or pinned-host allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, layout and result as mf_solve with the

@@ -28,7 +28,8 @@ PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
 # every entry point declared in include/mf.h
 EXPORTS = ["mf_default_options", "mf_analyze", "mf_symbolic_export", "mf_factor", "mf_get_factor_info",
            "mf_solve", "mf_batch_analyze", "mf_factor_batched", "mf_solve_batched", "mf_footprint_bytes",
-           "mf_debug_front", "mf_release", "mf_last_error", "mf_solve_noalloc"]
+           "mf_debug_front", "mf_release", "mf_last_error", "mf_solve_noalloc", "mf_set_operator",
+           "mf_set_operator_batched"]
 
 
 class mf_options(ctypes.Structure):
@@ -99,6 +100,10 @@ def lib():
         L.mf_solve_noalloc.argtypes = [ctypes.c_void_p, P, P, ctypes.c_int32, ctypes.c_int64, P,
                                        ctypes.POINTER(mf_solve_info)]
         L.mf_solve_noalloc.restype = ctypes.c_int
+        L.mf_set_operator.argtypes = [ctypes.c_void_p, P, ctypes.POINTER(mf_options), P]
+        L.mf_set_operator.restype = ctypes.c_int
+        L.mf_set_operator_batched.argtypes = [ctypes.c_void_p, P, ctypes.POINTER(mf_options), P]
+        L.mf_set_operator_batched.restype = ctypes.c_int
         L.mf_footprint_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(mf_options), ctypes.c_double]
         L.mf_footprint_bytes.restype = ctypes.c_int64
         L.mf_batch_analyze.argtypes = [ctypes.c_int32, P, ctypes.POINTER(ctypes.c_void_p)]
@@ -246,6 +251,7 @@ class Numeric:
         if values.numel() != sym.nnz or not values.is_contiguous():
             raise ValueError("values must be contiguous with nnz entries")
         num = numeric if numeric is not None else cls(sym)
+        num._opts = dict(opts)
         o = default_options(leaf_max=sym.options.leaf_max, **opts) if opts else None
         st = lib().mf_factor(sym._h, ctypes.c_void_p(values.data_ptr()), ctypes.byref(o) if o is not None else None,
                              _stream_ptr(stream), ctypes.byref(num._h))
@@ -256,6 +262,37 @@ class Numeric:
         inf = mf_factor_info()
         _check(lib().mf_get_factor_info(self._h, ctypes.byref(inf)))
         return inf
+
+    def set_operator(self, values, stream=None, **refine_opts):
+        """mf_set_operator: later solves use these values (same pattern) as the
+        operator and the current factors as the preconditioner; refine_opts
+        (target_omega, max_outer, gmres_m, gmres_tol, fallback, refine) replace the
+        factorization's refinement settings for those solves."""
+        import torch
+        if not (isinstance(values, torch.Tensor) and values.is_cuda and values.dtype == torch.float64):
+            raise TypeError("values must be a float64 CUDA tensor")
+        if values.numel() != self.sym.nnz or not values.is_contiguous():
+            raise ValueError("values must be contiguous with nnz entries")
+        o = self._refine_options(refine_opts, getattr(self, "_opts", {}))
+        _check(lib().mf_set_operator(self._h, ctypes.c_void_p(values.data_ptr()),
+                                     ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+        return self
+
+    _REFINE_KEYS = ("target_omega", "max_outer", "gmres_m", "gmres_tol", "fallback", "refine")
+
+    @staticmethod
+    def _refine_options(kw, factor_opts):
+        """The refinement fields of an mf_options for mf_set_operator: the given
+        ones, the rest as the last factorization set them (or the defaults)."""
+        bad = set(kw) - set(Numeric._REFINE_KEYS)
+        if bad:
+            raise TypeError(f"set_operator takes only refinement options, not {sorted(bad)}")
+        if not kw:
+            return None
+        full = {k: factor_opts[k] for k in Numeric._REFINE_KEYS if k in factor_opts}
+        full.update(kw)
+        full.setdefault("refine", -1)
+        return default_options(**full)
 
     def solve(self, b, x=None, stream=None, check=True):
         """b: float64 CUDA tensor (n,) or (nrhs, n) -- row r is right-hand side r
@@ -348,6 +385,7 @@ class Batch:
                     and v.numel() == nz):
                 raise TypeError("values[i] must be a contiguous float64 CUDA tensor with nnz_i entries")
         ptrs = (ctypes.c_void_p * len(values))(*[v.data_ptr() for v in values])
+        self._opts = dict(opts)
         o = default_options(leaf_max=self.syms[0].options.leaf_max, **opts) if opts else None
         _check(lib().mf_factor_batched(self._h, ctypes.cast(ptrs, ctypes.c_void_p),
                                        ctypes.byref(o) if o is not None else None, _stream_ptr(stream),
@@ -358,6 +396,21 @@ class Batch:
         inf = mf_factor_info()
         _check(lib().mf_get_factor_info(self._num, ctypes.byref(inf)))
         return inf
+
+    def set_operator(self, values, stream=None, **refine_opts):
+        """mf_set_operator_batched: one float64 CUDA tensor per system (nnz_i entries)."""
+        import torch
+        if len(values) != len(self.syms):
+            raise ValueError("one values tensor per system")
+        for v, nz in zip(values, self.nnzs):
+            if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+                    and v.numel() == nz):
+                raise TypeError("values[i] must be a contiguous float64 CUDA tensor with nnz_i entries")
+        ptrs = (ctypes.c_void_p * len(values))(*[v.data_ptr() for v in values])
+        o = Numeric._refine_options(refine_opts, getattr(self, "_opts", {}))
+        _check(lib().mf_set_operator_batched(self._num, ctypes.cast(ptrs, ctypes.c_void_p),
+                                             ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+        return self
 
     def solve(self, bs, xs=None, stream=None, check=True):
         """bs: list of float64 CUDA tensors, system i's shaped (n_i,) or (nrhs_i, n_i);

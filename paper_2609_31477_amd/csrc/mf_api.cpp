@@ -235,6 +235,7 @@ struct mf_num {
     int32_t* d_ones = nullptr;              // nseg ones: every system active
     int ones_cap = 0;
     bool factored = false;
+    bool stale = false;        // operator values replaced since the factorization (mf_set_operator)
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
     std::vector<std::array<int32_t, kNClass>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
     // equilibration: factors are of Dr J Dc (powers of two); residuals use J itself
@@ -702,18 +703,11 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     return true;
 }
 
-void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double* const* seg_values = nullptr) {
-    N->sweep.valid = false;
-    mf_sym* H = N->sym;
-    const Symbolic& S = H->S;
-    ensure_device_symbolic(H);
-    SymDev& D = *H->dev;
-    const int nf = S.nf;
-    const mf_options& o = N->opt;
-    if (!N->d_fn) {
-        HIPX(hipMalloc((void**)&N->d_fn, sizeof(FrontNum) * std::max(nf, 1)));
-        HIPX(hipHostMalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
-    }
+// The handle's own copy of the operator values (one array, or one per system of a
+// batch), scanned for NaN and Inf; the scan's result is read back by the next
+// synchronization on the stream (check_finite).
+void load_values(mf_num* N, const double* values_dev, const double* const* seg_values, hipStream_t st) {
+    const Symbolic& S = N->sym->S;
     if (!N->d_vals) HIPX(hipMalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
     if (!N->d_bad) {
         HIPX(hipMalloc((void**)&N->d_bad, sizeof(unsigned long long)));
@@ -730,6 +724,22 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     }
     HIPX(launch_nonfinite(N->d_vals, S.nnz, N->d_bad, st));
     HIPX(hipMemcpyAsync(N->h_bad, N->d_bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+}
+
+void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double* const* seg_values = nullptr) {
+    N->sweep.valid = false;
+    mf_sym* H = N->sym;
+    const Symbolic& S = H->S;
+    ensure_device_symbolic(H);
+    SymDev& D = *H->dev;
+    const int nf = S.nf;
+    const mf_options& o = N->opt;
+    if (!N->d_fn) {
+        HIPX(hipMalloc((void**)&N->d_fn, sizeof(FrontNum) * std::max(nf, 1)));
+        HIPX(hipHostMalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
+    }
+    load_values(N, values_dev, seg_values, st);
+    N->stale = false;
     // equilibration (values only: the pattern and the analysis are unchanged)
     const double* fvals = N->d_vals;
     N->scaled = o.scale > 0 && S.n > 0;
@@ -1502,15 +1512,18 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
         si.delayed_pivots = q < (int)N->seg_delayed.size() ? N->seg_delayed[q] : 0;
     }
     std::vector<char> active((size_t)nseg * nrhs);
+    // with a replaced operator the factors are only a preconditioner: plain
+    // refinement may diverge, so the correction is always the Krylov one
+    const int refine = (N->stale && o.refine > 0) ? 2 : o.refine;
     int it = 0;
-    while (o.refine > 0 && it < o.max_outer) {
+    while (refine > 0 && it < o.max_outer) {
         bool any = false;
         for (size_t q = 0; q < active.size(); q++) {
             active[q] = !(om[q] <= o.target_omega);
             any = any || active[q];
         }
         if (!any) break;
-        if (o.refine == 1) {
+        if (refine == 1) {
             apply_inverse(N, r, n, dv, n, nrhs, st);
         } else {
             const int mres = std::max(1, std::min(o.gmres_m, 200));
@@ -1548,7 +1561,7 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
         inf.delayed_pivots += N->seg_info[q].delayed_pivots;
     }
     if (info) *info = inf;
-    if (!(inf.omega <= o.target_omega) && o.refine > 0)
+    if (!(inf.omega <= o.target_omega) && refine > 0)
         throw Fail{MF_ERR_NOT_CONVERGED, "refinement stopped at omega = " + std::to_string(inf.omega)};
 }
 
@@ -1561,7 +1574,7 @@ void solve_with_fallback(mf_num* N, const double* b, double* x, int nrhs, int64_
         do_solve(N, b, x, nrhs, ld, st, info);
         return;
     } catch (const Fail& f) {
-        if (f.st != MF_ERR_NOT_CONVERGED || !N->opt.fallback || N->opt.prec == MF_FP64) throw;
+        if (f.st != MF_ERR_NOT_CONVERGED || !N->opt.fallback || (N->opt.prec == MF_FP64 && !N->stale)) throw;
     }
     N->opt.prec = MF_FP64;
     N->opt.refine = 1;
@@ -1756,6 +1769,54 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
     return MF_OK;
 }
 
+static mf_status set_operator_common(mf_num_t N, const double* values_dev, const double* const* seg_values,
+                                     const mf_options* opt, void* stream) {
+    if (!N || N->magic != kNumMagic) return fail(MF_ERR_ARG, "bad numeric handle");
+    if (!N->factored) return fail(MF_ERR_STATE, "mf_set_operator before a successful factorization");
+    const Symbolic& S = N->sym->S;
+    const bool batch = S.seg_n.size() > 1;
+    if (batch != (seg_values != nullptr))
+        return fail(MF_ERR_ARG, batch ? "a batch handle takes mf_set_operator_batched"
+                                      : "a single-system handle takes mf_set_operator");
+    if (!seg_values && !values_dev && S.nnz > 0) return fail(MF_ERR_ARG, "values_dev is null");
+    if (seg_values)
+        for (size_t q = 0; q < S.seg_n.size(); q++)
+            if (!seg_values[q] && S.seg_n[q] > 0) return fail(MF_ERR_ARG, "values_dev[i] is null");
+    if (opt) {
+        if (!(opt->target_omega > 0.0) || opt->max_outer < 0 || opt->gmres_m < 1 || !(opt->gmres_tol >= 0.0))
+            return fail(MF_ERR_ARG, "bad refinement options");
+        N->opt.target_omega = opt->target_omega;
+        N->opt.max_outer = opt->max_outer;
+        N->opt.gmres_m = opt->gmres_m;
+        N->opt.gmres_tol = opt->gmres_tol;
+        N->opt.fallback = opt->fallback;
+        if (opt->refine >= 0) N->opt.refine = opt->refine;
+    }
+    try {
+        const hipStream_t st = (hipStream_t)stream;
+        load_values(N, values_dev, seg_values, st);
+        HIPX(hipStreamSynchronize(st));
+        N->stale = true;
+        check_finite(N);
+    } catch (const Fail& f) {
+        N->factored = false;  // the operator copy is unusable: factor again before solving
+        return fail(f.st, f.msg);
+    } catch (const std::bad_alloc&) {
+        N->factored = false;
+        return fail(MF_ERR_OOM, "host allocation failed in mf_set_operator");
+    }
+    return MF_OK;
+}
+
+mf_status mf_set_operator(mf_num_t N, const double* values_dev, const mf_options* opt, void* stream) {
+    return set_operator_common(N, values_dev, nullptr, opt, stream);
+}
+
+mf_status mf_set_operator_batched(mf_num_t N, const double* const* values_dev, const mf_options* opt, void* stream) {
+    if (!values_dev) return fail(MF_ERR_ARG, "values_dev is null");
+    return set_operator_common(N, nullptr, values_dev, opt, stream);
+}
+
 // ---------------------------------------------------------------- no-allocation solve
 // Callers that cannot allocate (graph capture, tight serving loops) get the solve's
 // scratch from one statically sized device array per GPU instead of the handle's
@@ -1838,9 +1899,9 @@ mf_status mf_solve_noalloc(mf_num_t N, const double* b_dev, double* x_dev, int32
     }
     if (ld < n) return fail(MF_ERR_ARG, "ld < n");
     if (!b_dev || !x_dev || b_dev == x_dev) return fail(MF_ERR_ARG, "b_dev and x_dev must be distinct device buffers");
-    if (N->opt.refine > 1)
-        return fail(MF_ERR_ARG, "mf_solve_noalloc refines with FP64 iterative refinement only (refine 0 or 1): "
-                                "GMRES-IR needs its Krylov basis; use mf_solve");
+    if (N->opt.refine > 1 || (N->stale && N->opt.refine > 0))
+        return fail(MF_ERR_ARG, "mf_solve_noalloc refines with FP64 iterative refinement only (refine 0 or 1, "
+                                "operator not replaced): GMRES-IR needs its Krylov basis; use mf_solve");
     const int nseg = (int)S.seg_n.size();
     const int cnt = nseg * nrhs;
     if (cnt > kScratchMaxCounts) return fail(MF_ERR_ARG, "too many (system, right-hand side) pairs for mf_solve_noalloc");
