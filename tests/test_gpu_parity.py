@@ -349,3 +349,26 @@ def test_persistent_sweeps_match_level_sweeps_256x128(torch_cuda, prec, nrhs):
     for c in range(nrhs):
         assert check.omega_fast(A, X[c], np.atleast_2d(B)[c]) <= target
     num.release()
+
+
+@pytest.mark.parametrize("prec,variant", [
+    ("fp64", dict(position="p1")),
+    ("fp64", dict(lame="radial")),
+    ("fp64", dict(scheme="bdf2", hole="circle")),
+    ("fp64", dict(coupling="accumulator")),
+    ("fp32", dict(position="p1", lame="radial", scheme="bdf2", hole="circle", coupling="accumulator")),
+])
+def test_generator_variants(torch_cuda, prec, variant):
+    """The paper-faithful generator variants (linear position, radial Lame law,
+    BDF2, circular hole, force-accumulator root) against the oracle."""
+    s = build_2d(32, 16, 11, **variant)
+    B = s.b0[0]
+    target = OMEGA_TOL if prec == "fp64" else MIXED_OMEGA
+    X, info, num = gpu_solve(torch_cuda, s.n, s.rowptr, s.colind, s.values, s.root, B, prec=prec,
+                             target_omega=target)
+    fi = num.info()
+    print(f"{prec} {variant}: n={s.n} root={fi.root_order} delayed={fi.delayed_pivots} "
+          f"omega={info.omega:.2e} outer={info.outer_iters} inner={info.inner_iters}", flush=True)
+    Xo = oracle_solve(s.n, s.rowptr, s.colind, s.values, s.root, B)
+    assert_parity(s.to_scipy(), X, Xo, B, omega_tol=target, rel_tol=1e-8 if prec == "fp64" else 1e-6)
+    assert fi.root_order >= len(s.root)

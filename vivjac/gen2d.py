@@ -130,11 +130,108 @@ def _vector_block_rows(dofmap, nodes):
     return g.reshape(nodes.shape[0], -1)
 
 
+def p1_elasticity(invT, lam_int):
+    """Pseudo-solid element matrices of affine P1 triangles, (E, 3, 2, 3, 2) in
+    (node i, component a, node j, component b): lam_int * (d_a phi_i d_b phi_j +
+    delta_ab grad phi_i . grad phi_j + d_b phi_i d_a phi_j), the bilinear form of
+    lambda_s div div + 2 mu_s eps:eps with lambda_s = mu_s, whose integral over the
+    element is lam_int (the gradients are constant)."""
+    gref = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])
+    G = np.einsum("eab,ib->eia", invT, gref)                   # (E,3,2)
+    D = G[:, :, :, None, None] * G[:, None, None, :, :]        # d_a phi_i d_b phi_j
+    K = np.einsum("eia,eja->eij", G, G)
+    eye2 = np.eye(2)
+    A = D + K[:, :, None, :, None] * eye2[None, None, :, None, :] + np.transpose(D, (0, 1, 4, 3, 2))
+    return lam_int[:, None, None, None, None] * A
+
+
+def circle_map(X, Y, xc, yc, ax, by, blend=2.0):
+    """Move the lattice nodes around the rectangular hole [xc-ax, xc+ax] x [yc-by,
+    yc+by] so that its boundary lies on the ellipse of half-axes (ax, by) (a circle
+    when ax = by).  In normalised coordinates q = ((X-xc)/ax, (Y-yc)/by), the square
+    of radius s = max|q_i| is pulled toward the circle of radius s by the weight
+    w = (blend - s) / (blend - 1) on 1 <= s <= blend; nodes with s >= blend stay."""
+    qx, qy = (X - xc) / ax, (Y - yc) / by
+    s = np.maximum(np.abs(qx), np.abs(qy))
+    r = np.hypot(qx, qy)
+    w = np.clip((blend - s) / (blend - 1.0), 0.0, 1.0)
+    f = np.where(r > 0, (1.0 - w) + w * s / np.where(r > 0, r, 1.0), 1.0)
+    return xc + ax * qx * f, yc + by * qy * f
+
+
+def radial_lame(x, y, center, diameter):
+    """The paper's radial Lame distribution lambda_s = mu_s (Sec. 6, "Lame
+    coefficients"), read as printed: (r - (D/2)^2)^-2, r = distance to the centre."""
+    return (np.hypot(x - center[0], y - center[1]) - (diameter / 2) ** 2) ** -2.0
+
+
+def pseudo_solid_blocks(X, Y, tri, position, lame, center, diameter):
+    """Element matrices of the pseudo-solid block, (E, nl, 2, nl, 2) with nl = 3
+    (P1 position) or 6 (P2): lambda_s div div + 2 mu_s eps:eps with lambda_s = mu_s
+    equal to 1/|K| ("inv_area") or radial_lame ("radial"), integrated with the
+    7-point rule.  The P2 / inv_area combination is assembled inline by build_2d
+    (same matrices; kept there so the configured construction stays bitwise)."""
+    V = tri[:, :3]
+    x0, y0 = X[V[:, 0]], Y[V[:, 0]]
+    Jm = np.empty((tri.shape[0], 2, 2))
+    Jm[:, 0, 0] = X[V[:, 1]] - x0
+    Jm[:, 0, 1] = X[V[:, 2]] - x0
+    Jm[:, 1, 0] = Y[V[:, 1]] - y0
+    Jm[:, 1, 1] = Y[V[:, 2]] - y0
+    det = Jm[:, 0, 0] * Jm[:, 1, 1] - Jm[:, 0, 1] * Jm[:, 1, 0]
+    invT = np.empty_like(Jm)
+    invT[:, 0, 0] = Jm[:, 1, 1] / det
+    invT[:, 0, 1] = -Jm[:, 1, 0] / det
+    invT[:, 1, 0] = -Jm[:, 0, 1] / det
+    invT[:, 1, 1] = Jm[:, 0, 0] / det
+    qp, qw = radon7()
+    phi, gref, Lq = p2_tri(qp)
+    W = qw[None, :] * np.abs(det)[:, None]
+    if lame == "radial":
+        lamW = W * radial_lame(Lq @ X[V].T, Lq @ Y[V].T, center, diameter).T   # (E,Q)
+    else:
+        lamW = W / (0.5 * np.abs(det))[:, None]
+    if position == "p1":
+        return p1_elasticity(invT, lamW.sum(1))
+    G = np.einsum("eab,qib->eqia", invT, gref)
+    Dl = np.einsum("eq,eqia,eqjb->eiajb", lamW, G, G)
+    Kl = np.einsum("eq,eqia,eqja->eij", lamW, G, G)
+    eye2 = np.eye(2)
+    return Dl + Kl[:, :, None, :, None] * eye2[None, None, :, None, :] + np.transpose(Dl, (0, 1, 4, 3, 2))
+
+
+VARIANTS = {"position": ("p2", "p1"), "lame": ("inv_area", "radial"), "scheme": ("bdf1", "bdf2"),
+            "hole": ("square", "circle"), "coupling": ("master", "accumulator")}
+
+
 def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
-             alpha0: float = 100.0, nrhs: int = 1, Lx: float = 4.0, Ly: float = 2.0) -> System:
-    """Assemble the coupled Jacobian on an nx x ny mesh (nx, ny even)."""
+             alpha0: float = 100.0, nrhs: int = 1, Lx: float = 4.0, Ly: float = 2.0,
+             position: str = "p2", lame: str = "inv_area", scheme: str = "bdf1", hole: str = "square",
+             coupling: str = "master") -> System:
+    """Assemble the coupled Jacobian on an nx x ny mesh (nx, ny even).
+
+    Variants (defaults first; the defaults are the configured construction):
+      position  "p2" | "p1": mesh displacement on the P2 nodes, or linear on the
+                vertices as the paper discretizes the position (Sec. 3.3)
+      lame      "inv_area" | "radial": lambda_s = mu_s = 1/|K| per element, or the
+                paper's radial distribution of Sec. 6 ("Lame coefficients"), read
+                as printed, (r - (D/2)^2)^-2 with r the distance to the hole's
+                centre, evaluated at the quadrature points
+      scheme    "bdf1" | "bdf2": alpha0 is 1/dt; BDF2 scales the time-derivative
+                coefficient (mass block and the multiplier rows' s term) by 3/2
+      hole      "square" | "circle": the cell-aligned square hole, or the same
+                lattice mapped so that the hole boundary is a circle (circle_map)
+      coupling  "master" | "accumulator": s rows k s_c + sum_j m_j lambda_j,c = 0,
+                or two force-accumulator dofs F_c = sum_j m_j lambda_j,c with
+                k s_c + F_c = 0 (Sec. 4.2, global position master to global force
+                accumulator); the root then holds s and F."""
     if nx < 4 or ny < 4 or nx % 2 or ny % 2:
         raise ValueError("nx, ny must be even and >= 4")
+    for key, val in (("position", position), ("lame", lame), ("scheme", scheme), ("hole", hole),
+                     ("coupling", coupling)):
+        if val not in VARIANTS[key]:
+            raise ValueError(f"{key} must be one of {VARIANTS[key]}")
+    a_t = alpha0 * (1.5 if scheme == "bdf2" else 1.0)     # time-derivative coefficient
     hx, hy = Lx / nx, Ly / ny
     NX, NY = 2 * nx + 1, 2 * ny + 1
     a = max(1, nx // 16)
@@ -192,6 +289,8 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
     d_keep = np.ones((nn, 2), dtype=bool)
     d_keep[inlet | outlet, :] = False
     d_keep[wall, 1] = False
+    if position == "p1":
+        d_keep[~vert_mask, :] = False                  # linear position: vertices only
     d_dof = -np.ones((nn, 2), dtype=np.int64)
     d_dof[d_keep] = np.arange(int(d_keep.sum())) + nxt
     blocks["d"] = (nxt, nxt + int(d_keep.sum()))
@@ -203,11 +302,24 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
     nxt += 2 * g_nodes.size
     s_dof = np.array([nxt, nxt + 1])
     blocks["s"] = (nxt, nxt + 2)
-    n = nxt + 2
+    nxt += 2
+    f_dof = None
+    if coupling == "accumulator":
+        f_dof = np.array([nxt, nxt + 1])
+        blocks["F"] = (nxt, nxt + 2)
+        nxt += 2
+    n = nxt
 
     # ---- geometry (affine triangles)
     X = nI * (hx / 2)
     Y = nJ * (hy / 2)
+    xc, yc, ax, by = 0.5 * (i0 + i1) * hx, 0.5 * (j0 + j1) * hy, a * hx, b * hy
+    if hole == "circle":
+        X, Y = circle_map(X, Y, xc, yc, ax, by)
+        # affine P2 elements: the edge nodes sit at the straight edges' midpoints
+        for e, (va, vb) in enumerate([(0, 1), (1, 2), (2, 0)]):
+            X[tri[:, 3 + e]] = 0.5 * (X[tri[:, va]] + X[tri[:, vb]])
+            Y[tri[:, 3 + e]] = 0.5 * (Y[tri[:, va]] + Y[tri[:, vb]])
     x0, y0 = X[tri[:, 0]], Y[tri[:, 0]]
     Jm = np.empty((E, 2, 2))
     Jm[:, 0, 0] = X[tri[:, 1]] - x0
@@ -215,6 +327,8 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
     Jm[:, 1, 0] = Y[tri[:, 1]] - y0
     Jm[:, 1, 1] = Y[tri[:, 2]] - y0
     det = Jm[:, 0, 0] * Jm[:, 1, 1] - Jm[:, 0, 1] * Jm[:, 1, 0]
+    if not (det > 0).all():
+        raise AssertionError("inverted or degenerate triangle")
     area = 0.5 * np.abs(det)
     invT = np.empty((E, 2, 2))                          # J^{-T}
     invT[:, 0, 0] = Jm[:, 1, 1] / det
@@ -241,23 +355,29 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
 
     eye2 = np.eye(2)
     # velocity block, local (i,c),(j,c'):
-    Avel = (alpha0 * M + C)[:, :, None, :, None] * eye2[None, None, :, None, :]
+    Avel = (a_t * M + C)[:, :, None, :, None] * eye2[None, None, :, None, :]
     Avel = Avel + nu * (K[:, :, None, :, None] * eye2[None, None, :, None, :]
                         + np.transpose(D, (0, 1, 4, 3, 2)))
-    # pseudo-solid with lam_s = mu_s = 1/|K|
-    lam_s = (1.0 / area)[:, None, None, None, None]
-    Ad = lam_s * (D + K[:, :, None, :, None] * eye2[None, None, :, None, :]
-                  + np.transpose(D, (0, 1, 4, 3, 2)))
+    # pseudo-solid
+    if position == "p2" and lame == "inv_area":
+        # lam_s = mu_s = 1/|K|
+        lam_s = (1.0 / area)[:, None, None, None, None]
+        Ad = lam_s * (D + K[:, :, None, :, None] * eye2[None, None, :, None, :]
+                      + np.transpose(D, (0, 1, 4, 3, 2)))
+    else:
+        Ad = pseudo_solid_blocks(X, Y, tri, position, lame, (xc, yc), ax + by)
 
     T = _Triplets()
     ur = _vector_block_rows(u_dof, tri)                 # (E,12)
-    dr = _vector_block_rows(d_dof, tri)
+    dloc = tri[:, :3] if position == "p1" else tri
+    dr = _vector_block_rows(d_dof, dloc)
     T.add(ur[:, :, None], ur[:, None, :], Avel.reshape(E, 12, 12))
     pr = p_dof[tri_p]                                   # (E,3)
     Bflat = Bq.reshape(E, 3, 12)
     T.add(pr[:, :, None], ur[:, None, :], Bflat)                     # p rows
     T.add(ur[:, :, None], pr[:, None, :], np.transpose(Bflat, (0, 2, 1)))  # u rows
-    T.add(dr[:, :, None], dr[:, None, :], Ad.reshape(E, 12, 12))
+    nd = 2 * dloc.shape[1]
+    T.add(dr[:, :, None], dr[:, None, :], Ad.reshape(E, nd, nd))
 
     # ---- Gamma edges (hole perimeter), nodes (end, end, mid)
     edges = []
@@ -271,6 +391,8 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
     m_int = np.zeros(nn)
     for (pa, pb, pm, Le) in edges:
         en = np.array([node_of[pa[0] * NY + pa[1]], node_of[pb[0] * NY + pb[1]], node_of[pm[0] * NY + pm[1]]])
+        if hole == "circle":                            # straight edge between the mapped ends
+            Le = float(np.hypot(X[en[1]] - X[en[0]], Y[en[1]] - Y[en[0]]))
         Me = Le * Me_ref
         m_int[en] += Le * np.array([1 / 6, 1 / 6, 2 / 3])
         for c in range(2):
@@ -279,17 +401,23 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
             T.add(uu[:, None], ll[None, :], -Me)        # -<v, lambda>
             T.add(ll[:, None], uu[None, :], -Me)        # -<mu, u>
     gl = g_nodes
+    gd = gl[d_dof[gl, 0] >= 0]                          # Gamma nodes carrying position dofs
     R = _Triplets()                                     # rows that replace the Gamma d rows
     for c in range(2):
-        T.add(lam_dof[gl, c], s_dof[c], alpha0 * m_int[gl])   # +alpha0 <mu,1> s_c
-        T.add(s_dof[c], lam_dof[gl, c], m_int[gl])            # spring row: sum m_j lambda_j
+        T.add(lam_dof[gl, c], s_dof[c], a_t * m_int[gl])      # +alpha0 <mu,1> s_c
         T.add(s_dof[c], s_dof[c], k)
+        if f_dof is None:
+            T.add(s_dof[c], lam_dof[gl, c], m_int[gl])        # spring row: sum m_j lambda_j
+        else:
+            T.add(s_dof[c], f_dof[c], 1.0)                    # spring row: k s_c + F_c
+            T.add(f_dof[c], f_dof[c], 1.0)                    # accumulator: F_c - sum m_j lambda_j
+            T.add(f_dof[c], lam_dof[gl, c], -m_int[gl])
         # position masters: d_{i,c} - s_c = 0 replaces the Gamma displacement rows
-        R.add(d_dof[gl, c], d_dof[gl, c], 1.0)
-        R.add(d_dof[gl, c], s_dof[c], -1.0)
+        R.add(d_dof[gd, c], d_dof[gd, c], 1.0)
+        R.add(d_dof[gd, c], s_dof[c], -1.0)
 
     drop = np.zeros(n, dtype=bool)
-    drop[d_dof[gl].ravel()] = True
+    drop[d_dof[gd].ravel()] = True
     rr = np.concatenate(T.r)
     T.r, T.c, T.v = [np.where(drop[np.maximum(rr, 0)], -1, rr).astype(np.int32)] + R.r, \
         [np.concatenate(T.c)] + R.c, [np.concatenate(T.v)] + R.v
@@ -298,9 +426,13 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
 
     meta = dict(dim=2, nx=nx, ny=ny, seed=seed, k=k, nu=nu, alpha0=alpha0,
                 hole=(i0, i1, j0, j1), n_nodes=nn, n_vertices=nv, n_gamma_nodes=int(gl.size),
-                gamma_length=float(m_int.sum()))
+                gamma_length=float(m_int.sum()), fluid_area=float(area.sum()),
+                variant=dict(position=position, lame=lame, scheme=scheme, hole=hole, coupling=coupling),
+                time_coefficient=a_t, hole_center=(xc, yc), hole_half_widths=(ax, by),
+                mesh=dict(X=X, Y=Y, tri=tri, gamma_nodes=gl, vertex=vert_mask))
+    root = s_dof if f_dof is None else np.concatenate([s_dof, f_dof])
     return System(n=n, rowptr=A.indptr.astype(np.int64), colind=A.indices.astype(np.int32),
-                  values=A.data.astype(np.float64), root=s_dof.astype(np.int32),
+                  values=A.data.astype(np.float64), root=root.astype(np.int32),
                   blocks=blocks, meta=meta, b0=b0)
 
 
