@@ -19,4 +19,8 @@ Parts:
   paper hands to its direct solver (Sec. 4.3).
 * ``oracle.check`` -- independent checks used to pin the above: dense LU with
   partial pivoting, exact rational elimination, backward-error measures.
+* ``oracle.ale``   -- the full ALE Newton residual NL(U) of the paper (Sec.
+  3.1-3.2) on the 2D construction and its Jacobian by complex-step
+  differentiation of each element's residual (shape-derivative blocks
+  included), for the GPU element assembly.
 """

@@ -130,6 +130,79 @@ def _vector_block_rows(dofmap, nodes):
     return g.reshape(nodes.shape[0], -1)
 
 
+def mesh_2d(nx: int, ny: int, Lx: float = 4.0, Ly: float = 2.0) -> dict:
+    """The structured triangulation of the 2D construction: nx x ny cells of
+    [0,Lx]x[0,Ly] minus the hole cells [nx/2-a, nx/2+a) x [ny/2-b, ny/2+b)
+    (a = max(1, nx//16), b = max(1, ny//8)), each cell split along its
+    (i,j)->(i+1,j+1) diagonal into T1 = (00, 10, 11) and T2 = (00, 11, 01)
+    (counter-clockwise).  P2 nodes are the half-cell lattice points of fluid
+    cells, numbered in lexicographic (ix, iy) order; ``tri`` lists each
+    triangle's vertices then its edge midpoints (0,1), (1,2), (2,0)."""
+    hx, hy = Lx / nx, Ly / ny
+    NX, NY = 2 * nx + 1, 2 * ny + 1
+    a = max(1, nx // 16)
+    b = max(1, ny // 8)
+    i0, i1 = nx // 2 - a, nx // 2 + a
+    j0, j1 = ny // 2 - b, ny // 2 + b
+
+    # fluid cells and triangles (lattice coordinates)
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    ci, cj = ci.ravel(), cj.ravel()
+    fluid = ~((ci >= i0) & (ci < i1) & (cj >= j0) & (cj < j1))
+    ci, cj = ci[fluid], cj[fluid]
+    I0, J0 = 2 * ci, 2 * cj
+    # T1 = (00, 10, 11), T2 = (00, 11, 01)
+    vI = np.concatenate([np.stack([I0, I0 + 2, I0 + 2], 1), np.stack([I0, I0 + 2, I0], 1)])
+    vJ = np.concatenate([np.stack([J0, J0, J0 + 2], 1), np.stack([J0, J0 + 2, J0 + 2], 1)])
+    E = vI.shape[0]
+    mI = np.stack([(vI[:, 0] + vI[:, 1]) // 2, (vI[:, 1] + vI[:, 2]) // 2, (vI[:, 2] + vI[:, 0]) // 2], 1)
+    mJ = np.stack([(vJ[:, 0] + vJ[:, 1]) // 2, (vJ[:, 1] + vJ[:, 2]) // 2, (vJ[:, 2] + vJ[:, 0]) // 2], 1)
+    LI = np.concatenate([vI, mI], 1)
+    LJ = np.concatenate([vJ, mJ], 1)
+
+    used = np.zeros(NX * NY, dtype=bool)
+    used[(LI * NY + LJ).ravel()] = True
+    node_of = -np.ones(NX * NY, dtype=np.int64)
+    node_lat = np.flatnonzero(used)                    # lexicographic in (ix, iy)
+    node_of[node_lat] = np.arange(node_lat.size)
+    nn = node_lat.size
+    nI, nJ = node_lat // NY, node_lat % NY
+    tri = node_of[LI * NY + LJ]                        # (E, 6)
+
+    vert_mask = (nI % 2 == 0) & (nJ % 2 == 0)
+    vert_of = -np.ones(nn, dtype=np.int64)
+    vert_of[vert_mask] = np.arange(int(vert_mask.sum()))
+    nv = int(vert_mask.sum())
+    tri_p = vert_of[tri[:, :3]]
+
+    inlet = nI == 0
+    outlet = nI == NX - 1
+    wall = (nJ == 0) | (nJ == NY - 1)
+    on_gamma = (nI >= 2 * i0) & (nI <= 2 * i1) & (nJ >= 2 * j0) & (nJ <= 2 * j1)
+
+    return dict(hx=hx, hy=hy, NX=NX, NY=NY, a=a, b=b, hole=(i0, i1, j0, j1), E=E, tri=tri, node_of=node_of,
+                nn=nn, nI=nI, nJ=nJ, vert_mask=vert_mask, vert_of=vert_of, nv=nv, tri_p=tri_p, inlet=inlet,
+                outlet=outlet, wall=wall, on_gamma=on_gamma)
+
+
+def gamma_edges(m: dict):
+    """Edges of the hole boundary as (end node, end node, midpoint node), in the
+    order the 2D construction assembles them: bottom/top rows of the hole first,
+    then its left/right columns."""
+    i0, i1, j0, j1 = m["hole"]
+    NY, node_of = m["NY"], m["node_of"]
+    out = []
+    for i in range(i0, i1):
+        for jj in (j0, j1):
+            out.append((node_of[2 * i * NY + 2 * jj], node_of[(2 * i + 2) * NY + 2 * jj],
+                        node_of[(2 * i + 1) * NY + 2 * jj]))
+    for j in range(j0, j1):
+        for ii in (i0, i1):
+            out.append((node_of[2 * ii * NY + 2 * j], node_of[2 * ii * NY + 2 * j + 2],
+                        node_of[2 * ii * NY + 2 * j + 1]))
+    return np.array(out, dtype=np.int64)
+
+
 def p1_elasticity(invT, lam_int):
     """Pseudo-solid element matrices of affine P1 triangles, (E, 3, 2, 3, 2) in
     (node i, component a, node j, component b): lam_int * (d_a phi_i d_b phi_j +
@@ -232,47 +305,12 @@ def build_2d(nx: int, ny: int, seed: int, *, k: float = 0.5, nu: float = 0.01,
         if val not in VARIANTS[key]:
             raise ValueError(f"{key} must be one of {VARIANTS[key]}")
     a_t = alpha0 * (1.5 if scheme == "bdf2" else 1.0)     # time-derivative coefficient
-    hx, hy = Lx / nx, Ly / ny
-    NX, NY = 2 * nx + 1, 2 * ny + 1
-    a = max(1, nx // 16)
-    b = max(1, ny // 8)
-    i0, i1 = nx // 2 - a, nx // 2 + a
-    j0, j1 = ny // 2 - b, ny // 2 + b
-
-    # fluid cells and triangles (lattice coordinates)
-    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
-    ci, cj = ci.ravel(), cj.ravel()
-    fluid = ~((ci >= i0) & (ci < i1) & (cj >= j0) & (cj < j1))
-    ci, cj = ci[fluid], cj[fluid]
-    I0, J0 = 2 * ci, 2 * cj
-    # T1 = (00, 10, 11), T2 = (00, 11, 01)
-    vI = np.concatenate([np.stack([I0, I0 + 2, I0 + 2], 1), np.stack([I0, I0 + 2, I0], 1)])
-    vJ = np.concatenate([np.stack([J0, J0, J0 + 2], 1), np.stack([J0, J0 + 2, J0 + 2], 1)])
-    E = vI.shape[0]
-    mI = np.stack([(vI[:, 0] + vI[:, 1]) // 2, (vI[:, 1] + vI[:, 2]) // 2, (vI[:, 2] + vI[:, 0]) // 2], 1)
-    mJ = np.stack([(vJ[:, 0] + vJ[:, 1]) // 2, (vJ[:, 1] + vJ[:, 2]) // 2, (vJ[:, 2] + vJ[:, 0]) // 2], 1)
-    LI = np.concatenate([vI, mI], 1)
-    LJ = np.concatenate([vJ, mJ], 1)
-
-    used = np.zeros(NX * NY, dtype=bool)
-    used[(LI * NY + LJ).ravel()] = True
-    node_of = -np.ones(NX * NY, dtype=np.int64)
-    node_lat = np.flatnonzero(used)                    # lexicographic in (ix, iy)
-    node_of[node_lat] = np.arange(node_lat.size)
-    nn = node_lat.size
-    nI, nJ = node_lat // NY, node_lat % NY
-    tri = node_of[LI * NY + LJ]                        # (E, 6)
-
-    vert_mask = (nI % 2 == 0) & (nJ % 2 == 0)
-    vert_of = -np.ones(nn, dtype=np.int64)
-    vert_of[vert_mask] = np.arange(int(vert_mask.sum()))
-    nv = int(vert_mask.sum())
-    tri_p = vert_of[tri[:, :3]]
-
-    inlet = nI == 0
-    outlet = nI == NX - 1
-    wall = (nJ == 0) | (nJ == NY - 1)
-    on_gamma = (nI >= 2 * i0) & (nI <= 2 * i1) & (nJ >= 2 * j0) & (nJ <= 2 * j1)
+    m = mesh_2d(nx, ny, Lx, Ly)
+    hx, hy, NX, NY, a, b = m["hx"], m["hy"], m["NX"], m["NY"], m["a"], m["b"]
+    i0, i1, j0, j1 = m["hole"]
+    E, tri, node_of, nn, nI, nJ = m["E"], m["tri"], m["node_of"], m["nn"], m["nI"], m["nJ"]
+    vert_mask, vert_of, nv, tri_p = m["vert_mask"], m["vert_of"], m["nv"], m["tri_p"]
+    inlet, outlet, wall, on_gamma = m["inlet"], m["outlet"], m["wall"], m["on_gamma"]
 
     # ---- dof numbering
     nxt = 0
