@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmf.so")
-SOURCES = ["mf_symbolic.cpp", "mf_api.cpp", "mf_kernels.hip", "mf_sweep.hip"]
+SOURCES = ["mf_symbolic.cpp", "mf_api.cpp", "mf_kernels.hip", "mf_sweep.hip", "ale_api.cpp", "ale_kernels.hip"]
 ARCH = os.environ.get("MF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -143,3 +143,38 @@ def test_sweep_work_list_protocol(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.startswith("OK")
+
+
+def test_ale_exports_match_header():
+    hdr = open(os.path.join(ROOT, "include", "ale.h")).read()
+    declared = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(ale_\w+)\s*\(", hdr, flags=re.M))
+    assert declared == {"ale_create", "ale_residual", "ale_jacobian", "ale_device_bytes", "ale_release"}
+    L = mf.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_ale_create_rejects_missing_coupling_and_bad_indices():
+    """The set-up checks run on the host before anything touches a device: a
+    pattern without a coupling of the element terms, and out-of-range numbers."""
+    from paper_2609_31477_amd.ale import Assembly
+    from vivjac.ale2d import build_ale_2d
+    p = build_ale_2d(16, 8, 0)
+    # drop one (u, x) coupling from the pattern
+    r = int(p.u_dof[p.tri[40, 3], 0])           # an interior edge node's u_x row
+    assert r >= 0
+    lo, hi = int(p.rowptr[r]), int(p.rowptr[r + 1])
+    cols = p.colind[lo:hi]
+    drop = lo + int(np.flatnonzero(cols >= p.blocks["x"][0])[0])
+    p.colind = np.delete(p.colind, drop)
+    p.rowptr = p.rowptr.copy()
+    p.rowptr[r + 1:] -= 1
+    with pytest.raises(mf.MFError) as e:
+        Assembly(p)
+    assert e.value.status == mf.MF_ERR_PATTERN and "not in the pattern" in str(e.value)
+    q = build_ale_2d(16, 8, 0)
+    q.tri = q.tri.copy()
+    q.tri[3, 2] = q.u_dof.shape[0] + 5
+    with pytest.raises(mf.MFError) as e:
+        Assembly(q)
+    assert e.value.status == mf.MF_ERR_ARG and "tri" in str(e.value)
