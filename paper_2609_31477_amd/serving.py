@@ -372,7 +372,9 @@ class MFBackend:
         bs = [r.state["rhs"][r.steps_done] for r in members]
         xs = [r.state["xs"][r.steps_done] for r in members]
         with self.torch.cuda.stream(stream):
-            B.factor(vals, stream=stream, prec=self.prec, target_omega=self.target)
+            # a cohort factors once per Newton step: from its second step on, the
+            # planned schedule replays as a captured HIP graph
+            B.factor(vals, stream=stream, prec=self.prec, target_omega=self.target, plan=2)
             _, out = B.solve(bs, xs=xs, stream=stream)
         stream.synchronize()
         return {r.rid: {"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters}

@@ -106,3 +106,41 @@ def test_batch_ragged_right_hand_sides_equal_alone():
             continue
         assert np.array_equal(xs[i].cpu().numpy(), alone[i])
         assert infos[i].omega <= 1e-10
+
+
+@pytest.mark.gpu
+def test_config3_graph_replay_equals_alone():
+    """The 64 uneven systems of the batch workload (16x8..64x32 cells, seeds
+    100-163), FP32 fronts, factored as one batch with the planned schedule
+    replayed as a captured HIP graph over three Newton steps: every system's
+    solution is bitwise the one it gets alone (level by level), at every step."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from vivjac import newton_rhs, newton_values
+    dev = torch.device("cuda:0")
+    systems = []
+    for i in range(64):
+        rng = np.random.default_rng(100 + i)
+        nx = 16 + 4 * int(rng.integers(0, 13))
+        systems.append(build_2d(nx, nx // 2, 100 + i))
+    syms = [mf.Symbolic(s.n, s.rowptr, s.colind, s.root) for s in systems]
+    B = mf.Batch(syms)
+    for step in range(3):
+        vals = [torch.from_numpy(newton_values(s, step)).to(dev) for s in systems]
+        bs = [torch.from_numpy(newton_rhs(s, step)[0].copy()).to(dev) for s in systems]
+        B.factor(vals, prec="fp32", target_omega=1e-10, plan=2)
+        xs, infos = B.solve(bs)
+        torch.cuda.synchronize()
+        finfo = B.info()
+        print(f"step {step}: planned={finfo.planned} fallbacks={finfo.plan_fallbacks} "
+              f"omega_max={max(i.omega for i in infos):.1e}", flush=True)
+        for S, v, b, x in zip(syms, vals, bs, xs):
+            num = S.factor(v, prec="fp32", target_omega=1e-10)
+            xa, _ = num.solve(b)
+            assert np.array_equal(x.cpu().numpy(), xa.cpu().numpy())
+            num.release()
+        assert max(i.omega for i in infos) <= 1e-10
+        if step > 0:
+            assert finfo.planned == 2 or finfo.plan_fallbacks > 0
+    B.release()
