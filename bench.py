@@ -294,7 +294,7 @@ def bench_serving(args):
 
     def serve(reqs):
         be = MFBackend(prec="fp32", target_omega=args.target_omega, payloads=payloads)
-        sch = Scheduler(be, hbm_budget=200 << 30, max_slots=64)
+        sch = Scheduler(be, hbm_budget=200 << 30, max_slots=64, max_cohorts=args.max_cohorts or None)
         for r in reqs:
             sch.submit(r)
         t0 = time.perf_counter()
@@ -310,6 +310,7 @@ def bench_serving(args):
         wall = time.perf_counter() - t0
         be.close()
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()       # the next run starts from the same free memory
         worst = max(max(x["omega"] for x in r.results) for r in done)
         return summarize(done), sch, be, wall, worst
 
@@ -335,6 +336,7 @@ def bench_serving(args):
            "config": {"workload": f"serving: {args.requests} Poisson requests per rate, {100 * (1 - args.mix_3d):.0f}% "
                                   f"2D meshes 32x16..128x64 cells, {100 * args.mix_3d:.0f}% 3D boxes 24x12x6, "
                                   "5 Newton steps each, FP32 fronts + FP64 GMRES-IR, continuous batching, "
+                                  f"at most {args.max_cohorts or 'any number of'} cohorts at once, "
                                   f"omega<={args.target_omega:g}", "rates": rates},
            "p50_request_ms": top["p50_request_ms"], "p99_request_ms": top["p99_request_ms"],
            "p50_step_ms": top["p50_step_ms"], "p99_step_ms": top["p99_step_ms"], "per_rate": lines}
@@ -359,6 +361,8 @@ def main():
     ap.add_argument("--rates", default="", help="serving: comma-separated arrival rates, one run each")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests per rate")
     ap.add_argument("--mix-3d", type=float, default=0.3, help="serving: fraction of 3D requests")
+    ap.add_argument("--max-cohorts", type=int, default=2,
+                    help="serving: cohorts active at once (0: no cap); arrivals beyond it gather into the next")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")

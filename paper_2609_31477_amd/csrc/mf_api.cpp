@@ -9,6 +9,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <unordered_map>
+#include <map>
+#include <mutex>
+#include <shared_mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -48,6 +52,9 @@ hipError_t launch_scale(const DevSym& S, double* y, const double* x, const doubl
                         hipStream_t st);
 hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st);
+template <typename T>
+hipError_t launch_seg_copy(const SegCopy* segs, const int64_t* start, int nseg, int64_t total, T* out,
+                           hipStream_t st);
 hipError_t launch_nonfinite(const double* v, int64_t nnz, unsigned long long* first, hipStream_t st);
 hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count,
                               int32_t* overflow, hipStream_t st);
@@ -83,6 +90,120 @@ struct Fail {
                        std::string(#call) + ": " + hipGetErrorString(e_)};                             \
     } while (0)
 
+// Device and pinned host memory of the library's handles comes from a cache per
+// device and goes back to it, not to the runtime: hipFree and hipHostFree
+// synchronize the whole device, which would stall every other stream of a
+// serving loop whenever one request's handle is released.  A block goes back to
+// the cache only when nothing uses it any more: every entry point synchronizes
+// its stream before it returns, so a handle's blocks are idle when it is
+// released or when one of its calls replaces a buffer.  Sizes are rounded up to
+// an eighth of their power of two; when the device runs out, the cached blocks
+// are handed back to the runtime and the allocation is tried once more.
+// hipFree synchronizes the device, which would invalidate a graph capture that
+// another thread has in progress: captures hold this lock shared, and handing
+// cached blocks back to the runtime holds it exclusively.
+std::shared_mutex g_capture_mu;
+
+class MemCache {
+  public:
+    hipError_t get(void** p, size_t n, bool host) {
+        *p = nullptr;
+        int dev = 0;
+        if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return e;
+        const size_t b = bin(n);
+        {
+            // best fit among the idle blocks of at most 1.5 times the request
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(Key{dev, host, b});
+            if (it != free_.end() && it->first.dev == dev && it->first.host == host &&
+                it->first.bytes <= b + b / 2) {
+                *p = it->second;
+                idle_[host] -= it->first.bytes;
+                live_[*p] = it->first;
+                free_.erase(it);
+                return hipSuccess;
+            }
+        }
+        hipError_t e = raw_alloc(p, b, host);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            trim(dev, host, 0);
+            e = raw_alloc(p, b, host);
+        }
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu_);
+            live_[*p] = Key{dev, host, b};
+        }
+        return e;
+    }
+    hipError_t put(void* p) {
+        if (!p) return hipSuccess;
+        Key k;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = live_.find(p);
+            if (it == live_.end()) return hipErrorInvalidValue;
+            k = it->second;
+            live_.erase(it);
+            free_.emplace(k, p);
+            idle_[k.host] += k.bytes;
+            if (idle_[k.host] <= limit(k.host)) return hipSuccess;
+        }
+        trim(k.dev, k.host, limit(k.host) / 2);  // rare: too much idle memory kept
+        return hipSuccess;
+    }
+
+  private:
+    struct Key {
+        int dev = 0;
+        bool host = false;
+        size_t bytes = 0;
+        bool operator<(const Key& o) const {
+            return dev != o.dev ? dev < o.dev : (host != o.host ? host < o.host : bytes < o.bytes);
+        }
+    };
+    static size_t limit(bool host) { return host ? (size_t(1) << 30) : (size_t(16) << 30); }
+    static size_t bin(size_t n) {
+        n = std::max<size_t>(n, 256);
+        int e = 63 - __builtin_clzll(n);
+        const size_t step = (size_t)1 << std::max(e - 3, 8);
+        return (n + step - 1) / step * step;
+    }
+    static hipError_t raw_alloc(void** p, size_t b, bool host) {
+        return host ? hipHostMalloc(p, b, hipHostMallocDefault) : hipMalloc(p, b);
+    }
+    // hand idle blocks of one kind back to the runtime, largest first, until at
+    // most `keep` bytes stay idle
+    void trim(int dev, bool host, size_t keep) {
+        std::vector<void*> out;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (auto it = free_.end(); it != free_.begin() && idle_[host] > keep;) {
+                --it;
+                if (it->first.dev != dev || it->first.host != host) continue;
+                out.push_back(it->second);
+                idle_[host] -= it->first.bytes;
+                it = free_.erase(it);
+            }
+        }
+        if (out.empty()) return;
+        std::unique_lock<std::shared_mutex> nocap(g_capture_mu);
+        for (void* q : out) (void)(host ? hipHostFree(q) : hipFree(q));
+    }
+    std::mutex mu_;
+    std::multimap<Key, void*> free_;
+    std::unordered_map<void*, Key> live_;
+    size_t idle_[2] = {0, 0};
+};
+MemCache& mem_cache() {
+    static MemCache* c = new MemCache();  // lives until the process ends
+    return *c;
+}
+hipError_t dmalloc(void** p, size_t n) { return mem_cache().get(p, n, false); }
+hipError_t hmalloc(void** p, size_t n, unsigned) { return mem_cache().get(p, n, true); }
+hipError_t dfree(void* p) { return mem_cache().put(p); }
+hipError_t hfree(void* p) { return mem_cache().put(p); }
+
 constexpr size_t kMaxLds = 64 * 1024;
 constexpr size_t kSweepStaticLds = 36 * 1024;  // static LDS of the sweep kernels, with margin
 
@@ -90,7 +211,7 @@ template <typename V>
 void upload(V** dst, const std::vector<V>& src) {
     *dst = nullptr;
     size_t bytes = sizeof(V) * std::max<size_t>(src.size(), 1);
-    HIPX(hipMalloc((void**)dst, bytes));
+    HIPX(dmalloc((void**)dst, bytes));
     if (!src.empty()) HIPX(hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
 }
 
@@ -101,12 +222,19 @@ struct SymDev {
     std::vector<void*> allocs;
     std::vector<int32_t> slot_of;  // front id -> slot
     ~SymDev() {
-        for (void* p : allocs) (void)hipFree(p);
+        for (void* p : allocs) (void)dfree(p);
     }
     template <typename V>
     const V* put(const std::vector<V>& v) {
         V* p = nullptr;
         upload(&p, v);
+        allocs.push_back(p);
+        return p;
+    }
+    template <typename V>
+    V* alloc(size_t n) {
+        V* p = nullptr;
+        HIPX(dmalloc((void**)&p, sizeof(V) * std::max<size_t>(n, 1)));
         allocs.push_back(p);
         return p;
     }
@@ -139,14 +267,14 @@ struct Arena {
         }
         size_t sz = std::max(bytes, grow_hint);
         char* p = nullptr;
-        HIPX(hipMalloc((void**)&p, sz));
+        HIPX(dmalloc((void**)&p, sz));
         chunks.emplace_back(p, sz);
         ci = chunks.size() - 1;
         off = bytes;
         return p;
     }
     void release() {
-        for (auto& k : chunks) (void)hipFree(k.first);
+        for (auto& k : chunks) (void)dfree(k.first);
         chunks.clear();
         reset();
     }
@@ -164,7 +292,9 @@ struct mf_sym {
     uint32_t magic = kSymMagic;
     Symbolic S;
     mf_options opt;
-    std::unique_ptr<SymDev> dev;
+    std::shared_ptr<SymDev> dev;
+    // a light batch: its systems' device pattern data, shared with their handles
+    std::vector<std::shared_ptr<SymDev>> parts_dev;
 };
 
 struct mf_num {
@@ -217,9 +347,9 @@ struct mf_num {
         int32_t* d_ctr = nullptr;  // counters of both directions (2 + 3 nslots each)
         int32_t* h_err = nullptr;  // pinned: the two error words
         void free_device() {
-            if (d_buf) (void)hipFree(d_buf);
-            if (d_ctr) (void)hipFree(d_ctr);
-            if (h_err) (void)hipHostFree(h_err);
+            if (d_buf) (void)dfree(d_buf);
+            if (d_ctr) (void)dfree(d_ctr);
+            if (h_err) (void)hfree(h_err);
             d_buf = nullptr;
             d_ctr = nullptr;
             h_err = nullptr;
@@ -235,6 +365,7 @@ struct mf_num {
     int32_t* d_ones = nullptr;              // nseg ones: every system active
     int ones_cap = 0;
     bool factored = false;
+    hipStream_t last_stream = nullptr;  // stream of the last call (idle when the call returned)
     bool stale = false;        // operator values replaced since the factorization (mf_set_operator)
     std::vector<int32_t> lvl_mmax[2], lvl_Pmax[2], lvl_cnt[2];  // per level per precision
     std::vector<std::array<int32_t, kNClass>> lvl_cls_mmax[2], lvl_cls_Pmax[2];  // per level, precision, panel class
@@ -286,10 +417,10 @@ struct mf_num {
             drop_graph();
             if (cap_stream) (void)hipStreamDestroy(cap_stream);
             cap_stream = nullptr;
-            if (d_tmpl) (void)hipFree(d_tmpl);
-            if (d_tasks) (void)hipFree(d_tasks);
-            if (d_flag) (void)hipFree(d_flag);
-            if (h_flag) (void)hipHostFree(h_flag);
+            if (d_tmpl) (void)dfree(d_tmpl);
+            if (d_tasks) (void)dfree(d_tasks);
+            if (d_flag) (void)dfree(d_flag);
+            if (h_flag) (void)hfree(h_flag);
             d_tmpl = nullptr;
             d_tasks = nullptr;
             d_flag = nullptr;
@@ -319,39 +450,39 @@ struct mf_num {
         }
     } tuner;
     ~mf_num() {
-        for (void* p : kv_alloc) (void)hipFree(p);
+        for (void* p : kv_alloc) (void)dfree(p);
         sweep.free_device();
-        if (d_bad) (void)hipFree(d_bad);
-        if (h_bad) (void)hipHostFree(h_bad);
+        if (d_bad) (void)dfree(d_bad);
+        if (h_bad) (void)hfree(h_bad);
         if (tuner.e0) (void)hipEventDestroy(tuner.e0);
         if (tuner.e1) (void)hipEventDestroy(tuner.e1);
         plan.free_device();
         fronts.release();
         ints.release();
         wsp.release();
-        if (d_fn) (void)hipFree(d_fn);
-        if (h_fn) (void)hipHostFree(h_fn);
-        if (d_vals) (void)hipFree(d_vals);
-        if (d_vec) (void)hipFree(d_vec);
-        if (d_work) (void)hipFree(d_work);
-        if (d_kry) (void)hipFree(d_kry);
-        if (d_small) (void)hipFree(d_small);
-        if (h_small) (void)hipHostFree(h_small);
-        if (d_omega) (void)hipFree(d_omega);
-        if (d_respart) (void)hipFree(d_respart);
-        if (h_omega) (void)hipHostFree(h_omega);
-        if (d_active) (void)hipFree(d_active);
-        if (d_cat) (void)hipFree(d_cat);
-        if (d_ones) (void)hipFree(d_ones);
-        if (h_active) (void)hipHostFree(h_active);
-        if (d_tasks) (void)hipFree(d_tasks);
-        if (d_svals) (void)hipFree(d_svals);
-        if (d_dr) (void)hipFree(d_dr);
-        if (d_dc) (void)hipFree(d_dc);
-        if (d_rmax) (void)hipFree(d_rmax);
-        if (d_cmax) (void)hipFree(d_cmax);
-        if (d_sb) (void)hipFree(d_sb);
-        if (h_tasks) (void)hipHostFree(h_tasks);
+        if (d_fn) (void)dfree(d_fn);
+        if (h_fn) (void)hfree(h_fn);
+        if (d_vals) (void)dfree(d_vals);
+        if (d_vec) (void)dfree(d_vec);
+        if (d_work) (void)dfree(d_work);
+        if (d_kry) (void)dfree(d_kry);
+        if (d_small) (void)dfree(d_small);
+        if (h_small) (void)hfree(h_small);
+        if (d_omega) (void)dfree(d_omega);
+        if (d_respart) (void)dfree(d_respart);
+        if (h_omega) (void)hfree(h_omega);
+        if (d_active) (void)dfree(d_active);
+        if (d_cat) (void)dfree(d_cat);
+        if (d_ones) (void)dfree(d_ones);
+        if (h_active) (void)hfree(h_active);
+        if (d_tasks) (void)dfree(d_tasks);
+        if (d_svals) (void)dfree(d_svals);
+        if (d_dr) (void)dfree(d_dr);
+        if (d_dc) (void)dfree(d_dc);
+        if (d_rmax) (void)dfree(d_rmax);
+        if (d_cmax) (void)dfree(d_cmax);
+        if (d_sb) (void)dfree(d_sb);
+        if (h_tasks) (void)hfree(h_tasks);
     }
 };
 
@@ -366,9 +497,68 @@ void resolve_refine(mf_options& o) {
     if (o.refine < 0) o.refine = (o.prec == MF_FP64) ? 1 : 2;
 }
 
+// The unique-entry maps and the CSR pattern of a light batch, concatenated on
+// the device from its systems' own device copies (one segmented copy per array,
+// each (system, level) block shifted to its batch slots and sources).
+void build_light_maps(mf_sym* h, SymDev& D) {
+    const Symbolic& S = h->S;
+    DevSym& d = D.S;
+    for (const auto& P : h->parts_dev)
+        if (!P || P->device != D.device)
+            throw Fail{MF_ERR_ARG, "a batch analyzed on one device is factored on another"};
+    const int nq = (int)h->parts_dev.size();
+    std::vector<SegCopy> slot, row, col, sptr, src, rp, ci;
+    for (const Symbolic::UeBlock& b : S.ue_blocks) {
+        const DevSym& P = h->parts_dev[b.part]->S;
+        slot.push_back({P.ue_slot + b.u0, b.dst_u, b.cnt, b.slot_delta});
+        row.push_back({P.ue_row + b.u0, b.dst_u, b.cnt, 0});
+        col.push_back({P.ue_col + b.u0, b.dst_u, b.cnt, 0});
+        sptr.push_back({P.ue_src_ptr + b.u0, b.dst_u, b.cnt, b.dst_s - b.s0});
+        src.push_back({P.ue_src + b.s0, b.dst_s, b.scnt, S.seg_nnz0[b.part]});
+    }
+    for (int q = 0; q < nq; q++) {
+        const DevSym& P = h->parts_dev[q]->S;
+        const int64_t nz = (q + 1 < nq ? S.seg_nnz0[q + 1] : S.nnz) - S.seg_nnz0[q];
+        rp.push_back({P.csr_rowptr, S.seg_row0[q], S.seg_n[q], S.seg_nnz0[q]});
+        ci.push_back({P.csr_colind, S.seg_nnz0[q], nz, S.seg_row0[q]});
+    }
+    auto run = [&](const std::vector<SegCopy>& segs, auto* out) {
+        std::vector<int64_t> start(segs.size() + 1, 0);
+        for (size_t i = 0; i < segs.size(); i++) start[i + 1] = start[i] + segs[i].count;
+        HIPX(launch_seg_copy(D.put(segs), D.put(start), (int)segs.size(), start.back(), out, nullptr));
+    };
+    int32_t* ue_slot = D.alloc<int32_t>(S.n_ue);
+    int32_t* ue_row = D.alloc<int32_t>(S.n_ue);
+    int32_t* ue_col = D.alloc<int32_t>(S.n_ue);
+    int64_t* ue_src_ptr = D.alloc<int64_t>(S.n_ue + 1);
+    int32_t* ue_src = D.alloc<int32_t>(S.n_src);
+    int64_t* rowptr = D.alloc<int64_t>(S.n + 1);
+    int32_t* colind = D.alloc<int32_t>(S.nnz);
+    run(slot, ue_slot);
+    run(row, ue_row);
+    run(col, ue_col);
+    run(sptr, ue_src_ptr);
+    run(src, ue_src);
+    run(rp, rowptr);
+    run(ci, colind);
+    HIPX(hipMemcpy(ue_src_ptr + S.n_ue, &S.n_src, sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(rowptr + S.n, &S.nnz, sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPX(hipStreamSynchronize(nullptr));
+    d.ue_slot = ue_slot;
+    d.ue_row = ue_row;
+    d.ue_col = ue_col;
+    d.ue_src_ptr = ue_src_ptr;
+    d.ue_src = ue_src;
+    d.csr_rowptr = rowptr;
+    d.csr_colind = colind;
+}
+
+std::mutex g_symdev_mu;  // device pattern data is built once per handle, also when batches share it
+
 void ensure_device_symbolic(mf_sym* h) {
     int dev = 0;
     HIPX(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_symdev_mu);
     if (h->dev && h->dev->device == dev) return;
     const Symbolic& S = h->S;
     auto D = std::make_unique<SymDev>();
@@ -392,8 +582,6 @@ void ensure_device_symbolic(mf_sym* h) {
         imap.insert(imap.end(), S.imap.begin() + S.imap_off[f], S.imap.begin() + S.imap_off[f + 1]);
         imap_off[sl + 1] = (int64_t)imap.size();
     }
-    std::vector<int32_t> ue_slot(S.ue_front.size());
-    for (size_t i = 0; i < ue_slot.size(); i++) ue_slot[i] = D->slot_of[S.ue_front[i]];
     DevSym& d = D->S;
     d.nslots = nf;
     d.parent = D->put(parent);
@@ -403,13 +591,19 @@ void ensure_device_symbolic(mf_sym* h) {
     d.rows = D->put(rows);
     d.imap_off = D->put(imap_off);
     d.imap = D->put(imap);
-    d.ue_slot = D->put(ue_slot);
-    d.ue_row = D->put(S.ue_row);
-    d.ue_col = D->put(S.ue_col);
-    d.ue_src_ptr = D->put(S.ue_src_ptr);
-    d.ue_src = D->put(S.ue_src);
-    d.csr_rowptr = D->put(S.rowptr);
-    d.csr_colind = D->put(S.colind);
+    if (S.light) {
+        build_light_maps(h, *D);
+    } else {
+        std::vector<int32_t> ue_slot(S.ue_front.size());
+        for (size_t i = 0; i < ue_slot.size(); i++) ue_slot[i] = D->slot_of[S.ue_front[i]];
+        d.ue_slot = D->put(ue_slot);
+        d.ue_row = D->put(S.ue_row);
+        d.ue_col = D->put(S.ue_col);
+        d.ue_src_ptr = D->put(S.ue_src_ptr);
+        d.ue_src = D->put(S.ue_src);
+        d.csr_rowptr = D->put(S.rowptr);
+        d.csr_colind = D->put(S.colind);
+    }
     d.nseg = (int32_t)S.seg_n.size();
     d.seg_row0 = D->put(S.seg_row0);
     d.seg_n = D->put(S.seg_n);
@@ -462,14 +656,14 @@ LevelTasks upload_level_tasks(mf_num* N, const FrontNum* hf, int count, hipStrea
     const LevelTasks tk = level_task_count(hf, count, sw_force, nkid);
     const size_t total = level_task_total(tk);
     if (total > N->tasks_cap) {
-        if (N->d_tasks) HIPX(hipFree(N->d_tasks));
-        if (N->h_tasks) HIPX(hipHostFree(N->h_tasks));
+        if (N->d_tasks) HIPX(dfree(N->d_tasks));
+        if (N->h_tasks) HIPX(hfree(N->h_tasks));
         N->d_tasks = nullptr;
         N->h_tasks = nullptr;
         N->tasks_cap = 0;
         const size_t cap = total + total / 2 + 1024;
-        HIPX(hipMalloc((void**)&N->d_tasks, sizeof(int32_t) * cap));
-        HIPX(hipHostMalloc((void**)&N->h_tasks, sizeof(int32_t) * cap, hipHostMallocDefault));
+        HIPX(dmalloc((void**)&N->d_tasks, sizeof(int32_t) * cap));
+        HIPX(hmalloc((void**)&N->h_tasks, sizeof(int32_t) * cap, hipHostMallocDefault));
         N->tasks_cap = cap;
     }
     if (fill_level_tasks(hf, count, tk, nkid, N->h_tasks, N->tasks_cap) != total)
@@ -561,14 +755,14 @@ void build_plan(mf_num* N) {
         pl.tasks[L] = build_level_tasks(tm.data() + s0, s1 - s0, tasks, shape < 0 ? 0 : ((shape & 2) ? 16 : 64),
                                         kids.data());
     }
-    HIPX(hipMalloc((void**)&pl.d_tmpl, sizeof(FrontNum) * tm.size()));
+    HIPX(dmalloc((void**)&pl.d_tmpl, sizeof(FrontNum) * tm.size()));
     HIPX(hipMemcpy(pl.d_tmpl, tm.data(), sizeof(FrontNum) * tm.size(), hipMemcpyHostToDevice));
-    HIPX(hipMalloc((void**)&pl.d_tasks, sizeof(int32_t) * std::max<size_t>(tasks.size(), 1)));
+    HIPX(dmalloc((void**)&pl.d_tasks, sizeof(int32_t) * std::max<size_t>(tasks.size(), 1)));
     if (!tasks.empty())
         HIPX(hipMemcpy(pl.d_tasks, tasks.data(), sizeof(int32_t) * tasks.size(), hipMemcpyHostToDevice));
     for (int L = 0; L < S.nlevels; L++) pl.tasks[L] = place_tasks(pl.tasks[L], pl.d_tasks + toff[L]);
-    HIPX(hipMalloc((void**)&pl.d_flag, sizeof(int32_t)));
-    HIPX(hipHostMalloc((void**)&pl.h_flag, sizeof(int32_t), hipHostMallocDefault));
+    HIPX(dmalloc((void**)&pl.d_flag, sizeof(int32_t)));
+    HIPX(hmalloc((void**)&pl.h_flag, sizeof(int32_t), hipHostMallocDefault));
     pl.vec_len = voff;
     pl.din_cap = cap;
     pl.prec = o.prec;
@@ -659,7 +853,10 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
             pl.drop_graph();
             if (!pl.cap_stream) HIPX(hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
-            HIPX(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
+            std::shared_lock<std::shared_mutex> cap(g_capture_mu);
+            // relaxed: allocations and frees of other threads (other handles, other
+            // libraries) cannot invalidate this capture
+            HIPX(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeRelaxed));
             try {
                 enqueue(pl.cap_stream);
             } catch (...) {
@@ -708,10 +905,10 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
 // synchronization on the stream (check_finite).
 void load_values(mf_num* N, const double* values_dev, const double* const* seg_values, hipStream_t st) {
     const Symbolic& S = N->sym->S;
-    if (!N->d_vals) HIPX(hipMalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
+    if (!N->d_vals) HIPX(dmalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
     if (!N->d_bad) {
-        HIPX(hipMalloc((void**)&N->d_bad, sizeof(unsigned long long)));
-        HIPX(hipHostMalloc((void**)&N->h_bad, sizeof(unsigned long long), hipHostMallocDefault));
+        HIPX(dmalloc((void**)&N->d_bad, sizeof(unsigned long long)));
+        HIPX(hmalloc((void**)&N->h_bad, sizeof(unsigned long long), hipHostMallocDefault));
     }
     if (seg_values) {
         for (size_t q = 0; q < S.seg_n.size(); q++) {
@@ -735,8 +932,8 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     const int nf = S.nf;
     const mf_options& o = N->opt;
     if (!N->d_fn) {
-        HIPX(hipMalloc((void**)&N->d_fn, sizeof(FrontNum) * std::max(nf, 1)));
-        HIPX(hipHostMalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
+        HIPX(dmalloc((void**)&N->d_fn, sizeof(FrontNum) * std::max(nf, 1)));
+        HIPX(hmalloc((void**)&N->h_fn, sizeof(FrontNum) * std::max(nf, 1), hipHostMallocDefault));
     }
     load_values(N, values_dev, seg_values, st);
     N->stale = false;
@@ -745,11 +942,11 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     N->scaled = o.scale > 0 && S.n > 0;
     if (N->scaled) {
         if (!N->d_svals) {
-            HIPX(hipMalloc((void**)&N->d_svals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
-            HIPX(hipMalloc((void**)&N->d_dr, sizeof(double) * S.n));
-            HIPX(hipMalloc((void**)&N->d_dc, sizeof(double) * S.n));
-            HIPX(hipMalloc((void**)&N->d_rmax, sizeof(double) * S.n));
-            HIPX(hipMalloc((void**)&N->d_cmax, sizeof(unsigned long long) * S.n));
+            HIPX(dmalloc((void**)&N->d_svals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
+            HIPX(dmalloc((void**)&N->d_dr, sizeof(double) * S.n));
+            HIPX(dmalloc((void**)&N->d_dc, sizeof(double) * S.n));
+            HIPX(dmalloc((void**)&N->d_rmax, sizeof(double) * S.n));
+            HIPX(dmalloc((void**)&N->d_cmax, sizeof(unsigned long long) * S.n));
         }
         HIPX(launch_ruiz(D.S, N->d_vals, S.n, o.scale, N->d_dr, N->d_dc, N->d_rmax, N->d_cmax, N->d_svals, st));
         fvals = N->d_svals;
@@ -970,32 +1167,32 @@ void ensure_solve_buffers(mf_num* N, int nrhs) {
     const int nseg = (int)S.seg_n.size();
     size_t need = (size_t)std::max<int64_t>(N->vec_len, 1) * nrhs;
     if (need > N->vec_cap) {
-        if (N->d_vec) HIPX(hipFree(N->d_vec));
+        if (N->d_vec) HIPX(dfree(N->d_vec));
         N->d_vec = nullptr;
-        HIPX(hipMalloc((void**)&N->d_vec, sizeof(double) * need));
+        HIPX(dmalloc((void**)&N->d_vec, sizeof(double) * need));
         N->vec_cap = need;
     }
     size_t wneed = (size_t)std::max<int64_t>(n, 1) * nrhs * 2;
     if (wneed > N->work_cap) {
-        if (N->d_work) HIPX(hipFree(N->d_work));
+        if (N->d_work) HIPX(dfree(N->d_work));
         N->d_work = nullptr;
-        HIPX(hipMalloc((void**)&N->d_work, sizeof(double) * wneed));
+        HIPX(dmalloc((void**)&N->d_work, sizeof(double) * wneed));
         N->work_cap = wneed;
     }
     if (nrhs * nseg > N->omega_cap) {
-        if (N->d_omega) HIPX(hipFree(N->d_omega));
-        if (N->h_omega) HIPX(hipHostFree(N->h_omega));
-        if (N->d_active) HIPX(hipFree(N->d_active));
-        if (N->h_active) HIPX(hipHostFree(N->h_active));
+        if (N->d_omega) HIPX(dfree(N->d_omega));
+        if (N->h_omega) HIPX(hfree(N->h_omega));
+        if (N->d_active) HIPX(dfree(N->d_active));
+        if (N->h_active) HIPX(hfree(N->h_active));
         N->d_omega = nullptr;
         N->h_omega = nullptr;
         N->d_active = nullptr;
         N->h_active = nullptr;
         const int cnt = nrhs * nseg;
-        HIPX(hipMalloc((void**)&N->d_omega, sizeof(unsigned long long) * kResQ * cnt));
-        HIPX(hipHostMalloc((void**)&N->h_omega, sizeof(unsigned long long) * kResQ * cnt, hipHostMallocDefault));
-        HIPX(hipMalloc((void**)&N->d_active, sizeof(int32_t) * cnt));
-        HIPX(hipHostMalloc((void**)&N->h_active, sizeof(int32_t) * cnt, hipHostMallocDefault));
+        HIPX(dmalloc((void**)&N->d_omega, sizeof(unsigned long long) * kResQ * cnt));
+        HIPX(hmalloc((void**)&N->h_omega, sizeof(unsigned long long) * kResQ * cnt, hipHostMallocDefault));
+        HIPX(dmalloc((void**)&N->d_active, sizeof(int32_t) * cnt));
+        HIPX(hmalloc((void**)&N->h_active, sizeof(int32_t) * cnt, hipHostMallocDefault));
         N->omega_cap = cnt;
     }
 }
@@ -1069,15 +1266,15 @@ void build_sweep_plan(mf_num* N) {
     for (int dir = 0; dir < 2; dir++) need_ints += tk[dir].size() + bp[dir].size() + nt[dir].size();
     need_ints += need.size() + (listed.size() + 3) / 4;
     if (need_ints > P.cap) {
-        if (P.d_buf) HIPX(hipFree(P.d_buf));
+        if (P.d_buf) HIPX(dfree(P.d_buf));
         P.d_buf = nullptr;
         P.cap = 0;
-        HIPX(hipMalloc((void**)&P.d_buf, sizeof(int32_t) * need_ints));
+        HIPX(dmalloc((void**)&P.d_buf, sizeof(int32_t) * need_ints));
         P.cap = need_ints;
     }
     if (!P.d_ctr) {
-        HIPX(hipMalloc((void**)&P.d_ctr, sizeof(int32_t) * 2 * (2 + 3 * (size_t)std::max(ns, 1))));
-        HIPX(hipHostMalloc((void**)&P.h_err, sizeof(int32_t) * 2, hipHostMallocDefault));
+        HIPX(dmalloc((void**)&P.d_ctr, sizeof(int32_t) * 2 * (2 + 3 * (size_t)std::max(ns, 1))));
+        HIPX(hmalloc((void**)&P.h_err, sizeof(int32_t) * 2, hipHostMallocDefault));
         P.h_err[0] = P.h_err[1] = 0;
     }
     std::vector<int32_t> host;
@@ -1131,9 +1328,9 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
     if (N->scaled) {
         const size_t need = (size_t)S.n * nrhs;
         if (need > N->sb_cap) {
-            if (N->d_sb) HIPX(hipFree(N->d_sb));
+            if (N->d_sb) HIPX(dfree(N->d_sb));
             N->d_sb = nullptr;
-            HIPX(hipMalloc((void**)&N->d_sb, sizeof(double) * need));
+            HIPX(dmalloc((void**)&N->d_sb, sizeof(double) * need));
             N->sb_cap = need;
         }
         HIPX(launch_diag_scale(S.n, N->d_dr, b, ldb, N->d_sb, S.n, nrhs, st));
@@ -1226,9 +1423,9 @@ void residual(mf_num* N, const double* b, int64_t ldb, const double* x, int64_t 
     const int cnt = nrhs * nseg;
     const size_t pneed = residual_part_size(S.n, nrhs);
     if (pneed > N->respart_cap) {
-        if (N->d_respart) HIPX(hipFree(N->d_respart));
+        if (N->d_respart) HIPX(dfree(N->d_respart));
         N->d_respart = nullptr;
-        HIPX(hipMalloc((void**)&N->d_respart, sizeof(double) * pneed));
+        HIPX(dmalloc((void**)&N->d_respart, sizeof(double) * pneed));
         N->respart_cap = pneed;
     }
     HIPX(launch_residual(N->sym->dev->S, N->d_vals, S.n, x, ldx, b, ldb, r, S.n, nrhs, N->d_omega, N->d_respart, st));
@@ -1257,7 +1454,7 @@ const DevSym& krylov_view(mf_num* N, int nrhs) {
     const DevSym& DS = N->sym->dev->S;
     if (nrhs == 1) return DS;
     if (N->kv_nrhs == nrhs) return N->kv;
-    for (void* p : N->kv_alloc) HIPX(hipFree(p));
+    for (void* p : N->kv_alloc) HIPX(dfree(p));
     N->kv_alloc.clear();
     N->kv_nrhs = 0;
     const Symbolic& S = N->sym->S;
@@ -1297,25 +1494,25 @@ void ensure_krylov(mf_num* N, int mres, int nrhs) {
     // V (mres + 1 vectors) | w | trial x | trial r | reduction scratch
     size_t need = (size_t)len * (mres + 4) + (size_t)512 * nq * (mres + 2);
     if (need > N->kry_cap) {
-        if (N->d_kry) HIPX(hipFree(N->d_kry));
+        if (N->d_kry) HIPX(dfree(N->d_kry));
         N->d_kry = nullptr;
-        HIPX(hipMalloc((void**)&N->d_kry, sizeof(double) * need));
+        HIPX(dmalloc((void**)&N->d_kry, sizeof(double) * need));
         N->kry_cap = need;
     }
     size_t sneed = (size_t)2 * nq * (mres + 2);
     if (sneed > N->small_cap) {
-        if (N->d_small) HIPX(hipFree(N->d_small));
-        if (N->h_small) HIPX(hipHostFree(N->h_small));
+        if (N->d_small) HIPX(dfree(N->d_small));
+        if (N->h_small) HIPX(hfree(N->h_small));
         N->d_small = nullptr;
         N->h_small = nullptr;
-        HIPX(hipMalloc((void**)&N->d_small, sizeof(double) * sneed));
-        HIPX(hipHostMalloc((void**)&N->h_small, sizeof(double) * sneed, hipHostMallocDefault));
+        HIPX(dmalloc((void**)&N->d_small, sizeof(double) * sneed));
+        HIPX(hmalloc((void**)&N->h_small, sizeof(double) * sneed, hipHostMallocDefault));
         N->small_cap = sneed;
     }
     if (!N->d_ones || N->ones_cap < nq) {
-        if (N->d_ones) HIPX(hipFree(N->d_ones));
+        if (N->d_ones) HIPX(dfree(N->d_ones));
         N->d_ones = nullptr;
-        HIPX(hipMalloc((void**)&N->d_ones, sizeof(int32_t) * nq));
+        HIPX(dmalloc((void**)&N->d_ones, sizeof(int32_t) * nq));
         std::vector<int32_t> ones(nq, 1);
         HIPX(hipMemcpy(N->d_ones, ones.data(), sizeof(int32_t) * nq, hipMemcpyHostToDevice));
         N->ones_cap = nq;
@@ -1693,9 +1890,11 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
     if (N->opt.scale < 0 || N->opt.scale > 64) return fail(MF_ERR_ARG, "scale must be in [0, 64] sweeps");
     if (N->opt.sweep < 0 || N->opt.sweep > 1) return fail(MF_ERR_ARG, "sweep must be 0 or 1");
     N->factored = false;
+    N->last_stream = (hipStream_t)stream;
     try {
         HIPX(hipGetDevice(&N->device));
         do_factor(N, values_dev, (hipStream_t)stream, seg_values);
+        HIPX(hipStreamSynchronize((hipStream_t)stream));  // every call returns with its stream idle
     } catch (const Fail& f) {
         if (fresh) *inout = fresh.release();  // keep the handle so the caller can release it
         return fail(f.st, f.msg);
@@ -1724,9 +1923,25 @@ mf_status mf_batch_analyze(int32_t count, const mf_sym_t* syms, mf_sym_t* out) {
     try {
         auto h = std::make_unique<mf_sym>();
         h->opt = syms[0]->opt;
-        merge_symbolic(h->S, parts);
+        // With a device present, each system's pattern data goes to the device
+        // once (kept with its handle, shared with every batch it joins) and the
+        // batch's maps are concatenated there; the host merges only per-front data.
+        int dev = -1, ndev = 0;
+        const bool light = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 && hipGetDevice(&dev) == hipSuccess;
+        if (light) {
+            for (int32_t i = 0; i < count; i++) {
+                mf_sym* p = const_cast<mf_sym*>(syms[i]);
+                ensure_device_symbolic(p);
+                h->parts_dev.push_back(p->dev);
+            }
+        } else {
+            (void)hipGetLastError();  // no device: the host merge below needs none
+        }
+        merge_symbolic(h->S, parts, light);
         *out = h.release();
         return MF_OK;
+    } catch (const Fail& f) {
+        return fail(f.st, f.msg);
     } catch (const std::invalid_argument& e) {
         return fail(MF_ERR_ARG, e.what());
     } catch (const std::bad_alloc&) {
@@ -1759,8 +1974,10 @@ mf_status mf_solve(mf_num_t N, const double* b_dev, double* x_dev, int32_t nrhs,
     }
     if (ld < n) return fail(MF_ERR_ARG, "ld < n");
     if (!b_dev || !x_dev || b_dev == x_dev) return fail(MF_ERR_ARG, "b_dev and x_dev must be distinct device buffers");
+    N->last_stream = (hipStream_t)stream;
     try {
         solve_with_fallback(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
+        HIPX(hipStreamSynchronize((hipStream_t)stream));
     } catch (const Fail& f) {
         return fail(f.st, f.msg);
     } catch (const std::bad_alloc&) {
@@ -1942,7 +2159,9 @@ mf_status mf_solve_noalloc(mf_num_t N, const double* b_dev, double* x_dev, int32
         N->h_active = g_host_active;
         N->omega_cap = cnt;
         N->opt.sweep = 0;  // the persistent sweeps keep task lists in handle memory
+        N->last_stream = (hipStream_t)stream;
         do_solve(N, b_dev, x_dev, nrhs, ld, (hipStream_t)stream, info);
+        HIPX(hipStreamSynchronize((hipStream_t)stream));
     } catch (const Fail& f) {
         return fail(f.st, f.msg);
     } catch (const std::bad_alloc&) {
@@ -1972,12 +2191,13 @@ mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const
         for (int q = 0; q < nseg; q++) info[q] = mf_solve_info{};
     if (nmax == 0 || S.n == 0) return MF_OK;
     hipStream_t st = (hipStream_t)stream;
+    N->last_stream = st;
     try {
         const size_t need = (size_t)S.n * nmax * 2;
         if (need > N->cat_cap) {
-            if (N->d_cat) HIPX(hipFree(N->d_cat));
+            if (N->d_cat) HIPX(dfree(N->d_cat));
             N->d_cat = nullptr;
-            HIPX(hipMalloc((void**)&N->d_cat, sizeof(double) * need));
+            HIPX(dmalloc((void**)&N->d_cat, sizeof(double) * need));
             N->cat_cap = need;
         }
         double* B = N->d_cat;
@@ -2006,6 +2226,7 @@ mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const
             HIPX(hipMemcpy2DAsync(x_dev[q], sizeof(double) * S.seg_n[q], X + S.seg_row0[q], sizeof(double) * S.n,
                                   sizeof(double) * S.seg_n[q], nr, hipMemcpyDeviceToDevice, st));
         }
+        HIPX(hipStreamSynchronize(st));
         if (info)
             for (int q = 0; q < nseg; q++) info[q] = N->seg_info[q];
         if (rc != MF_OK) return fail(rc, msg);
@@ -2069,7 +2290,9 @@ void mf_release(void* handle) {
         delete h;
     } else if (magic == kNumMagic) {
         mf_num* N = (mf_num*)handle;
-        (void)hipDeviceSynchronize();
+        // its calls returned with their streams idle; this only guards against a
+        // caller that released the handle from another thread mid-call
+        (void)hipStreamSynchronize(N->last_stream);
         N->magic = 0;
         delete N;
     }

@@ -118,6 +118,12 @@ struct DevSym {
     const int64_t* seg_n;        // nseg: rows of each segment
 };
 
+// One block of a segmented copy: out[dst + i] = src[i] + add for i < count.
+struct SegCopy {
+    const void* src;
+    int64_t dst, count, add;
+};
+
 // Persistent sweeps (k_fwd_persist / k_bwd_persist): one launch per direction
 // runs every front of every system from a ticket-ordered list of tasks.  Fronts
 // of order <= kSwWhole are one task; larger fronts split into 64-row blocks of

@@ -54,12 +54,27 @@ struct Symbolic {
     double nominal_nnz_lu = 0.0;
     // systems of a batch (block-diagonal merge); one segment for a single system
     std::vector<int64_t> seg_row0{0}, seg_n{0}, seg_nnz0{0};
+    // A light merge keeps the pattern and the unique-entry maps of its systems
+    // where they are (their device copies) instead of concatenating them on the
+    // host: rowptr, colind and the ue_* arrays stay empty, and each (system,
+    // level) block of unique entries is described for a device-side copy.
+    struct UeBlock {
+        int32_t part;
+        int32_t slot_delta;   // batch slot = the system's own slot + slot_delta
+        int64_t u0, cnt;      // entries [u0, u0 + cnt) of the system's own maps
+        int64_t dst_u;        // their first batch entry
+        int64_t s0, scnt;     // their CSR sources [s0, s0 + scnt) in the system's map
+        int64_t dst_s;        // first batch source
+    };
+    bool light = false;
+    int64_t n_ue = 0, n_src = 0;
+    std::vector<UeBlock> ue_blocks;
 };
 
 // Block-diagonal merge of several analyzed patterns (a batch): fronts, rows and
 // maps are concatenated with offsets; each front keeps its height in its own
 // tree, so a tree level of the batch is the union of the systems' levels.
-void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts);
+void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts, bool light = false);
 
 // Runs the specified analysis; throws std::runtime_error / std::invalid_argument.
 void analyze_pattern(Symbolic& S, int64_t n, const int64_t* rowptr, const int32_t* colind,

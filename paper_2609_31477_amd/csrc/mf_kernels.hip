@@ -1873,6 +1873,36 @@ hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st) {
     return MF_CHECK_LAUNCH();
 }
 
+// Segmented copy with an offset per segment (start[s] = elements before segment
+// s, start[nseg] = total): the device-side concatenation of the pattern maps of
+// the systems of a batch.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_seg_copy(const SegCopy* __restrict__ segs, const int64_t* __restrict__ start,
+                                                       int nseg, T* __restrict__ out) {
+    const int64_t total = start[nseg];
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (int64_t)gridDim.x * kThreads) {
+        int lo = 0, hi = nseg - 1;  // last segment whose start is <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const SegCopy g = segs[lo];
+        const int64_t o = i - start[lo];
+        out[g.dst + o] = ((const T*)g.src)[o] + (T)g.add;
+    }
+}
+template <typename T>
+hipError_t launch_seg_copy(const SegCopy* segs, const int64_t* start, int nseg, int64_t total, T* out,
+                           hipStream_t st) {
+    if (nseg > 0 && total > 0)
+        hipLaunchKernelGGL(k_seg_copy<T>, dim3((unsigned)std::min<int64_t>((total + kThreads - 1) / kThreads, 8192)),
+                           dim3(kThreads), 0, st, segs, start, nseg, out);
+    return MF_CHECK_LAUNCH();
+}
+template hipError_t launch_seg_copy<int32_t>(const SegCopy*, const int64_t*, int, int64_t, int32_t*, hipStream_t);
+template hipError_t launch_seg_copy<int64_t>(const SegCopy*, const int64_t*, int, int64_t, int64_t*, hipStream_t);
+
 int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 
 // cls_mmax[kNClass], cls_Pmax[kNClass]: per panel class of this precision in the level (0 = none)

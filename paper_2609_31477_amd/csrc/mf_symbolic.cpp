@@ -504,7 +504,7 @@ void analyze_pattern(Symbolic& S, int64_t n, const int64_t* rowptr, const int32_
     }
 }
 
-void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
+void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts, bool light) {
     M = Symbolic();
     M.seg_row0.clear();
     M.seg_n.clear();
@@ -527,8 +527,13 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
     M.nnz = NNZ;
     M.nf = NF;
     M.leaf_max = parts.empty() ? 64 : parts[0]->leaf_max;
-    M.rowptr.resize(N + 1);
-    M.colind.resize(NNZ);
+    M.light = light;
+    M.n_ue = NUE;
+    M.n_src = NSRC;
+    if (!light) {
+        M.rowptr.resize(N + 1);
+        M.colind.resize(NNZ);
+    }
     M.root.reserve(NROOT);
     M.perm.resize(N);
     M.var_etree.resize(N);
@@ -541,7 +546,7 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
     M.level.resize(NF);
     M.imap.resize(NIMAP);
     M.imap_off.resize(NF + 1);
-    M.rowptr[0] = 0;
+    if (!light) M.rowptr[0] = 0;
     M.front_ptr[0] = 0;
     M.rows_ptr[0] = 0;
     M.imap_off[0] = 0;
@@ -553,8 +558,10 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
         M.seg_n.push_back(P.n);
         M.seg_nnz0.push_back(eoff);
         const int32_t v32 = (int32_t)voff;
-        for (int64_t r = 0; r < P.n; r++) M.rowptr[voff + r + 1] = P.rowptr[r + 1] + eoff;
-        for (int64_t t = 0; t < P.nnz; t++) M.colind[eoff + t] = P.colind[t] + v32;
+        if (!light) {
+            for (int64_t r = 0; r < P.n; r++) M.rowptr[voff + r + 1] = P.rowptr[r + 1] + eoff;
+            for (int64_t t = 0; t < P.nnz; t++) M.colind[eoff + t] = P.colind[t] + v32;
+        }
         for (int32_t v : P.root) M.root.push_back(v + v32);
         for (int64_t i = 0; i < P.n; i++) {
             M.perm[voff + i] = P.perm[i] + v32;
@@ -601,14 +608,45 @@ void merge_symbolic(Symbolic& M, const std::vector<const Symbolic*>& parts) {
     }
     // unique entries in level order, system by system within a level
     M.level_ue_ptr.assign(M.nlevels + 1, 0);
+    std::vector<int32_t> foffs(parts.size() + 1, 0);
+    for (size_t q = 0; q < parts.size(); q++) foffs[q + 1] = foffs[q] + parts[q]->nf;
+    if (light) {
+        // per (level, system): where the system's own maps go in the batch; a
+        // system's level-l fronts follow those of the systems before it, so
+        // batch slot = level start + fronts of earlier systems at l + own index
+        int64_t uo = 0, so = 0;
+        for (int32_t l = 0; l < M.nlevels; l++) {
+            int32_t before = 0;
+            for (size_t q = 0; q < parts.size(); q++) {
+                const Symbolic& P = *parts[q];
+                if (l >= P.nlevels) continue;
+                const int64_t u0 = P.level_ue_ptr[l], u1 = P.level_ue_ptr[l + 1];
+                const int32_t own = P.level_ptr[l + 1] - P.level_ptr[l];
+                Symbolic::UeBlock b;
+                b.part = (int32_t)q;
+                b.slot_delta = M.level_ptr[l] + before - P.level_ptr[l];
+                b.u0 = u0;
+                b.cnt = u1 - u0;
+                b.dst_u = uo;
+                b.s0 = P.ue_src_ptr[u0];
+                b.scnt = P.ue_src_ptr[u1] - P.ue_src_ptr[u0];
+                b.dst_s = so;
+                if (b.cnt) M.ue_blocks.push_back(b);
+                uo += b.cnt;
+                so += b.scnt;
+                before += own;
+            }
+            M.level_ue_ptr[l + 1] = uo;
+        }
+        if (M.nnz > INT32_MAX) throw std::invalid_argument("batch nnz above 2^31-1 is not supported");
+        return;
+    }
     M.ue_front.resize(NUE);
     M.ue_row.resize(NUE);
     M.ue_col.resize(NUE);
     M.ue_src_ptr.resize(NUE + 1);
     M.ue_src.resize(NSRC);
     M.ue_src_ptr[0] = 0;
-    std::vector<int32_t> foffs(parts.size() + 1, 0);
-    for (size_t q = 0; q < parts.size(); q++) foffs[q + 1] = foffs[q] + parts[q]->nf;
     int64_t uo = 0, so = 0;
     for (int32_t l = 0; l < M.nlevels; l++) {
         for (size_t q = 0; q < parts.size(); q++) {

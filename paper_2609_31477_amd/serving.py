@@ -97,10 +97,15 @@ MAX_LEVEL_FRONTS = 65535  # fronts per tree level of one batch (library limit)
 class Scheduler:
     """Admission by footprint + continuous batching over Newton steps."""
 
-    def __init__(self, backend, hbm_budget: int, max_slots: int = 64):
+    def __init__(self, backend, hbm_budget: int, max_slots: int = 64, max_cohorts: int | None = None):
+        """``max_cohorts``: at most this many cohorts active at once (None: no cap).
+        With a cap, arrivals wait while it is reached and then form one larger
+        cohort, so a tick runs a few large batches instead of many small ones
+        (each batch has a fixed cost per tree level)."""
         self.backend = backend
         self.budget = int(hbm_budget)
         self.max_slots = max_slots
+        self.max_cohorts = max_cohorts
         self.used = 0
         self.active: list[Request] = []
         self.waiting: list = []       # heap of (arrival, rid, request)
@@ -121,6 +126,8 @@ class Scheduler:
 
     def _admit(self, now):
         self._start_preparation(now)
+        if self.max_cohorts is not None and len({r.cohort for r in self.active}) >= self.max_cohorts:
+            return                     # cohort cap reached: arrivals gather for the next cohort
         cohort = self.cohorts
         admitted = 0
         levels = []
@@ -148,6 +155,10 @@ class Scheduler:
             self.active.append(req)
         if admitted:
             cohort += 1
+        form = getattr(self.backend, "form_cohort", None)
+        if form is not None:
+            for c in range(self.cohorts, cohort):
+                form(c, [r for r in self.active if r.cohort == c])
         self.cohorts = cohort
 
     def run(self, clock=None, idle_sleep=True, on_tick=None):
@@ -166,7 +177,11 @@ class Scheduler:
                 elif idle_sleep:
                     self.backend.idle_until(nxt, clock)
                 continue
-            batch = list(self.active)
+            ready = getattr(self.backend, "cohort_ready", None)
+            batch = [r for r in self.active if ready is None or ready(r.cohort)]
+            if not batch:              # every admitted cohort is still being merged
+                self.backend.wait_cohort(self.active[0].cohort)
+                continue
             ts = clock()
             infos = self.backend.step(batch)
             te = clock()
@@ -280,7 +295,8 @@ class MFBackend:
         self.sym_cache = {}     # mesh -> Future of its analysis (Symbolic, level fronts)
         self.sym_bytes = {}     # mesh -> device bytes of its pattern data (charged to the budget)
         self.times = {"prepare": 0.0, "analyze": 0.0, "merge": 0.0, "factor_solve": 0.0}
-        self.batches = {}       # tuple of request ids -> Batch (one per live cohort)
+        self.cohort_futs = {}   # cohort -> Future of its merged Batch
+        self.cohort_left = {}   # cohort -> requests not finished yet
 
     def build(self, req):
         from vivjac import build_2d, build_3d
@@ -359,22 +375,38 @@ class MFBackend:
         with self.lock:
             return int(sum(self.sym_bytes.values()))
 
-    def _run_cohort(self, key, members, stream):
+    def _merge(self, members):
         from . import Batch
-        B = self.batches.get(key)
-        if B is None:
-            tm = time.perf_counter()
-            B = Batch([r.state["sym"] for r in members])
-            with self.lock:
-                self.batches[key] = B
-                self.times["merge"] += time.perf_counter() - tm
+        tm = time.perf_counter()
+        B = Batch([r.state["sym"] for r in members])
+        with self.lock:
+            self.times["merge"] += time.perf_counter() - tm
+        return B
+
+    def form_cohort(self, cohort, members):
+        """A new cohort's merged analysis is built on the preparation pool, off the
+        tick path: the cohort takes its first step in the first tick after it."""
+        with self.lock:
+            self.cohort_left[cohort] = len(members)
+        self.cohort_futs[cohort] = self.prep_pool.submit(self._merge, members)
+
+    def cohort_ready(self, cohort):
+        f = self.cohort_futs.get(cohort)
+        return f is not None and f.done()
+
+    def wait_cohort(self, cohort):
+        self.cohort_futs[cohort].result()
+
+    def _run_cohort(self, cohort, members, stream):
+        B = self.cohort_futs[cohort].result()
         vals = [r.state["vals"][r.steps_done] for r in members]
         bs = [r.state["rhs"][r.steps_done] for r in members]
         xs = [r.state["xs"][r.steps_done] for r in members]
         with self.torch.cuda.stream(stream):
             # a cohort factors once per Newton step: from its second step on, the
-            # planned schedule replays as a captured HIP graph
-            B.factor(vals, stream=stream, prec=self.prec, target_omega=self.target, plan=2)
+            # planned schedule enqueues every level at once (one synchronization);
+            # cohorts run from several threads, so no graph is captured here
+            B.factor(vals, stream=stream, prec=self.prec, target_omega=self.target, plan=1)
             _, out = B.solve(bs, xs=xs, stream=stream)
         stream.synchronize()
         return {r.rid: {"omega": inf.omega, "outer": inf.outer_iters, "inner": inf.inner_iters}
@@ -382,22 +414,20 @@ class MFBackend:
 
     def step(self, batch):
         t0 = time.perf_counter()
-        merge0 = self.times["merge"]
         groups = {}
         for r in batch:
-            groups.setdefault((r.cohort, r.steps_done), []).append(r)
+            groups.setdefault(r.cohort, []).append(r)
         infos = {}
-        live = set()
         futs = []
-        for i, members in enumerate(groups.values()):
-            key = tuple(r.rid for r in members)
-            live.add(key)
-            futs.append(self.pool.submit(self._run_cohort, key, members, self.streams[i % len(self.streams)]))
+        for i, (cohort, members) in enumerate(groups.items()):
+            if len({r.steps_done for r in members}) != 1:
+                raise AssertionError("the requests of a cohort step together")
+            if cohort not in self.cohort_futs:   # stepped without a scheduler: merge now
+                self.form_cohort(cohort, members)
+            futs.append(self.pool.submit(self._run_cohort, cohort, members, self.streams[i % len(self.streams)]))
         for f in futs:                 # each cohort waits for its own stream
             infos.update(f.result())
-        self.times["factor_solve"] += time.perf_counter() - t0 - (self.times["merge"] - merge0)
-        for key in [k for k in self.batches if k not in live]:
-            self.batches.pop(key).release()
+        self.times["factor_solve"] += time.perf_counter() - t0
         return [infos[r.rid] for r in batch]
 
     def release(self, req):
@@ -405,13 +435,19 @@ class MFBackend:
         st["sym"] = None
         st["vals"] = None
         st["rhs"] = None
+        with self.lock:
+            self.cohort_left[req.cohort] -= 1
+            last = self.cohort_left[req.cohort] == 0
+        if last:                       # the cohort's batch goes with its last request
+            del self.cohort_left[req.cohort]
+            self.cohort_futs.pop(req.cohort).result().release()
 
     def close(self):
         self.pool.shutdown(wait=True)
         self.prep_pool.shutdown(wait=True)
-        for B in self.batches.values():
-            B.release()
-        self.batches.clear()
+        for f in self.cohort_futs.values():
+            f.result().release()
+        self.cohort_futs.clear()
 
     def idle_until(self, t, clock):
         dt = t - clock()

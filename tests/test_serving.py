@@ -175,3 +175,22 @@ def test_preparation_runs_off_the_tick_path():
     assert be.calls[0] == [0] and be.calls[1] == [0] and be.calls[2] == [0]
     assert 1 in be.calls[3]
     assert r1.admitted is not None and r1.admitted > r0.admitted
+
+
+def test_cohort_cap_bounds_concurrent_cohorts():
+    """With max_cohorts = 2 no tick runs more than two cohorts; every request
+    still finishes, and arrivals held back join a later, larger cohort."""
+    reqs = poisson_requests(60, rate=400.0, seed=11, allow_3d=False)
+    be = FakeBackend()
+    sch = Scheduler(be, hbm_budget=10 ** 12, max_cohorts=2)
+    for r in reqs:
+        sch.submit(r)
+    seen = []
+    done = sch.run(clock=be.clock, on_tick=lambda sc: seen.append(len({r.cohort for r in sc.active})))
+    assert len(done) == 60
+    assert max(seen) <= 2
+    free = Scheduler(FakeBackend(), hbm_budget=10 ** 12)
+    for r in poisson_requests(60, rate=400.0, seed=11, allow_3d=False):
+        free.submit(r)
+    free.run(clock=free.backend.clock)
+    assert sch.cohorts < free.cohorts            # fewer, larger cohorts under the cap
