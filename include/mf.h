@@ -309,7 +309,12 @@ mf_status mf_solve_noalloc(mf_num_t num, const double* b_dev, double* x_dev, int
  * the paper factors one system at a time (its method per system is unchanged).
  *
  * mf_batch_analyze merges already-analyzed systems into one block-diagonal plan
- * (a symbolic handle of its own; the inputs may be released afterwards).  Each
+ * (a symbolic handle of its own; the inputs may be released afterwards).  With
+ * a device present, each system's pattern maps go to the current device once
+ * (kept with the system's handle and shared with every batch it joins) and the
+ * batch's maps are concatenated there at its first factorization; the host then
+ * merges only per-front data.  Such a batch is factored on the device it was
+ * analyzed on (MF_ERR_ARG otherwise).  Each
  * system keeps its own fronts, tree heights, panel shapes and root front, and
  * every reduction of the solve and of the refinement is done per system, so a
  * system's factors and solution are bitwise the same alone and in any batch.
