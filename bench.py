@@ -354,9 +354,10 @@ def main():
     ap.add_argument("--ny", type=int, default=128)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--target-omega", type=float, default=1e-10)
-    ap.add_argument("--workload", default="newton", choices=["newton", "batch", "serving"],
+    ap.add_argument("--workload", default="newton", choices=["newton", "batch", "serving", "ale"],
                     help="newton: 256x128 Newton steps (default); batch: 64 uneven systems in one batched "
-                         "factor+solve; serving: Poisson request stream through the continuous-batching loop")
+                         "factor+solve; serving: Poisson request stream through the continuous-batching loop; "
+                         "ale: the full ALE Newton iteration (GPU assembly with shape derivatives) at 256x128")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--rates", default="", help="serving: comma-separated arrival rates, one run each")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests per rate")
@@ -396,6 +397,14 @@ def main():
         return bench_batch(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "ale":
+        r = bench_ale(args.nx, args.ny, args.seed)
+        res = {"metric": METRIC, "value": round(r["newton_iterations"] / r["seconds"], 4), "unit": "Newton iterations/s",
+               "n_gpus": 1, "steps": r["newton_iterations"], "warmup": 1, "ms_per_step": r["ms_per_iteration"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": r.pop("workload"), "n": r["n"], "nnz": r["nnz"]}, "ale": r}
+        print(json.dumps(res), flush=True)
+        return res
     dev = torch.device("cuda:0")
     t = time.perf_counter()
     s = build_2d(args.nx, args.ny, args.seed)
