@@ -167,6 +167,47 @@ def bench_ale(nx=256, ny=128, seed=1):
             "assembly_ms": round(t_jac, 4), "residual_ms": round(t_res, 4)}
 
 
+def bench_mixed_3d(steps=4, warmup=1):
+    """FP64 against FP32 and BF16 fronts (FP64 root, FP64 GMRES-IR to 1e-10) on the
+    3D box of the serving mix (24x12x6 hexahedra, n = 84,825): Newton steps with
+    the 1% value stream, one right-hand side each."""
+    import numpy as np
+    import torch
+
+    import paper_2609_31477_amd as mf
+    from vivjac import build_3d, newton_rhs, newton_values
+    s = build_3d(24, 12, 6, seed=3)
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    dev = torch.device("cuda:0")
+    vals = [torch.from_numpy(newton_values(s, k)).to(dev) for k in range(3)]
+    rhs = [torch.from_numpy(newton_rhs(s, k)[0].copy()).to(dev) for k in range(3)]
+    x = torch.empty_like(rhs[0])
+    out = {"workload": "3D box 24x12x6 hexahedra (n 84,825), Newton steps with 1% value changes, 1 RHS, "
+                       "omega <= 1e-10; mixed: FP64 root and FP64 GMRES-IR"}
+    for prec in ("fp64", "fp32", "bf16"):
+        num, ts, tf, inner, om = None, [], [], [], []
+        for it in range(warmup + steps):
+            k = it % 3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            num = S.factor(vals[k], numeric=num, prec=prec, target_omega=1e-10, max_outer=30)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = num.solve(rhs[k], x=x)
+            torch.cuda.synchronize()
+            if it >= warmup:
+                ts.append(time.perf_counter() - t0)
+                tf.append(t1 - t0)
+                inner.append(info.inner_iters)
+                om.append(info.omega)
+        num.release()
+        out[prec] = {"ms_per_step": round(1e3 * float(np.mean(ts)), 3), "factor_ms": round(1e3 * float(np.mean(tf)), 3),
+                     "inner_per_step": round(float(np.mean(inner)), 2), "omega_max": float(max(om))}
+    for prec in ("fp32", "bf16"):
+        out[prec]["speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out[prec]["ms_per_step"], 4)
+    return out
+
+
 def bench_batch(args, summary_only=False):
     """64 independent 2D systems (seeds 100-163, nx = 16 + 4 U{0..12}, ny = nx/2) factored
     and solved together, FP32 fronts (FP64 roots) with FP64 GMRES-IR to omega <= 1e-10."""
@@ -649,6 +690,8 @@ def main():
     if not args.no_extras and args.prec == "fp64":
         res["ale_newton"] = bench_ale()
         log(f"ale newton: {json.dumps(res['ale_newton'])}")
+        res["mixed_3d"] = bench_mixed_3d()
+        log(f"mixed 3d: {json.dumps(res['mixed_3d'])}")
         gm = {}
         for pr in ("fp64", "fp32", "bf16"):
             tf, fl = gemm_micro(pr)
