@@ -177,6 +177,29 @@ __device__ __forceinline__ void stage_diag(gptr<const T> F, int64_t m, int j0, i
     }
 }
 
+// The same staging in two halves, for a block task whose diagonal block does not
+// depend on what it waits for: the loads are issued before the waits (so they
+// are in flight meanwhile) and the block goes to LDS after the last update.
+template <typename T>
+struct DiagPre {
+    static constexpr int kQ = kSwB * kSwB / kSwT;
+    T tmp[kQ];
+    __device__ __forceinline__ void load(gptr<const T> F, int64_t m, int j0, int bs) {
+#pragma unroll
+        for (int q = 0; q < kQ; q++) {
+            const int e = threadIdx.x + q * kSwT, a = e / kSwB, r = e % kSwB;
+            tmp[q] = F[(j0 + min(r, bs - 1)) + (int64_t)(j0 + min(a, bs - 1)) * m];
+        }
+    }
+    __device__ __forceinline__ void store(int bs, T* dblk) const {
+#pragma unroll
+        for (int q = 0; q < kQ; q++) {
+            const int e = threadIdx.x + q * kSwT, a = e / kSwB, r = e % kSwB;
+            dblk[e] = (a < bs && r < bs) ? tmp[q] : T(0);
+        }
+    }
+};
+
 // acc[c] += sum_{a < n} F[r, col0 + a] y[a + c * ldy] for one row r (n <= 256),
 // in order of a, with the row's entries loaded 16 at a time ahead of their use.
 // NR: right-hand sides handled per pass (1, or kSwRhs with nrc of them live);
@@ -279,6 +302,35 @@ __device__ __forceinline__ void block_gemv(gptr<const T> F, int64_t m, int r0, i
     __syncthreads();
 }
 
+// block_gemv for one right-hand side in two halves: the row's tile entries are
+// loaded before the task waits for the vector block they multiply (they do not
+// depend on it), and the product is formed after the wait; the same operations
+// in the same order as block_gemv<T, 1>.
+template <typename T>
+struct GemvPre1 {
+    static constexpr int kQ = kSwB / 4;
+    T f[kQ];
+    __device__ __forceinline__ void load(gptr<const T> F, int64_t m, int r0, int nr, int col0, int ncol) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int r = r0 + min(lane, nr - 1);
+#pragma unroll
+        for (int q = 0; q < kQ; q++) f[q] = F[r + (int64_t)(col0 + min(w + 4 * q, ncol - 1)) * m];
+    }
+    __device__ __forceinline__ void gemv(int ncol, const double* y, double* part, double* sub) const {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQ; q++) {
+            const int a = w + 4 * q;
+            if (a < ncol) acc += (double)f[q] * y[a];
+        }
+        part[(w * kSwRhs) * 64 + lane] = acc;
+        __syncthreads();
+        if (w == 0) sub[0] = (part[lane] + part[kSwRhs * 64 + lane]) + (part[2 * kSwRhs * 64 + lane] + part[3 * kSwRhs * 64 + lane]);
+        __syncthreads();
+    }
+};
+
 struct SweepLds {
     double z[kSwWhole * kSwRhs];  // whole front: its rows; blocks: own rows [0, 64 nrc) and a vector block after
     union {                       // never live at the same time
@@ -331,18 +383,23 @@ __device__ void fwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     double* zr = L.z;              // own rows, column c at c * 64
     double* yb = L.z + 64 * kSwRhs;  // one finished block of y
     double* v = A.vec + d.voff * A.nrhs;
+    DiagPre<T> pre;
+    if (fs) pre.load(F, m, r0, nr);
     if (tid < nr) gather_row<NR>(A, s, d, r0 + tid, zr, r0, 64);
     const int nblk = fs ? (r0 / kSwB) : (k + kSwB - 1) / kSwB;
     for (int j = 0; j < nblk; j++) {
-        wait_geq(A, A.blk + s, j + 1);
         const int j0 = j * kSwB, bs = min(kSwB, k - j0);
+        GemvPre1<T> g;
+        if constexpr (NR == 1) g.load(F, m, r0, nr, j0, bs);  // in flight during the wait
+        wait_geq(A, A.blk + s, j + 1);
         for (int e = tid; e < bs * nrc; e += kSwT) {
             const int a = e % bs, c = e / bs;
             yb[a + c * 64] = ld_dev(v + j0 + a + (int64_t)(A.c0 + c) * m);
         }
         __syncthreads();
         double sub[NR];
-        block_gemv<T, NR>(F, m, r0, nr, j0, bs, yb, 64, nrc, L.u.part, sub);
+        if constexpr (NR == 1) g.gemv(bs, yb, L.u.part, sub);
+        else block_gemv<T, NR>(F, m, r0, nr, j0, bs, yb, 64, nrc, L.u.part, sub);
         if (tid < 64 && lane < nr) {
 #pragma unroll
             for (int c = 0; c < NR; c++)
@@ -352,7 +409,7 @@ __device__ void fwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     }
     if (fs) {
         T* dblk = (T*)L.u.dblk;
-        stage_diag<T>(F, m, r0, nr, dblk);
+        pre.store(nr, dblk);
         __syncthreads();
         if (tid < 64) solve_lower<T>(dblk, 0, nr, zr, 64, nrc);
         __syncthreads();
@@ -450,6 +507,8 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     double* v = A.vec + d.voff * A.nrhs;
     double* tr = L.z;
     double* xb = L.z + 64 * kSwRhs;
+    DiagPre<T> pre;
+    pre.load(F, m, r0, nr);
     if (tid < nr)
         for (int c = 0; c < nrc; c++) tr[tid + c * 64] = v[r0 + tid + (int64_t)(A.c0 + c) * m];
     for (int j0 = k; j0 < m; j0 += kSwB) {
@@ -471,15 +530,18 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     }
     const int nfs = (k + kSwB - 1) / kSwB, me = r0 / kSwB;
     for (int j = nfs - 1; j > me; j--) {
-        wait_geq(A, A.blk + s, nfs - j);
         const int j0 = j * kSwB, bs = min(kSwB, k - j0);
+        GemvPre1<T> g;
+        if constexpr (NR == 1) g.load(F, m, r0, nr, j0, bs);  // in flight during the wait
+        wait_geq(A, A.blk + s, nfs - j);
         for (int e = tid; e < bs * nrc; e += kSwT) {
             const int a = e % bs, c = e / bs;
             xb[a + c * 64] = ld_dev(v + j0 + a + (int64_t)(A.c0 + c) * m);
         }
         __syncthreads();
         double sub[NR];
-        block_gemv<T, NR>(F, m, r0, nr, j0, bs, xb, 64, nrc, L.u.part, sub);
+        if constexpr (NR == 1) g.gemv(bs, xb, L.u.part, sub);
+        else block_gemv<T, NR>(F, m, r0, nr, j0, bs, xb, 64, nrc, L.u.part, sub);
         if (tid < 64 && lane < nr) {
 #pragma unroll
             for (int c = 0; c < NR; c++)
@@ -488,7 +550,7 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
         __syncthreads();
     }
     T* dblk = (T*)L.u.dblk;
-    stage_diag<T>(F, m, r0, nr, dblk);
+    pre.store(nr, dblk);
     __syncthreads();
     if (tid < 64) solve_upper<T>(dblk, 0, nr, tr, 64, nrc);
     __syncthreads();
