@@ -583,7 +583,7 @@ __device__ void bwd_task(const SweepArgs& A, int s, int32_t code, SweepLds& L) {
 // One kernel per direction: work-groups take bundles of tasks by ticket until
 // the list is exhausted.
 template <bool FWD, int NR>
-__global__ __launch_bounds__(kSwT, 3) void k_sweep_persist(SweepArgs A) {
+__global__ __launch_bounds__(kSwT, NR == 1 ? 3 : 1) void k_sweep_persist(SweepArgs A) {
     __shared__ SweepLds L;
     __shared__ int ticket;
     for (;;) {
