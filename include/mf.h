@@ -75,8 +75,9 @@ typedef struct {
                               soon as the refined iterate meets target_omega (its
                               true FP64 residual is checked after every inner step),
                               which normally ends it first */
-    int32_t refine;        /* 0 = none, 1 = classical FP64 refinement, 2 = GMRES-IR
-                              (default: 1 for MF_FP64, 2 otherwise; -1 = by precision) */
+    int32_t refine;        /* 0 = none, 1 = classical FP64 refinement, 2 = GMRES-IR,
+                              3 = classical steps while each cuts omega at least tenfold,
+                              then GMRES-IR (default -1: 1 for MF_FP64, 3 otherwise) */
     int32_t panel_nb;      /* reserved (the panel width is chosen per front from its order) */
     int32_t profile;       /* 1 = time the factorization phases with HIP events on the
                               caller's stream (reported in mf_factor_info; default 0) */
@@ -236,10 +237,10 @@ mf_status mf_get_factor_info(mf_num_t num, mf_factor_info* info);
  *   b_dev, x_dev   device FP64, n x nrhs column-major with leading dimension ld >= n
  *                  (b_dev == x_dev is not allowed); read / written on `stream`
  *   info           may be NULL
- * Refinement: classical (x += M^{-1} r) for FP64 factors, GMRES-IR
+ * Refinement: classical (x += M^{-1} r) for FP64 factors; for reduced-precision
+ * factors classical steps while each cuts omega at least tenfold, then GMRES-IR
  * (left-preconditioned GMRES on M^{-1} J d = M^{-1} r, FP64 vectors, all
- * right-hand sides in lockstep) for reduced-precision factors, with the FP64
- * fallback of mf_options.fallback.  MF_ERR_NOT_CONVERGED leaves the best x
+ * right-hand sides in lockstep), with the FP64 fallback of mf_options.fallback.  MF_ERR_NOT_CONVERGED leaves the best x
  * written.  Errors: MF_ERR_STATE (no successful mf_factor), MF_ERR_ARG,
  * MF_ERR_DEVICE, MF_ERR_OOM.
  */

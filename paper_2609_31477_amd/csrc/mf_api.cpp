@@ -494,7 +494,7 @@ mf_status fail(mf_status st, const std::string& msg) {
 }
 
 void resolve_refine(mf_options& o) {
-    if (o.refine < 0) o.refine = (o.prec == MF_FP64) ? 1 : 2;
+    if (o.refine < 0) o.refine = (o.prec == MF_FP64) ? 1 : 3;
 }
 
 // The unique-entry maps and the CSR pattern of a light batch, concatenated on
@@ -1712,15 +1712,21 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
     // with a replaced operator the factors are only a preconditioner: plain
     // refinement may diverge, so the correction is always the Krylov one
     const int refine = (N->stale && o.refine > 0) ? 2 : o.refine;
+    // refine 3: classical steps while each cuts the worst active omega at least
+    // tenfold, the Krylov correction from the first step that does not
+    bool krylov = refine == 2;
     int it = 0;
     while (refine > 0 && it < o.max_outer) {
         bool any = false;
+        double before = 0.0;
         for (size_t q = 0; q < active.size(); q++) {
             active[q] = !(om[q] <= o.target_omega);
             any = any || active[q];
+            if (active[q]) before = std::max(before, om[q] == om[q] ? om[q] : INFINITY);
         }
         if (!any) break;
-        if (refine == 1) {
+        const bool classical = refine == 1 || (refine == 3 && !krylov);
+        if (classical) {
             apply_inverse(N, r, n, dv, n, nrhs, st);
         } else {
             const int mres = std::max(1, std::min(o.gmres_m, 200));
@@ -1735,6 +1741,12 @@ void do_solve(mf_num* N, const double* b, double* x, int nrhs, int64_t ld, hipSt
         HIPX(launch_axpy(N->sym->dev->S, n, x, ld, dv, n, N->d_active, nrhs, st));
         residual(N, b, ld, x, ld, r, nrhs, st, om, &et);
         it++;
+        if (refine == 3 && classical) {
+            double after = 0.0;
+            for (size_t q = 0; q < active.size(); q++)
+                if (active[q]) after = std::max(after, om[q] == om[q] ? om[q] : INFINITY);
+            if (!(after <= 0.1 * before)) krylov = true;
+        }
         for (int q = 0; q < nseg; q++) {
             bool stepped = false;
             double wq = 0.0, eq = 0.0;
@@ -1886,6 +1898,7 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
     }
     resolve_refine(N->opt);
     if (N->opt.prec < MF_FP64 || N->opt.prec > MF_BF16) return fail(MF_ERR_ARG, "bad precision");
+    if (N->opt.refine > 3) return fail(MF_ERR_ARG, "bad refinement mode (0..3, or -1 for the default)");
     if (!(N->opt.pivot_u >= 0.0 && N->opt.pivot_u <= 1.0)) return fail(MF_ERR_ARG, "pivot_u must be in [0, 1]");
     if (N->opt.scale < 0 || N->opt.scale > 64) return fail(MF_ERR_ARG, "scale must be in [0, 64] sweeps");
     if (N->opt.sweep < 0 || N->opt.sweep > 1) return fail(MF_ERR_ARG, "sweep must be 0 or 1");
@@ -2000,7 +2013,8 @@ static mf_status set_operator_common(mf_num_t N, const double* values_dev, const
         for (size_t q = 0; q < S.seg_n.size(); q++)
             if (!seg_values[q] && S.seg_n[q] > 0) return fail(MF_ERR_ARG, "values_dev[i] is null");
     if (opt) {
-        if (!(opt->target_omega > 0.0) || opt->max_outer < 0 || opt->gmres_m < 1 || !(opt->gmres_tol >= 0.0))
+        if (!(opt->target_omega > 0.0) || opt->max_outer < 0 || opt->gmres_m < 1 || !(opt->gmres_tol >= 0.0)
+            || opt->refine > 3)
             return fail(MF_ERR_ARG, "bad refinement options");
         N->opt.target_omega = opt->target_omega;
         N->opt.max_outer = opt->max_outer;

@@ -178,3 +178,21 @@ def test_ale_create_rejects_missing_coupling_and_bad_indices():
     with pytest.raises(mf.MFError) as e:
         Assembly(q)
     assert e.value.status == mf.MF_ERR_ARG and "tri" in str(e.value)
+
+
+def test_factor_rejects_bad_options_before_any_device_call():
+    """Option checks run on the host before the device is touched, so a bad
+    refinement mode or precision is an argument error with no handle made."""
+    import ctypes
+    rp, ci = graph_csr(4, [(0, 1), (1, 2), (2, 3)])
+    S = mf.Symbolic(4, rp, ci, [])
+    L = mf.lib()
+    for field, value in (("refine", 4), ("refine", 9), ("prec", 7), ("pivot_u", 2.0)):
+        o = mf.mf_options()
+        L.mf_default_options(ctypes.byref(o))
+        setattr(o, field, value)
+        h = ctypes.c_void_p()
+        st = L.mf_factor(S._h, ctypes.c_void_p(64), ctypes.byref(o), None, ctypes.byref(h))
+        assert st == mf.MF_ERR_ARG, (field, value)
+        assert h.value is None
+        assert field.split("_")[0] in L.mf_last_error().decode() or "precision" in L.mf_last_error().decode()
