@@ -9,7 +9,8 @@ to a componentwise backward error <= 1e-10.  Workload: the 2D construction at
 All inputs are resident in HBM before the timed region.
 
 Beside the headline it reports, on the same line: the mixed path on the same
-workload (FP32 fronts, FP64 root, FP64 GMRES-IR); the same matrix with eight
+workload (FP32 fronts, FP64 root, adaptive FP64 refinement: classical steps
+while each cuts omega tenfold, then GMRES-IR); the same matrix with eight
 right-hand sides in FP64, FP32 and BF16 (the precision comparison); the
 dominant kernel against its roofline and the Schur GEMM, solve sweeps and
 extend-add against theirs; a large-K Schur GEMM on one dense front in each
@@ -168,7 +169,7 @@ def bench_ale(nx=256, ny=128, seed=1):
 
 
 def bench_mixed_3d(steps=4, warmup=1):
-    """FP64 against FP32 and BF16 fronts (FP64 root, FP64 GMRES-IR to 1e-10) on the
+    """FP64 against FP32 and BF16 fronts (FP64 root, adaptive FP64 refinement to 1e-10) on the
     3D box of the serving mix (24x12x6 hexahedra, n = 84,825): Newton steps with
     the 1% value stream, one right-hand side each."""
     import numpy as np
@@ -183,7 +184,7 @@ def bench_mixed_3d(steps=4, warmup=1):
     rhs = [torch.from_numpy(newton_rhs(s, k)[0].copy()).to(dev) for k in range(3)]
     x = torch.empty_like(rhs[0])
     out = {"workload": "3D box 24x12x6 hexahedra (n 84,825), Newton steps with 1% value changes, 1 RHS, "
-                       "omega <= 1e-10; mixed: FP64 root and FP64 GMRES-IR"}
+                       "omega <= 1e-10; mixed: FP64 root and adaptive FP64 refinement (classical, then GMRES-IR)"}
     for prec in ("fp64", "fp32", "bf16"):
         num, ts, tf, inner, om = None, [], [], [], []
         for it in range(warmup + steps):
@@ -210,7 +211,7 @@ def bench_mixed_3d(steps=4, warmup=1):
 
 def bench_batch(args, summary_only=False):
     """64 independent 2D systems (seeds 100-163, nx = 16 + 4 U{0..12}, ny = nx/2) factored
-    and solved together, FP32 fronts (FP64 roots) with FP64 GMRES-IR to omega <= 1e-10."""
+    and solved together, FP32 fronts (FP64 roots) with adaptive FP64 refinement to omega <= 1e-10."""
     import numpy as np
     import torch
 
@@ -249,7 +250,7 @@ def bench_batch(args, summary_only=False):
     if summary_only:
         B.release()
         return {"workload": "64 uneven 2D systems (16x8..64x32 cells), one batched factor+solve per step, FP32 fronts, "
-                            "FP64 roots, GMRES-IR to omega<=1e-10, factorization replayed as a captured HIP graph",
+                            "FP64 roots, adaptive FP64 refinement to omega<=1e-10, factorization replayed as a captured HIP graph",
                 "value": round(64 * args.steps / el, 3), "unit": "solves/s",
                 "ms_per_step": round(1e3 * el / args.steps, 3), "p99_ms": round(1e3 * float(np.percentile(ts, 99)), 3),
                 "omega_max": float(max(i.omega for i in infos)), "steps": args.steps}
@@ -257,7 +258,7 @@ def bench_batch(args, summary_only=False):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "64 uneven 2D VIV Jacobians (16x8..64x32 cells, seeds 100-163), one batched "
-                                  "factor+solve per step, FP32 fronts, FP64 roots, FP64 GMRES-IR, omega<=1e-10",
+                                  "factor+solve per step, FP32 fronts, FP64 roots, adaptive FP64 refinement, omega<=1e-10",
                       "n_total": int(sum(s.n for s in systems)), "fronts": view.nfronts, "levels": view.nlevels},
            "front_tflops": round(view.nominal_flops * args.steps / el / 1e12, 4),
            "p99_ms": round(1e3 * float(np.percentile(ts, 99)), 3),
@@ -318,7 +319,7 @@ def serving_parts(meshes, seed=11):
 def bench_serving(args):
     """Poisson streams of mixed requests (70% 2D meshes 32x16..128x64 cells, 30% 3D
     boxes of 24x12x6 hexahedra; Re ~ U[100,300]; U_r ~ U[2,12] in 2D, U[2.5,17.5] in
-    3D), 5 Newton steps each, FP32 fronts + FP64 GMRES-IR to 1e-10, continuous
+    3D), 5 Newton steps each, FP32 fronts + adaptive FP64 refinement to 1e-10, continuous
     batching; one run per arrival rate."""
     import torch
 
@@ -376,7 +377,7 @@ def bench_serving(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"serving: {args.requests} Poisson requests per rate, {100 * (1 - args.mix_3d):.0f}% "
                                   f"2D meshes 32x16..128x64 cells, {100 * args.mix_3d:.0f}% 3D boxes 24x12x6, "
-                                  "5 Newton steps each, FP32 fronts + FP64 GMRES-IR, continuous batching, "
+                                  "5 Newton steps each, FP32 fronts + adaptive FP64 refinement, continuous batching, "
                                   f"at most {args.max_cohorts or 'any number of'} cohorts at once, "
                                   f"omega<={args.target_omega:g}", "rates": rates},
            "p50_request_ms": top["p50_request_ms"], "p99_request_ms": top["p99_request_ms"],
@@ -590,7 +591,7 @@ def main():
     }
     if mixed is not None:
         mv = args.steps / mixed["elapsed"]
-        res["mixed"] = {"precision": "fp32 fronts, fp64 root + GMRES-IR", "value": round(mv, 4), "unit": "solves/s",
+        res["mixed"] = {"precision": "fp32 fronts, fp64 root + adaptive refinement (classical, then GMRES-IR)", "value": round(mv, 4), "unit": "solves/s",
                         "ms_per_step": round(1e3 * mixed["elapsed"] / args.steps, 3),
                         "p99_ms": round(float(np.percentile(mixed["step_ms"], 99)), 3),
                         "factor_ms": round(1e3 * mixed["t_factor"], 3),
@@ -601,7 +602,7 @@ def main():
     if eight:
         base = eight["fp64"]["steps"] / eight["fp64"]["elapsed"]
         res["eight_rhs"] = {"workload": "the same 256x128 Newton steps with 8 right-hand sides N(0,1) per step; "
-                                        "mixed paths: FP64 root, FP64 residual, GMRES-IR over the 8 in lockstep",
+                                        "mixed paths: FP64 root, FP64 residual, adaptive refinement over the 8 in lockstep",
                             "unit": "solves/s (one solve = factor + 8-column solve)"}
         for pr, r in eight.items():
             v = r["steps"] / r["elapsed"]
