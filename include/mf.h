@@ -95,8 +95,10 @@ typedef struct {
                               storage, tile lists and launch shapes, and the following
                               factorizations on the handle enqueue all levels at once with
                               a single synchronization at the end; a front that outgrows
-                              its capacity makes that call repeat the factorization level
-                              by level (same result) and enlarges the plan.  On the
+                              its capacity makes that call factor the levels from that
+                              front's level on with per-level synchronization, on top of
+                              the planned levels below it (same result), and enlarges the
+                              plan.  On the
                               256x128 Jacobians it is no faster: the extra empty panel
                               rounds that capacities add cost about what the per-level
                               synchronizations do.  2 = the same, with the planned
@@ -223,7 +225,7 @@ typedef struct {
     double panel_flops;         /* nominal panel flops (no delays): per window pivot, scaling + rank-1 update */
     int32_t panel_launches;     /* panel kernel launches timed */
     int32_t planned;            /* 1 if this factorization ran on the planned schedule, 2 as a graph replay */
-    int32_t plan_fallbacks;     /* planned runs on this handle repeated level by level (overflow) */
+    int32_t plan_fallbacks;     /* planned runs on this handle finished level by level (overflow) */
     int32_t tuned;              /* 1 if this factorization used the tuner's chosen shapes */
 } mf_factor_info;
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -56,7 +57,7 @@ template <typename T>
 hipError_t launch_seg_copy(const SegCopy* segs, const int64_t* start, int nseg, int64_t total, T* out,
                            hipStream_t st);
 hipError_t launch_nonfinite(const double* v, int64_t nnz, unsigned long long* first, hipStream_t st);
-hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count,
+hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count, int level,
                               int32_t* overflow, hipStream_t st);
 hipError_t launch_residual(const DevSym& S, const double* val, int64_t n, const double* x, int64_t ldx,
                            const double* b, int64_t ldb, double* r, int64_t ldr, int nrhs,
@@ -823,19 +824,21 @@ void check_finite(const mf_num* N) {
 }
 
 // The planned schedule: every level enqueued at once, one synchronization at the
-// end.  Returns false (nothing usable) when a front outgrew its capacity.
-bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
+// end.  Returns -1 when it finished, else the first level where a front outgrew
+// its capacity: the levels below it are finished (factors, bookkeeping in h_fn,
+// storage in the plan's layout) and the caller continues from that level.
+int factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     mf_sym* H = N->sym;
     const Symbolic& S = H->S;
     SymDev& D = *H->dev;
     const mf_options& o = N->opt;
     mf_num::Plan& pl = N->plan;
     auto enqueue = [&](hipStream_t q) {
-        HIPX(launch_fill_i32(pl.d_flag, 0, q));
+        HIPX(launch_fill_i32(pl.d_flag, INT_MAX, q));
         for (int L = 0; L < S.nlevels; L++) {
             const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
             const bool full = o.tune && N->tuner.done() && (N->tuner.pick[L] & 1);
-            HIPX(launch_level_setup(D.S, N->d_fn, pl.d_tmpl, s0, s1 - s0, pl.d_flag, q));
+            HIPX(launch_level_setup(D.S, N->d_fn, pl.d_tmpl, s0, s1 - s0, L, pl.d_flag, q));
             const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
             if (pl.lvl_cnt[0][L])
                 HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, pl.lvl_mmax[0][L],
@@ -879,9 +882,10 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     HIPX(hipMemcpyAsync(pl.h_flag, pl.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
     check_finite(N);
-    if (*pl.h_flag) {
+    if (*pl.h_flag != INT_MAX) {
         N->plan_fallbacks++;
-        return false;
+        if (*pl.h_flag < 0 || *pl.h_flag >= S.nlevels) throw Fail{MF_ERR_STATE, "internal: bad overflow level"};
+        return *pl.h_flag;
     }
     for (int p = 0; p < 2; p++) {
         N->lvl_mmax[p] = pl.lvl_mmax[p];
@@ -897,7 +901,7 @@ bool factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
     N->info.tuned = (o.tune && N->tuner.done()) ? 1 : 0;
     N->info.plan_fallbacks = N->plan_fallbacks;
     N->factored = true;
-    return true;
+    return -1;
 }
 
 // The handle's own copy of the operator values (one array, or one per system of a
@@ -953,7 +957,13 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     }
     const bool use_plan = o.plan != 0 && o.profile == 0 && N->plan.valid && N->plan.prec == o.prec &&
                           !(o.tune && !N->tuner.done());  // tuner trials run level by level
-    if (use_plan && factor_planned(N, fvals, st)) return;
+    // first level factored here: above 0 when a planned run overflowed there (the
+    // levels below it are finished in the plan's storage, which the arenas keep)
+    int L0 = 0;
+    if (use_plan) {
+        L0 = factor_planned(N, fvals, st);
+        if (L0 < 0) return;
+    }
     if (N->fronts.chunks.empty()) {
         double tot = 0;
         for (int f = 0; f < nf; f++) tot += (double)S.mnom[f] * S.mnom[f];
@@ -962,17 +972,34 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         N->ints.grow_hint = (size_t)(sizeof(int32_t) * (S.rows.size() * 4 + (size_t)nf * (3 + 7 * kNBMax))) + (16u << 20);
         N->wsp.grow_hint = (64u << 20);
     }
-    N->fronts.reset();
-    N->ints.reset();
+    if (L0 == 0) {
+        N->fronts.reset();
+        N->ints.reset();
+    }
     for (int p = 0; p < 2; p++) {
-        N->lvl_mmax[p].assign(S.nlevels, 0);
-        N->lvl_Pmax[p].assign(S.nlevels, 0);
-        N->lvl_cnt[p].assign(S.nlevels, 0);
-        N->lvl_cls_mmax[p].assign(S.nlevels, {});
-        N->lvl_cls_Pmax[p].assign(S.nlevels, {});
+        if (L0 == 0) {
+            N->lvl_mmax[p].assign(S.nlevels, 0);
+            N->lvl_Pmax[p].assign(S.nlevels, 0);
+            N->lvl_cnt[p].assign(S.nlevels, 0);
+            N->lvl_cls_mmax[p].assign(S.nlevels, {});
+            N->lvl_cls_Pmax[p].assign(S.nlevels, {});
+            continue;
+        }
+        const mf_num::Plan& pl = N->plan;
+        N->lvl_mmax[p] = pl.lvl_mmax[p];
+        N->lvl_Pmax[p] = pl.lvl_Pmax[p];
+        N->lvl_cnt[p] = pl.lvl_cnt[p];
+        N->lvl_cls_mmax[p] = pl.lvl_cls_mmax[p];
+        N->lvl_cls_Pmax[p] = pl.lvl_cls_Pmax[p];
+        for (int L = L0; L < S.nlevels; L++) {
+            N->lvl_mmax[p][L] = N->lvl_Pmax[p][L] = N->lvl_cnt[p][L] = 0;
+            N->lvl_cls_mmax[p][L] = {};
+            N->lvl_cls_Pmax[p][L] = {};
+        }
     }
     std::vector<int32_t> dout(nf, 0);
     FrontNum* hf = N->h_fn;
+    for (int sl = 0; sl < S.level_ptr[L0]; sl++) dout[sl] = hf[sl].P - hf[sl].k;
     const bool prof = o.profile != 0;
     hipEvent_t ev[2][5] = {};
     if (prof)
@@ -997,11 +1024,11 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         HIPX(hipEventCreate(&N->tuner.e0));
         HIPX(hipEventCreate(&N->tuner.e1));
     }
-    int64_t voff = 0;
+    int64_t voff = L0 ? N->plan.vec_len : 0;  // after every vector block of the plan
     mf_factor_info info{};
     info.factor_flops = S.nominal_flops;
     int64_t front_bytes = 0;
-    for (int L = 0; L < S.nlevels; L++) {
+    for (int L = L0; L < S.nlevels; L++) {
         const int s0 = S.level_ptr[L], s1 = S.level_ptr[L + 1];
         for (int sl = s0; sl < s1; sl++) {
             const int f = S.level_fronts[sl];
@@ -1142,6 +1169,7 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
     }
     N->vec_len = voff;
     info.factor_bytes = front_bytes;
+    if (L0 > 0) info = finished_info(N);  // the levels below L0 are only in h_fn
     info.plan_fallbacks = N->plan_fallbacks;
     info.tuned = tuned ? 1 : 0;
     if (tuning && ++N->tuner.trials == mf_num::Tuner::kShapes)

@@ -37,6 +37,8 @@ __host__ __device__ inline int class_nb(int cls, int prec) {
 // Per-front numeric state, indexed by "slot" (fronts in level order, so the
 // fronts of one tree level are contiguous).  Written by the host before a level
 // is assembled; k / k0 are updated by the factorization kernels.
+// FrontNum::prec of a front that the planned schedule skips after a capacity overflow.
+constexpr int32_t kSkipPrec = 2;
 struct FrontNum {
     void* F;         // dense front, column-major m x m (double or float)
     int32_t* iv;     // rowpiv[P] | colperm[P] | rowperm[P] | colvar[m] | npairs, pairs[4*kNBMax]
@@ -46,7 +48,7 @@ struct FrontNum {
     int32_t din;     // delayed-in count
     int32_t k;       // eliminated so far / in total
     int32_t k0;      // k at the start of the current panel
-    int32_t prec;    // 0: double front, 1: float front
+    int32_t prec;    // 0: double front, 1: float front (kSkipPrec: no kernel takes it)
     int32_t npiv;    // nominal pivots
     int32_t mnom;    // nominal order
     int32_t pcur;    // end of the not-yet-tried fully summed columns [k, pcur); [pcur, P) are delayed

@@ -1143,11 +1143,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(FrontNum* fn, int slot0,
 // finished bookkeeping, and the front's order and fully summed count follow from
 // it.  Everything else (storage, scratch, vector offset) comes from the template,
 // whose din field holds the capacity the storage was sized for.  A front that
-// would outgrow it raises *overflow and is clamped to the capacity, which keeps
-// every later access of the level inside its allocations; the caller discards
-// such a factorization.  One thread per front.
+// would outgrow it lowers *overflow (INT_MAX when none) to its level and is
+// clamped to the capacity, which keeps every access inside its allocations.
+// From then on fronts are given a precision no kernel takes (kSkipPrec), so
+// the rest of the schedule only pays its launches; the caller redoes the levels
+// from the first overflowing one with per-level synchronization.  One thread
+// per front.
 __global__ __launch_bounds__(kThreads) void k_level_setup(DevSym S, FrontNum* fn, const FrontNum* tmpl, int slot0,
-                                                          int count, int32_t* overflow) {
+                                                          int count, int level, int32_t* overflow) {
     const int q = blockIdx.x * kThreads + threadIdx.x;
     if (q >= count) return;
     const int s = slot0 + q;
@@ -1157,9 +1160,11 @@ __global__ __launch_bounds__(kThreads) void k_level_setup(DevSym S, FrontNum* fn
         const int cs = S.child_slot[t];
         din += fn[cs].P - fn[cs].k;
     }
+    bool skip = *overflow != INT_MAX;  // an earlier level overflowed
     if (din > d.din) {
-        *overflow = 1;
+        atomicMin(overflow, level);
         din = d.din;
+        skip = true;
     }
     d.din = din;
     d.m = d.mnom + din;
@@ -1169,6 +1174,7 @@ __global__ __launch_bounds__(kThreads) void k_level_setup(DevSym S, FrontNum* fn
     d.pcur = d.P;
     d.x0 = 0;
     d.x1 = 0;
+    if (skip) d.prec = kSkipPrec;
     fn[s] = d;
 }
 
@@ -1849,11 +1855,11 @@ hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count,
+hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count, int level,
                               int32_t* overflow, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_level_setup, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, st, S, fn, tmpl,
-                       slot0, count, overflow);
+                       slot0, count, level, overflow);
     return MF_CHECK_LAUNCH();
 }
 // first[0] = smallest CSR position holding NaN or Inf (left at ~0 if none)

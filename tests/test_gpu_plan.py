@@ -2,8 +2,8 @@
 has factored once level by level, the next factorizations reuse its front
 capacities and enqueue every tree level at once.  They must produce exactly the factors of the level-by-level
 schedule (same arithmetic in every kernel, only storage and launch shapes
-differ), and a front that outgrows its capacity must make the call repeat the
-factorization level by level, again with the same result."""
+differ), and a front that outgrows its capacity must make the call continue
+level by level from that front's level, again with the same result."""
 import numpy as np
 import pytest
 
@@ -50,16 +50,19 @@ def test_planned_equals_levelwise(torch_cuda, prec, plan):
         assert np.array_equal(x_p, x_l)
 
 
-def test_plan_overflow_falls_back(torch_cuda):
+@pytest.mark.parametrize("plan", [1, 2])
+def test_plan_overflow_falls_back(torch_cuda, plan):
+    """The overflowing run keeps the planned levels below the first front that
+    outgrew its capacity and factors the rest level by level."""
     s = build_2d(32, 16, 1)
     S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
     v, b = newton_values(s, 0), newton_rhs(s, 0)[0]
     # u = 0 accepts any nonzero pivot: few delays, so small capacities (no solve:
     # such factors are too inaccurate for refinement to reach the target) ...
-    num = S.factor(torch_cuda.from_numpy(v).to(torch_cuda.device("cuda:0")), pivot_u=0.0, plan=1)
+    num = S.factor(torch_cuda.from_numpy(v).to(torch_cuda.device("cuda:0")), pivot_u=0.0, plan=plan)
     few = num.info().delayed_pivots
     # ... which u = 1 (pivot must be the largest entry of its column) outgrows
-    num, x1, _ = run(torch_cuda, S, v, b, num, pivot_u=1.0, plan=1)
+    num, x1, _ = run(torch_cuda, S, v, b, num, pivot_u=1.0, plan=plan)
     f1 = num.info()
     _, x_ref, _ = run(torch_cuda, S, v, b, None, pivot_u=1.0, plan=0)
     print(f"delayed: u=0 {few}, u=1 {f1.delayed_pivots}; planned={f1.planned} fallbacks={f1.plan_fallbacks}",
@@ -68,9 +71,9 @@ def test_plan_overflow_falls_back(torch_cuda):
     assert f1.planned == 0 and f1.plan_fallbacks == 1
     assert np.array_equal(x1, x_ref)
     # the enlarged plan now holds
-    num, x2, _ = run(torch_cuda, S, v, b, num, pivot_u=1.0, plan=1)
+    num, x2, _ = run(torch_cuda, S, v, b, num, pivot_u=1.0, plan=plan)
     f2 = num.info()
-    assert f2.planned == 1 and f2.plan_fallbacks == 1
+    assert f2.planned == plan and f2.plan_fallbacks == 1
     assert np.array_equal(x2, x_ref)
 
 
