@@ -415,12 +415,17 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     }
     uint64_t elim = 0;
     int nb = 0;
-    // The window rotates through the registers two columns at a time: in the pair
+    // The window rotates through the registers G columns at a time: in the group
     // of steps starting at column c0, slot j of every row holds window column
-    // (c0 + j) mod NB, so the columns being factored are slots 0 and 1, every
+    // (c0 + j) mod NB, so the columns being factored are slots 0 .. G-1, every
     // register index is a compile-time constant and the step loop stays rolled (a
-    // fully unrolled loop would not fit the instruction cache).  After NB / 2 pairs
-    // each column is back in its own slot.
+    // fully unrolled loop would not fit the instruction cache).  After NB / G
+    // groups each column is back in its own slot.
+    // (more where the window's registers leave room for the extra temporaries;
+    // G = NB needs no rotation at all)
+    constexpr int G = (NB == 8 || (NB % 8 == 0 && NB * RS * sizeof(T) <= 32 * sizeof(double))) ? 8
+                      : (NB % 4 == 0 && NB * RS * sizeof(T) <= 64 * sizeof(double))           ? 4
+                                                                                               : 2;
     static_assert(NB % 2 == 0, "window width must be even");
     // Eliminated columns keep their multipliers in place.  The published pivot row
     // carries zeros in the eliminated slots (written by the lanes of those slots after
@@ -547,16 +552,28 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
         for (int c = 0; c < w; c++) lds_barrier();
     } else {
 #pragma unroll 1
-        for (int c0 = 0; c0 < NB; c0 += 2) {
+        for (int c0 = 0; c0 < NB; c0 += G) {
             step(c0, std::integral_constant<int, 0>());
             step(c0, std::integral_constant<int, 1>());
+            if constexpr (G >= 4) {
+                step(c0, std::integral_constant<int, 2>());
+                step(c0, std::integral_constant<int, 3>());
+            }
+            if constexpr (G == 8) {
+                step(c0, std::integral_constant<int, 4>());
+                step(c0, std::integral_constant<int, 5>());
+                step(c0, std::integral_constant<int, 6>());
+                step(c0, std::integral_constant<int, 7>());
+            }
 #pragma unroll
             for (int r = 0; r < RS; r++) {
-                const T t0 = v[r][0], t1 = v[r][1];
+                T t[G];
 #pragma unroll
-                for (int j = 0; j + 2 < NB; j++) v[r][j] = v[r][j + 2];
-                v[r][NB - 2] = t0;
-                v[r][NB - 1] = t1;
+                for (int g = 0; g < G; g++) t[g] = v[r][g];
+#pragma unroll
+                for (int j = 0; j + G < NB; j++) v[r][j] = v[r][j + G];
+#pragma unroll
+                for (int g = 0; g < G; g++) v[r][NB - G + g] = t[g];
             }
         }
     }
