@@ -79,9 +79,16 @@ typedef struct {
 } ale_desc;
 
 /* Build the device data and the fixed-order summation lists (host work plus
- * uploads, once per problem).  Errors: MF_ERR_ARG (bad sizes or indices),
- * MF_ERR_PATTERN (a coupling missing from the pattern), MF_ERR_OOM,
- * MF_ERR_DEVICE. */
+ * uploads, once per problem, on the current device).  The description's arrays
+ * are host memory owned by the caller and copied here; they may be freed on
+ * return.  Errors: MF_ERR_ARG (bad sizes or indices), MF_ERR_PATTERN (a
+ * coupling missing from the pattern), MF_ERR_OOM, MF_ERR_DEVICE.
+ *
+ * The assembly calls below are enqueued on `stream` and return before they
+ * finish.  They share the handle's element scratch, so calls on one handle must
+ * be ordered (one stream, or synchronized between streams); different handles
+ * are independent.  A handle is used on the device it was created on
+ * (MF_ERR_ARG otherwise). */
 mf_status ale_create(const ale_desc* desc, ale_t* out);
 
 /* NL(U): U_dev and R_dev are device FP64 vectors of n entries, on `stream`. */
@@ -94,6 +101,8 @@ mf_status ale_jacobian(ale_t p, const double* U_dev, double* values_dev, double*
 /* Device bytes held by the problem (element scratch and summation lists). */
 int64_t ale_device_bytes(ale_t p);
 
+/* Free the handle's device data (the frees wait for the device's work).
+ * NULL is ignored. */
 void ale_release(ale_t p);
 
 #ifdef __cplusplus

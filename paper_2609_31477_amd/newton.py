@@ -11,7 +11,9 @@ than factoring again.
 
 Policy (host control only; every step runs in the library):
   * the first step, and any step after a refresh was called for, factors its own
-    values in ``prec`` and solves with GMRES-IR (FP64 fallback enabled);
+    values in ``prec`` and solves with the library's default refinement for that
+    precision (classical FP64 steps while they converge fast, then GMRES-IR; FP64
+    fallback enabled);
   * every other step replaces the operator and solves with the kept factors, with
     at most ``reuse_m`` x ``reuse_outer`` GMRES iterations per right-hand side and
     no fallback;
