@@ -26,12 +26,13 @@
 namespace mf {
 
 // kernel launchers (mf_kernels.hip)
-// ev (nullable): 4 events recorded after assembly, panels, Schur GEMM and finalize
+// ev (nullable): 4 events recorded after assembly, panels, Schur GEMM and finalize;
+// part 1: through the panel rounds, part 2: Schur GEMM and finalize, 0: all
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
                                const LevelTasks& tk, hipStream_t st, hipEvent_t* ev, bool bf16_schur,
-                               std::vector<hipEvent_t>* pev, bool panel_full = false);
+                               std::vector<hipEvent_t>* pev, bool panel_full = false, int part = 0);
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
@@ -430,6 +431,7 @@ struct mf_num {
         }
     } plan;
     int32_t plan_fallbacks = 0;
+    hipEvent_t ev_level = nullptr;  // end of a level's panel rounds (synchronizing schedule)
     // Launch-shape tuner (options.tune): per tree level, the panel block (4 or 8
     // waves for fronts of order <= 512) and the swap tile width (16 or 64
     // columns).  Neither changes any result.  Trial factorization c runs shape c
@@ -455,6 +457,7 @@ struct mf_num {
         sweep.free_device();
         if (d_bad) (void)dfree(d_bad);
         if (h_bad) (void)hfree(h_bad);
+        if (ev_level) (void)hipEventDestroy(ev_level);
         if (tuner.e0) (void)hipEventDestroy(tuner.e0);
         if (tuner.e1) (void)hipEventDestroy(tuner.e1);
         plan.free_device();
@@ -1093,24 +1096,40 @@ void do_factor(mf_num* N, const double* values_dev, hipStream_t st, const double
         const bool full = shape >= 0 && (shape & 1);
         const int64_t u0 = S.level_ue_ptr[L], u1 = S.level_ue_ptr[L + 1];
         if (tuning) HIPX(hipEventRecord(N->tuner.e0, st));
-        // fronts of both precisions may share a level; each kernel skips the other kind
-        if (N->lvl_cnt[0][L]) {
-            if (prof) HIPX(hipEventRecord(ev[0][0], st));
-            HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
-                                             N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), fvals,
-                                             u0, u1, o.pivot_u, 0, tk, st, prof ? &ev[0][1] : nullptr, false,
-                                             prof ? &pev : nullptr, full));
-        }
-        if (N->lvl_cnt[1][L]) {
-            if (prof) HIPX(hipEventRecord(ev[1][0], st));
-            HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
-                                            N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), fvals,
-                                            u0, u1, o.pivot_u, 1, tk, st, prof ? &ev[1][1] : nullptr,
-                                            o.prec == MF_BF16, prof ? &pev : nullptr, full));
-        }
+        // Outside profiling and tuning the level runs in two parts: the host waits only
+        // for the panel rounds (after which every delayed-out count is final) and sets
+        // up the next level while the Schur GEMM and finalize of this one run.  Every
+        // buffer the next set-up rewrites is either host memory this level no longer
+        // reads or device memory written in stream order after this level's kernels.
+        const bool split = !prof && !tuning;
+        auto launch = [&](int part) {
+            // fronts of both precisions may share a level; each kernel skips the other kind
+            if (N->lvl_cnt[0][L]) {
+                if (prof) HIPX(hipEventRecord(ev[0][0], st));
+                HIPX(launch_level_factor<double>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[0][L],
+                                                 N->lvl_cls_mmax[0][L].data(), N->lvl_cls_Pmax[0][L].data(), fvals,
+                                                 u0, u1, o.pivot_u, 0, tk, st, prof ? &ev[0][1] : nullptr, false,
+                                                 prof ? &pev : nullptr, full, part));
+            }
+            if (N->lvl_cnt[1][L]) {
+                if (prof) HIPX(hipEventRecord(ev[1][0], st));
+                HIPX(launch_level_factor<float>(D.S, N->d_fn, s0, s1 - s0, N->lvl_mmax[1][L],
+                                                N->lvl_cls_mmax[1][L].data(), N->lvl_cls_Pmax[1][L].data(), fvals,
+                                                u0, u1, o.pivot_u, 1, tk, st, prof ? &ev[1][1] : nullptr,
+                                                o.prec == MF_BF16, prof ? &pev : nullptr, full, part));
+            }
+        };
+        launch(split ? 1 : 0);
         if (tuning) HIPX(hipEventRecord(N->tuner.e1, st));
         HIPX(hipMemcpyAsync(hf + s0, N->d_fn + s0, sizeof(FrontNum) * (s1 - s0), hipMemcpyDeviceToHost, st));
-        HIPX(hipStreamSynchronize(st));
+        if (split) {
+            if (!N->ev_level) HIPX(hipEventCreateWithFlags(&N->ev_level, hipEventDisableTiming));
+            HIPX(hipEventRecord(N->ev_level, st));
+            launch(2);
+            HIPX(hipEventSynchronize(N->ev_level));
+        } else {
+            HIPX(hipStreamSynchronize(st));
+        }
         if (L == 0) check_finite(N);
         if (tuning) HIPX(hipEventElapsedTime(&N->tuner.ms[L][N->tuner.trials], N->tuner.e0, N->tuner.e1));
         info.levels++;
@@ -1937,9 +1956,13 @@ static mf_status factor_common(mf_sym_t h, const double* values_dev, const doubl
         do_factor(N, values_dev, (hipStream_t)stream, seg_values);
         HIPX(hipStreamSynchronize((hipStream_t)stream));  // every call returns with its stream idle
     } catch (const Fail& f) {
+        // also on errors (a level's Schur update may still be running when the
+        // bookkeeping read after its panel rounds reports a singular root)
+        (void)hipStreamSynchronize((hipStream_t)stream);
         if (fresh) *inout = fresh.release();  // keep the handle so the caller can release it
         return fail(f.st, f.msg);
     } catch (const std::bad_alloc&) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
         if (fresh) *inout = fresh.release();
         return fail(MF_ERR_OOM, "host allocation failed in mf_factor");
     }

@@ -1929,55 +1929,61 @@ template hipError_t launch_seg_copy<int64_t>(const SegCopy*, const int64_t*, int
 int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 
 // cls_mmax[kNClass], cls_Pmax[kNClass]: per panel class of this precision in the level (0 = none)
+// part 1: extend-add, value scatter and the panel rounds (after which every
+// front's eliminated count, and so its delayed-out count, is final); part 2: the
+// Schur GEMM and finalize; part 0: both.
 template <typename T>
 hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int count, int mmax, const int* cls_mmax,
                                const int* cls_Pmax, const double* vals, int64_t u0, int64_t u1, double u, int prec,
                                const LevelTasks& tk, hipStream_t st, hipEvent_t* ev, bool bf16_schur,
-                               std::vector<hipEvent_t>* pev, bool panel_full) {
+                               std::vector<hipEvent_t>* pev, bool panel_full, int part) {
     if (count <= 0) return hipSuccess;
     if (mmax > 4096) return hipErrorInvalidValue;
-    if (tk.ngather)
-        hipLaunchKernelGGL(k_gather<T>, dim3(tk.ngather), dim3(kThreads), 0, st, S, fn, slot0, prec, tk.gather);
-    if (u1 > u0)
-        hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                           st, S, fn, vals, u0, u1, prec);
-    if (ev) (void)hipEventRecord(ev[0], st);
-    int rounds = 0, Pmax = 0;
-    for (int c = 0; c < kNClass; c++) {
-        if (cls_mmax[c] <= 0) continue;
-        const int nbc = class_nb(c, prec);
-        rounds = std::max(rounds, (cls_Pmax[c] + nbc - 1) / nbc);
-        Pmax = std::max(Pmax, cls_Pmax[c]);
-    }
-    {
-        const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
-        for (int t = 0; t < rounds; t++) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (pev && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-                (void)hipEventRecord(e0, st);
-                pev->push_back(e0);
-                pev->push_back(e1);
+    if (part != 2) {
+        if (tk.ngather)
+            hipLaunchKernelGGL(k_gather<T>, dim3(tk.ngather), dim3(kThreads), 0, st, S, fn, slot0, prec, tk.gather);
+        if (u1 > u0)
+            hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((u1 - u0 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                               st, S, fn, vals, u0, u1, prec);
+        if (ev) (void)hipEventRecord(ev[0], st);
+        int rounds = 0, Pmax = 0;
+        for (int c = 0; c < kNClass; c++) {
+            if (cls_mmax[c] <= 0) continue;
+            const int nbc = class_nb(c, prec);
+            rounds = std::max(rounds, (cls_Pmax[c] + nbc - 1) / nbc);
+            Pmax = std::max(Pmax, cls_Pmax[c]);
+        }
+        {
+            const size_t panel_lds = 2 * sizeof(int) * (size_t)Pmax;
+            for (int t = 0; t < rounds; t++) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (pev && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+                    (void)hipEventRecord(e0, st);
+                    pev->push_back(e0);
+                    pev->push_back(e1);
+                }
+                // levels of class-0 fronts (order <= 512, window 32): 4 waves per front, one
+                // per SIMD, with one or two rows per lane (same arithmetic as 8 waves),
+                // unless panel_full asks for the 8-wave kernel
+                if (panel_full)
+                    hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+                else if (mmax <= kPanelSmallThreads)
+                    hipLaunchKernelGGL((k_panel_small<T, 1>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
+                                       slot0, u, prec);
+                else if (mmax <= 2 * kPanelSmallThreads)
+                    hipLaunchKernelGGL((k_panel_small<T, 2>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
+                                       slot0, u, prec);
+                else
+                    hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
+                if (e1) (void)hipEventRecord(e1, st);
+                if (tk.nswap)
+                    hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tk.nswap), dim3(kThreads), 0, st, fn, slot0, prec, tk.swap,
+                                       tk.swap_cols);
+                if (tk.ng0) hipLaunchKernelGGL(k_gemm<T>, dim3(tk.ng0), dim3(kThreads), 0, st, fn, slot0, 0, prec, tk.g0);
             }
-            // levels of class-0 fronts (order <= 512, window 32): 4 waves per front, one
-            // per SIMD, with one or two rows per lane (same arithmetic as 8 waves),
-            // unless panel_full asks for the 8-wave kernel
-            if (panel_full)
-                hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
-            else if (mmax <= kPanelSmallThreads)
-                hipLaunchKernelGGL((k_panel_small<T, 1>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
-                                   slot0, u, prec);
-            else if (mmax <= 2 * kPanelSmallThreads)
-                hipLaunchKernelGGL((k_panel_small<T, 2>), dim3(count), dim3(kPanelSmallThreads), panel_lds, st, fn,
-                                   slot0, u, prec);
-            else
-                hipLaunchKernelGGL(k_panel<T>, dim3(count), dim3(kPanelThreads), panel_lds, st, fn, slot0, u, prec);
-            if (e1) (void)hipEventRecord(e1, st);
-            if (tk.nswap)
-                hipLaunchKernelGGL(k_swap_trsm<T>, dim3(tk.nswap), dim3(kThreads), 0, st, fn, slot0, prec, tk.swap,
-                                   tk.swap_cols);
-            if (tk.ng0) hipLaunchKernelGGL(k_gemm<T>, dim3(tk.ng0), dim3(kThreads), 0, st, fn, slot0, 0, prec, tk.g0);
         }
     }
+    if (part == 1) return MF_CHECK_LAUNCH();
     if (ev) (void)hipEventRecord(ev[1], st);
     if (tk.ng1) {
         if (bf16_schur && sizeof(T) == 4)
@@ -1993,10 +1999,10 @@ hipError_t launch_level_factor(const DevSym& S, FrontNum* fn, int slot0, int cou
 
 template hipError_t launch_level_factor<double>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
                                                 const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
-                                                hipEvent_t*, bool, std::vector<hipEvent_t>*, bool);
+                                                hipEvent_t*, bool, std::vector<hipEvent_t>*, bool, int);
 template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, int, int, const int*, const int*,
                                                const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
-                                               hipEvent_t*, bool, std::vector<hipEvent_t>*, bool);
+                                               hipEvent_t*, bool, std::vector<hipEvent_t>*, bool, int);
 
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
