@@ -1418,7 +1418,7 @@ void apply_inverse(mf_num* N, const double* b, int64_t ldb, double* x, int64_t l
         // right-hand-side chunk so that the largest front's vectors fit in LDS
         int nrc = (int)std::max<size_t>(1, budget / (sizeof(double) * (size_t)mm));
         nrc = std::min(nrc, nrhs - c0);
-        if (hybrid) nrc = std::min(nrc, kSwRhs);
+        nrc = std::min(nrc, kSwRhs);  // the sweep kernels take at most kSwRhs columns per pass
         for (int L = 0; L < S.nlevels; L++) {
             if (!level_runs(L)) continue;
             const int s0 = S.level_ptr[L], cnt = S.level_ptr[L + 1] - s0;

@@ -1297,6 +1297,95 @@ __device__ __forceinline__ double row_dot_tiled(gptr<const T> Fcol0, int64_t m, 
     return (p[0] + p[1]) + (p[2] + p[3]);
 }
 
+// Several right-hand sides at once (NR of them, nrc live; column c of a vector
+// at c * ld): every factor entry is loaded once and used for all columns, and
+// each column's sum is formed with exactly the operations, in the order, of the
+// one-column function, so a column's result does not depend on how many are
+// solved together.  Columns c >= nrc repeat column nrc - 1; their results are
+// not used.
+template <typename T, int NR>
+__device__ __forceinline__ void block_dot_n(gptr<const T> Fi, int64_t m, const double* z, int ldz, int bs, int nrc,
+                                            double* out) {
+    if constexpr (NR == 1) {
+        out[0] = block_dot<T>(Fi, m, z, bs);
+    } else {
+        const double* zc[NR];
+        double acc[NR][8];
+#pragma unroll
+        for (int c = 0; c < NR; c++) {
+            zc[c] = z + min(c, nrc - 1) * ldz;
+#pragma unroll
+            for (int q = 0; q < 8; q++) acc[c][q] = 0.0;
+        }
+        if (bs == kBS) {
+            constexpr int kChunk = sizeof(T) == 4 ? kBS / 2 : kBS / 4;  // fewer ahead: the accumulators need the registers
+#pragma unroll
+            for (int c0 = 0; c0 < kBS; c0 += kChunk) {
+                T raw[kChunk];
+#pragma unroll
+                for (int a = 0; a < kChunk; a++) raw[a] = Fi[(int64_t)(c0 + a) * m];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int a = 0; a < kChunk; a++) {
+                    const double f = (double)raw[a];
+#pragma unroll
+                    for (int c = 0; c < NR; c++) acc[c][a & 7] += f * zc[c][c0 + a];
+                }
+            }
+        } else {
+            for (int a = 0; a < bs; a++) {
+                const double f = (double)Fi[(int64_t)a * m];
+#pragma unroll
+                for (int c = 0; c < NR; c++) acc[c][a & 7] += f * zc[c][a];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+            out[c] = ((acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3])) +
+                     ((acc[c][4] + acc[c][5]) + (acc[c][6] + acc[c][7]));
+    }
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ void row_dot_tiled_n(gptr<const T> Fcol0, int64_t m, const double* xv, int ldx, int ncols,
+                                                int nrc, double* out) {
+    if constexpr (NR == 1) {
+        out[0] = row_dot_tiled<T>(Fcol0, m, xv, ncols);
+    } else {
+        const double* xc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; c++) xc[c] = xv + min(c, nrc - 1) * ldx;
+        double p[NR][4];
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+            double a0[NR], a1[NR], a2[NR], a3[NR];
+#pragma unroll
+            for (int c = 0; c < NR; c++) a0[c] = a1[c] = a2[c] = a3[c] = 0.0;
+            int j = g;
+            for (; j + 12 < ncols; j += 16) {
+                const double f0 = (double)Fcol0[(int64_t)j * m], f1 = (double)Fcol0[(int64_t)(j + 4) * m];
+                const double f2 = (double)Fcol0[(int64_t)(j + 8) * m], f3 = (double)Fcol0[(int64_t)(j + 12) * m];
+#pragma unroll
+                for (int c = 0; c < NR; c++) {
+                    a0[c] += f0 * xc[c][j];
+                    a1[c] += f1 * xc[c][j + 4];
+                    a2[c] += f2 * xc[c][j + 8];
+                    a3[c] += f3 * xc[c][j + 12];
+                }
+            }
+            for (; j < ncols; j += 4) {
+                const double f0 = (double)Fcol0[(int64_t)j * m];
+#pragma unroll
+                for (int c = 0; c < NR; c++) a0[c] += f0 * xc[c][j];
+            }
+#pragma unroll
+            for (int c = 0; c < NR; c++) p[c][g] = (a0[c] + a1[c]) + (a2[c] + a3[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NR; c++) out[c] = (p[c][0] + p[c][1]) + (p[c][2] + p[c][3]);
+    }
+}
+
 // Diagonal blocks of the sweeps staged through LDS (blocks of more than one
 // wave): while the block's threads form the dot products of one diagonal block,
 // waves 1.. load the next block into registers and store it to LDS after their
@@ -1328,7 +1417,7 @@ struct DiagStage {
 
 // FUSE (one-wave blocks of small-front levels): the same block also forms
 // c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
-template <typename T, int TT, bool FUSE>
+template <typename T, int TT, bool FUSE, int NR>
 __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
                                                       const double* b, int64_t ldb, double* vec, int nrhs, int c0,
                                                       int nrc, const uint8_t* skip) {
@@ -1370,9 +1459,13 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
         }
     }
     __syncthreads();
+    // the diagonal blocks' chains: one right-hand side on wave 0; several, one
+    // per wave of a multi-wave block (or all on the one wave of a small-front block)
+    constexpr int kCW = (NR > 1 && TT > 64) ? (NR < TT / 64 ? NR : TT / 64) : 1;  // waves with chains
+    constexpr int kCN = NR / kCW;                                               // chains per wave
     for (int j0 = 0; j0 < k; j0 += kBS) {
         const int bs = min(kBS, k - j0);
-        if (wid == 0) {
+        if (wid < kCW && wid < nrc) {
             // every lane loads an in-range entry (row and column clamped into the
             // block) and masks it afterwards: the 64 loads are unconditional and all
             // in flight together instead of one branch (and wait) per column
@@ -1389,15 +1482,23 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             double Lr[kBS];
 #pragma unroll
             for (int a = 0; a < kBS; a++) Lr[a] = ((lane < bs) & (a < lane)) ? (double)raw[a] : 0.0;
-            for (int c = 0; c < nrc; c++) {
-                double x = lane < bs ? zs[j0 + lane + c * m] : 0.0;
+            // a wave's chains (columns wid + kCW q) step together: independent, so
+            // their latencies overlap; each is the one-column chain.  Columns
+            // >= nrc repeat column nrc - 1 and are not stored.
+            double x[kCN];
 #pragma unroll
-                for (int a = 0; a < kBS - 1; a++) {
-                    const double xa = readlane_d(x, a);  // uniform broadcast, no LDS round trip
-                    x -= Lr[a] * xa;
+            for (int q = 0; q < kCN; q++) x[q] = lane < bs ? zs[j0 + lane + min(wid + kCW * q, nrc - 1) * m] : 0.0;
+#pragma unroll
+            for (int a = 0; a < kBS - 1; a++) {
+#pragma unroll
+                for (int q = 0; q < kCN; q++) {
+                    const double xa = readlane_d(x[q], a);  // uniform broadcast, no LDS round trip
+                    x[q] -= Lr[a] * xa;
                 }
-                if (lane < bs) zs[j0 + lane + c * m] = x;
             }
+#pragma unroll
+            for (int q = 0; q < kCN; q++)
+                if (wid + kCW * q < nrc && lane < bs) zs[j0 + lane + (wid + kCW * q) * m] = x[q];
         }
         __syncthreads();
         if constexpr (kStage) {
@@ -1406,21 +1507,34 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             if (nxt) st1.load(F, m, j0 + kBS, min(kBS, k - j0 - kBS));
             for (int i = j0 + bs + tid; i < k; i += TT) {
                 const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
+                double o[NR];
+                block_dot_n<T, NR>(Fi, m, zs + j0, m, bs, nrc, o);
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) zs[i + c * m] -= o[c];
             }
             if (nxt) st1.store(dblk);
         } else {
             for (int i = j0 + bs + tid; i < k; i += TT) {
                 const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                for (int c = 0; c < nrc; c++) zs[i + c * m] -= block_dot<T>(Fi, m, zs + j0 + c * m, bs);
+                double o[NR];
+                block_dot_n<T, NR>(Fi, m, zs + j0, m, bs, nrc, o);
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) zs[i + c * m] -= o[c];
             }
         }
         __syncthreads();
     }
     if constexpr (FUSE) {
         if (k > 0) {
-            for (int i = k + tid; i < m; i += TT)
-                for (int c = 0; c < nrc; c++) zs[i + c * m] -= row_dot_tiled<T>(F + i, m, zs + c * m, k);
+            for (int i = k + tid; i < m; i += TT) {
+                double o[NR];
+                row_dot_tiled_n<T, NR>(F + i, m, zs, m, k, nrc, o);
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) zs[i + c * m] -= o[c];
+            }
             __syncthreads();
         }
     }
@@ -1453,12 +1567,60 @@ __device__ __forceinline__ double tile_dot(gptr<const T> Fcol0, int64_t m, const
     return r;
 }
 
+// tile_dot for NR right-hand sides (column c of xv at c * ldx; part holds NR x
+// 256 doubles): each entry loaded once, each column's sums formed and combined
+// as tile_dot does.  Wave 0 gets the results in out; columns >= nrc repeat
+// column nrc - 1.
+template <typename T, int NR>
+__device__ __forceinline__ void tile_dot_n(gptr<const T> Fcol0, int64_t m, const double* xv, int ldx, int ncols,
+                                           int nrc, double* part, double* out) {
+    if constexpr (NR == 1) {
+        out[0] = tile_dot<T>(Fcol0, m, xv, ncols, part);
+    } else {
+        const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+        const double* xc[NR];
+        double a0[NR], a1[NR], a2[NR], a3[NR];
+#pragma unroll
+        for (int c = 0; c < NR; c++) {
+            xc[c] = xv + min(c, nrc - 1) * ldx;
+            a0[c] = a1[c] = a2[c] = a3[c] = 0.0;
+        }
+        int j = g;
+        for (; j + 12 < ncols; j += 16) {
+            const double f0 = (double)Fcol0[(int64_t)j * m], f1 = (double)Fcol0[(int64_t)(j + 4) * m];
+            const double f2 = (double)Fcol0[(int64_t)(j + 8) * m], f3 = (double)Fcol0[(int64_t)(j + 12) * m];
+#pragma unroll
+            for (int c = 0; c < NR; c++) {
+                a0[c] += f0 * xc[c][j];
+                a1[c] += f1 * xc[c][j + 4];
+                a2[c] += f2 * xc[c][j + 8];
+                a3[c] += f3 * xc[c][j + 12];
+            }
+        }
+        for (; j < ncols; j += 4) {
+            const double f0 = (double)Fcol0[(int64_t)j * m];
+#pragma unroll
+            for (int c = 0; c < NR; c++) a0[c] += f0 * xc[c][j];
+        }
+#pragma unroll
+        for (int c = 0; c < NR; c++) part[(c * 4 + g) * 64 + lane] = (a0[c] + a1[c]) + (a2[c] + a3[c]);
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+            for (int c = 0; c < NR; c++)
+                out[c] = (part[(c * 4) * 64 + lane] + part[(c * 4 + 1) * 64 + lane]) +
+                         (part[(c * 4 + 2) * 64 + lane] + part[(c * 4 + 3) * 64 + lane]);
+        }
+        __syncthreads();
+    }
+}
+
 // c[i] = z[i] - sum_{j<k} L[i, j] y[j] for rows i in [k, m); block (x: 64-row tile, y: front)
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int slot0, int want_prec, double* vec,
                                                        int nrhs, int c0, int nrc, const uint8_t* skip) {
     extern __shared__ double ys[];
-    __shared__ double part[kThreads];
+    __shared__ double part[kThreads * NR];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
     if (d.prec != want_prec || (skip && skip[s])) return;
@@ -1471,19 +1633,22 @@ __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int s
         for (int c = 0; c < nrc; c++) ys[j + c * k] = v[j + (int64_t)(c0 + c) * m];
     __syncthreads();
     const int i = min(i0 + (int)(threadIdx.x & 63), m - 1);  // clamped rows compute, never store
-    for (int c = 0; c < nrc; c++) {
-        const double t = tile_dot<T>(F + i, m, ys + c * k, k, part);
-        if (threadIdx.x < 64 && i0 + (int)threadIdx.x < m) v[i + (int64_t)(c0 + c) * m] -= t;
+    double t[NR];
+    tile_dot_n<T, NR>(F + i, m, ys, k, k, nrc, part, t);
+    if (threadIdx.x < 64 && i0 + (int)threadIdx.x < m) {
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+            if (c < nrc) v[i + (int64_t)(c0 + c) * m] -= t[c];
     }
 }
 
 // t[i] = y[i] - sum_{j in [k,m)} U[i, j] x[colvar[j]] for rows i < k, in place in vec
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int slot0, int want_prec, const double* x,
                                                        int64_t ldx, double* vec, int nrhs, int c0, int nrc,
                                                        const uint8_t* skip) {
     extern __shared__ double xs[];
-    __shared__ double part[kThreads];
+    __shared__ double part[kThreads * NR];
     const int s = slot0 + blockIdx.y;
     const FrontNum d = fn[s];
     if (d.prec != want_prec || (skip && skip[s])) return;
@@ -1500,15 +1665,18 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
     }
     __syncthreads();
     const int i = min(i0 + (int)(threadIdx.x & 63), k - 1);  // clamped rows compute, never store
-    for (int c = 0; c < nrc; c++) {
-        const double t = tile_dot<T>(F + i + (int64_t)k * m, m, xs + c * nc, nc, part);
-        if (threadIdx.x < 64 && i0 + (int)threadIdx.x < k) v[i + (int64_t)(c0 + c) * m] -= t;
+    double t[NR];
+    tile_dot_n<T, NR>(F + i + (int64_t)k * m, m, xs, nc, nc, nrc, part, t);
+    if (threadIdx.x < 64 && i0 + (int)threadIdx.x < k) {
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+            if (c < nrc) v[i + (int64_t)(c0 + c) * m] -= t[c];
     }
 }
 
 // FUSE (one-wave blocks of small-front levels): the same block first forms
 // t = y - U12 x[colvar[k:m]], which k_bwd_gemv does otherwise.
-template <typename T, int TT, bool FUSE>
+template <typename T, int TT, bool FUSE, int NR>
 __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
                                                       int64_t ldx, const double* vec, int nrhs, int c0, int nrc,
                                                       const uint8_t* skip) {
@@ -1542,15 +1710,21 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
                 for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
             }
             __syncthreads();
-            for (int i = tid; i < k; i += TT)
-                for (int c = 0; c < nrc; c++)
-                    ts[i + c * k] -= row_dot_tiled<T>(F + i + (int64_t)k * m, m, xs + c * nc, nc);
+            for (int i = tid; i < k; i += TT) {
+                double o[NR];
+                row_dot_tiled_n<T, NR>(F + i + (int64_t)k * m, m, xs, nc, nc, nrc, o);
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) ts[i + c * k] -= o[c];
+            }
         }
     }
     __syncthreads();
+    constexpr int kCW = (NR > 1 && TT > 64) ? (NR < TT / 64 ? NR : TT / 64) : 1;  // waves with chains
+    constexpr int kCN = NR / kCW;                                               // chains per wave
     for (int j1 = k; j1 > 0; j1 -= kBS) {
         const int j0 = max(0, j1 - kBS), bs = j1 - j0;
-        if (wid == 0) {
+        if (wid < kCW && wid < nrc) {
             T raw[kBS];  // clamped unconditional loads, as in the forward sweep
             const int lr = j0 + min(lane, bs - 1);
             if constexpr (kStage) {
@@ -1569,19 +1743,26 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
             // dividing (within 1.5 ulp of the quotient)
             const int ld = min(lane, bs - 1);
             const double rd = 1.0 / (double)(kStage ? dblk[ld * kBS + ld] : F[lr + (int64_t)lr * m]);
-            for (int c = 0; c < nrc; c++) {
-                double xl = lane < bs ? ts[j0 + lane + c * k] : 0.0;
+            // a wave's chains step together, as in the forward sweep
+            double xl[kCN];
 #pragma unroll
-                for (int a = kBS - 1; a >= 0; a--) {
-                    if (a < bs) {
-                        // row a's value and diagonal reciprocal are broadcast from lane a
-                        const double xa = readlane_d(xl, a) * readlane_d(rd, a);
-                        if (lane == a) xl = xa;
-                        if (lane < a) xl -= Ur[a] * xa;
+            for (int q = 0; q < kCN; q++) xl[q] = lane < bs ? ts[j0 + lane + min(wid + kCW * q, nrc - 1) * k] : 0.0;
+#pragma unroll
+            for (int a = kBS - 1; a >= 0; a--) {
+                if (a < bs) {
+                    // row a's value and diagonal reciprocal are broadcast from lane a
+                    const double ra = readlane_d(rd, a);
+#pragma unroll
+                    for (int q = 0; q < kCN; q++) {
+                        const double xa = readlane_d(xl[q], a) * ra;
+                        if (lane == a) xl[q] = xa;
+                        if (lane < a) xl[q] -= Ur[a] * xa;
                     }
                 }
-                if (lane < bs) ts[j0 + lane + c * k] = xl;
             }
+#pragma unroll
+            for (int q = 0; q < kCN; q++)
+                if (wid + kCW * q < nrc && lane < bs) ts[j0 + lane + (wid + kCW * q) * k] = xl[q];
         }
         __syncthreads();
         if constexpr (kStage) {
@@ -1590,13 +1771,21 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
             if (nxt) st1.load(F, m, max(0, j0 - kBS), j0 - max(0, j0 - kBS));
             for (int i = tid; i < j0; i += TT) {
                 const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
+                double o[NR];
+                block_dot_n<T, NR>(Fi, m, ts + j0, k, bs, nrc, o);
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) ts[i + c * k] -= o[c];
             }
             if (nxt) st1.store(dblk);
         } else {
             for (int i = tid; i < j0; i += TT) {
                 const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                for (int c = 0; c < nrc; c++) ts[i + c * k] -= block_dot<T>(Fi, m, ts + j0 + c * k, bs);
+                double o[NR];
+                block_dot_n<T, NR>(Fi, m, ts + j0, k, bs, nrc, o);
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) ts[i + c * k] -= o[c];
             }
         }
         __syncthreads();
@@ -2004,22 +2193,46 @@ template hipError_t launch_level_factor<float>(const DevSym&, FrontNum*, int, in
                                                const double*, int64_t, int64_t, double, int, const LevelTasks&, hipStream_t,
                                                hipEvent_t*, bool, std::vector<hipEvent_t>*, bool, int);
 
+// One right-hand side per pass, or up to kSwRhs of them (nrc, at most kSwRhs).
+template <typename T, int NR>
+static void level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
+                      int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
+                      const uint8_t* skip) {
+    // levels of small fronts: one wave per front (the diagonal sweep is one wave's work anyway)
+    // (and the L21 product in the same one-wave block)
+    if (mmax <= kTriSmallOrder) {
+        hipLaunchKernelGGL((k_fwd_tri<T, 64, true, NR>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc,
+                           st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
+        return;
+    }
+    hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads, false, NR>), dim3(count), dim3(kTriThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
+    hipLaunchKernelGGL((k_fwd_gemv<T, NR>), dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc, skip);
+}
+template <typename T, int NR>
+static void level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx, const double* vec,
+                      int nrhs, int c0, int nrc, int mmax, hipStream_t st, const uint8_t* skip) {
+    if (mmax <= kTriSmallOrder) {  // U12 product and sweep in one one-wave block
+        hipLaunchKernelGGL((k_bwd_tri<T, 64, true, NR>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc,
+                           st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
+        return;
+    }
+    hipLaunchKernelGGL((k_bwd_gemv<T, NR>), dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc,
+                       skip);
+    hipLaunchKernelGGL((k_bwd_tri<T, kTriThreads, false, NR>), dim3(count), dim3(kTriThreads),
+                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
+}
+
 template <typename T>
 hipError_t launch_level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count, int prec, const double* b,
                             int64_t ldb, double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
                             const uint8_t* skip) {
     if (count <= 0) return hipSuccess;
-    // levels of small fronts: one wave per front (the diagonal sweep is one wave's work anyway)
-    // (and the L21 product in the same one-wave block)
-    if (mmax <= kTriSmallOrder) {
-        hipLaunchKernelGGL((k_fwd_tri<T, 64, true>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st,
-                           S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
-        return MF_CHECK_LAUNCH();
-    }
-    hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads, false>), dim3(count), dim3(kTriThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
-    hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, vec, nrhs, c0, nrc, skip);
+    if (nrc < 1 || nrc > kSwRhs) return hipErrorInvalidValue;
+    if (nrc == 1) level_fwd<T, 1>(S, fn, slot0, count, prec, b, ldb, vec, nrhs, c0, nrc, mmax, st, skip);
+    else level_fwd<T, kSwRhs>(S, fn, slot0, count, prec, b, ldb, vec, nrhs, c0, nrc, mmax, st, skip);
     return MF_CHECK_LAUNCH();
 }
 template <typename T>
@@ -2027,16 +2240,9 @@ hipError_t launch_level_bwd(const FrontNum* fn, int slot0, int count, int prec, 
                             const double* vec, int nrhs, int c0, int nrc, int mmax, hipStream_t st,
                             const uint8_t* skip) {
     if (count <= 0) return hipSuccess;
-    if (mmax <= kTriSmallOrder) {  // U12 product and sweep in one one-wave block
-        hipLaunchKernelGGL((k_bwd_tri<T, 64, true>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc, st,
-                           fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
-        return MF_CHECK_LAUNCH();
-    }
-    hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, (double*)vec, nrhs, c0, nrc,
-                       skip);
-    hipLaunchKernelGGL((k_bwd_tri<T, kTriThreads, false>), dim3(count), dim3(kTriThreads),
-                       sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
+    if (nrc < 1 || nrc > kSwRhs) return hipErrorInvalidValue;
+    if (nrc == 1) level_bwd<T, 1>(fn, slot0, count, prec, x, ldx, vec, nrhs, c0, nrc, mmax, st, skip);
+    else level_bwd<T, kSwRhs>(fn, slot0, count, prec, x, ldx, vec, nrhs, c0, nrc, mmax, st, skip);
     return MF_CHECK_LAUNCH();
 }
 template hipError_t launch_level_fwd<double>(const DevSym&, const FrontNum*, int, int, int, const double*, int64_t,

@@ -202,12 +202,11 @@ struct DiagPre {
 
 // acc[c] += sum_{a < n} F[r, col0 + a] y[a + c * ldy] for one row r (n <= 256),
 // in order of a, with the row's entries loaded 16 at a time ahead of their use.
-// NR: right-hand sides handled per pass (1, or kSwRhs with nrc of them live);
-// fewer entries are loaded ahead when NR > 1, to bound the registers.
+// NR: right-hand sides handled per pass (1, or kSwRhs with nrc of them live).
 template <typename T, int NR>
 __device__ __forceinline__ void row_dot(gptr<const T> F, int64_t m, int r, int col0, int n, const double* y, int ldy,
                                         int nrc, double* acc) {
-    constexpr int kC = NR == 1 ? 16 : 4;
+    constexpr int kC = 16;
     for (int a0 = 0; a0 < n; a0 += kC) {
         T f[kC];
 #pragma unroll
@@ -223,43 +222,69 @@ __device__ __forceinline__ void row_dot(gptr<const T> F, int64_t m, int r, int c
     }
 }
 
-// Wave 0: forward substitution with the unit lower diagonal block in LDS on
-// rows [j0, j0 + bs) of z (columns c at c * ldz).
-template <typename T>
+// Forward substitution with the unit lower diagonal block in LDS on rows
+// [j0, j0 + bs) of z (columns c at c * ldz), called by the whole work-group.
+// One right-hand side: wave 0.  Several: column c goes to wave c mod 4, and a
+// wave's chains advance together, one step at a time (each step reads the
+// block's column once), so their latencies overlap.  Each column's operations
+// are those of a chain run alone.  Columns c >= nrc repeat column nrc - 1 and
+// are not stored.
+template <int NR>
+struct ChainSplit {
+    static constexpr int kW = NR == 1 ? 1 : (NR < kSwT / 64 ? NR : kSwT / 64);  // waves with chains
+    static constexpr int kN = NR / kW;                                           // chains per wave
+};
+template <typename T, int NR>
 __device__ __forceinline__ void solve_lower(const T* dblk, int j0, int bs, double* z, int ldz, int nrc) {
-    const int lane = threadIdx.x & 63;
+    using C = ChainSplit<NR>;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= C::kW || w >= nrc) return;
+    double x[C::kN];
+#pragma unroll
+    for (int q = 0; q < C::kN; q++) x[q] = lane < bs ? z[j0 + lane + min(w + C::kW * q, nrc - 1) * ldz] : 0.0;
     // a fixed 63 steps (entries beyond the block are staged as zeros), so the
-    // loop unrolls by 8 and the LDS reads run ahead of the dependent chain
-    for (int c = 0; c < nrc; c++) {
-        double x = lane < bs ? z[j0 + lane + c * ldz] : 0.0;
+    // loop unrolls and the LDS reads run ahead of the dependent chains
 #pragma unroll 8
-        for (int a = 0; a < kSwB - 1; a++) {
-            const double l = (double)dblk[a * kSwB + lane];
-            const double xa = readlane_d(x, a);
-            if (lane > a) x -= l * xa;
+    for (int a = 0; a < kSwB - 1; a++) {
+        const double l = (double)dblk[a * kSwB + lane];
+#pragma unroll
+        for (int q = 0; q < C::kN; q++) {
+            const double xa = readlane_d(x[q], a);
+            if (lane > a) x[q] -= l * xa;
         }
-        if (lane < bs) z[j0 + lane + c * ldz] = x;
     }
+#pragma unroll
+    for (int q = 0; q < C::kN; q++)
+        if (w + C::kW * q < nrc && lane < bs) z[j0 + lane + (w + C::kW * q) * ldz] = x[q];
 }
 
-// Wave 0: back substitution with the upper diagonal block in LDS on rows
-// [j0, j0 + bs) of t (columns c at c * ldt).
-template <typename T>
+// Back substitution with the upper diagonal block in LDS on rows [j0, j0 + bs)
+// of t (columns c at c * ldt), by the whole work-group, the chains split over
+// the waves as in solve_lower.
+template <typename T, int NR>
 __device__ __forceinline__ void solve_upper(const T* dblk, int j0, int bs, double* t, int ldt, int nrc) {
-    const int lane = threadIdx.x & 63;
+    using C = ChainSplit<NR>;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= C::kW || w >= nrc) return;
     const int ld = min(lane, bs - 1);
     const double rd = 1.0 / (double)dblk[ld * kSwB + ld];
-    for (int c = 0; c < nrc; c++) {
-        double xl = lane < bs ? t[j0 + lane + c * ldt] : 0.0;
+    double xl[C::kN];
+#pragma unroll
+    for (int q = 0; q < C::kN; q++) xl[q] = lane < bs ? t[j0 + lane + min(w + C::kW * q, nrc - 1) * ldt] : 0.0;
 #pragma unroll 8
-        for (int a = kSwB - 1; a >= 0; a--) {
-            const double u = (double)dblk[a * kSwB + lane];
-            const double xa = readlane_d(xl, a) * readlane_d(rd, a);
-            if (lane == a) xl = xa;
-            if (lane < a) xl -= u * xa;
+    for (int a = kSwB - 1; a >= 0; a--) {
+        const double u = (double)dblk[a * kSwB + lane];
+        const double ra = readlane_d(rd, a);
+#pragma unroll
+        for (int q = 0; q < C::kN; q++) {
+            const double xa = readlane_d(xl[q], a) * ra;
+            if (lane == a) xl[q] = xa;
+            if (lane < a) xl[q] -= u * xa;
         }
-        if (lane < bs) t[j0 + lane + c * ldt] = xl;
     }
+#pragma unroll
+    for (int q = 0; q < C::kN; q++)
+        if (w + C::kW * q < nrc && lane < bs) t[j0 + lane + (w + C::kW * q) * ldt] = xl[q];
 }
 
 // acc[c] (rows r0 + lane) -= sum over the block's columns of F[r, col0 + a] y[a, c]:
@@ -273,7 +298,7 @@ __device__ __forceinline__ void block_gemv(gptr<const T> F, int64_t m, int r0, i
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; c++) acc[c] = 0.0;
-    constexpr int kC = NR == 1 ? kSwB / 4 : 4;
+    constexpr int kC = kSwB / 4;
     for (int q0 = 0; q0 < kSwB / 4; q0 += kC) {
         T f[kC];
 #pragma unroll
@@ -354,7 +379,7 @@ __device__ void fwd_whole(const SweepArgs& A, int s, const FrontNum& d, SweepLds
         const int bs = min(kSwB, k - j0);
         stage_diag<T>(F, m, j0, bs, dblk);
         __syncthreads();
-        if (tid < 64) solve_lower<T>(dblk, j0, bs, z, m, nrc);
+        solve_lower<T, NR>(dblk, j0, bs, z, m, nrc);
         __syncthreads();
         if (tid >= j0 + bs && tid < m) {
             double acc[NR];
@@ -411,7 +436,7 @@ __device__ void fwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
         T* dblk = (T*)L.u.dblk;
         pre.store(nr, dblk);
         __syncthreads();
-        if (tid < 64) solve_lower<T>(dblk, 0, nr, zr, 64, nrc);
+        solve_lower<T, NR>(dblk, 0, nr, zr, 64, nrc);
         __syncthreads();
     }
     if (tid < nr)
@@ -475,7 +500,7 @@ __device__ void bwd_whole(const SweepArgs& A, int s, const FrontNum& d, SweepLds
         __syncthreads();
         stage_diag<T>(F, m, j0, bs, dblk);
         __syncthreads();
-        if (tid < 64) solve_upper<T>(dblk, j0, bs, t, k, nrc);
+        solve_upper<T, NR>(dblk, j0, bs, t, k, nrc);
         __syncthreads();
         if (tid < j0) {
             double acc[NR];
@@ -552,7 +577,7 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     T* dblk = (T*)L.u.dblk;
     pre.store(nr, dblk);
     __syncthreads();
-    if (tid < 64) solve_upper<T>(dblk, 0, nr, tr, 64, nrc);
+    solve_upper<T, NR>(dblk, 0, nr, tr, 64, nrc);
     __syncthreads();
     if (tid < nr) {
         const int var = colvar[r0 + tid];
