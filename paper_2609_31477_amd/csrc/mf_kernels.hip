@@ -1490,6 +1490,9 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
             for (int q = 0; q < kCN; q++) x[q] = lane < bs ? zs[j0 + lane + min(wid + kCW * q, nrc - 1) * m] : 0.0;
 #pragma unroll
             for (int a = 0; a < kBS - 1; a++) {
+                // the steps after the block's last row would only subtract zeros
+                // (Lr vanishes there): a small front stops after bs - 1 steps
+                if (a + 1 >= bs) break;
 #pragma unroll
                 for (int q = 0; q < kCN; q++) {
                     const double xa = readlane_d(x[q], a);  // uniform broadcast, no LDS round trip
@@ -2271,7 +2274,11 @@ __global__ __launch_bounds__(kThreads) void k_ruiz_max(const int64_t* rp, const 
             const int j = ci[t];
             const double a = fabs(di * val[t] * dc[j]);
             mx = fmax(mx, a);
-            atomicMax(cmax + j, (unsigned long long)__double_as_longlong(a));
+            // a plain read first: any value it returns is at most the column's
+            // current maximum, so the atomic is skipped only where it could not
+            // raise it (most entries, once a column's large entries have landed)
+            const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
+            if (ab > cmax[j]) atomicMax(cmax + j, ab);
         }
     }
     for (int off = 8; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 16));
