@@ -1318,7 +1318,8 @@ __device__ __forceinline__ void block_dot_n(gptr<const T> Fi, int64_t m, const d
             for (int q = 0; q < 8; q++) acc[c][q] = 0.0;
         }
         if (bs == kBS) {
-            constexpr int kChunk = sizeof(T) == 4 ? kBS / 2 : kBS / 4;  // fewer ahead: the accumulators need the registers
+            // fewer entries ahead than block_dot: the accumulators need the registers
+            constexpr int kChunk = sizeof(T) == 4 ? kBS / 2 : kBS / 4;
 #pragma unroll
             for (int c0 = 0; c0 < kBS; c0 += kChunk) {
                 T raw[kChunk];
@@ -1418,9 +1419,10 @@ struct DiagStage {
 // FUSE (one-wave blocks of small-front levels): the same block also forms
 // c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
 template <typename T, int TT, bool FUSE, int NR>
-__global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0, int want_prec,
-                                                      const double* b, int64_t ldb, double* vec, int nrhs, int c0,
-                                                      int nrc, const uint8_t* skip) {
+__global__ __launch_bounds__(TT, TT == 64 && NR > 1 ? 3 : 1) void k_fwd_tri(DevSym S, const FrontNum* fn, int slot0,
+                                                                   int want_prec, const double* b, int64_t ldb,
+                                                                   double* vec, int nrhs, int c0, int nrc,
+                                                                   const uint8_t* skip) {
     extern __shared__ double zs[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
@@ -1459,86 +1461,92 @@ __global__ __launch_bounds__(TT) void k_fwd_tri(DevSym S, const FrontNum* fn, in
         }
     }
     __syncthreads();
-    // the diagonal blocks' chains: one right-hand side on wave 0; several, one
-    // per wave of a multi-wave block (or all on the one wave of a small-front block)
-    constexpr int kCW = (NR > 1 && TT > 64) ? (NR < TT / 64 ? NR : TT / 64) : 1;  // waves with chains
-    constexpr int kCN = NR / kCW;                                               // chains per wave
-    for (int j0 = 0; j0 < k; j0 += kBS) {
-        const int bs = min(kBS, k - j0);
-        if (wid < kCW && wid < nrc) {
-            // every lane loads an in-range entry (row and column clamped into the
-            // block) and masks it afterwards: the 64 loads are unconditional and all
-            // in flight together instead of one branch (and wait) per column
-            T raw[kBS];
-            const int lr = j0 + min(lane, bs - 1);
-            if constexpr (kStage) {
+    // the columns in groups of NR (one group unless a one-wave block serves more
+    // columns than NR; a staged block, TT > 64, is always called with nrc <= NR)
+    for (int cg = 0; cg < nrc; cg += NR) {
+        double* const zg = zs + (int64_t)cg * m;
+        const int ng = min(NR, nrc - cg);
+        // the diagonal blocks' chains: one right-hand side on wave 0; several, one
+        // per wave of a multi-wave block (or all on the one wave of a small-front block)
+        constexpr int kCW = (NR > 1 && TT > 64) ? (NR < TT / 64 ? NR : TT / 64) : 1;  // waves with chains
+        constexpr int kCN = NR / kCW;                                               // chains per wave
+        for (int j0 = 0; j0 < k; j0 += kBS) {
+            const int bs = min(kBS, k - j0);
+            if (wid < kCW && wid < ng) {
+                // every lane loads an in-range entry (row and column clamped into the
+                // block) and masks it afterwards: the 64 loads are unconditional and all
+                // in flight together instead of one branch (and wait) per column
+                T raw[kBS];
+                const int lr = j0 + min(lane, bs - 1);
+                if constexpr (kStage) {
 #pragma unroll
-                for (int a = 0; a < kBS; a++) raw[a] = dblk[a * kBS + lane];
-            } else {
+                    for (int a = 0; a < kBS; a++) raw[a] = dblk[a * kBS + lane];
+                } else {
 #pragma unroll
-                for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
-            }
-            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
-            double Lr[kBS];
-#pragma unroll
-            for (int a = 0; a < kBS; a++) Lr[a] = ((lane < bs) & (a < lane)) ? (double)raw[a] : 0.0;
-            // a wave's chains (columns wid + kCW q) step together: independent, so
-            // their latencies overlap; each is the one-column chain.  Columns
-            // >= nrc repeat column nrc - 1 and are not stored.
-            double x[kCN];
-#pragma unroll
-            for (int q = 0; q < kCN; q++) x[q] = lane < bs ? zs[j0 + lane + min(wid + kCW * q, nrc - 1) * m] : 0.0;
-#pragma unroll
-            for (int a = 0; a < kBS - 1; a++) {
-                // the steps after the block's last row would only subtract zeros
-                // (Lr vanishes there): a small front stops after bs - 1 steps
-                if (a + 1 >= bs) break;
-#pragma unroll
-                for (int q = 0; q < kCN; q++) {
-                    const double xa = readlane_d(x[q], a);  // uniform broadcast, no LDS round trip
-                    x[q] -= Lr[a] * xa;
+                    for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
                 }
-            }
+                if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+                double Lr[kBS];
 #pragma unroll
-            for (int q = 0; q < kCN; q++)
-                if (wid + kCW * q < nrc && lane < bs) zs[j0 + lane + (wid + kCW * q) * m] = x[q];
-        }
-        __syncthreads();
-        if constexpr (kStage) {
-            const bool nxt = wid > 0 && j0 + kBS < k;
-            DiagStage<T, TT> st1;
-            if (nxt) st1.load(F, m, j0 + kBS, min(kBS, k - j0 - kBS));
-            for (int i = j0 + bs + tid; i < k; i += TT) {
-                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                double o[NR];
-                block_dot_n<T, NR>(Fi, m, zs + j0, m, bs, nrc, o);
+                for (int a = 0; a < kBS; a++) Lr[a] = ((lane < bs) & (a < lane)) ? (double)raw[a] : 0.0;
+                // a wave's chains (columns wid + kCW q) step together: independent, so
+                // their latencies overlap; each is the one-column chain.  Columns
+                // >= ng repeat column ng - 1 and are not stored.
+                double x[kCN];
 #pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) zs[i + c * m] -= o[c];
-            }
-            if (nxt) st1.store(dblk);
-        } else {
-            for (int i = j0 + bs + tid; i < k; i += TT) {
-                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                double o[NR];
-                block_dot_n<T, NR>(Fi, m, zs + j0, m, bs, nrc, o);
+                for (int q = 0; q < kCN; q++) x[q] = lane < bs ? zg[j0 + lane + min(wid + kCW * q, ng - 1) * m] : 0.0;
 #pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) zs[i + c * m] -= o[c];
-            }
-        }
-        __syncthreads();
-    }
-    if constexpr (FUSE) {
-        if (k > 0) {
-            for (int i = k + tid; i < m; i += TT) {
-                double o[NR];
-                row_dot_tiled_n<T, NR>(F + i, m, zs, m, k, nrc, o);
+                for (int a = 0; a < kBS - 1; a++) {
+                    // the steps after the block's last row would only subtract zeros
+                    // (Lr vanishes there): a small front stops after bs - 1 steps
+                    if (a + 1 >= bs) break;
 #pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) zs[i + c * m] -= o[c];
+                    for (int q = 0; q < kCN; q++) {
+                        const double xa = readlane_d(x[q], a);  // uniform broadcast, no LDS round trip
+                        x[q] -= Lr[a] * xa;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kCN; q++)
+                    if (wid + kCW * q < ng && lane < bs) zg[j0 + lane + (wid + kCW * q) * m] = x[q];
             }
             __syncthreads();
+            if constexpr (kStage) {
+                const bool nxt = wid > 0 && j0 + kBS < k;
+                DiagStage<T, TT> st1;
+                if (nxt) st1.load(F, m, j0 + kBS, min(kBS, k - j0 - kBS));
+                for (int i = j0 + bs + tid; i < k; i += TT) {
+                    const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                    double o[NR];
+                    block_dot_n<T, NR>(Fi, m, zg + j0, m, bs, ng, o);
+#pragma unroll
+                    for (int c = 0; c < NR; c++)
+                        if (c < ng) zg[i + c * m] -= o[c];
+                }
+                if (nxt) st1.store(dblk);
+            } else {
+                for (int i = j0 + bs + tid; i < k; i += TT) {
+                    const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                    double o[NR];
+                    block_dot_n<T, NR>(Fi, m, zg + j0, m, bs, ng, o);
+#pragma unroll
+                    for (int c = 0; c < NR; c++)
+                        if (c < ng) zg[i + c * m] -= o[c];
+                }
+            }
+            __syncthreads();
+        }
+        if constexpr (FUSE) {
+            if (k > 0) {
+                for (int i = k + tid; i < m; i += TT) {
+                    double o[NR];
+                    row_dot_tiled_n<T, NR>(F + i, m, zg, m, k, ng, o);
+#pragma unroll
+                    for (int c = 0; c < NR; c++)
+                        if (c < ng) zg[i + c * m] -= o[c];
+                }
+                __syncthreads();
+            }
         }
     }
     for (int i = tid; i < m; i += TT)
@@ -1680,9 +1688,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
 // FUSE (one-wave blocks of small-front levels): the same block first forms
 // t = y - U12 x[colvar[k:m]], which k_bwd_gemv does otherwise.
 template <typename T, int TT, bool FUSE, int NR>
-__global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec, double* x,
-                                                      int64_t ldx, const double* vec, int nrhs, int c0, int nrc,
-                                                      const uint8_t* skip) {
+__global__ __launch_bounds__(TT, TT == 64 && NR > 1 ? 3 : 1) void k_bwd_tri(const FrontNum* fn, int slot0, int want_prec,
+                                                                   double* x, int64_t ldx, const double* vec, int nrhs,
+                                                                   int c0, int nrc, const uint8_t* skip) {
     extern __shared__ double ts[];
     const int s = slot0 + blockIdx.x;
     const FrontNum d = fn[s];
@@ -1704,94 +1712,104 @@ __global__ __launch_bounds__(TT) void k_bwd_tri(const FrontNum* fn, int slot0, i
     }
     for (int i = tid; i < k; i += TT)
         for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
+    // FUSE: the solution values of the columns [k, m), after ts
+    double* const xs = ts + (int64_t)k * nrc;
+    const int nc = m - k;
     if constexpr (FUSE) {
-        const int nc = m - k;
         if (nc > 0 && k > 0) {
-            double* xs = ts + (int64_t)k * nrc;  // the columns' solution values, after ts
             for (int j = tid; j < nc; j += TT) {
                 const int var = colvar[k + j];
                 for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
             }
-            __syncthreads();
-            for (int i = tid; i < k; i += TT) {
-                double o[NR];
-                row_dot_tiled_n<T, NR>(F + i + (int64_t)k * m, m, xs, nc, nc, nrc, o);
-#pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) ts[i + c * k] -= o[c];
-            }
         }
     }
     __syncthreads();
-    constexpr int kCW = (NR > 1 && TT > 64) ? (NR < TT / 64 ? NR : TT / 64) : 1;  // waves with chains
-    constexpr int kCN = NR / kCW;                                               // chains per wave
-    for (int j1 = k; j1 > 0; j1 -= kBS) {
-        const int j0 = max(0, j1 - kBS), bs = j1 - j0;
-        if (wid < kCW && wid < nrc) {
-            T raw[kBS];  // clamped unconditional loads, as in the forward sweep
-            const int lr = j0 + min(lane, bs - 1);
-            if constexpr (kStage) {
+    // the columns in groups of NR, as in the forward sweep
+    for (int cg = 0; cg < nrc; cg += NR) {
+        double* const tg = ts + (int64_t)cg * k;
+        const int ng = min(NR, nrc - cg);
+        if constexpr (FUSE) {
+            if (nc > 0 && k > 0) {
+                for (int i = tid; i < k; i += TT) {
+                    double o[NR];
+                    row_dot_tiled_n<T, NR>(F + i + (int64_t)k * m, m, xs + (int64_t)cg * nc, nc, nc, ng, o);
 #pragma unroll
-                for (int a = 0; a < kBS; a++) raw[a] = dblk[a * kBS + lane];
-            } else {
-#pragma unroll
-                for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+                    for (int c = 0; c < NR; c++)
+                        if (c < ng) tg[i + c * k] -= o[c];
+                }
+                __syncthreads();
             }
-            __builtin_amdgcn_sched_barrier(0);
-            double Ur[kBS];
+        }
+        constexpr int kCW = (NR > 1 && TT > 64) ? (NR < TT / 64 ? NR : TT / 64) : 1;  // waves with chains
+        constexpr int kCN = NR / kCW;                                               // chains per wave
+        for (int j1 = k; j1 > 0; j1 -= kBS) {
+            const int j0 = max(0, j1 - kBS), bs = j1 - j0;
+            if (wid < kCW && wid < ng) {
+                T raw[kBS];  // clamped unconditional loads, as in the forward sweep
+                const int lr = j0 + min(lane, bs - 1);
+                if constexpr (kStage) {
 #pragma unroll
-            for (int a = 0; a < kBS; a++) Ur[a] = ((lane < bs) & (a >= lane) & (a < bs)) ? (double)raw[a] : 0.0;
-            // each lane's reciprocal of its own diagonal entry, taken in parallel
-            // once per block: the sequential sweep then multiplies instead of
-            // dividing (within 1.5 ulp of the quotient)
-            const int ld = min(lane, bs - 1);
-            const double rd = 1.0 / (double)(kStage ? dblk[ld * kBS + ld] : F[lr + (int64_t)lr * m]);
-            // a wave's chains step together, as in the forward sweep
-            double xl[kCN];
+                    for (int a = 0; a < kBS; a++) raw[a] = dblk[a * kBS + lane];
+                } else {
 #pragma unroll
-            for (int q = 0; q < kCN; q++) xl[q] = lane < bs ? ts[j0 + lane + min(wid + kCW * q, nrc - 1) * k] : 0.0;
+                    for (int a = 0; a < kBS; a++) raw[a] = F[lr + (int64_t)(j0 + min(a, bs - 1)) * m];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                double Ur[kBS];
 #pragma unroll
-            for (int a = kBS - 1; a >= 0; a--) {
-                if (a < bs) {
-                    // row a's value and diagonal reciprocal are broadcast from lane a
-                    const double ra = readlane_d(rd, a);
+                for (int a = 0; a < kBS; a++) Ur[a] = ((lane < bs) & (a >= lane) & (a < bs)) ? (double)raw[a] : 0.0;
+                // each lane's reciprocal of itg own diagonal entry, taken in parallel
+                // once per block: the sequential sweep then multiplies instead of
+                // dividing (within 1.5 ulp of the quotient)
+                const int ld = min(lane, bs - 1);
+                const double rd = 1.0 / (double)(kStage ? dblk[ld * kBS + ld] : F[lr + (int64_t)lr * m]);
+                // a wave's chains step together, as in the forward sweep
+                double xl[kCN];
 #pragma unroll
-                    for (int q = 0; q < kCN; q++) {
-                        const double xa = readlane_d(xl[q], a) * ra;
-                        if (lane == a) xl[q] = xa;
-                        if (lane < a) xl[q] -= Ur[a] * xa;
+                for (int q = 0; q < kCN; q++) xl[q] = lane < bs ? tg[j0 + lane + min(wid + kCW * q, ng - 1) * k] : 0.0;
+#pragma unroll
+                for (int a = kBS - 1; a >= 0; a--) {
+                    if (a < bs) {
+                        // row a's value and diagonal reciprocal are broadcast from lane a
+                        const double ra = readlane_d(rd, a);
+#pragma unroll
+                        for (int q = 0; q < kCN; q++) {
+                            const double xa = readlane_d(xl[q], a) * ra;
+                            if (lane == a) xl[q] = xa;
+                            if (lane < a) xl[q] -= Ur[a] * xa;
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int q = 0; q < kCN; q++)
-                if (wid + kCW * q < nrc && lane < bs) ts[j0 + lane + (wid + kCW * q) * k] = xl[q];
+                for (int q = 0; q < kCN; q++)
+                    if (wid + kCW * q < ng && lane < bs) tg[j0 + lane + (wid + kCW * q) * k] = xl[q];
+            }
+            __syncthreads();
+            if constexpr (kStage) {
+                const bool nxt = wid > 0 && j0 > 0;
+                DiagStage<T, TT> st1;
+                if (nxt) st1.load(F, m, max(0, j0 - kBS), j0 - max(0, j0 - kBS));
+                for (int i = tid; i < j0; i += TT) {
+                    const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                    double o[NR];
+                    block_dot_n<T, NR>(Fi, m, tg + j0, k, bs, ng, o);
+#pragma unroll
+                    for (int c = 0; c < NR; c++)
+                        if (c < ng) tg[i + c * k] -= o[c];
+                }
+                if (nxt) st1.store(dblk);
+            } else {
+                for (int i = tid; i < j0; i += TT) {
+                    const gptr<const T> Fi = F + i + (int64_t)j0 * m;
+                    double o[NR];
+                    block_dot_n<T, NR>(Fi, m, tg + j0, k, bs, ng, o);
+#pragma unroll
+                    for (int c = 0; c < NR; c++)
+                        if (c < ng) tg[i + c * k] -= o[c];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if constexpr (kStage) {
-            const bool nxt = wid > 0 && j0 > 0;
-            DiagStage<T, TT> st1;
-            if (nxt) st1.load(F, m, max(0, j0 - kBS), j0 - max(0, j0 - kBS));
-            for (int i = tid; i < j0; i += TT) {
-                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                double o[NR];
-                block_dot_n<T, NR>(Fi, m, ts + j0, k, bs, nrc, o);
-#pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) ts[i + c * k] -= o[c];
-            }
-            if (nxt) st1.store(dblk);
-        } else {
-            for (int i = tid; i < j0; i += TT) {
-                const gptr<const T> Fi = F + i + (int64_t)j0 * m;
-                double o[NR];
-                block_dot_n<T, NR>(Fi, m, ts + j0, k, bs, nrc, o);
-#pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) ts[i + c * k] -= o[c];
-            }
-        }
-        __syncthreads();
     }
     for (int i = tid; i < k; i += TT) {
         const int var = colvar[i];
@@ -2203,9 +2221,12 @@ static void level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count,
                       const uint8_t* skip) {
     // levels of small fronts: one wave per front (the diagonal sweep is one wave's work anyway)
     // (and the L21 product in the same one-wave block)
+    // (several right-hand sides: four at a time there, which keeps the one-wave
+    // blocks at a register count that leaves room for more waves per SIMD)
     if (mmax <= kTriSmallOrder) {
-        hipLaunchKernelGGL((k_fwd_tri<T, 64, true, NR>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc,
-                           st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc, skip);
+        hipLaunchKernelGGL((k_fwd_tri<T, 64, true, (NR > 4 ? 4 : NR)>), dim3(count), dim3(64),
+                           sizeof(double) * (size_t)mmax * nrc, st, S, fn, slot0, prec, b, ldb, vec, nrhs, c0, nrc,
+                           skip);
         return;
     }
     hipLaunchKernelGGL((k_fwd_tri<T, kTriThreads, false, NR>), dim3(count), dim3(kTriThreads),
@@ -2216,9 +2237,9 @@ static void level_fwd(const DevSym& S, const FrontNum* fn, int slot0, int count,
 template <typename T, int NR>
 static void level_bwd(const FrontNum* fn, int slot0, int count, int prec, double* x, int64_t ldx, const double* vec,
                       int nrhs, int c0, int nrc, int mmax, hipStream_t st, const uint8_t* skip) {
-    if (mmax <= kTriSmallOrder) {  // U12 product and sweep in one one-wave block
-        hipLaunchKernelGGL((k_bwd_tri<T, 64, true, NR>), dim3(count), dim3(64), sizeof(double) * (size_t)mmax * nrc,
-                           st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
+    if (mmax <= kTriSmallOrder) {  // U12 product and sweep in one one-wave block (four columns at a time)
+        hipLaunchKernelGGL((k_bwd_tri<T, 64, true, (NR > 4 ? 4 : NR)>), dim3(count), dim3(64),
+                           sizeof(double) * (size_t)mmax * nrc, st, fn, slot0, prec, x, ldx, vec, nrhs, c0, nrc, skip);
         return;
     }
     hipLaunchKernelGGL((k_bwd_gemv<T, NR>), dim3((mmax + kGemvRows - 1) / kGemvRows, count), dim3(kThreads),
