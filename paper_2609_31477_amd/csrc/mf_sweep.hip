@@ -287,52 +287,14 @@ __device__ __forceinline__ void solve_upper(const T* dblk, int j0, int bs, doubl
         if (w + C::kW * q < nrc && lane < bs) t[j0 + lane + (w + C::kW * q) * ldt] = xl[q];
 }
 
-// acc[c] (rows r0 + lane) -= sum over the block's columns of F[r, col0 + a] y[a, c]:
-// the 64 columns are split over the 4 waves (a = wave + 4 q), and the partial
-// sums are combined in wave order by wave 0, which returns them in sub.
+// acc[c] (rows r0 + lane) -= sum over a tile's columns of F[r, col0 + a] y[a, c],
+// in two halves: the tile's entries are loaded first (before the task waits for
+// the vector block they multiply, or while the previous tile is multiplied: they
+// do not depend on it), and the product is formed afterwards.  The 64 columns are
+// split over the 4 waves (a = wave + 4 q), and the partial sums are combined in
+// wave order by wave 0, which returns them in sub.
 template <typename T, int NR>
-__device__ __forceinline__ void block_gemv(gptr<const T> F, int64_t m, int r0, int nr, int col0, int ncol,
-                                           const double* y, int ldy, int nrc, double* part, double* sub) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r = r0 + min(lane, nr - 1);
-    double acc[NR];
-#pragma unroll
-    for (int c = 0; c < NR; c++) acc[c] = 0.0;
-    constexpr int kC = kSwB / 4;
-    for (int q0 = 0; q0 < kSwB / 4; q0 += kC) {
-        T f[kC];
-#pragma unroll
-        for (int q = 0; q < kC; q++) f[q] = F[r + (int64_t)(col0 + min(w + 4 * (q0 + q), ncol - 1)) * m];
-#pragma unroll
-        for (int q = 0; q < kC; q++) {
-            const int a = w + 4 * (q0 + q);
-            if (a < ncol) {
-#pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) acc[c] += (double)f[q] * y[a + c * ldy];
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < NR; c++)
-        if (c < nrc) part[(w * kSwRhs + c) * 64 + lane] = acc[c];
-    __syncthreads();
-    if (w == 0) {
-#pragma unroll
-        for (int c = 0; c < NR; c++)
-            if (c < nrc)
-                sub[c] = (part[(0 * kSwRhs + c) * 64 + lane] + part[(1 * kSwRhs + c) * 64 + lane]) +
-                         (part[(2 * kSwRhs + c) * 64 + lane] + part[(3 * kSwRhs + c) * 64 + lane]);
-    }
-    __syncthreads();
-}
-
-// block_gemv for one right-hand side in two halves: the row's tile entries are
-// loaded before the task waits for the vector block they multiply (they do not
-// depend on it), and the product is formed after the wait; the same operations
-// in the same order as block_gemv<T, 1>.
-template <typename T>
-struct GemvPre1 {
+struct GemvPre {
     static constexpr int kQ = kSwB / 4;
     T f[kQ];
     __device__ __forceinline__ void load(gptr<const T> F, int64_t m, int r0, int nr, int col0, int ncol) {
@@ -341,17 +303,32 @@ struct GemvPre1 {
 #pragma unroll
         for (int q = 0; q < kQ; q++) f[q] = F[r + (int64_t)(col0 + min(w + 4 * q, ncol - 1)) * m];
     }
-    __device__ __forceinline__ void gemv(int ncol, const double* y, double* part, double* sub) const {
+    __device__ __forceinline__ void gemv(int ncol, const double* y, int ldy, int nrc, double* part,
+                                         double* sub) const {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        double acc = 0.0;
+        double acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; c++) acc[c] = 0.0;
 #pragma unroll
         for (int q = 0; q < kQ; q++) {
             const int a = w + 4 * q;
-            if (a < ncol) acc += (double)f[q] * y[a];
+            if (a < ncol) {
+#pragma unroll
+                for (int c = 0; c < NR; c++)
+                    if (c < nrc) acc[c] += (double)f[q] * y[a + c * ldy];
+            }
         }
-        part[(w * kSwRhs) * 64 + lane] = acc;
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+            if (c < nrc) part[(w * kSwRhs + c) * 64 + lane] = acc[c];
         __syncthreads();
-        if (w == 0) sub[0] = (part[lane] + part[kSwRhs * 64 + lane]) + (part[2 * kSwRhs * 64 + lane] + part[3 * kSwRhs * 64 + lane]);
+        if (w == 0) {
+#pragma unroll
+            for (int c = 0; c < NR; c++)
+                if (c < nrc)
+                    sub[c] = (part[(0 * kSwRhs + c) * 64 + lane] + part[(1 * kSwRhs + c) * 64 + lane]) +
+                             (part[(2 * kSwRhs + c) * 64 + lane] + part[(3 * kSwRhs + c) * 64 + lane]);
+        }
         __syncthreads();
     }
 };
@@ -359,7 +336,7 @@ struct GemvPre1 {
 struct SweepLds {
     double z[kSwWhole * kSwRhs];  // whole front: its rows; blocks: own rows [0, 64 nrc) and a vector block after
     union {                       // never live at the same time
-        double part[4 * kSwRhs * 64];  // block_gemv partial sums
+        double part[4 * kSwRhs * 64];  // GemvPre partial sums
         double dblk[kSwB * kSwB];      // staged diagonal block (as double or float)
     } u;
 };
@@ -414,8 +391,8 @@ __device__ void fwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     const int nblk = fs ? (r0 / kSwB) : (k + kSwB - 1) / kSwB;
     for (int j = 0; j < nblk; j++) {
         const int j0 = j * kSwB, bs = min(kSwB, k - j0);
-        GemvPre1<T> g;
-        if constexpr (NR == 1) g.load(F, m, r0, nr, j0, bs);  // in flight during the wait
+        GemvPre<T, NR> g;
+        g.load(F, m, r0, nr, j0, bs);  // in flight during the wait
         wait_geq(A, A.blk + s, j + 1);
         for (int e = tid; e < bs * nrc; e += kSwT) {
             const int a = e % bs, c = e / bs;
@@ -423,8 +400,7 @@ __device__ void fwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
         }
         __syncthreads();
         double sub[NR];
-        if constexpr (NR == 1) g.gemv(bs, yb, L.u.part, sub);
-        else block_gemv<T, NR>(F, m, r0, nr, j0, bs, yb, 64, nrc, L.u.part, sub);
+        g.gemv(bs, yb, 64, nrc, L.u.part, sub);
         if (tid < 64 && lane < nr) {
 #pragma unroll
             for (int c = 0; c < NR; c++)
@@ -536,6 +512,10 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
     pre.load(F, m, r0, nr);
     if (tid < nr)
         for (int c = 0; c < nrc; c++) tr[tid + c * 64] = v[r0 + tid + (int64_t)(A.c0 + c) * m];
+    // the contribution columns 64 at a time, the next tile's entries loaded while
+    // the current one is multiplied
+    GemvPre<T, NR> g;
+    if (k < m) g.load(F, m, r0, nr, k, min(kSwB, m - k));
     for (int j0 = k; j0 < m; j0 += kSwB) {
         const int bs = min(kSwB, m - j0);
         for (int e = tid; e < bs * nrc; e += kSwT) {
@@ -544,20 +524,24 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
             xb[a + c * 64] = var >= 0 ? ld_dev(A.x + var + (int64_t)(A.c0 + c) * A.ldx) : 0.0;
         }
         __syncthreads();
+        const bool more = j0 + kSwB < m;
+        GemvPre<T, NR> gn;
+        if (more) gn.load(F, m, r0, nr, j0 + kSwB, min(kSwB, m - j0 - kSwB));
         double sub[NR];
-        block_gemv<T, NR>(F, m, r0, nr, j0, bs, xb, 64, nrc, L.u.part, sub);
+        g.gemv(bs, xb, 64, nrc, L.u.part, sub);
         if (tid < 64 && lane < nr) {
 #pragma unroll
             for (int c = 0; c < NR; c++)
                 if (c < nrc) tr[lane + c * 64] -= sub[c];
         }
         __syncthreads();
+        if (more) g = gn;
     }
     const int nfs = (k + kSwB - 1) / kSwB, me = r0 / kSwB;
     for (int j = nfs - 1; j > me; j--) {
         const int j0 = j * kSwB, bs = min(kSwB, k - j0);
-        GemvPre1<T> g;
-        if constexpr (NR == 1) g.load(F, m, r0, nr, j0, bs);  // in flight during the wait
+        GemvPre<T, NR> g;
+        g.load(F, m, r0, nr, j0, bs);  // in flight during the wait
         wait_geq(A, A.blk + s, nfs - j);
         for (int e = tid; e < bs * nrc; e += kSwT) {
             const int a = e % bs, c = e / bs;
@@ -565,8 +549,7 @@ __device__ void bwd_block(const SweepArgs& A, int s, const FrontNum& d, int r0, 
         }
         __syncthreads();
         double sub[NR];
-        if constexpr (NR == 1) g.gemv(bs, xb, L.u.part, sub);
-        else block_gemv<T, NR>(F, m, r0, nr, j0, bs, xb, 64, nrc, L.u.part, sub);
+        g.gemv(bs, xb, 64, nrc, L.u.part, sub);
         if (tid < 64 && lane < nr) {
 #pragma unroll
             for (int c = 0; c < NR; c++)
