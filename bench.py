@@ -392,6 +392,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--nrhs", type=int, default=1, choices=[1, 8],
+                    help="right-hand sides per Newton step of the timed leg (8: the precision comparison's shape)")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=128)
     ap.add_argument("--seed", type=int, default=1)
@@ -458,8 +460,8 @@ def main():
     x.zero_()
     # the precision comparison: the same matrices with eight right-hand sides
     # (the first eight rows of each step's seeded stream)
-    rhs8 = [] if args.no_extras else [torch.from_numpy(newton_rhs(s, k, nrhs=8).copy()).to(dev)
-                                      for k in range(nsteps_newton)]
+    rhs8 = [] if args.no_extras and args.nrhs == 1 else [torch.from_numpy(newton_rhs(s, k, nrhs=8).copy()).to(dev)
+                                                         for k in range(nsteps_newton)]
     x8 = torch.empty(8, s.n, dtype=torch.float64, device=dev) if rhs8 else None
     t = time.perf_counter()
     S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
@@ -549,12 +551,13 @@ def main():
             solver.release()
         return out
 
-    main = run_path(args.prec)
-    mixed = None if args.no_mixed or args.prec != "fp64" else run_path("fp32")
+    main = run_path(args.prec, nrhs=args.nrhs)
+    mixed = None if args.no_mixed or args.prec != "fp64" else run_path("fp32", nrhs=args.nrhs)
     eight = {}
-    if rhs8 and args.prec == "fp64" and not args.no_mixed:
+    if rhs8 and args.prec == "fp64" and not args.no_mixed and not args.no_extras and args.nrhs == 1:
         for pr in ("fp64", "fp32", "bf16"):
-            eight[pr] = run_path(pr, nrhs=8, steps=3, warmup=1, profile=False)
+            # the FP64 leg also times one 8-column sweep pair alone
+            eight[pr] = run_path(pr, nrhs=8, steps=3, warmup=1, profile=(pr == "fp64"))
     elapsed, step_ms, omegas, iters, finfo, t_factor = (main["elapsed"], main["step_ms"], main["omegas"],
                                                          main["iters"], main["finfo"], main["t_factor"])
 
@@ -576,7 +579,7 @@ def main():
         "config": {
             "workload": f"2D VIV Newton Jacobian {args.nx}x{args.ny} cells (P2-P1 flow, P2 mesh displacement, "
                         f"P2 multiplier, 2 position dofs), seed {args.seed}, {nsteps_newton} Newton steps cycled, "
-                        f"1 RHS, multifrontal factor+solve, omega<=" + f"{args.target_omega:g}",
+                        f"{args.nrhs} RHS, multifrontal factor+solve, omega<=" + f"{args.target_omega:g}",
             "n": s.n, "nnz": s.nnz, "fronts": view.nfronts, "levels": view.nlevels,
             "precision": args.prec,
         },
@@ -610,6 +613,14 @@ def main():
                                     "omega_max": float(max(r["omegas"])), "outer_max": int(max(r["iters"])),
                                     "inner_per_step": round(sum(r["inner"]) / len(r["inner"]), 1),
                                     "speedup_vs_fp64": round(v / base, 4)}
+            if r["t_sweep"]:
+                # every factor entry is read once for all eight columns
+                b8 = view.nominal_nnz_lu * 8.0
+                res["eight_rhs"][pr]["sweep_pair"] = {
+                    "bound": "hbm", "ms": round(r["t_sweep"], 4), "bytes": b8,
+                    "achieved": round(b8 / (r["t_sweep"] * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(b8 / (r["t_sweep"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                    "kernel": "forward + backward sweep pair over 8 columns plus one residual"}
     if finfo is not None and finfo.schur_launches:
         res["phases_ms"] = {"assemble": round(finfo.t_assemble_ms, 3), "panel_loop": round(finfo.t_panel_ms, 3),
                             "panel_kernel": round(finfo.t_panel_kernel_ms, 3), "schur": round(finfo.t_schur_ms, 3),
