@@ -220,3 +220,31 @@ def test_newton_256x128_planned_bitwise(torch_cuda):
         assert same
     num_l.release()
     num_p.release()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_newton_256x128_columns_bitwise_alone(torch_cuda, prec):
+    """The sweeps take up to eight right-hand sides per pass (each factor entry
+    loaded once for all of them) with every column's arithmetic that of a column
+    alone.  Without refinement, each of eleven columns (a pass of eight, then one
+    of three: the one-wave small-front kernels take them four at a time, so the
+    passes have 4+4 and 3 live columns there, 8 and 3 elsewhere) equals the same
+    column swept alone, bit for bit, through the persistent upper tree and the
+    level kernels of the lower levels."""
+    torch = torch_cuda
+    s = build_2d(256, 128, 1)
+    dev = torch.device("cuda:0")
+    S = mf.Symbolic(s.n, s.rowptr, s.colind, s.root)
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((11, s.n))
+    num = S.factor(torch.from_numpy(newton_values(s, 1)).to(dev), prec=prec, refine=0)
+    X, _ = num.solve(torch.from_numpy(B.copy()).to(dev), check=False)
+    X = X.cpu().numpy()
+    for c in range(11):
+        x1, _ = num.solve(torch.from_numpy(B[c].copy()).to(dev), check=False)
+        x1 = x1.cpu().numpy()
+        nd = int((X[c] != x1).sum())
+        print(f"{prec} column {c}: {nd} entries differ from the column alone", flush=True)
+        assert nd == 0
+    num.release()
