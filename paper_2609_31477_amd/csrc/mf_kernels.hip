@@ -584,13 +584,11 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // ---- final column and row positions
     const int nrej = w - nb;
     const int pc_new = pc - nrej;
+    // accepted columns go to [k0, k0 + nb) in step order, delayed ones to
+    // [pc_new, pc) in window order (their rank among the delayed)
+    if (tid < w && !((elim >> tid) & 1ull)) col_dst[tid] = pc_new + __popcll(~elim & ((1ull << tid) - 1ull));
+    if (tid < nb) col_dst[acc_col[tid]] = kd0 + tid;
     if (tid == 0) {
-        int t = 0, rj = 0;
-        for (int c = 0; c < w; c++) {
-            if ((elim >> c) & 1ull) continue;
-            col_dst[c] = pc_new + rj++;
-        }
-        for (t = 0; t < nb; t++) col_dst[acc_col[t]] = kd0 + t;
         // untried columns displaced by the delayed block move into freed window slots
         int nm = 0;
         int fslot = kd0 + nb;
@@ -611,6 +609,9 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     // row permutation: the pivot row of step t goes to position k0 + t; the rows
     // displaced from [k0, k0 + nb) take, in increasing order, the positions the
     // pivot rows vacated beyond k0 + nb (one wave, ballots for the ranks)
+    // (LDS written and read back by lanes of the one wave: its LDS accesses are
+    // carried out in program order)
+    __shared__ int ispiv_s[NB], vac_s[NB];
     if (wid == 0) {
         const bool has = lane < nb;
         const int pr = has ? piv_row[lane] : 0;
@@ -618,28 +619,18 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             lmap[lane] = pr;             // position k0 + lane receives pivot row pr
             dstm[pr - kd0] = kd0 + lane;
         }
-        // is position k0 + lane itself a pivot row?
-        bool slot_is_piv = false;
-        for (int t = 0; t < nb; t++) slot_is_piv = slot_is_piv || (piv_row[t] == kd0 + lane);
+        // is position k0 + lane itself a pivot row?  (pivot rows are never above k0)
+        if (lane < NB) ispiv_s[lane] = 0;
+        if (has && pr < kd0 + nb) ispiv_s[pr - kd0] = 1;
+        const bool slot_is_piv = has && ispiv_s[lane] != 0;
         const bool displaced = has && !slot_is_piv;           // row k0 + lane must move away
         const bool vacancy = has && (pr >= kd0 + nb);          // position pr frees up
         const uint64_t bd = __ballot(displaced), bv = __ballot(vacancy);
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         // the i-th displaced row (in lane order) takes the i-th vacancy (in lane order)
+        if (vacancy) vac_s[__popcll(bv & below)] = pr;
         if (displaced) {
-            int rd = __popcll(bd & below);
-            uint64_t rest = bv;
-            int q = 0;
-            for (int b = 0; b < 64; b++) {
-                if ((rest >> b) & 1ull) {
-                    if (rd == 0) {
-                        q = b;
-                        break;
-                    }
-                    rd--;
-                }
-            }
-            const int p = piv_row[q];
+            const int p = vac_s[__popcll(bd & below)];
             lmap[p - kd0] = kd0 + lane;
             dstm[lane] = p;
         }
