@@ -379,6 +379,20 @@ __device__ __forceinline__ PivCand cand_wave2(PivCand a) {
     return r;
 }
 
+// Reciprocal of an accepted pivot (finite, nonzero): the hardware estimate
+// refined by Newton steps e = 1 - x r, r += r e (two for double, whose estimate
+// is good to about half the bits; one for float), a shorter dependent chain than
+// the correctly rounded quotient 1 / x and within an ulp of it.
+__device__ __forceinline__ double pivot_recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float pivot_recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <typename T, int NB, int RS, int TH>
 __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* dyn) {
     constexpr int kWaves = TH / 64;
@@ -510,7 +524,7 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
             }
             // one reciprocal of the (uniform) pivot, then a multiply per row: shorter
             // dependency chain than a full division per row, within 1.5 ulp of it
-            const T rpiv = T(1) / ur[U];
+            const T rpiv = pivot_recip(ur[U]);
             // multipliers (zero for rows that are not updated, so their entries stay
             // exactly unchanged)
             T lr[RS];
@@ -843,7 +857,8 @@ __global__ __launch_bounds__(kThreads) void k_swap_trsm(FrontNum* fn, int slot0,
             const int a = idx % nb, b = idx / nb;
             l11[q] = idx < nb * nb ? F[(kd0 + a) + (int64_t)(kd0 + b) * m] : T(0);
         }
-        const int pdv = tid < np ? pairs[1 + 2 * tid] : 0, psv = tid < np ? pairs[2 + 2 * tid] : 0;
+        // (the list's slots exist up to 2 kNBMax pairs: loaded without waiting for np)
+        const int pdv = tid < 2 * kNBMax ? pairs[1 + 2 * tid] : 0, psv = tid < 2 * kNBMax ? pairs[2 + 2 * tid] : 0;
 #pragma unroll
         for (int q = 0; q < kL; q++) {
             const int idx = tid + q * kThreads;
