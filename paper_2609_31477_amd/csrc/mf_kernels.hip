@@ -421,12 +421,16 @@ __device__ __forceinline__ void panel_front(FrontNum* fn, int s, double u, int* 
     T v[RS][NB];
     int pstep[RS];
 #pragma unroll
-    for (int r = 0; r < RS; r++) {
-        const int row = kd0 + tid + TH * r;
-        pstep[r] = row < m ? -1 : -2;
+    for (int r = 0; r < RS; r++) pstep[r] = kd0 + tid + TH * r < m ? -1 : -2;
+    // issued column by column, so the first column steps wait only for the first
+    // columns while the rest of the window is still arriving
 #pragma unroll
-        for (int c = 0; c < NB; c++) v[r][c] = (row < m && c < w) ? F[row + (int64_t)(kd0 + c) * m] : T(0);
-    }
+    for (int c = 0; c < NB; c++)
+#pragma unroll
+        for (int r = 0; r < RS; r++) {
+            const int row = kd0 + tid + TH * r;
+            v[r][c] = (row < m && c < w) ? F[row + (int64_t)(kd0 + c) * m] : T(0);
+        }
     uint64_t elim = 0;
     int nb = 0;
     // The window rotates through the registers G columns at a time: in the group
