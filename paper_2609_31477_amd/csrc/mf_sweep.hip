@@ -133,10 +133,12 @@ __device__ __forceinline__ void gather_row(const SweepArgs& A, int s, const Fron
     const int m = d.m, P = d.P;
     const int src = i < P ? as_global(iv_rowperm(d.iv, P, m))[i] : i;
     const int32_t* rows = A.S.rows + A.S.rows_ptr[s];
+    // (columns c >= nrc repeat column nrc - 1, so no load waits on a per-column
+    // branch; they are not stored)
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; c++)
-        acc[c] = (c < A.nrc && src < d.npiv) ? A.b[rows[src] + (int64_t)(A.c0 + c) * A.ldb] : 0.0;
+        acc[c] = src < d.npiv ? A.b[rows[src] + (int64_t)(A.c0 + min(c, A.nrc - 1)) * A.ldb] : 0.0;
     int dseg = 0;
     for (int tt = A.S.child_ptr[s]; tt < A.S.child_ptr[s + 1]; tt++) {
         const int cs = A.S.child_slot[tt];
@@ -147,8 +149,7 @@ __device__ __forceinline__ void gather_row(const SweepArgs& A, int s, const Fron
             const double* vc = A.vec + dc->voff * A.nrhs;
             const int cm = dc->m;
 #pragma unroll
-            for (int c = 0; c < NR; c++)
-                if (c < A.nrc) acc[c] += ld_dev(vc + ck + ci + (int64_t)(A.c0 + c) * cm);
+            for (int c = 0; c < NR; c++) acc[c] += ld_dev(vc + ck + ci + (int64_t)(A.c0 + min(c, A.nrc - 1)) * cm);
         }
         dseg += dout;
     }
@@ -207,6 +208,12 @@ template <typename T, int NR>
 __device__ __forceinline__ void row_dot(gptr<const T> F, int64_t m, int r, int col0, int n, const double* y, int ldy,
                                         int nrc, double* acc) {
     constexpr int kC = 16;
+    // every column accumulated without a per-column branch (columns c >= nrc
+    // repeat column nrc - 1; their sums are not used), so the products of a
+    // batch of entries issue as one block
+    const double* yc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; c++) yc[c] = y + min(c, nrc - 1) * ldy;
     for (int a0 = 0; a0 < n; a0 += kC) {
         T f[kC];
 #pragma unroll
@@ -215,8 +222,7 @@ __device__ __forceinline__ void row_dot(gptr<const T> F, int64_t m, int r, int c
         for (int q = 0; q < kC; q++) {
             if (a0 + q < n) {
 #pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) acc[c] += (double)f[q] * y[a0 + q + c * ldy];
+                for (int c = 0; c < NR; c++) acc[c] += (double)f[q] * yc[c][a0 + q];
             }
         }
     }
@@ -306,28 +312,31 @@ struct GemvPre {
     __device__ __forceinline__ void gemv(int ncol, const double* y, int ldy, int nrc, double* part,
                                          double* sub) const {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        // no per-column branches (as in row_dot): columns c >= nrc repeat column
+        // nrc - 1 and their sums are not used
+        const double* yc[NR];
         double acc[NR];
 #pragma unroll
-        for (int c = 0; c < NR; c++) acc[c] = 0.0;
+        for (int c = 0; c < NR; c++) {
+            yc[c] = y + min(c, nrc - 1) * ldy;
+            acc[c] = 0.0;
+        }
 #pragma unroll
         for (int q = 0; q < kQ; q++) {
             const int a = w + 4 * q;
             if (a < ncol) {
 #pragma unroll
-                for (int c = 0; c < NR; c++)
-                    if (c < nrc) acc[c] += (double)f[q] * y[a + c * ldy];
+                for (int c = 0; c < NR; c++) acc[c] += (double)f[q] * yc[c][a];
             }
         }
 #pragma unroll
-        for (int c = 0; c < NR; c++)
-            if (c < nrc) part[(w * kSwRhs + c) * 64 + lane] = acc[c];
+        for (int c = 0; c < NR; c++) part[(w * kSwRhs + c) * 64 + lane] = acc[c];
         __syncthreads();
         if (w == 0) {
 #pragma unroll
             for (int c = 0; c < NR; c++)
-                if (c < nrc)
-                    sub[c] = (part[(0 * kSwRhs + c) * 64 + lane] + part[(1 * kSwRhs + c) * 64 + lane]) +
-                             (part[(2 * kSwRhs + c) * 64 + lane] + part[(3 * kSwRhs + c) * 64 + lane]);
+                sub[c] = (part[(0 * kSwRhs + c) * 64 + lane] + part[(1 * kSwRhs + c) * 64 + lane]) +
+                         (part[(2 * kSwRhs + c) * 64 + lane] + part[(3 * kSwRhs + c) * 64 + lane]);
         }
         __syncthreads();
     }
