@@ -1426,6 +1426,16 @@ struct DiagStage {
     }
 };
 
+// The nrc columns of one row of a vector block, loaded into registers before
+// any is stored (a loop that loads and stores to LDS in each iteration would wait
+// for every load in turn): W = 1, or kSwRhs for passes of several columns
+// (nrc <= kSwRhs; columns beyond nrc load column nrc - 1 and are not used).
+template <int W, typename Src>
+__device__ __forceinline__ void load_cols(double (&r)[W], int nrc, Src src) {
+#pragma unroll
+    for (int c = 0; c < W; c++) r[c] = src(min(c, nrc - 1));
+}
+
 // FUSE (one-wave blocks of small-front levels): the same block also forms
 // c = z[k:m] - L21 y, which k_fwd_gemv does otherwise.
 template <typename T, int TT, bool FUSE, int NR>
@@ -1453,10 +1463,17 @@ __global__ __launch_bounds__(TT, TT == 64 && NR > 1 ? 3 : 1) void k_fwd_tri(DevS
             st0.store(dblk);
         }
     }
+    constexpr int kCL = NR == 1 ? 1 : kSwRhs;  // columns a row's loads cover
     for (int i = tid; i < m; i += TT) {
         const int src = i < P ? rowperm[i] : i;
-        for (int c = 0; c < nrc; c++)
-            zs[i + c * m] = (src < d.npiv) ? b[rows[src] + (int64_t)(c0 + c) * ldb] : 0.0;
+        double zr[kCL];
+        if (src < d.npiv) {
+            const double* br = b + rows[src];
+            load_cols<kCL>(zr, nrc, [&](int c) { return br[(int64_t)(c0 + c) * ldb]; });
+        } else {
+#pragma unroll
+            for (int c = 0; c < kCL; c++) zr[c] = 0.0;
+        }
         int dseg = 0;
         for (int tt = cb; tt < ce; tt++) {
             const int cs = S.child_slot[tt];
@@ -1464,11 +1481,17 @@ __global__ __launch_bounds__(TT, TT == 64 && NR > 1 ? 3 : 1) void k_fwd_tri(DevS
             const int dout = dc.P - dc.k;
             const int ci = child_pos(src, d.npiv, d.din, dseg, dout, S.imap + S.imap_off[cs]);
             if (ci >= 0) {
-                const double* vc = vec + dc.voff * nrhs;
-                for (int c = 0; c < nrc; c++) zs[i + c * m] += vc[dc.k + ci + (int64_t)(c0 + c) * dc.m];
+                const double* vc = vec + dc.voff * nrhs + dc.k + ci;
+                double t[kCL];
+                load_cols<kCL>(t, nrc, [&](int c) { return vc[(int64_t)(c0 + c) * dc.m]; });
+#pragma unroll
+                for (int c = 0; c < kCL; c++) zr[c] += t[c];
             }
             dseg += dout;
         }
+#pragma unroll
+        for (int c = 0; c < kCL; c++)
+            if (c < nrc) zs[i + c * m] = zr[c];
     }
     __syncthreads();
     // the columns in groups of NR (one group unless a one-wave block serves more
@@ -1650,8 +1673,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_gemv(const FrontNum* fn, int s
     if (i0 >= m || k == 0) return;
     const gptr<const T> F = as_global((const T*)d.F);
     double* v = vec + d.voff * nrhs;
-    for (int j = threadIdx.x; j < k; j += kThreads)
-        for (int c = 0; c < nrc; c++) ys[j + c * k] = v[j + (int64_t)(c0 + c) * m];
+    for (int j = threadIdx.x; j < k; j += kThreads) {
+        double t[NR];
+        load_cols<NR>(t, nrc, [&](int c) { return v[j + (int64_t)(c0 + c) * m]; });
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+            if (c < nrc) ys[j + c * k] = t[c];
+    }
     __syncthreads();
     const int i = min(i0 + (int)(threadIdx.x & 63), m - 1);  // clamped rows compute, never store
     double t[NR];
@@ -1682,7 +1710,11 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gemv(const FrontNum* fn, int s
     const int nc = m - k;
     for (int j = threadIdx.x; j < nc; j += kThreads) {
         const int var = colvar[k + j];
-        for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
+        double t[NR];
+        load_cols<NR>(t, nrc, [&](int c) { return var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0; });
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+            if (c < nrc) xs[j + c * nc] = t[c];
     }
     __syncthreads();
     const int i = min(i0 + (int)(threadIdx.x & 63), k - 1);  // clamped rows compute, never store
@@ -1720,8 +1752,14 @@ __global__ __launch_bounds__(TT, TT == 64 && NR > 1 ? 3 : 1) void k_bwd_tri(cons
             st0.store(dblk);
         }
     }
-    for (int i = tid; i < k; i += TT)
-        for (int c = 0; c < nrc; c++) ts[i + c * k] = v[i + (int64_t)(c0 + c) * m];
+    constexpr int kCL = NR == 1 ? 1 : kSwRhs;  // columns a row's loads cover
+    for (int i = tid; i < k; i += TT) {
+        double t[kCL];
+        load_cols<kCL>(t, nrc, [&](int c) { return v[i + (int64_t)(c0 + c) * m]; });
+#pragma unroll
+        for (int c = 0; c < kCL; c++)
+            if (c < nrc) ts[i + c * k] = t[c];
+    }
     // FUSE: the solution values of the columns [k, m), after ts
     double* const xs = ts + (int64_t)k * nrc;
     const int nc = m - k;
@@ -1729,7 +1767,11 @@ __global__ __launch_bounds__(TT, TT == 64 && NR > 1 ? 3 : 1) void k_bwd_tri(cons
         if (nc > 0 && k > 0) {
             for (int j = tid; j < nc; j += TT) {
                 const int var = colvar[k + j];
-                for (int c = 0; c < nrc; c++) xs[j + c * nc] = var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0;
+                double t[kCL];
+                load_cols<kCL>(t, nrc, [&](int c) { return var >= 0 ? x[var + (int64_t)(c0 + c) * ldx] : 0.0; });
+#pragma unroll
+                for (int c = 0; c < kCL; c++)
+                    if (c < nrc) xs[j + c * nc] = t[c];
             }
         }
     }
