@@ -14,7 +14,8 @@ while each cuts omega tenfold, then GMRES-IR); the same matrix with eight
 right-hand sides in FP64, FP32 and BF16 (the precision comparison); the
 dominant kernel against its roofline and the Schur GEMM, solve sweeps and
 extend-add against theirs; a large-K Schur GEMM on one dense front in each
-precision; the 64-system batch; and the CPU oracle on a bounded sample.
+precision; the 64-system batch; a short serving stream (40 requests at 16/s);
+and the CPU oracle on a bounded sample.
 
 Prints ONE JSON line (rank 0).  --gpus above 1 is refused: this build measures
 one GPU.
@@ -316,11 +317,12 @@ def serving_parts(meshes, seed=11):
         return dict(zip(meshes, ex.map(value_parts, meshes, [seed] * len(meshes))))
 
 
-def bench_serving(args):
+def bench_serving(args, summary_only=False):
     """Poisson streams of mixed requests (70% 2D meshes 32x16..128x64 cells, 30% 3D
     boxes of 24x12x6 hexahedra; Re ~ U[100,300]; U_r ~ U[2,12] in 2D, U[2.5,17.5] in
     3D), 5 Newton steps each, FP32 fronts + adaptive FP64 refinement to 1e-10, continuous
-    batching; one run per arrival rate."""
+    batching; one run per arrival rate.  summary_only: return the per-rate lines
+    (no JSON line of its own)."""
     import torch
 
     from paper_2609_31477_amd.serving import MFBackend, Scheduler, poisson_requests, summarize
@@ -371,6 +373,15 @@ def bench_serving(args):
                 "host_phase_s": {k: round(v, 3) for k, v in be.times.items()}}
         log(json.dumps(line))
         lines.append(line)
+    if summary_only:
+        return {"workload": f"serving: {args.requests} Poisson requests per rate, {100 * (1 - args.mix_3d):.0f}% 2D "
+                            f"meshes 32x16..128x64 cells, {100 * args.mix_3d:.0f}% 3D boxes 24x12x6, 5 Newton steps "
+                            "each, FP32 fronts + adaptive FP64 refinement, continuous batching, at most "
+                            f"{args.max_cohorts} cohorts at once, omega<={args.target_omega:g} (the full rate sweep: "
+                            "--workload serving)",
+                "per_rate": [{k: l[k] for k in ("rate", "requests", "requests_3d", "solves", "solves_per_s",
+                                                 "p50_request_ms", "p99_request_ms", "p50_step_ms", "p99_step_ms",
+                                                 "mean_batch", "omega_max")} for l in lines]}
     top = max(lines, key=lambda l: l["solves_per_s"])
     res = {"metric": METRIC, "value": top["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
            "steps": top["solves"], "warmup": len(warm), "ms_per_step": round(1e3 / top["solves_per_s"], 3),
@@ -714,6 +725,12 @@ def main():
         res["gemm_large_k"] = gm
         res["batch"] = bench_batch(argparse.Namespace(steps=5, warmup=1, prec="fp32", target_omega=args.target_omega),
                                    summary_only=True)
+        log(f"batch: {json.dumps(res['batch'])}")
+        # a short serving stream at one moderate rate (config 4's shape)
+        res["serving"] = bench_serving(argparse.Namespace(rates="16", rate=16.0, requests=40, seed=args.seed,
+                                                          mix_3d=0.3, target_omega=args.target_omega, max_cohorts=2),
+                                       summary_only=True)
+        log(f"serving: {json.dumps(res['serving'])}")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(view.nominal_flops, full=not args.cpu_fit, nx=args.nx, ny=args.ny)
     print(json.dumps(res), flush=True)
