@@ -57,6 +57,9 @@ hipError_t launch_fill_i32(int32_t* y, int32_t v, hipStream_t st);
 template <typename T>
 hipError_t launch_seg_copy(const SegCopy* segs, const int64_t* start, int nseg, int64_t total, T* out,
                            hipStream_t st);
+template <typename T>
+hipError_t launch_seg_scatter(const SegOut* segs, const int64_t* start, int nseg, int64_t total, const T* in,
+                              hipStream_t st);
 hipError_t launch_nonfinite(const double* v, int64_t nnz, unsigned long long* first, hipStream_t st);
 hipError_t launch_level_setup(const DevSym& S, FrontNum* fn, const FrontNum* tmpl, int slot0, int count, int level,
                               int32_t* overflow, hipStream_t st);
@@ -317,6 +320,9 @@ struct mf_num {
     size_t kry_cap = 0;
     double* d_small = nullptr;  // device coefficients (dots, combination weights)
     double* h_small = nullptr;  // pinned mirror
+    char* d_seg = nullptr;      // segment lists of the batch gathers and scatters
+    char* h_seg = nullptr;      // pinned mirror
+    size_t seg_cap = 0;         // bytes
     unsigned long long* d_omega = nullptr;
     double* d_respart = nullptr;            // residual per-block maxima
     size_t respart_cap = 0;
@@ -472,6 +478,8 @@ struct mf_num {
         if (d_kry) (void)dfree(d_kry);
         if (d_small) (void)dfree(d_small);
         if (h_small) (void)hfree(h_small);
+        if (d_seg) (void)dfree(d_seg);
+        if (h_seg) (void)hfree(h_seg);
         if (d_omega) (void)dfree(d_omega);
         if (d_respart) (void)dfree(d_respart);
         if (h_omega) (void)hfree(h_omega);
@@ -910,6 +918,45 @@ int factor_planned(mf_num* N, const double* fvals, hipStream_t st) {
 // The handle's own copy of the operator values (one array, or one per system of a
 // batch), scanned for NaN and Inf; the scan's result is read back by the next
 // synchronization on the stream (check_finite).
+// The segment lists of one batch gather or scatter, written to the pinned
+// staging buffer (every entry point returns with its stream synchronized, so the
+// buffer is free again when the next call writes it).  Layout: for each list,
+// the segments, then their start offsets (prefix sums, nseg + 1 entries).
+struct SegLists {
+    size_t bytes = 0;
+    template <typename S>
+    static size_t need(size_t nseg) {
+        return ((sizeof(S) * nseg + 15) & ~size_t(15)) + ((sizeof(int64_t) * (nseg + 1) + 15) & ~size_t(15));
+    }
+};
+char* seg_staging(mf_num* N, size_t bytes) {
+    if (bytes > N->seg_cap) {
+        if (N->d_seg) HIPX(dfree(N->d_seg));
+        if (N->h_seg) HIPX(hfree(N->h_seg));
+        N->d_seg = nullptr;
+        N->h_seg = nullptr;
+        HIPX(dmalloc((void**)&N->d_seg, bytes));
+        HIPX(hmalloc((void**)&N->h_seg, bytes, hipHostMallocDefault));
+        N->seg_cap = bytes;
+    }
+    return N->h_seg;
+}
+// Writes the list (segments and starts) at byte offset off of the staging
+// buffer; returns the total count and advances off.
+template <typename S>
+int64_t put_segments(mf_num* N, size_t& off, const std::vector<S>& segs, const S** d_segs, const int64_t** d_start) {
+    S* hs = (S*)(N->h_seg + off);
+    std::copy(segs.begin(), segs.end(), hs);
+    *d_segs = (const S*)(N->d_seg + off);
+    off += (sizeof(S) * segs.size() + 15) & ~size_t(15);
+    int64_t* st = (int64_t*)(N->h_seg + off);
+    st[0] = 0;
+    for (size_t q = 0; q < segs.size(); q++) st[q + 1] = st[q] + segs[q].count;
+    *d_start = (const int64_t*)(N->d_seg + off);
+    off += (sizeof(int64_t) * (segs.size() + 1) + 15) & ~size_t(15);
+    return st[segs.size()];
+}
+
 void load_values(mf_num* N, const double* values_dev, const double* const* seg_values, hipStream_t st) {
     const Symbolic& S = N->sym->S;
     if (!N->d_vals) HIPX(dmalloc((void**)&N->d_vals, sizeof(double) * std::max<int64_t>(S.nnz, 1)));
@@ -918,10 +965,21 @@ void load_values(mf_num* N, const double* values_dev, const double* const* seg_v
         HIPX(hmalloc((void**)&N->h_bad, sizeof(unsigned long long), hipHostMallocDefault));
     }
     if (seg_values) {
+        // every system's values into the batch's array in one launch
+        std::vector<SegCopy> segs;
         for (size_t q = 0; q < S.seg_n.size(); q++) {
             const int64_t nz = (q + 1 < S.seg_n.size() ? S.seg_nnz0[q + 1] : S.nnz) - S.seg_nnz0[q];
-            if (nz) HIPX(hipMemcpyAsync(N->d_vals + S.seg_nnz0[q], seg_values[q], sizeof(double) * nz,
-                                        hipMemcpyDeviceToDevice, st));
+            if (nz) segs.push_back(SegCopy{seg_values[q], S.seg_nnz0[q], nz, 0});
+        }
+        if (!segs.empty()) {
+            const size_t bytes = SegLists::need<SegCopy>(segs.size());
+            seg_staging(N, bytes);
+            size_t off = 0;
+            const SegCopy* ds;
+            const int64_t* dst;
+            const int64_t total = put_segments(N, off, segs, &ds, &dst);
+            HIPX(hipMemcpyAsync(N->d_seg, N->h_seg, off, hipMemcpyHostToDevice, st));
+            HIPX(launch_seg_copy<double>(ds, dst, (int)segs.size(), total, N->d_vals, st));
         }
     } else if (S.nnz && values_dev != N->d_vals) {
         HIPX(hipMemcpyAsync(N->d_vals, values_dev, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, st));
@@ -2270,11 +2328,27 @@ mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const
         // systems with fewer right-hand sides get zero columns: their solution is
         // exactly zero with omega 0, so they never refine
         if (ragged) HIPX(launch_fill(B, 0.0, S.n * nmax, st));
+        // every system's columns in (one gather launch) and out (one scatter launch)
+        std::vector<SegCopy> gin;
+        std::vector<SegOut> sout;
         for (int q = 0; q < nseg; q++) {
             const int nr = nrhs ? nrhs[q] : 1;
-            if (!S.seg_n[q] || !nr) continue;
-            HIPX(hipMemcpy2DAsync(B + S.seg_row0[q], sizeof(double) * S.n, b_dev[q], sizeof(double) * S.seg_n[q],
-                                  sizeof(double) * S.seg_n[q], nr, hipMemcpyDeviceToDevice, st));
+            for (int c = 0; c < nr && S.seg_n[q]; c++) {
+                const int64_t col = (int64_t)c * S.n + S.seg_row0[q], own = (int64_t)c * S.seg_n[q];
+                gin.push_back(SegCopy{b_dev[q] + own, col, S.seg_n[q], 0});
+                sout.push_back(SegOut{x_dev[q] + own, col, S.seg_n[q]});
+            }
+        }
+        seg_staging(N, SegLists::need<SegCopy>(gin.size()) + SegLists::need<SegOut>(sout.size()));
+        size_t off = 0;
+        const SegCopy* d_gin = nullptr;
+        const SegOut* d_sout = nullptr;
+        const int64_t *d_gst = nullptr, *d_sst = nullptr;
+        const int64_t ntot = put_segments(N, off, gin, &d_gin, &d_gst);
+        put_segments(N, off, sout, &d_sout, &d_sst);
+        if (!gin.empty()) {
+            HIPX(hipMemcpyAsync(N->d_seg, N->h_seg, off, hipMemcpyHostToDevice, st));
+            HIPX(launch_seg_copy<double>(d_gin, d_gst, (int)gin.size(), ntot, B, st));
         }
         mf_status rc = MF_OK;
         std::string msg;
@@ -2285,12 +2359,7 @@ mf_status mf_solve_batched(mf_num_t N, const double* const* b_dev, double* const
             rc = f.st;
             msg = f.msg;
         }
-        for (int q = 0; q < nseg; q++) {
-            const int nr = nrhs ? nrhs[q] : 1;
-            if (!S.seg_n[q] || !nr) continue;
-            HIPX(hipMemcpy2DAsync(x_dev[q], sizeof(double) * S.seg_n[q], X + S.seg_row0[q], sizeof(double) * S.n,
-                                  sizeof(double) * S.seg_n[q], nr, hipMemcpyDeviceToDevice, st));
-        }
+        if (!sout.empty()) HIPX(launch_seg_scatter<double>(d_sout, d_sst, (int)sout.size(), ntot, X, st));
         HIPX(hipStreamSynchronize(st));
         if (info)
             for (int q = 0; q < nseg; q++) info[q] = N->seg_info[q];

@@ -125,6 +125,12 @@ struct SegCopy {
     const void* src;
     int64_t dst, count, add;
 };
+// One segment of a scatter out of a single array: count entries from in[src..]
+// to dst.
+struct SegOut {
+    void* dst;
+    int64_t src, count;
+};
 
 // Persistent sweeps (k_fwd_persist / k_bwd_persist): one launch per direction
 // runs every front of every system from a ticket-ordered list of tasks.  Fronts

@@ -2174,9 +2174,38 @@ __global__ __launch_bounds__(kThreads) void k_seg_copy(const SegCopy* __restrict
         }
         const SegCopy g = segs[lo];
         const int64_t o = i - start[lo];
-        out[g.dst + o] = ((const T*)g.src)[o] + (T)g.add;
+        if constexpr (std::is_integral<T>::value) out[g.dst + o] = ((const T*)g.src)[o] + (T)g.add;
+        else out[g.dst + o] = ((const T*)g.src)[o];  // values: copied bit for bit
     }
 }
+// The reverse: segment g of `in` (from g.src, g.count entries) to its own
+// destination g.dst, for all segments in one launch.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_seg_scatter(const SegOut* __restrict__ segs,
+                                                          const int64_t* __restrict__ start, int nseg,
+                                                          const T* __restrict__ in) {
+    const int64_t total = start[nseg];
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (int64_t)gridDim.x * kThreads) {
+        int lo = 0, hi = nseg - 1;  // last segment whose start is <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const SegOut g = segs[lo];
+        const int64_t o = i - start[lo];
+        ((T*)g.dst)[o] = in[g.src + o];
+    }
+}
+template <typename T>
+hipError_t launch_seg_scatter(const SegOut* segs, const int64_t* start, int nseg, int64_t total, const T* in,
+                              hipStream_t st) {
+    if (nseg > 0 && total > 0)
+        hipLaunchKernelGGL(k_seg_scatter<T>, dim3((unsigned)std::min<int64_t>((total + kThreads - 1) / kThreads, 8192)),
+                           dim3(kThreads), 0, st, segs, start, nseg, in);
+    return MF_CHECK_LAUNCH();
+}
+template hipError_t launch_seg_scatter<double>(const SegOut*, const int64_t*, int, int64_t, const double*, hipStream_t);
 template <typename T>
 hipError_t launch_seg_copy(const SegCopy* segs, const int64_t* start, int nseg, int64_t total, T* out,
                            hipStream_t st) {
@@ -2187,6 +2216,7 @@ hipError_t launch_seg_copy(const SegCopy* segs, const int64_t* start, int nseg, 
 }
 template hipError_t launch_seg_copy<int32_t>(const SegCopy*, const int64_t*, int, int64_t, int32_t*, hipStream_t);
 template hipError_t launch_seg_copy<int64_t>(const SegCopy*, const int64_t*, int, int64_t, int64_t*, hipStream_t);
+template hipError_t launch_seg_copy<double>(const SegCopy*, const int64_t*, int, int64_t, double*, hipStream_t);
 
 int panel_nb(int prec, int m) { return class_nb(front_class(m), prec); }
 
