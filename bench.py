@@ -33,7 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Newton-step solves/s & front TFLOP/s, mixed vs FP64 @1e-10 bwd err; p99"
-PANEL_TRAFFIC = {(256, 128, "fp64"): 10631663}  # bytes per panel launch, profiles/panel_traffic_256x128.txt
+PANEL_TRAFFIC = {(256, 128, "fp64"): 10685912}  # bytes per panel launch, profiles/panel_traffic_256x128.txt
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}      # dense MFMA TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0
 

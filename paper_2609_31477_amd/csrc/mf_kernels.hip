@@ -1909,12 +1909,23 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int64_t* rp, const 
         const int64_t row = row0 + threadIdx.x / 16;
         double acc = 0.0, den = 0.0, asum = 0.0;
         if (row < r1) {
-            for (int64_t t = rp[row] + sub; t < rp[row + 1]; t += 16) {
-                const double a = val[t];
-                const double xv = xc[ci[t]];
-                acc = fma(a, xv, acc);
-                den = fma(fabs(a), fabs(xv), den);
-                asum += fabs(a);
+            // two entries per lane and pass, both loaded (and both x gathered)
+            // before either is used; the sums take them in the same order as one
+            // at a time
+            const int64_t te = rp[row + 1];
+            for (int64_t t = rp[row] + sub; t < te; t += 32) {
+                const bool two = t + 16 < te;
+                const double a0 = val[t], a1 = two ? val[t + 16] : 0.0;
+                const int j0 = ci[t], j1 = two ? ci[t + 16] : j0;
+                const double x0 = xc[j0], x1 = xc[j1];
+                acc = fma(a0, x0, acc);
+                den = fma(fabs(a0), fabs(x0), den);
+                asum += fabs(a0);
+                if (two) {
+                    acc = fma(a1, x1, acc);
+                    den = fma(fabs(a1), fabs(x1), den);
+                    asum += fabs(a1);
+                }
             }
         }
         for (int off = 8; off > 0; off >>= 1) {
